@@ -1,0 +1,157 @@
+/*
+ * fcgmg — restricted additive smoothing and geometric multigrid for finite cell Stokes problems
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Saberi & Vogel, "A restricted additive smoother for finite cell flow problems"
+ * (arXiv 2403.11636). The library implements the hot path of its geometric multigrid solver on a
+ * uniform Cartesian background grid of the unit box [0,1]^d (d = 2, 3):
+ *   - the finite cell Stokes operator L of Eq. (12): Q1-Q1 velocity/pressure with the local L2
+ *     projection stabilisation of Eq. (10)-(11), the fictitious-domain weight alpha of Eq. (5)-(7)
+ *     integrated on cut cells by a quadtree/octree, symmetric Nitsche terms on Dirichlet walls;
+ *   - the restricted additive smoother of Eq. (14)-(15) under the three cache policies of
+ *     Sec. 3.1.2 (cache_inverse, cache_matrix, cache_none);
+ *   - the grid transfers of Eq. (13) (one GPU: T = identity, R = P^T), the coarsest direct solve,
+ *     the V-cycle and the standalone solver settings of Sec. 4.
+ *
+ * Conventions for every call
+ *   - Vectors (x, b, r, ...) are caller-owned DEVICE buffers of FP64, contiguous, laid out as d+1
+ *     fields [u_x | u_y | (u_z) | p] of (n_l+1)^d values each, nodes numbered lexicographically
+ *     with x fastest; n_l = n_cells >> (n_levels-1-l) cells per axis on level l (level 0 is the
+ *     coarsest, level n_levels-1 the finest). The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = default stream). Calls are asynchronous on that stream
+ *     unless stated otherwise; inputs must stay valid until the stream reaches the call.
+ *   - Return value: FCGMG_OK or a negative FCGMG_E_* code; fcgmg_last_error() gives a message
+ *     (thread-local). No exception crosses the interface.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently on distinct streams.
+ */
+#ifndef FCGMG_H
+#define FCGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcgmg_ctx* fcgmg_h;
+
+/* Cache policies of Sec. 3.1.2. */
+enum {
+  FCGMG_CACHE_INVERSE = 0, /* store the d+1 kept rows of L_i^{-1} (shared per regular patch class) */
+  FCGMG_CACHE_MATRIX = 1,  /* store L_i (sparse pattern values), factorise at every application    */
+  FCGMG_CACHE_NONE = 2     /* assemble L_i on the fly (incl. cut-cell integration), factorise, solve */
+};
+
+/* Face codes, faces ordered x-, x+, y-, y+, z-, z+. */
+enum {
+  FCGMG_BC_NOSLIP = 0,  /* Dirichlet (Nitsche), w = 0                                  */
+  FCGMG_BC_INFLOW = 1,  /* Dirichlet (Nitsche), parabolic inflow of Eq. (16), H = 1     */
+  FCGMG_BC_NEUMANN = 2  /* pseudo-traction h = 0 ("do-nothing")                         */
+};
+
+enum {
+  FCGMG_OK = 0,
+  FCGMG_E_ARG = -1,      /* invalid argument                                                  */
+  FCGMG_E_NOMEM = -2,    /* device allocation failed                                          */
+  FCGMG_E_HIP = -3,      /* HIP runtime error                                                 */
+  FCGMG_E_SINGULAR = -4, /* a local block L_i or the coarsest operator is singular             */
+  FCGMG_E_NOCONV = -5,   /* solve: max_iter reached (x holds the last iterate)                */
+  FCGMG_E_NAN = -6       /* solve: non-finite residual                                        */
+};
+
+typedef struct {
+  int dim;           /* 2 or 3                                                                 */
+  int n_cells;       /* finest-level cells per axis; divisible by 2^(n_levels-1)               */
+  int n_levels;      /* levels of the hierarchy (Algorithm 1, uniform case: full coarsening)    */
+  int quad_depth;    /* space-tree depth for cut-cell integration                              */
+  int cache_policy;  /* FCGMG_CACHE_*                                                          */
+  int nu_pre;        /* pre-smoothing sweeps per V-cycle                                       */
+  int nu_post;       /* post-smoothing sweeps per V-cycle                                      */
+  int force;         /* body force: 0 none, 1 manufactured (curl of x^2(1-x)^2 y^2(1-y)^2 ...)  */
+  int bc[6];         /* FCGMG_BC_* per face                                                    */
+  double eta;        /* viscosity                                                              */
+  double alpha_fict; /* alpha in the fictitious part, Eq. (7)                                  */
+  double nitsche_beta; /* Nitsche parameter: lambda = beta * eta / h_l                         */
+  double omega;      /* damping, omega_i = omega * I in Eq. (15)                                */
+  double ubar;       /* inflow amplitude, Eq. (16)                                             */
+} fcgmg_params;
+
+typedef struct {
+  int64_t n_cells_axis;   /* n_l                                                                */
+  int64_t n_nodes;        /* (n_l+1)^d                                                          */
+  int64_t n_cut_cells;    /* cells cut by an obstacle surface                                   */
+  int64_t n_fict_cells;   /* cells entirely inside obstacles                                    */
+  int64_t n_classes;      /* regular patch classes (one shared local block each)                */
+  int64_t n_irregular;    /* patches with an individual local block                             */
+  int64_t irregular_cols; /* sum of |S_i| over irregular patches                                */
+  int64_t cached_bytes;   /* device bytes of policy-cached patch data on this level             */
+} fcgmg_level_stats;
+
+/* Build the hierarchy of Algorithm 1 (uniform case: every level fully coarsened), classify cells,
+ * integrate cut cells, classify vertex patches (Eq. 15 subdomains) into shared regular classes and
+ * individual patches, and set up the chosen cache policy (Sec. 3.1.2) and the coarsest-grid direct
+ * solver (Sec. 3). `balls` is a HOST array of n_balls x 4 doubles (centre x, y, z, radius; z
+ * ignored in 2D): the fictitious part of Eq. (7) is the union of the closed balls.
+ * Synchronises `stream`. Errors: E_ARG (bad sizes), E_NOMEM, E_HIP, E_SINGULAR (names the patch). */
+int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_balls, void* stream,
+                          fcgmg_h* out);
+
+/* Number of levels / FP64 values of one vector on `level` ((d+1)*(n_l+1)^d). */
+int fcgmg_num_levels(fcgmg_h h, int* n_levels);
+int fcgmg_num_dofs(fcgmg_h h, int level, int64_t* n_dof);
+
+/* Statistics of one level (host struct). */
+int fcgmg_level_stats_get(fcgmg_h h, int level, fcgmg_level_stats* out);
+
+/* Right-hand side b = (f, g) of Eq. (9) on `level` (body force weighted by alpha, Nitsche data
+ * terms of the Dirichlet walls, h = 0 on Neumann walls). Writes (d+1)*(n_l+1)^d values to b. */
+int fcgmg_rhs(fcgmg_h h, int level, double* b, void* stream);
+
+/* r = b - L x on `level` (Eq. 12, 14). x, b read; r written; r must not alias x or b. */
+int fcgmg_residual(fcgmg_h h, int level, const double* x, const double* b, double* r, void* stream);
+
+/* `sweeps` applications of Eq. (14) with the smoother S of Eq. (15):
+ *   x <- x + sum_i R~_i^T omega L_i^{-1} R_i (b - L x),
+ * every subdomain reading the same residual and writing only the DoFs of its own node (restricted
+ * prolongation R~_i). x is updated in place; b is read. */
+int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream);
+
+/* b_coarse = R r_fine with R = P^T (Eq. 13, T = identity): level `fine_level` to fine_level-1. */
+int fcgmg_restrict(fcgmg_h h, int fine_level, const double* r_fine, double* b_coarse, void* stream);
+
+/* x_fine += P e_coarse (Q1 interpolation, Sec. 3): level fine_level-1 to `fine_level`. */
+int fcgmg_prolongate_add(fcgmg_h h, int fine_level, const double* e_coarse, double* x_fine, void* stream);
+
+/* x = L_0^{-1} b on the coarsest level (direct solver, Sec. 3; bordered with sum(p) = 0 when the
+ * constant pressure is in the kernel). */
+int fcgmg_coarse_solve(fcgmg_h h, const double* b, double* x, void* stream);
+
+/* One V-cycle on the finest level (Sec. 3, 4): nu_pre sweeps, residual restriction, recursive
+ * coarse correction from a zero guess, prolongation, nu_post sweeps. x updated in place. */
+int fcgmg_vcycle(fcgmg_h h, double* x, const double* b, void* stream);
+
+/* Standalone GMG (Sec. 4): V-cycles until ||b - L x||_2 <= rtol ||b - L x0||_2 (Euclidean norm
+ * over all DoFs) or max_iter cycles. Synchronises `stream` once per cycle to read the norm.
+ * *iters, *rel_res receive the cycle count and final ratio (also on E_NOCONV / E_NAN).
+ * res_hist (optional HOST array of max_iter+1 doubles) receives the residual norms. */
+int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter, int* iters,
+                double* rel_res, double* res_hist, void* stream);
+
+/* ||v||_2 of a level vector, written to *out (host) after synchronising `stream`. */
+int fcgmg_norm(fcgmg_h h, int level, const double* v, double* out, void* stream);
+
+/* Device bytes held by the handle (all levels, all policy data). */
+int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
+
+/* Release every device buffer of the handle. NULL is accepted. */
+void fcgmg_destroy(fcgmg_h h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* fcgmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCGMG_H */

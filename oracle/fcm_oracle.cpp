@@ -440,8 +440,8 @@ void assemble_level(Prob& P, int l) {
   }
 }
 
-// y = L x on level l (plain stencil product).
-void matvec(const Prob& P, int l, const double* x, double* y) {
+// y = L x on level l (plain stencil product); with absolute = true, y = |L| x (entrywise |L|).
+void matvec(const Prob& P, int l, const double* x, double* y, bool absolute = false) {
   const Level& L = P.lev[l];
   const int d = P.d, nf = d + 1, no = nstencil(d);
   const long N = L.N;
@@ -462,7 +462,10 @@ void matvec(const Prob& P, int l, const double* x, double* y) {
         }
         if (!in) continue;
         long j = node_index(d, L.n, cc);
-        for (int g = 0; g < nf; ++g) s += L.st[st_index(d, i, f, o, g)] * x[g * N + j];
+        for (int g = 0; g < nf; ++g) {
+          const double a = L.st[st_index(d, i, f, o, g)];
+          s += (absolute ? std::fabs(a) : a) * x[g * N + j];
+        }
       }
       y[f * N + i] = s;
     }
@@ -985,6 +988,9 @@ void orc_rhs(void* h, int l, double* b) {
 }
 
 void orc_matvec(void* h, int l, const double* x, double* y) { matvec(*static_cast<Prob*>(h), l, x, y); }
+
+// y = |L| x (used by tests to bound rounding errors of residuals componentwise).
+void orc_abs_matvec(void* h, int l, const double* x, double* y) { matvec(*static_cast<Prob*>(h), l, x, y, true); }
 
 void orc_residual(void* h, int l, const double* x, const double* b, double* r) {
   residual(*static_cast<Prob*>(h), l, x, b, r);

@@ -54,6 +54,7 @@ def lib():
         L.orc_cell_kinds.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_byte)]
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p]
         L.orc_matvec.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p]
+        L.orc_abs_matvec.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p]
         L.orc_residual.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, c_double_p]
         L.orc_smooth.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_int]
@@ -170,6 +171,13 @@ class Oracle:
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.zeros_like(x)
         lib().orc_matvec(self.h, level, _dp(x), _dp(y))
+        return y
+
+    def abs_matvec(self, level: int, x: np.ndarray) -> np.ndarray:
+        """|L| x with the entrywise absolute value of the level operator."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        lib().orc_abs_matvec(self.h, level, _dp(x), _dp(y))
         return y
 
     def residual(self, level: int, x: np.ndarray, b: np.ndarray) -> np.ndarray:

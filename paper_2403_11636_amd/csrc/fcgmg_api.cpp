@@ -1,0 +1,638 @@
+// Host planner and C-ABI of the fcgmg library (see include/fcgmg.h).
+//
+// Set-up follows Saberi & Vogel (arXiv 2403.11636): the level hierarchy of Algorithm 1 (uniform
+// background grid: every cell coarsened at each step), cell classification and cut-cell
+// integration, classification of the vertex patches of Eq. (15) into shared regular classes and
+// individual patches, the cache policy of Sec. 3.1.2 and the coarsest-grid direct solver (Sec. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fcgmg_impl.h"
+
+using namespace fcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define FCG_HIP(call)                                                                            \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail(FCGMG_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int dev_alloc(Ctx& c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return FCGMG_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(FCGMG_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  c.allocs.push_back(*p);
+  c.bytes += bytes;
+  return FCGMG_OK;
+}
+
+template <class T>
+int alloc_n(Ctx& c, T** p, size_t n) {
+  return dev_alloc(c, reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reference element data of uncut cells and Nitsche face matrices (host, once per level).
+// ---------------------------------------------------------------------------------------------
+template <int D>
+void build_consts(const Ctx& c, Level& L) {
+  constexpr int NN = 1 << D;
+  OpConsts& oc = L.consts_h;
+  std::memset(&oc, 0, sizeof(oc));
+  oc.n = L.n;
+  oc.h = L.h;
+  const double eta = c.prm.eta;
+  oc.lam = c.prm.nitsche_beta * eta / L.h;
+  const double lo[3] = {0, 0, 0};
+  // kind 0: alpha = 1 (no obstacle); kind 1: alpha = alpha_f everywhere (one ball covering the cell)
+  const double cover[4] = {0.5 * L.h, 0.5 * L.h, 0.5 * L.h, 4.0 * L.h};
+  for (int kind = 0; kind < 2; ++kind) {
+    Geom g{cover, kind, 0, c.prm.alpha_fict};
+    double acc[PT<D>::NEL] = {0};
+    tree_quadrature<D>(g, lo, L.h, [&](const double* x, double w, double alpha) {
+      double phi[NN], gr[NN][3];
+      q1<D>(lo, L.h, x, phi, gr);
+      for (int e = 0; e < PT<D>::NEL; ++e) acc[e] += point_entry<D>(e, eta, w * alpha, phi, gr);
+    });
+    for (int ab = 0; ab < NN * NN; ++ab) {
+      oc.K[kind][ab] = acc[ab];
+      for (int cc = 0; cc < D; ++cc) oc.B[kind][cc][ab] = acc[(1 + cc) * NN * NN + ab];
+    }
+  }
+  // stabilisation: -(1/eta)(M - m m^T / |K|), exact 2^d Gauss (no alpha)
+  {
+    Geom g{nullptr, 0, 0, 1.0};
+    double M[NN * NN] = {0}, m[NN] = {0};
+    tree_quadrature<D>(g, lo, L.h, [&](const double* x, double w, double) {
+      double phi[NN], gr[NN][3];
+      q1<D>(lo, L.h, x, phi, gr);
+      for (int a = 0; a < NN; ++a) {
+        m[a] += w * phi[a];
+        for (int b = 0; b < NN; ++b) M[a * NN + b] += w * phi[a] * phi[b];
+      }
+    });
+    const double vol = std::pow(L.h, D);
+    for (int a = 0; a < NN; ++a)
+      for (int b = 0; b < NN; ++b) oc.C[a * NN + b] = -(1.0 / eta) * (M[a * NN + b] - m[a] * m[b] / vol);
+  }
+  // Nitsche face terms: -(v, n.eta grad u) - (n.eta grad v, u) + (v, lambda u) per component and
+  // (v, n p) + (n q, u) on each Dirichlet wall (2-point Gauss per tangential direction).
+  for (int k = 0; k < D; ++k)
+    for (int sd = 0; sd < 2; ++sd) {
+      const int face = 2 * k + sd;
+      const int code = c.prm.bc[face];
+      oc.dirichlet[face] = code != FCGMG_BC_NEUMANN;
+      if (!oc.dirichlet[face]) continue;
+      const double nk = sd ? 1.0 : -1.0;
+      const double w = D == 2 ? 0.5 * L.h : 0.25 * L.h * L.h;
+      for (int gp = 0; gp < (1 << (D - 1)); ++gp) {
+        double x[3] = {0, 0, 0};
+        int t = 0;
+        for (int j = 0; j < D; ++j) {
+          if (j == k) {
+            x[j] = sd ? L.h : 0.0;
+          } else {
+            x[j] = L.h * (((gp >> t) & 1) ? FCG_GB : FCG_GA);
+            ++t;
+          }
+        }
+        double phi[NN], gr[NN][3];
+        q1<D>(lo, L.h, x, phi, gr);
+        for (int a = 0; a < NN; ++a)
+          for (int b = 0; b < NN; ++b) {
+            oc.FK[face][a * NN + b] += w * (-eta * phi[a] * nk * gr[b][k] - eta * nk * gr[a][k] * phi[b] +
+                                            oc.lam * phi[a] * phi[b]);
+            oc.FB[face][a * NN + b] += w * phi[a] * nk * phi[b];
+          }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Patch classification: a patch whose 6^d cell window (clipped to the grid) holds no cut cell
+// and only one kind of uncut cell has a block L_i determined by its distances to the walls
+// (clipped at 3) and that kind; such patches share one class. All others are individual.
+// ---------------------------------------------------------------------------------------------
+template <int D>
+void classify_patches(const Level& L, const std::vector<signed char>& kinds, std::vector<int>& node_class,
+                      std::vector<int>& class_rep, std::vector<int>& irr_nodes) {
+  const int n = L.n;
+  const int64_t m = n + 1;  // summed-area tables over cells, size (n+1)^D
+  std::vector<int> sat_cut(D == 2 ? m * m : m * m * m, 0), sat_fic(sat_cut.size(), 0);
+  auto sidx = [&](int x, int y, int z) { return (int64_t)x + m * ((int64_t)y + m * (int64_t)z); };
+  for (int z = 0; z < (D == 3 ? n : 1); ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const int64_t cell = x + (int64_t)n * (y + (int64_t)n * z);
+        const int kc = kinds[cell] == 2, kf = kinds[cell] == 1;
+        const int zz = D == 3 ? z + 1 : 0;
+        if (D == 2) {
+          sat_cut[sidx(x + 1, y + 1, 0)] = kc + sat_cut[sidx(x, y + 1, 0)] + sat_cut[sidx(x + 1, y, 0)] - sat_cut[sidx(x, y, 0)];
+          sat_fic[sidx(x + 1, y + 1, 0)] = kf + sat_fic[sidx(x, y + 1, 0)] + sat_fic[sidx(x + 1, y, 0)] - sat_fic[sidx(x, y, 0)];
+        } else {
+          auto upd = [&](std::vector<int>& S, int v) {
+            S[sidx(x + 1, y + 1, zz)] = v + S[sidx(x, y + 1, zz)] + S[sidx(x + 1, y, zz)] + S[sidx(x + 1, y + 1, zz - 1)] -
+                                        S[sidx(x, y, zz)] - S[sidx(x, y + 1, zz - 1)] - S[sidx(x + 1, y, zz - 1)] +
+                                        S[sidx(x, y, zz - 1)];
+          };
+          upd(sat_cut, kc);
+          upd(sat_fic, kf);
+        }
+      }
+  auto box_sum = [&](const std::vector<int>& S, const int* lo, const int* hi) -> int64_t {
+    // inclusive cell ranges lo..hi
+    if (D == 2)
+      return S[sidx(hi[0] + 1, hi[1] + 1, 0)] - S[sidx(lo[0], hi[1] + 1, 0)] - S[sidx(hi[0] + 1, lo[1], 0)] +
+             S[sidx(lo[0], lo[1], 0)];
+    return S[sidx(hi[0] + 1, hi[1] + 1, hi[2] + 1)] - S[sidx(lo[0], hi[1] + 1, hi[2] + 1)] -
+           S[sidx(hi[0] + 1, lo[1], hi[2] + 1)] - S[sidx(hi[0] + 1, hi[1] + 1, lo[2])] + S[sidx(lo[0], lo[1], hi[2] + 1)] +
+           S[sidx(lo[0], hi[1] + 1, lo[2])] + S[sidx(hi[0] + 1, lo[1], lo[2])] - S[sidx(lo[0], lo[1], lo[2])];
+  };
+  std::map<int, int> key2cls;
+  node_class.assign(L.N, 0);
+  class_rep.clear();
+  irr_nodes.clear();
+  for (int64_t node = 0; node < L.N; ++node) {
+    int c[3] = {(int)(node % m), (int)((node / m) % m), D == 3 ? (int)(node / (m * m)) : 0};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int64_t tot = 1;
+    int key = 0;
+    for (int k = 0; k < D; ++k) {
+      lo[k] = std::max(c[k] - 3, 0);
+      hi[k] = std::min(c[k] + 2, n - 1);
+      tot *= (hi[k] - lo[k] + 1);
+      key = key * 16 + std::min(c[k], 3) * 4 + std::min(n - c[k], 3);
+    }
+    const int64_t ncut = box_sum(sat_cut, lo, hi);
+    const int64_t nfic = box_sum(sat_fic, lo, hi);
+    if (ncut == 0 && (nfic == 0 || nfic == tot)) {
+      key = key * 2 + (nfic ? 1 : 0);
+      auto it = key2cls.find(key);
+      int cls;
+      if (it == key2cls.end()) {
+        cls = (int)class_rep.size();
+        key2cls[key] = cls;
+        class_rep.push_back((int)node);
+      } else {
+        cls = it->second;
+      }
+      node_class[node] = cls;
+    } else {
+      node_class[node] = -(int)irr_nodes.size() - 1;
+      irr_nodes.push_back((int)node);
+    }
+  }
+}
+
+// Dense inverse by Gaussian elimination with partial pivoting (host; coarsest grid only).
+bool dense_inverse(int n, std::vector<double>& A, std::vector<double>& Inv) {
+  Inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Inv[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::fabs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > best) {
+        best = std::fabs(A[(size_t)i * n + k]);
+        p = i;
+      }
+    if (!(best > 0.0)) return false;
+    if (p != k)
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+        std::swap(Inv[(size_t)k * n + j], Inv[(size_t)p * n + j]);
+      }
+    const double piv = A[(size_t)k * n + k];
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const double l = A[(size_t)i * n + k] / piv;
+      if (l == 0.0) continue;
+      for (int j = k; j < n; ++j) A[(size_t)i * n + j] -= l * A[(size_t)k * n + j];
+      for (int j = 0; j < n; ++j) Inv[(size_t)i * n + j] -= l * Inv[(size_t)k * n + j];
+    }
+    for (int j = k; j < n; ++j) A[(size_t)k * n + j] /= piv;
+    for (int j = 0; j < n; ++j) Inv[(size_t)k * n + j] /= piv;
+  }
+  return true;
+}
+
+constexpr int kCoarseMaxDofs = 6000;
+constexpr int kRedBlocks = 512;
+
+template <int D>
+int setup_impl(Ctx& c, hipStream_t s) {
+  const fcgmg_params& P = c.prm;
+  const int nlev = P.n_levels;
+  c.lev.resize(nlev);
+  int rc;
+  if ((rc = alloc_n(c, &c.err, 1))) return rc;
+  const int imax = INT_MAX;
+  FCG_HIP(hipMemcpyAsync(c.err, &imax, sizeof(int), hipMemcpyHostToDevice, s));
+  if (!c.balls_h.empty()) {
+    if ((rc = alloc_n(c, &c.balls, c.balls_h.size()))) return rc;
+    FCG_HIP(hipMemcpyAsync(c.balls, c.balls_h.data(), c.balls_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  if ((rc = alloc_n(c, &c.red, kRedBlocks + 1))) return rc;
+  FCG_HIP(hipHostMalloc((void**)&c.red_host, sizeof(double), hipHostMallocDefault));
+  if (P.cache_policy == FCGMG_CACHE_MATRIX) {
+    std::vector<int> enc;
+    pattern_entries<D>(enc);
+    c.n_pattern = (int)enc.size();
+    if ((rc = alloc_n(c, &c.pattern, enc.size()))) return rc;
+    FCG_HIP(hipMemcpyAsync(c.pattern, enc.data(), enc.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    FCG_HIP(hipStreamSynchronize(s));  // enc must outlive the copy
+  }
+  signed char* kinds_d = nullptr;
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = c.lev[l];
+    L.n = P.n_cells >> (nlev - 1 - l);
+    L.h = 1.0 / L.n;
+    L.N = 1;
+    L.ncells = 1;
+    for (int k = 0; k < D; ++k) {
+      L.N *= (L.n + 1);
+      L.ncells *= L.n;
+    }
+    const int64_t nd = (D + 1) * L.N;
+    if ((rc = alloc_n(c, &L.r, nd))) return rc;
+    if (l < nlev - 1) {
+      if ((rc = alloc_n(c, &L.x, nd))) return rc;
+      if ((rc = alloc_n(c, &L.b, nd))) return rc;
+    }
+    // cells
+    FCG_HIP(hipMallocAsync((void**)&kinds_d, L.ncells, s));
+    FCG_HIP(k_classify_cells<D>(c, L, kinds_d, s));
+    std::vector<signed char> kinds(L.ncells);
+    FCG_HIP(hipMemcpyAsync(kinds.data(), kinds_d, L.ncells, hipMemcpyDeviceToHost, s));
+    FCG_HIP(hipStreamSynchronize(s));
+    FCG_HIP(hipFreeAsync(kinds_d, s));
+    std::vector<int> info(L.ncells), cut_list;
+    for (int64_t i = 0; i < L.ncells; ++i) {
+      if (kinds[i] == 2) {
+        info[i] = (int)cut_list.size();
+        cut_list.push_back((int)i);
+      } else {
+        info[i] = kinds[i] == 1 ? -2 : -1;
+        if (kinds[i] == 1) ++L.n_fict;
+      }
+    }
+    L.n_cut = (int64_t)cut_list.size();
+    if ((rc = alloc_n(c, &L.cell_info, L.ncells))) return rc;
+    FCG_HIP(hipMemcpyAsync(L.cell_info, info.data(), L.ncells * sizeof(int), hipMemcpyHostToDevice, s));
+    int* cut_d = nullptr;
+    if (L.n_cut) {
+      if ((rc = alloc_n(c, &L.cut_mats, (size_t)L.n_cut * PT<D>::NEL))) return rc;
+      FCG_HIP(hipMallocAsync((void**)&cut_d, L.n_cut * sizeof(int), s));
+      FCG_HIP(hipMemcpyAsync(cut_d, cut_list.data(), L.n_cut * sizeof(int), hipMemcpyHostToDevice, s));
+      FCG_HIP(k_cut_matrices<D>(c, L, cut_d, s));
+      FCG_HIP(hipFreeAsync(cut_d, s));
+    }
+    build_consts<D>(c, L);
+    if ((rc = alloc_n(c, &L.consts, 1))) return rc;
+    FCG_HIP(hipMemcpyAsync(L.consts, &L.consts_h, sizeof(OpConsts), hipMemcpyHostToDevice, s));
+    // patches
+    std::vector<int> ncls, reps, irr;
+    classify_patches<D>(L, kinds, ncls, reps, irr);
+    L.n_classes = (int64_t)reps.size();
+    L.n_irr = (int64_t)irr.size();
+    L.irr_cols = 0;
+    for (int node : irr) {
+      int cc[3] = {(int)(node % (L.n + 1)), (int)((node / (L.n + 1)) % (L.n + 1)), D == 3 ? (int)(node / ((int64_t)(L.n + 1) * (L.n + 1))) : 0};
+      int64_t nv = 1, np = 1;
+      for (int k = 0; k < D; ++k) {
+        nv *= std::min(cc[k] + 2, L.n) - std::max(cc[k] - 2, 0) + 1;
+        np *= std::min(cc[k] + 1, L.n) - std::max(cc[k] - 1, 0) + 1;
+      }
+      L.irr_cols += D * nv + np;
+    }
+    if ((rc = alloc_n(c, &L.node_class, L.N))) return rc;
+    FCG_HIP(hipMemcpyAsync(L.node_class, ncls.data(), L.N * sizeof(int), hipMemcpyHostToDevice, s));
+    if (L.n_classes) {
+      if ((rc = alloc_n(c, &L.class_rep, L.n_classes))) return rc;
+      FCG_HIP(hipMemcpyAsync(L.class_rep, reps.data(), L.n_classes * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    if (L.n_irr) {
+      if ((rc = alloc_n(c, &L.irr_nodes, L.n_irr))) return rc;
+      FCG_HIP(hipMemcpyAsync(L.irr_nodes, irr.data(), L.n_irr * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    // the host vectors above must outlive the asynchronous copies
+    FCG_HIP(hipStreamSynchronize(s));
+    // cache policy (Sec. 3.1.2)
+    if (P.cache_policy == FCGMG_CACHE_INVERSE) {
+      const size_t row = (size_t)(D + 1) * PT<D>::ZSP;
+      if ((rc = alloc_n(c, &L.Zcls, L.n_classes * row))) return rc;
+      if ((rc = alloc_n(c, &L.Zirr, L.n_irr * row))) return rc;
+      L.cached_bytes = (L.n_classes + L.n_irr) * row * sizeof(double);
+      FCG_HIP(k_patch_inverse_rows<D>(c, L, L.class_rep, L.n_classes, L.Zcls, s));
+      FCG_HIP(k_patch_inverse_rows<D>(c, L, L.irr_nodes, L.n_irr, L.Zirr, s));
+    } else if (P.cache_policy == FCGMG_CACHE_MATRIX) {
+      if ((rc = alloc_n(c, &L.Mcls, L.n_classes * (size_t)c.n_pattern))) return rc;
+      if ((rc = alloc_n(c, &L.Mirr, L.n_irr * (size_t)c.n_pattern))) return rc;
+      L.cached_bytes = (L.n_classes + L.n_irr) * (size_t)c.n_pattern * sizeof(double);
+      FCG_HIP(k_store_matrices<D>(c, L, L.class_rep, L.n_classes, L.Mcls, s));
+      FCG_HIP(k_store_matrices<D>(c, L, L.irr_nodes, L.n_irr, L.Mirr, s));
+      if (l > 0) FCG_HIP(k_patch_solve<D>(c, L, P.cache_policy, nullptr, nullptr, s));  // validation pass
+    } else {
+      if (l > 0) FCG_HIP(k_patch_solve<D>(c, L, P.cache_policy, nullptr, nullptr, s));  // validation pass
+    }
+    int errv = INT_MAX;
+    FCG_HIP(hipMemcpyAsync(&errv, c.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    FCG_HIP(hipStreamSynchronize(s));
+    if (errv != INT_MAX)
+      return fail(FCGMG_E_SINGULAR, "singular local block L_i of patch node " + std::to_string(errv) + " on level " +
+                                        std::to_string(l));
+  }
+  // coarsest level: dense operator, bordered when the constant pressure lies in the kernel
+  {
+    Level& L = c.lev[0];
+    const int nd = (int)((D + 1) * L.N);
+    if (nd > kCoarseMaxDofs)
+      return fail(FCGMG_E_ARG, "coarsest level has " + std::to_string(nd) + " DoFs; the direct solver accepts at most " +
+                                   std::to_string(kCoarseMaxDofs) + " (use more levels)");
+    bool all_dir = true;
+    for (int k = 0; k < 2 * D; ++k)
+      if (P.bc[k] == FCGMG_BC_NEUMANN) all_dir = false;
+    c.bordered = all_dir && (c.balls_h.empty() || P.alpha_fict == 1.0);
+    double* A_d = nullptr;
+    FCG_HIP(hipMallocAsync((void**)&A_d, (size_t)nd * nd * sizeof(double), s));
+    FCG_HIP(k_coarse_matrix<D>(c, L, A_d, nd, s));
+    std::vector<double> A((size_t)nd * nd);
+    FCG_HIP(hipMemcpyAsync(A.data(), A_d, A.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FCG_HIP(hipStreamSynchronize(s));
+    FCG_HIP(hipFreeAsync(A_d, s));
+    const int m = nd + (c.bordered ? 1 : 0);
+    std::vector<double> Ab((size_t)m * m, 0.0), Inv;
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j) Ab[(size_t)i * m + j] = A[(size_t)i * nd + j];
+    if (c.bordered)
+      for (int i = (int)(D * L.N); i < nd; ++i) {
+        Ab[(size_t)i * m + nd] = 1.0;
+        Ab[(size_t)nd * m + i] = 1.0;
+      }
+    if (!dense_inverse(m, Ab, Inv)) return fail(FCGMG_E_SINGULAR, "singular coarsest-grid operator");
+    std::vector<double> Ic((size_t)nd * nd);
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j) Ic[(size_t)i * nd + j] = Inv[(size_t)i * m + j];
+    c.coarse_n = nd;
+    if ((rc = alloc_n(c, &c.coarse_inv, Ic.size()))) return rc;
+    FCG_HIP(hipMemcpyAsync(c.coarse_inv, Ic.data(), Ic.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    FCG_HIP(hipStreamSynchronize(s));
+  }
+  return FCGMG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Operations (dimension-dispatched).
+// ---------------------------------------------------------------------------------------------
+template <int D>
+int residual_impl(const Ctx& c, int l, const double* x, const double* b, double* r, hipStream_t s) {
+  FCG_HIP(k_residual<D>(c, c.lev[l], x, b, r, s));
+  return FCGMG_OK;
+}
+
+template <int D>
+int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
+  const Level& L = c.lev[l];
+  FCG_HIP(k_residual<D>(c, L, x, b, L.r, s));
+  if (c.prm.cache_policy == FCGMG_CACHE_INVERSE) {
+    FCG_HIP(k_apply_inverse<D>(c, L, L.r, x, s));
+  } else {
+    FCG_HIP(k_patch_solve<D>(c, L, c.prm.cache_policy, L.r, x, s));
+  }
+  return FCGMG_OK;
+}
+
+int coarse_impl(const Ctx& c, const double* b, double* x, hipStream_t s) {
+  FCG_HIP(k_dense_matvec(c.coarse_inv, c.coarse_n, b, x, s));
+  return FCGMG_OK;
+}
+
+template <int D>
+int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
+  if (l == 0) return coarse_impl(c, b, x, s);
+  int rc;
+  for (int i = 0; i < c.prm.nu_pre; ++i)
+    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+  const Level& L = c.lev[l];
+  const Level& C = c.lev[l - 1];
+  FCG_HIP(k_residual<D>(c, L, x, b, L.r, s));
+  FCG_HIP(k_restrict<D>(c, l, L.r, C.b, s));
+  FCG_HIP(k_zero(C.x, (D + 1) * C.N, s));
+  if ((rc = vcycle_impl<D>(c, l - 1, C.x, C.b, s))) return rc;
+  FCG_HIP(k_prolong_add<D>(c, l, C.x, x, s));
+  for (int i = 0; i < c.prm.nu_post; ++i)
+    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+  return FCGMG_OK;
+}
+
+int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {
+  FCG_HIP(k_sumsq(v, n, c.red, kRedBlocks, s));
+  FCG_HIP(k_finish_sumsq(c.red, kRedBlocks, c.red + kRedBlocks, s));
+  FCG_HIP(hipMemcpyAsync(c.red_host, c.red + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  FCG_HIP(hipStreamSynchronize(s));
+  *out = std::sqrt(*c.red_host);
+  return FCGMG_OK;
+}
+
+bool valid_level(const Ctx* c, int l) { return c && l >= 0 && l < (int)c->lev.size(); }
+
+}  // namespace
+
+struct fcgmg_ctx : public Ctx {};
+
+extern "C" {
+
+const char* fcgmg_last_error(void) { return g_err.c_str(); }
+
+void fcgmg_destroy(fcgmg_h h) {
+  if (!h) return;
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->red_host) (void)hipHostFree(h->red_host);
+  delete h;
+}
+
+int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_balls, void* stream, fcgmg_h* out) {
+  g_err.clear();
+  if (!prm || !out) return fail(FCGMG_E_ARG, "null argument");
+  *out = nullptr;
+  const fcgmg_params& P = *prm;
+  if (P.dim != 2 && P.dim != 3) return fail(FCGMG_E_ARG, "dim must be 2 or 3");
+  if (P.n_levels < 1 || P.n_levels > 20) return fail(FCGMG_E_ARG, "n_levels out of range");
+  if (P.n_cells < 1 || ((P.n_cells >> (P.n_levels - 1)) << (P.n_levels - 1)) != P.n_cells)
+    return fail(FCGMG_E_ARG, "n_cells must be a positive multiple of 2^(n_levels-1)");
+  if ((int64_t)P.n_cells + 1 > (P.dim == 2 ? 46340 : 1290))
+    return fail(FCGMG_E_ARG, "grid too large for 32-bit node indices");
+  if (P.quad_depth < 0 || P.quad_depth > 7) return fail(FCGMG_E_ARG, "quad_depth must be in [0,7]");
+  if (P.cache_policy < 0 || P.cache_policy > 2) return fail(FCGMG_E_ARG, "unknown cache policy");
+  if (!(P.eta > 0) || !(P.alpha_fict >= 0) || !(P.nitsche_beta > 0) || !std::isfinite(P.omega))
+    return fail(FCGMG_E_ARG, "eta, nitsche_beta must be > 0, alpha_fict >= 0, omega finite");
+  if (P.nu_pre < 0 || P.nu_post < 0) return fail(FCGMG_E_ARG, "negative smoothing steps");
+  for (int k = 0; k < 6; ++k)
+    if (P.bc[k] < 0 || P.bc[k] > 2) return fail(FCGMG_E_ARG, "unknown boundary code");
+  if (n_balls < 0 || (n_balls > 0 && !balls)) return fail(FCGMG_E_ARG, "bad obstacle list");
+  for (int i = 0; i < n_balls; ++i)
+    if (!(balls[4 * i + 3] > 0)) return fail(FCGMG_E_ARG, "obstacle radius must be > 0");
+  fcgmg_ctx* c = new fcgmg_ctx();
+  c->prm = P;
+  c->balls_h.assign(balls, balls + 4 * (size_t)n_balls);
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = P.dim == 2 ? setup_impl<2>(*c, s) : setup_impl<3>(*c, s);
+  if (rc != FCGMG_OK) {
+    std::string keep = g_err;
+    (void)hipStreamSynchronize(s);
+    fcgmg_destroy(c);
+    g_err = keep;
+    return rc;
+  }
+  *out = c;
+  return FCGMG_OK;
+}
+
+int fcgmg_num_levels(fcgmg_h h, int* n) {
+  if (!h || !n) return fail(FCGMG_E_ARG, "null argument");
+  *n = (int)h->lev.size();
+  return FCGMG_OK;
+}
+
+int fcgmg_num_dofs(fcgmg_h h, int level, int64_t* n) {
+  if (!valid_level(h, level) || !n) return fail(FCGMG_E_ARG, "bad handle or level");
+  *n = (h->prm.dim + 1) * h->lev[level].N;
+  return FCGMG_OK;
+}
+
+int fcgmg_level_stats_get(fcgmg_h h, int level, fcgmg_level_stats* o) {
+  if (!valid_level(h, level) || !o) return fail(FCGMG_E_ARG, "bad handle or level");
+  const Level& L = h->lev[level];
+  o->n_cells_axis = L.n;
+  o->n_nodes = L.N;
+  o->n_cut_cells = L.n_cut;
+  o->n_fict_cells = L.n_fict;
+  o->n_classes = L.n_classes;
+  o->n_irregular = L.n_irr;
+  o->irregular_cols = L.irr_cols;
+  o->cached_bytes = (int64_t)L.cached_bytes;
+  return FCGMG_OK;
+}
+
+int fcgmg_rhs(fcgmg_h h, int level, double* b, void* stream) {
+  if (!valid_level(h, level) || !b) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = h->prm.dim == 2 ? k_rhs<2>(*h, h->lev[level], b, s) : k_rhs<3>(*h, h->lev[level], b, s);
+  if (e != hipSuccess) return fail(FCGMG_E_HIP, std::string("rhs: ") + hipGetErrorString(e));
+  return FCGMG_OK;
+}
+
+int fcgmg_residual(fcgmg_h h, int level, const double* x, const double* b, double* r, void* stream) {
+  if (!valid_level(h, level) || !x || !b || !r) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  if (r == x || r == b) return fail(FCGMG_E_ARG, "r must not alias x or b");
+  hipStream_t s = (hipStream_t)stream;
+  return h->prm.dim == 2 ? residual_impl<2>(*h, level, x, b, r, s) : residual_impl<3>(*h, level, x, b, r, s);
+}
+
+int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream) {
+  if (!valid_level(h, level) || !x || !b || sweeps < 0) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < sweeps; ++i) {
+    const int rc = h->prm.dim == 2 ? sweep_impl<2>(*h, level, x, b, s) : sweep_impl<3>(*h, level, x, b, s);
+    if (rc) return rc;
+  }
+  return FCGMG_OK;
+}
+
+int fcgmg_restrict(fcgmg_h h, int fine_level, const double* rf, double* bc, void* stream) {
+  if (!valid_level(h, fine_level) || fine_level < 1 || !rf || !bc) return fail(FCGMG_E_ARG, "bad level or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = h->prm.dim == 2 ? k_restrict<2>(*h, fine_level, rf, bc, s) : k_restrict<3>(*h, fine_level, rf, bc, s);
+  if (e != hipSuccess) return fail(FCGMG_E_HIP, std::string("restrict: ") + hipGetErrorString(e));
+  return FCGMG_OK;
+}
+
+int fcgmg_prolongate_add(fcgmg_h h, int fine_level, const double* ec, double* xf, void* stream) {
+  if (!valid_level(h, fine_level) || fine_level < 1 || !ec || !xf) return fail(FCGMG_E_ARG, "bad level or pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e =
+      h->prm.dim == 2 ? k_prolong_add<2>(*h, fine_level, ec, xf, s) : k_prolong_add<3>(*h, fine_level, ec, xf, s);
+  if (e != hipSuccess) return fail(FCGMG_E_HIP, std::string("prolongate: ") + hipGetErrorString(e));
+  return FCGMG_OK;
+}
+
+int fcgmg_coarse_solve(fcgmg_h h, const double* b, double* x, void* stream) {
+  if (!h || !b || !x) return fail(FCGMG_E_ARG, "null argument");
+  return coarse_impl(*h, b, x, (hipStream_t)stream);
+}
+
+int fcgmg_vcycle(fcgmg_h h, double* x, const double* b, void* stream) {
+  if (!h || !x || !b) return fail(FCGMG_E_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int top = (int)h->lev.size() - 1;
+  return h->prm.dim == 2 ? vcycle_impl<2>(*h, top, x, b, s) : vcycle_impl<3>(*h, top, x, b, s);
+}
+
+int fcgmg_norm(fcgmg_h h, int level, const double* v, double* out, void* stream) {
+  if (!valid_level(h, level) || !v || !out) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  return norm_impl(*h, v, (h->prm.dim + 1) * h->lev[level].N, out, (hipStream_t)stream);
+}
+
+int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter, int* iters, double* rel_res,
+                double* res_hist, void* stream) {
+  if (!h || !x || !b || !iters || !rel_res || max_iter < 0 || !(rtol >= 0))
+    return fail(FCGMG_E_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int top = (int)h->lev.size() - 1;
+  const Level& L = h->lev[top];
+  const int64_t nd = (h->prm.dim + 1) * L.N;
+  int rc;
+  *iters = 0;
+  *rel_res = 0;
+  double r0;
+  if ((rc = h->prm.dim == 2 ? residual_impl<2>(*h, top, x, b, L.r, s) : residual_impl<3>(*h, top, x, b, L.r, s)))
+    return rc;
+  if ((rc = norm_impl(*h, L.r, nd, &r0, s))) return rc;
+  if (res_hist) res_hist[0] = r0;
+  if (!std::isfinite(r0)) return fail(FCGMG_E_NAN, "non-finite initial residual");
+  if (r0 == 0.0) return FCGMG_OK;
+  for (int it = 1; it <= max_iter; ++it) {
+    if ((rc = fcgmg_vcycle(h, x, b, stream))) return rc;
+    if ((rc = h->prm.dim == 2 ? residual_impl<2>(*h, top, x, b, L.r, s) : residual_impl<3>(*h, top, x, b, L.r, s)))
+      return rc;
+    double rn;
+    if ((rc = norm_impl(*h, L.r, nd, &rn, s))) return rc;
+    if (res_hist) res_hist[it] = rn;
+    *iters = it;
+    *rel_res = rn / r0;
+    if (!std::isfinite(rn)) return fail(FCGMG_E_NAN, "non-finite residual at cycle " + std::to_string(it));
+    if (rn <= rtol * r0) return FCGMG_OK;
+  }
+  return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
+                                  std::to_string(*rel_res) + ")");
+}
+
+int fcgmg_device_bytes(fcgmg_h h, size_t* bytes) {
+  if (!h || !bytes) return fail(FCGMG_E_ARG, "null argument");
+  *bytes = h->bytes;
+  return FCGMG_OK;
+}
+
+}  // extern "C"

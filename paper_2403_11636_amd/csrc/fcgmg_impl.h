@@ -1,0 +1,280 @@
+// Internal declarations of the fcgmg library: level data, operator constants, geometry and the
+// element integrals of the finite cell Stokes operator (Saberi & Vogel, Eq. 5-12).
+//
+// The element routines are __host__ __device__: the host planner evaluates the uncut reference
+// cells and the Nitsche face matrices once per level; the kernels integrate cut cells (setup, and
+// on the fly for the cache_none policy of Sec. 3.1.2) and the right-hand side.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fcgmg.h"
+
+namespace fcg {
+
+// ------------------------------------------------------------------------------------------------
+// Patch geometry per dimension. A vertex patch (subdomain S_i of Eq. 15) of node i holds the d
+// velocity components of the 5^d nodes within max-norm distance 2 and the pressures of the 3^d
+// nodes within distance 1; its block L_i is assembled from the 6^d cells around i.
+// Column layout of a patch vector (and of the cache_inverse rows Z_i): component-major velocity
+// [c][5^d window, x fastest] followed by the 3^d pressure window; out-of-grid entries are zero.
+// ------------------------------------------------------------------------------------------------
+template <int D>
+struct PT {
+  static constexpr int NN = 1 << D;                   // nodes per cell
+  static constexpr int NV = D == 2 ? 25 : 125;        // velocity window nodes (5^d)
+  static constexpr int NP = D == 2 ? 9 : 27;          // pressure window nodes (3^d)
+  static constexpr int NW = D == 2 ? 36 : 216;        // window cells (6^d)
+  static constexpr int BW = D == 2 ? 6 : 31;          // half bandwidth of K_i (lexicographic)
+  static constexpr int NB = BW + 1;                   // band storage width
+  static constexpr int ZS = D * NV + NP;              // |S_i| of an interior patch: 59 / 402
+  static constexpr int ZSP = (ZS + 63) / 64 * 64;     // padded row length: 64 / 448
+  static constexpr int NEL = (D + 1) * NN * NN;       // stored entries of one cut cell (K, B_c)
+  static constexpr int THREADS = D == 2 ? 64 : 256;   // block size of the patch kernels
+  static constexpr int NST = D == 2 ? 9 : 27;         // node stencil offsets (3^d)
+};
+
+// Per-level operator constants (device resident, read through uniform loads).
+struct OpConsts {
+  double K[2][64];      // [0 physical, 1 fictitious] eta*alpha*int grad phi_a . grad phi_b
+  double B[2][3][64];   // [kind][c]: -int alpha d_c phi_a phi_b  (a: velocity node, b: pressure)
+  double C[64];         // -(1/eta) (M_ab - m_a m_b / |K|)
+  double FK[6][64];     // Nitsche face matrix of face f (zero when the face is not Dirichlet)
+  double FB[6][64];     // int_F phi_a n_k phi_b on face f (velocity component k = axis of f)
+  int dirichlet[6];
+  int n;                // cells per axis
+  double h, lam;
+};
+
+struct Geom {
+  const double* balls;  // nballs x 4 (centre, radius)
+  int nballs;
+  int q;                // space-tree depth
+  double alpha_f;
+};
+
+struct Level {
+  int n = 0;
+  double h = 0;
+  int64_t N = 0, ncells = 0;
+  int* cell_info = nullptr;   // -1 physical, -2 fictitious, >=0 index into cut_mats
+  double* cut_mats = nullptr; // n_cut x NEL: K (NN x NN) then B_c (NN x NN) for c < d
+  int64_t n_cut = 0, n_fict = 0;
+  int* node_class = nullptr;  // >=0 regular class id, <0: -(irregular index)-1
+  int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
+  int* irr_nodes = nullptr;   // centre node of each irregular patch
+  int* class_rep = nullptr;   // representative node of each class
+  double* Zcls = nullptr;     // cache_inverse: n_classes x (d+1) x ZSP
+  double* Zirr = nullptr;     // cache_inverse: n_irr x (d+1) x ZSP
+  double* Mcls = nullptr;     // cache_matrix: n_classes x n_pattern
+  double* Mirr = nullptr;     // cache_matrix: n_irr x n_pattern
+  OpConsts* consts = nullptr; // device copy
+  OpConsts consts_h;          // host copy
+  double* r = nullptr;        // residual scratch, (d+1) N
+  double* x = nullptr;        // V-cycle iterate (levels below the finest)
+  double* b = nullptr;        // V-cycle right-hand side (levels below the finest)
+  size_t cached_bytes = 0;
+};
+
+struct Ctx {
+  fcgmg_params prm{};
+  std::vector<double> balls_h;
+  double* balls = nullptr;
+  std::vector<Level> lev;
+  double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (ndof x ndof)
+  int coarse_n = 0;
+  bool bordered = false;
+  double* red = nullptr;         // reduction scratch
+  double* red_host = nullptr;    // pinned host word
+  int* err = nullptr;            // device error flag: first failing patch node, or INT_MAX
+  int* pattern = nullptr;        // cache_matrix sparse pattern (encoded entries)
+  int n_pattern = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  Geom geom() const { return Geom{balls, (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
+  Geom geom_host() const { return Geom{balls_h.data(), (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
+};
+
+// ------------------------------------------------------------------------------------------------
+// Geometry (Eq. 7): alpha = 1 outside every ball, alpha_f inside or on a ball.
+// ------------------------------------------------------------------------------------------------
+template <int D>
+__host__ __device__ inline double alpha_at(const Geom& g, const double* x) {
+  for (int i = 0; i < g.nballs; ++i) {
+    const double* b = g.balls + 4 * i;
+    double s = 0;
+    for (int k = 0; k < D; ++k) {
+      double t = x[k] - b[k];
+      s += t * t;
+    }
+    if (s <= b[3] * b[3]) return g.alpha_f;
+  }
+  return 1.0;
+}
+
+// Box [lo, lo+s]^D: 0 physical, 1 fictitious (inside a ball), 2 cut.
+template <int D>
+__host__ __device__ inline int box_kind(const Geom& g, const double* lo, double s) {
+  bool cut = false;
+  for (int i = 0; i < g.nballs; ++i) {
+    const double* b = g.balls + 4 * i;
+    double dmin2 = 0, dmax2 = 0;
+    for (int k = 0; k < D; ++k) {
+      double a = lo[k] - b[k], e = lo[k] + s - b[k];
+      double m = a > 0 ? a : (e < 0 ? -e : 0.0);
+      dmin2 += m * m;
+      double M = fmax(fabs(a), fabs(e));
+      dmax2 += M * M;
+    }
+    double r2 = b[3] * b[3];
+    if (dmax2 <= r2) return 1;
+    if (dmin2 < r2) cut = true;
+  }
+  return cut ? 2 : 0;
+}
+
+// Q1 basis of a cell (lower corner lo, size h) at x: values and physical gradients.
+template <int D>
+__host__ __device__ inline void q1(const double* lo, double h, const double* x, double* phi, double (*gr)[3]) {
+  double t[3], u[3];
+  const double ih = 1.0 / h;
+  for (int k = 0; k < D; ++k) {
+    t[k] = (x[k] - lo[k]) * ih;
+    u[k] = 1.0 - t[k];
+  }
+  for (int a = 0; a < (1 << D); ++a) {
+    double f[3];
+    for (int k = 0; k < D; ++k) f[k] = ((a >> k) & 1) ? t[k] : u[k];
+    double v = f[0] * f[1];
+    if (D == 3) v *= f[2];
+    phi[a] = v;
+    for (int j = 0; j < D; ++j) {
+      double gj = ((a >> j) & 1) ? ih : -ih;
+      for (int k = 0; k < D; ++k)
+        if (k != j) gj *= f[k];
+      gr[a][j] = gj;
+    }
+  }
+}
+
+// Two-point Gauss abscissae on [0,1].
+#define FCG_GA (0.21132486540518711775)
+#define FCG_GB (0.78867513459481288225)
+
+// Space-tree quadrature of one cell: visits every Gauss point (x, w, alpha) of the leaves. A box is
+// split into its 2^D children while it is cut and shallower than q; every leaf gets the 2^D-point
+// Gauss rule with alpha evaluated at each point. Iterative depth-first traversal (no recursion).
+template <int D, class F>
+__host__ __device__ inline void tree_quadrature(const Geom& g, const double* lo0, double h, F&& visit) {
+  int child[8];
+  double lo[8][3];
+  for (int k = 0; k < 3; ++k) lo[0][k] = k < D ? lo0[k] : 0.0;
+  int t = 0;
+  child[0] = 0;
+  for (;;) {
+    const double s = h / (double)(1 << t);
+    bool descend = false;
+    if (t < g.q && t < 7) descend = box_kind<D>(g, lo[t], s) == 2;
+    if (descend) {
+      ++t;
+      child[t] = 0;
+      for (int k = 0; k < D; ++k) lo[t][k] = lo[t - 1][k];
+      continue;
+    }
+    const double w = D == 2 ? 0.25 * s * s : 0.125 * s * s * s;
+    for (int p = 0; p < (1 << D); ++p) {
+      double x[3] = {0, 0, 0};
+      for (int k = 0; k < D; ++k) x[k] = lo[t][k] + s * (((p >> k) & 1) ? FCG_GB : FCG_GA);
+      visit(x, w, alpha_at<D>(g, x));
+    }
+    // advance to the next sibling, climbing while the current box was the last child
+    while (t > 0 && child[t] == (1 << D) - 1) --t;
+    if (t == 0) break;
+    ++child[t];
+    const double sp = h / (double)(1 << (t - 1));
+    for (int k = 0; k < D; ++k) lo[t][k] = lo[t - 1][k] + (((child[t] >> k) & 1) ? 0.5 * sp : 0.0);
+  }
+}
+
+// Entry e of a cell's alpha-weighted element data: e < NN*NN: K[a][b] = eta int alpha grad.grad;
+// else B_c[a][b] = -int alpha d_c phi_a phi_b with c = e / (NN*NN) - 1.
+template <int D>
+__host__ __device__ inline double point_entry(int e, double eta, double wa, const double* phi, double (*gr)[3]) {
+  constexpr int NN = 1 << D;
+  const int blk = e / (NN * NN), ab = e % (NN * NN), a = ab / NN, b = ab % NN;
+  if (blk == 0) {
+    double s = 0;
+    for (int k = 0; k < D; ++k) s += gr[a][k] * gr[b][k];
+    return wa * eta * s;
+  }
+  return -wa * gr[a][blk - 1] * phi[b];
+}
+
+__host__ __device__ inline double gfun0(double t) { return t * t * (1 - t) * (1 - t); }
+__host__ __device__ inline double gfun1(double t) { return 2 * t - 6 * t * t + 4 * t * t * t; }
+__host__ __device__ inline double gfun2(double t) { return 2 - 12 * t + 12 * t * t; }
+__host__ __device__ inline double gfun3(double t) { return -12 + 24 * t; }
+
+// Body force of the manufactured solution u = curl psi (psi = prod g(x_k), g = t^2 (1-t)^2,
+// 3D: u = (g g' g, -g' g g, 0)), p = sum x_k^3 - d/4:  f = -eta Lap u + grad p.
+template <int D>
+__host__ __device__ inline void body_force(int kind, double eta, const double* x, double* f) {
+  f[0] = f[1] = f[2] = 0;
+  if (kind != 1) return;
+  const double X = x[0], Y = x[1];
+  if (D == 2) {
+    f[0] = -eta * (gfun2(X) * gfun1(Y) + gfun0(X) * gfun3(Y)) + 3 * X * X;
+    f[1] = eta * (gfun3(X) * gfun0(Y) + gfun1(X) * gfun2(Y)) + 3 * Y * Y;
+  } else {
+    const double Z = x[2];
+    f[0] = -eta * (gfun2(X) * gfun1(Y) * gfun0(Z) + gfun0(X) * gfun3(Y) * gfun0(Z) + gfun0(X) * gfun1(Y) * gfun2(Z)) +
+           3 * X * X;
+    f[1] = eta * (gfun3(X) * gfun0(Y) * gfun0(Z) + gfun1(X) * gfun2(Y) * gfun0(Z) + gfun1(X) * gfun0(Y) * gfun2(Z)) +
+           3 * Y * Y;
+    f[2] = 3 * Z * Z;
+  }
+}
+
+// Dirichlet data on face (axis k, side s): zero, or the parabolic inflow of Eq. (16) (H = 1;
+// product profile in 3D) pointing into the box.
+template <int D>
+__host__ __device__ inline void wall_data(int code, double ubar, int k, int s, const double* x, double* w) {
+  w[0] = w[1] = w[2] = 0;
+  if (code != FCGMG_BC_INFLOW) return;
+  double prof = ubar;
+  for (int j = 0; j < D; ++j)
+    if (j != k) prof *= 4.0 * x[j] * (1.0 - x[j]);
+  w[k] = s ? -prof : prof;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Kernel launchers (fcgmg_kernels.hip). All return hipError_t of the launch.
+// ------------------------------------------------------------------------------------------------
+template <int D> hipError_t k_classify_cells(const Ctx& c, Level& L, signed char* kinds, hipStream_t s);
+template <int D> hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStream_t s);
+template <int D> hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s);
+template <int D> hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const double* b, double* r,
+                                       hipStream_t s);
+template <int D> hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count,
+                                                 double* Z, hipStream_t s);
+template <int D> hipError_t k_apply_inverse(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s);
+template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,
+                                          hipStream_t s);
+template <int D> hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int64_t count,
+                                             double* M, hipStream_t s);
+template <int D> hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hipStream_t s);
+template <int D> hipError_t k_restrict(const Ctx& c, int fine, const double* rf, double* bc, hipStream_t s);
+template <int D> hipError_t k_prolong_add(const Ctx& c, int fine, const double* xc, double* xf, hipStream_t s);
+hipError_t k_dense_matvec(const double* A, int n, const double* b, double* x, hipStream_t s);
+hipError_t k_sumsq(const double* v, int64_t n, double* partial, int nblocks, hipStream_t s);
+hipError_t k_finish_sumsq(const double* partial, int nblocks, double* out, hipStream_t s);
+hipError_t k_zero(double* v, int64_t n, hipStream_t s);
+template <int D> int pattern_size();
+template <int D> void pattern_entries(std::vector<int>& enc);
+
+}  // namespace fcg

@@ -1,0 +1,778 @@
+// Vertex-patch kernels of the restricted additive smoother (Saberi & Vogel, Eq. 15, Sec. 3.1.2).
+//
+// Local block of subdomain S_i:  L_i = [[I_d (x) K_i, B_i], [B_i^T, C_i]]
+//   K_i : velocity block of the 5^d window (the viscous form and the Nitsche terms act on each
+//         velocity component alike, so the d velocity blocks are one scalar SPD matrix), stored as
+//         a lower band (lexicographic order, half bandwidth 6 / 31);
+//   B_i : d blocks 5^d x 3^d;  C_i : 3^d x 3^d stabilisation block.
+// The local direct solve ("LU ... down to machine accuracy", Sec. 3.1.2) is done as the block LU
+// with the pressure Schur complement S = C - sum_c B_c^T K^{-1} B_c; K = L L^T by a banded
+// Cholesky, -S by a dense Cholesky. Entries of the window that fall outside the grid are replaced
+// by decoupled identity rows (velocity) / -1 diagonals (pressure), which leaves the in-grid
+// solution unchanged.
+//
+// Included by fcgmg_kernels.hip (single translation unit for all device code).
+
+namespace fcg {
+
+namespace {
+
+template <int D>
+struct PatchLDS {
+  static constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB, NPX = PT<D>::NP + 2;
+  double Kb[NV * NB];        // lower band of K_i: Kb[i*NB + (i-j)] = K[i][j]
+  double X[D * NV * NPX];    // per component c: [B_c | g_c | e_m] -> [V_c | z_c | y] -> [W_c | . | q]
+  double S[NP * NP];         // C - sum V^T V, then the Cholesky factor of -S (lower)
+  double Sinv[NP * NP];      // S^{-1} (inverse rows only)
+  double t[NP];              // reduced pressure right-hand side, then the pressure solution
+  double w[D][NP];           // y^T V_c = row m of K^{-1} B_c
+  double tc[D][NP];          // S^{-1} w_c (inverse rows only)
+  double qg[D];              // y^T z_c
+  double cellbuf[PT<D>::NEL];
+  double lball[4 * kMaxLocalBalls];
+  int cnt;
+  int bad;
+};
+
+template <int D>
+__device__ __forceinline__ int vel_center() {
+  return D == 2 ? 12 : 62;
+}
+template <int D>
+__device__ __forceinline__ int pres_center() {
+  return D == 2 ? 4 : 13;
+}
+
+// Window index helpers: velocity window 5^d (offset -2), pressure window 3^d (offset -1),
+// cell window 6^d (cell lower corner offset -3), all lexicographic with x fastest.
+template <int D>
+__device__ __forceinline__ bool vel_in_grid(const int* c, int n, int v) {
+  const int o[3] = {v % 5 - 2, (v / 5) % 5 - 2, D == 3 ? v / 25 - 2 : 0};
+  for (int k = 0; k < D; ++k)
+    if (c[k] + o[k] < 0 || c[k] + o[k] > n) return false;
+  return true;
+}
+template <int D>
+__device__ __forceinline__ bool pres_in_grid(const int* c, int n, int q) {
+  const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, D == 3 ? q / 9 - 1 : 0};
+  for (int k = 0; k < D; ++k)
+    if (c[k] + o[k] < 0 || c[k] + o[k] > n) return false;
+  return true;
+}
+
+// Assemble K_i, B_i, C_i of the patch centred at node c from the 6^d cell window (Eq. 15:
+// L_i = R_i L R_i^T). source 0: cut cells from the stored integrals; source 1: cut cells
+// integrated on the fly (cache_none). One barrier per window cell; within a cell every (a, b)
+// pair lands in a distinct entry.
+template <int D>
+__device__ void patch_assemble(PatchLDS<D>& sh, const OpConsts* __restrict__ oc, const int* __restrict__ cell_info,
+                               const double* __restrict__ cut, const Geom& g, double eta, const int* c,
+                               int source) {
+  constexpr int NN = 1 << D, NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB, NPX = NP + 2, NW = PT<D>::NW;
+  constexpr int NEL = PT<D>::NEL;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = oc->n;
+  for (int i = tid; i < NV * NB; i += nt) sh.Kb[i] = 0;
+  for (int i = tid; i < D * NV * NPX; i += nt) sh.X[i] = 0;
+  for (int i = tid; i < NP * NP; i += nt) sh.S[i] = 0;
+  __syncthreads();
+  for (int w = 0; w < NW; ++w) {
+    const int wk[3] = {w % 6, (w / 6) % 6, D == 3 ? w / 36 : 0};
+    int cc[3] = {0, 0, 0};
+    bool in = true;
+    for (int k = 0; k < D; ++k) {
+      cc[k] = c[k] + wk[k] - 3;
+      if (cc[k] < 0 || cc[k] > n - 1) in = false;
+    }
+    if (!in) continue;
+    const int64_t cell = D == 2 ? cc[0] + (int64_t)n * cc[1] : cc[0] + (int64_t)n * (cc[1] + (int64_t)n * cc[2]);
+    const int info = cell_info[cell];
+    const double* Kp;
+    const double* Bp;
+    int bstride;
+    if (info >= 0) {
+      if (source == 1) {
+        double lo[3] = {0, 0, 0};
+        for (int k = 0; k < D; ++k) lo[k] = cc[k] * oc->h;
+        const int nb = cull_balls<D>(g, lo, oc->h, sh.lball, &sh.cnt);
+        Geom gl = g;
+        if (nb >= 0) {
+          gl.balls = sh.lball;
+          gl.nballs = nb;
+        }
+        constexpr int NPER = (NEL + PT<D>::THREADS - 1) / PT<D>::THREADS;
+        double acc[NPER];
+        for (int k = 0; k < NPER; ++k) acc[k] = 0;
+        integrate_cell_entries<D>(gl, lo, oc->h, eta, acc, NPER);
+        for (int k = 0; k < NPER; ++k) {
+          const int e = tid + k * nt;
+          if (e < NEL) sh.cellbuf[e] = acc[k];
+        }
+        __syncthreads();
+        Kp = sh.cellbuf;
+      } else {
+        Kp = cut + (int64_t)info * NEL;
+      }
+      Bp = Kp + NN * NN;
+      bstride = NN * NN;
+    } else {
+      const int kind = info == -1 ? 0 : 1;
+      Kp = oc->K[kind];
+      Bp = oc->B[kind][0];
+      bstride = 64;
+    }
+    int fmask = 0;
+    for (int k = 0; k < D; ++k) {
+      if (cc[k] == 0 && oc->dirichlet[2 * k]) fmask |= 1 << (2 * k);
+      if (cc[k] == n - 1 && oc->dirichlet[2 * k + 1]) fmask |= 1 << (2 * k + 1);
+    }
+    for (int it = tid; it < NN * NN * (D + 2); it += nt) {
+      const int blk = it / (NN * NN), ab = it % (NN * NN), a = ab / NN, b = ab % NN;
+      int va = 0, vb = 0, qa = 0, qb = 0, mv = 1, mq = 1;
+      bool va_ok = true, vb_ok = true, qa_ok = true, qb_ok = true;
+      for (int k = 0; k < D; ++k) {
+        const int ak = (a >> k) & 1, bk = (b >> k) & 1;
+        const int xa = wk[k] + ak - 1, xb = wk[k] + bk - 1;  // velocity window coordinate
+        const int pa = wk[k] + ak - 2, pb = wk[k] + bk - 2;  // pressure window coordinate
+        va_ok = va_ok && xa >= 0 && xa <= 4;
+        vb_ok = vb_ok && xb >= 0 && xb <= 4;
+        qa_ok = qa_ok && pa >= 0 && pa <= 2;
+        qb_ok = qb_ok && pb >= 0 && pb <= 2;
+        va += xa * mv;
+        vb += xb * mv;
+        qa += pa * mq;
+        qb += pb * mq;
+        mv *= 5;
+        mq *= 3;
+      }
+      if (blk == 0) {
+        if (va_ok && vb_ok && va >= vb) {
+          double v = Kp[a * NN + b];
+          for (int f = 0; f < 2 * D; ++f)
+            if (fmask & (1 << f)) v += oc->FK[f][a * NN + b];
+          sh.Kb[va * NB + (va - vb)] += v;
+        }
+      } else if (blk <= D) {
+        const int cmp = blk - 1;
+        if (va_ok && qb_ok) {
+          double v = Bp[cmp * bstride + a * NN + b];
+          for (int sd = 0; sd < 2; ++sd)
+            if (fmask & (1 << (2 * cmp + sd))) v += oc->FB[2 * cmp + sd][a * NN + b];
+          sh.X[(cmp * NV + va) * NPX + qb] += v;
+        }
+      } else {
+        if (qa_ok && qb_ok) sh.S[qa * NP + qb] += oc->C[a * NN + b];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Decouple window positions that lie outside the grid (truncated patches at the walls).
+template <int D>
+__device__ void patch_pad(PatchLDS<D>& sh, const int* c, int n) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB;
+  for (int v = threadIdx.x; v < NV; v += blockDim.x)
+    if (!vel_in_grid<D>(c, n, v)) sh.Kb[v * NB] = 1.0;
+  for (int q = threadIdx.x; q < NP; q += blockDim.x)
+    if (!pres_in_grid<D>(c, n, q)) sh.S[q * NP + q] = -1.0;
+  __syncthreads();
+}
+
+// Banded Cholesky K = L L^T in place (right-looking, one barrier pair per column).
+template <int D>
+__device__ void band_cholesky(PatchLDS<D>& sh) {
+  constexpr int NV = PT<D>::NV, NB = PT<D>::NB, BW = PT<D>::BW;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < NV; ++k) {
+    const double dkk = sh.Kb[k * NB];
+    if (tid == 0 && !(dkk > 0.0)) sh.bad = 1;
+    const double l = sqrt(dkk);
+    const int last = k + BW < NV - 1 ? k + BW : NV - 1;
+    const int m = last - k;
+    __syncthreads();
+    for (int i = k + 1 + tid; i <= last; i += nt) sh.Kb[i * NB + (i - k)] /= l;
+    if (tid == 0) sh.Kb[k * NB] = l;
+    __syncthreads();
+    for (int p = tid; p < m * m; p += nt) {
+      const int ii = k + 1 + p / m, jj = k + 1 + p % m;
+      if (jj <= ii) sh.Kb[ii * NB + (ii - jj)] -= sh.Kb[ii * NB + (ii - k)] * sh.Kb[jj * NB + (jj - k)];
+    }
+    __syncthreads();
+  }
+}
+
+// Forward substitution L V = X for the columns [c][col], col < ncol (thread per column).
+template <int D>
+__device__ void band_forward(PatchLDS<D>& sh, int ncol) {
+  constexpr int NV = PT<D>::NV, NB = PT<D>::NB, BW = PT<D>::BW, NPX = PT<D>::NP + 2;
+  for (int t = threadIdx.x; t < D * ncol; t += blockDim.x) {
+    const int cmp = t / ncol, col = t % ncol;
+    double* Xc = sh.X + cmp * NV * NPX + col;
+    for (int i = 0; i < NV; ++i) {
+      double v = Xc[i * NPX];
+      const int k0 = i - BW > 0 ? i - BW : 0;
+      for (int k = k0; k < i; ++k) v -= sh.Kb[i * NB + (i - k)] * Xc[k * NPX];
+      Xc[i * NPX] = v / sh.Kb[i * NB];
+    }
+  }
+  __syncthreads();
+}
+
+// Back substitution L^T W = V for the columns [c][col], col < ncol, plus the e_m column of c = 0.
+template <int D>
+__device__ void band_backward(PatchLDS<D>& sh, int ncol) {
+  constexpr int NV = PT<D>::NV, NB = PT<D>::NB, BW = PT<D>::BW, NP = PT<D>::NP, NPX = NP + 2;
+  for (int t = threadIdx.x; t < D * ncol + 1; t += blockDim.x) {
+    const int cmp = t < D * ncol ? t / ncol : 0;
+    const int col = t < D * ncol ? t % ncol : NP + 1;
+    double* Xc = sh.X + cmp * NV * NPX + col;
+    for (int i = NV - 1; i >= 0; --i) {
+      double v = Xc[i * NPX];
+      const int k1 = i + BW < NV - 1 ? i + BW : NV - 1;
+      for (int k = i + 1; k <= k1; ++k) v -= sh.Kb[k * NB + (k - i)] * Xc[k * NPX];
+      Xc[i * NPX] = v / sh.Kb[i * NB];
+    }
+  }
+  __syncthreads();
+}
+
+// S <- S - sum_c V_c^T V_c; with_rhs: t <- t - sum_c V_c^T z_c, qg_c = y^T z_c; w_c = y^T V_c.
+template <int D>
+__device__ void schur_update(PatchLDS<D>& sh, bool with_rhs) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NPX = NP + 2;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int mc = vel_center<D>();
+  for (int e = tid; e < NP * NP; e += nt) {
+    const int i = e / NP, j = e % NP;
+    double s = 0;
+    for (int cmp = 0; cmp < D; ++cmp) {
+      const double* Xc = sh.X + cmp * NV * NPX;
+      for (int k = 0; k < NV; ++k) s += Xc[k * NPX + i] * Xc[k * NPX + j];
+    }
+    sh.S[e] -= s;
+  }
+  const double* y = sh.X + (NP + 1);  // e_m column of component 0 after the forward pass
+  for (int e = tid; e < D * NP + (with_rhs ? NP + D : 0); e += nt) {
+    if (e < D * NP) {
+      const int cmp = e / NP, i = e % NP;
+      const double* Xc = sh.X + cmp * NV * NPX;
+      double s = 0;
+      for (int k = mc; k < NV; ++k) s += y[k * NPX] * Xc[k * NPX + i];
+      sh.w[cmp][i] = s;
+    } else if (e < D * NP + NP) {
+      const int i = e - D * NP;
+      double s = 0;
+      for (int cmp = 0; cmp < D; ++cmp) {
+        const double* Xc = sh.X + cmp * NV * NPX;
+        for (int k = 0; k < NV; ++k) s += Xc[k * NPX + i] * Xc[k * NPX + NP];
+      }
+      sh.t[i] -= s;
+    } else {
+      const int cmp = e - D * NP - NP;
+      const double* Xc = sh.X + cmp * NV * NPX;
+      double s = 0;
+      for (int k = mc; k < NV; ++k) s += y[k * NPX] * Xc[k * NPX + NP];
+      sh.qg[cmp] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Dense Cholesky of F = -S (lower factor in sh.S).
+template <int D>
+__device__ void schur_cholesky(PatchLDS<D>& sh) {
+  constexpr int NP = PT<D>::NP;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < NP * NP; e += nt) sh.S[e] = -sh.S[e];
+  __syncthreads();
+  for (int k = 0; k < NP; ++k) {
+    const double dkk = sh.S[k * NP + k];
+    if (tid == 0 && !(dkk > 0.0)) sh.bad = 1;
+    const double l = sqrt(dkk);
+    __syncthreads();
+    for (int i = k + 1 + tid; i < NP; i += nt) sh.S[i * NP + k] /= l;
+    if (tid == 0) sh.S[k * NP + k] = l;
+    __syncthreads();
+    const int m = NP - 1 - k;
+    for (int p = tid; p < m * m; p += nt) {
+      const int ii = k + 1 + p / m, jj = k + 1 + p % m;
+      if (jj <= ii) sh.S[ii * NP + jj] -= sh.S[ii * NP + k] * sh.S[jj * NP + k];
+    }
+    __syncthreads();
+  }
+}
+
+// p = S^{-1} t = -F^{-1} t by forward/back substitution with the factor of F (first wavefront;
+// each row's dot product is a wavefront reduction). Result overwrites sh.t.
+template <int D>
+__device__ void schur_solve(PatchLDS<D>& sh) {
+  constexpr int NP = PT<D>::NP;
+  const int lane = threadIdx.x;
+  if (lane < 64) {
+    for (int i = 0; i < NP; ++i) {
+      double s = lane < i ? sh.S[i * NP + lane] * sh.t[lane] : 0.0;
+      s = wave_sum(s);
+      if (lane == 0) sh.t[i] = (-sh.t[i] - s) / sh.S[i * NP + i];
+    }
+    for (int i = NP - 1; i >= 0; --i) {
+      double s = (lane > i && lane < NP) ? sh.S[lane * NP + i] * sh.t[lane] : 0.0;
+      s = wave_sum(s);
+      if (lane == 0) sh.t[i] = (sh.t[i] - s) / sh.S[i * NP + i];
+    }
+  }
+  __syncthreads();
+}
+
+// Place the stored sparse pattern values of a patch (cache_matrix) into the zeroed LDS blocks.
+template <int D>
+__device__ void patch_load_pattern(PatchLDS<D>& sh, const int* __restrict__ pattern, int npat,
+                                   const double* __restrict__ vals) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB, NPX = NP + 2;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < NV * NB; i += nt) sh.Kb[i] = 0;
+  for (int i = tid; i < D * NV * NPX; i += nt) sh.X[i] = 0;
+  for (int i = tid; i < NP * NP; i += nt) sh.S[i] = 0;
+  __syncthreads();
+  for (int e = tid; e < npat; e += nt) {
+    const int code = pattern[e];
+    const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
+    const double v = vals[e];
+    if (type == 0) {
+      sh.Kb[i * NB + (i - j)] = v;
+    } else if (type <= D) {
+      sh.X[((type - 1) * NV + i) * NPX + j] = v;
+    } else {
+      sh.S[i * NP + j] = v;
+      sh.S[j * NP + i] = v;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+// Sparse pattern of L_i kept by cache_matrix: lower band entries of K between window nodes at
+// max-norm distance <= 1, all structural entries of the d blocks B_c, lower triangle of C.
+template <int D>
+void pattern_entries(std::vector<int>& enc) {
+  enc.clear();
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP;
+  auto vco = [](int v, int* o) {
+    o[0] = v % 5;
+    o[1] = (v / 5) % 5;
+    o[2] = D == 3 ? v / 25 : 0;
+  };
+  auto qco = [](int q, int* o) {
+    o[0] = q % 3 + 1;
+    o[1] = (q / 3) % 3 + 1;
+    o[2] = D == 3 ? q / 9 + 1 : 0;
+  };
+  auto near = [](const int* a, const int* b) {
+    for (int k = 0; k < D; ++k)
+      if (a[k] - b[k] > 1 || b[k] - a[k] > 1) return false;
+    return true;
+  };
+  for (int i = 0; i < NV; ++i)
+    for (int j = 0; j <= i; ++j) {
+      int a[3], b[3];
+      vco(i, a);
+      vco(j, b);
+      if (near(a, b)) enc.push_back((0 << 24) | (i << 12) | j);
+    }
+  for (int c = 0; c < D; ++c)
+    for (int i = 0; i < NV; ++i)
+      for (int q = 0; q < NP; ++q) {
+        int a[3], b[3];
+        vco(i, a);
+        qco(q, b);
+        if (near(a, b)) enc.push_back(((1 + c) << 24) | (i << 12) | q);
+      }
+  for (int i = 0; i < NP; ++i)
+    for (int j = 0; j <= i; ++j) {
+      int a[3], b[3];
+      qco(i, a);
+      qco(j, b);
+      if (near(a, b)) enc.push_back(((D + 1) << 24) | (i << 12) | j);
+    }
+}
+
+template <int D>
+int pattern_size() {
+  std::vector<int> e;
+  pattern_entries<D>(e);
+  return (int)e.size();
+}
+
+// ================================================================================================
+// cache_inverse set-up (Sec. 3.1.2): the d+1 rows of L_i^{-1} that the restricted prolongation
+// keeps (velocity components and pressure of the centre node), written as (d+1) x ZSP rows in the
+// patch column layout. One block per patch.
+// ================================================================================================
+template <int D>
+__global__ void __launch_bounds__(PT<D>::THREADS) patch_inverse_rows_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, const int* __restrict__ nodes, int64_t count, double* __restrict__ Z, int* err) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NPX = NP + 2, ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
+  __shared__ PatchLDS<D> sh;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = oc->n;
+  const int ip = pres_center<D>(), mc = vel_center<D>();
+  for (int64_t pi = blockIdx.x; pi < count; pi += gridDim.x) {
+    const int64_t node = nodes[pi];
+    int c[3];
+    node_coords<D>(node, n, c);
+    if (tid == 0) sh.bad = 0;
+    patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 0);
+    patch_pad<D>(sh, c, n);
+    if (tid < NV) sh.X[tid * NPX + NP + 1] = tid == mc ? 1.0 : 0.0;  // e_m column (component 0)
+    band_cholesky<D>(sh);
+    // forward: columns 0..NP-1 of every component and the e_m column of component 0
+    for (int t = tid; t < D * NP + 1; t += nt) {
+      const int cmp = t < D * NP ? t / NP : 0;
+      const int col = t < D * NP ? t % NP : NP + 1;
+      double* Xc = sh.X + cmp * NV * NPX + col;
+      constexpr int NB = PT<D>::NB, BW = PT<D>::BW;
+      for (int i = 0; i < NV; ++i) {
+        double v = Xc[i * NPX];
+        const int k0 = i - BW > 0 ? i - BW : 0;
+        for (int k = k0; k < i; ++k) v -= sh.Kb[i * NB + (i - k)] * Xc[k * NPX];
+        Xc[i * NPX] = v / sh.Kb[i * NB];
+      }
+    }
+    __syncthreads();
+    schur_update<D>(sh, false);
+    schur_cholesky<D>(sh);
+    // S^{-1} = -F^{-1}, column j by forward/back substitution (thread per column)
+    for (int j = tid; j < NP; j += nt) {
+      double u[NP];
+      for (int i = 0; i < NP; ++i) {
+        double s = i == j ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) s -= sh.S[i * NP + k] * u[k];
+        u[i] = s / sh.S[i * NP + i];
+      }
+      for (int i = NP - 1; i >= 0; --i) {
+        double s = u[i];
+        for (int k = i + 1; k < NP; ++k) s -= sh.S[k * NP + i] * u[k];
+        u[i] = s / sh.S[i * NP + i];
+      }
+      for (int i = 0; i < NP; ++i) sh.Sinv[i * NP + j] = -u[i];
+    }
+    __syncthreads();
+    band_backward<D>(sh, NP);  // W_c = K^{-1} B_c, q = K^{-1} e_m
+    for (int e = tid; e < D * NP; e += nt) {
+      const int cmp = e / NP, j = e % NP;
+      double s = 0;
+      for (int i = 0; i < NP; ++i) s += sh.Sinv[j * NP + i] * sh.w[cmp][i];
+      sh.tc[cmp][j] = s;
+    }
+    __syncthreads();
+    double* Zp = Z + pi * (int64_t)(D + 1) * ZSP;
+    for (int e = tid; e < (D + 1) * ZSP; e += nt) {
+      const int f = e / ZSP, col = e % ZSP;
+      double val = 0;
+      if (col < D * NV) {
+        const int cp = col / NV, k = col % NV;
+        if (vel_in_grid<D>(c, n, k)) {
+          const double* Wr = sh.X + (cp * NV + k) * NPX;
+          double s = 0;
+          if (f < D) {
+            for (int j = 0; j < NP; ++j) s += Wr[j] * sh.tc[f][j];
+            if (f == cp) s += sh.X[k * NPX + NP + 1];
+          } else {
+            for (int j = 0; j < NP; ++j) s -= Wr[j] * sh.Sinv[j * NP + ip];
+          }
+          val = s;
+        }
+      } else if (col < ZS) {
+        const int j = col - D * NV;
+        if (pres_in_grid<D>(c, n, j)) val = f < D ? -sh.tc[f][j] : sh.Sinv[ip * NP + j];
+      }
+      Zp[e] = val;
+    }
+    if (tid == 0 && sh.bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
+template <int D>
+hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count, double* Z,
+                                hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const int64_t nb = count < 262144 ? count : 262144;
+  patch_inverse_rows_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
+      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, Z, c.err);
+  return hipGetLastError();
+}
+
+// ================================================================================================
+// cache_matrix set-up: store the sparse pattern values of L_i (Sec. 3.1.2, "stored using a sparse
+// format"). One block per patch.
+// ================================================================================================
+template <int D>
+__global__ void __launch_bounds__(PT<D>::THREADS) store_matrices_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, const int* __restrict__ nodes, int64_t count, const int* __restrict__ pattern, int npat,
+    double* __restrict__ M) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB, NPX = NP + 2;
+  __shared__ PatchLDS<D> sh;
+  for (int64_t pi = blockIdx.x; pi < count; pi += gridDim.x) {
+    int c[3];
+    node_coords<D>(nodes[pi], oc->n, c);
+    patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 0);
+    for (int e = threadIdx.x; e < npat; e += blockDim.x) {
+      const int code = pattern[e];
+      const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
+      double v;
+      if (type == 0)
+        v = sh.Kb[i * NB + (i - j)];
+      else if (type <= D)
+        v = sh.X[((type - 1) * NV + i) * NPX + j];
+      else
+        v = sh.S[i * NP + j];
+      M[pi * npat + e] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <int D>
+hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int64_t count, double* M, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const int64_t nb = count < 262144 ? count : 262144;
+  store_matrices_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
+      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, c.pattern, c.n_pattern, M);
+  return hipGetLastError();
+}
+
+// ================================================================================================
+// cache_matrix / cache_none application: for every node i, retrieve or assemble L_i, factorise,
+// solve L_i y = R_i r and add omega * (kept entries of y) to x (Eq. 14-15). One block per patch.
+// x == nullptr: factorise only and report singular blocks (set-up validation).
+// ================================================================================================
+template <int D>
+__global__ void __launch_bounds__(PT<D>::THREADS) patch_solve_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
+    const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
+    const double* __restrict__ r, double* __restrict__ x, double omega, int* err) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NPX = NP + 2;
+  __shared__ PatchLDS<D> sh;
+  const int tid = threadIdx.x;
+  const int n = oc->n;
+  const int mc = vel_center<D>(), ip = pres_center<D>();
+  for (int64_t node = blockIdx.x; node < N; node += gridDim.x) {
+    int c[3];
+    node_coords<D>(node, n, c);
+    if (tid == 0) sh.bad = 0;
+    if (policy == FCGMG_CACHE_MATRIX) {
+      const int cls = node_class[node];
+      const double* vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
+      patch_load_pattern<D>(sh, pattern, npat, vals);
+    } else {
+      patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 1);
+    }
+    patch_pad<D>(sh, c, n);
+    // right-hand side g = R_i r (zero outside the grid) and the e_m column
+    for (int e = tid; e < D * NV + NP; e += blockDim.x) {
+      if (e < D * NV) {
+        const int cmp = e / NV, v = e % NV;
+        double val = 0;
+        if (vel_in_grid<D>(c, n, v)) {
+          int cc[3] = {c[0] + v % 5 - 2, c[1] + (v / 5) % 5 - 2, D == 3 ? c[2] + v / 25 - 2 : 0};
+          val = r ? r[cmp * N + node_index<D>(cc, n)] : 0.0;
+        }
+        sh.X[(cmp * NV + v) * NPX + NP] = val;
+        if (cmp == 0) sh.X[v * NPX + NP + 1] = v == mc ? 1.0 : 0.0;
+      } else {
+        const int q = e - D * NV;
+        double val = 0;
+        if (pres_in_grid<D>(c, n, q)) {
+          int cc[3] = {c[0] + q % 3 - 1, c[1] + (q / 3) % 3 - 1, D == 3 ? c[2] + q / 9 - 1 : 0};
+          val = r ? r[D * N + node_index<D>(cc, n)] : 0.0;
+        }
+        sh.t[q] = val;
+      }
+    }
+    __syncthreads();
+    band_cholesky<D>(sh);
+    band_forward<D>(sh, NPX);
+    schur_update<D>(sh, true);
+    schur_cholesky<D>(sh);
+    schur_solve<D>(sh);
+    if (x != nullptr && tid <= D) {
+      double y;
+      if (tid < D) {
+        double s = sh.qg[tid];
+        for (int j = 0; j < NP; ++j) s -= sh.w[tid][j] * sh.t[j];
+        y = s;
+      } else {
+        y = sh.t[ip];
+      }
+      x[tid * N + node] += omega * y;
+    }
+    if (tid == 0 && sh.bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
+template <int D>
+hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x, hipStream_t s) {
+  const int64_t nb = L.N < 131072 ? L.N : 131072;
+  patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
+      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
+      c.n_pattern, L.N, r, x, c.prm.omega, c.err);
+  return hipGetLastError();
+}
+
+// ================================================================================================
+// cache_inverse application (Eq. 14-15 with the stored rows Z_i): y_f = Z_i[f,:] . R_i r,
+// x[i, f] += omega y_f.
+//   Regular patches: node tiles with the residual tile (+2 halo) in LDS; the class's rows are
+//   wavefront-uniform, so the loop over classes present in a wavefront reads them with scalar
+//   loads ("waterfall" over distinct classes).
+//   Irregular patches: one wavefront per patch, lanes over the patch columns, rows streamed
+//   coalesced from HBM, reduction across the wavefront.
+// ================================================================================================
+template <int D>
+struct TileShape;
+template <>
+struct TileShape<2> {
+  static constexpr int TX = 32, TY = 8, TZ = 1;
+};
+template <>
+struct TileShape<3> {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+
+template <int D>
+__global__ void __launch_bounds__(256) apply_regular_kernel(int n, int64_t N, const int* __restrict__ node_class,
+                                                            const double* __restrict__ Zcls,
+                                                            const double* __restrict__ r, double* __restrict__ x,
+                                                            double omega) {
+  constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
+  constexpr int HX = TX + 4, HY = TY + 4, HZ = D == 3 ? TZ + 4 : 1;
+  constexpr int PLANE = HX * HY * HZ;
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, ZSP = PT<D>::ZSP;
+  __shared__ double rt[(D + 1) * PLANE];
+  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = D == 3 ? threadIdx.x / (TX * TY) : 0;
+  const int ntx = (n + 1 + TX - 1) / TX, nty = (n + 1 + TY - 1) / TY;
+  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = D == 3 ? blockIdx.x / (ntx * nty) : 0;
+  const int ox = bx * TX - 2, oy = by * TY - 2, oz = D == 3 ? bz * TZ - 2 : 0;
+  for (int e = threadIdx.x; e < (D + 1) * PLANE; e += 256) {
+    const int f = e / PLANE, p = e % PLANE;
+    const int gx = ox + p % HX, gy = oy + (p / HX) % HY, gz = D == 3 ? oz + p / (HX * HY) : 0;
+    double v = 0;
+    if (gx >= 0 && gx <= n && gy >= 0 && gy <= n && (D == 2 || (gz >= 0 && gz <= n))) {
+      const int64_t j = D == 2 ? gx + (int64_t)(n + 1) * gy : gx + (int64_t)(n + 1) * (gy + (int64_t)(n + 1) * gz);
+      v = r[f * N + j];
+    }
+    rt[e] = v;
+  }
+  __syncthreads();
+  const int gx = bx * TX + tx, gy = by * TY + ty, gz = D == 3 ? bz * TZ + tz : 0;
+  const bool inside = gx <= n && gy <= n && (D == 2 || gz <= n);
+  const int64_t node = D == 2 ? gx + (int64_t)(n + 1) * gy : gx + (int64_t)(n + 1) * (gy + (int64_t)(n + 1) * gz);
+  const int cls = inside ? node_class[node] : -1;
+  bool todo = cls >= 0;
+  double y[D + 1];
+  for (int f = 0; f <= D; ++f) y[f] = 0;
+  const int base = tx + 2 + HX * (ty + 2 + (D == 3 ? HY * (tz + 2) : 0));
+  while (__ballot(todo) != 0) {
+    if (todo) {
+      const int c0 = __builtin_amdgcn_readfirstlane(cls);
+      if (cls == c0) {
+        const double* __restrict__ Z = Zcls + (int64_t)c0 * (D + 1) * ZSP;
+#pragma unroll
+        for (int cmp = 0; cmp < D; ++cmp) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int off = (v % 5 - 2) + HX * ((v / 5) % 5 - 2) + (D == 3 ? HX * HY * (v / 25 - 2) : 0);
+            const double gv = rt[cmp * PLANE + base + off];
+#pragma unroll
+            for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + cmp * NV + v] * gv;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int off = (q % 3 - 1) + HX * ((q / 3) % 3 - 1) + (D == 3 ? HX * HY * (q / 9 - 1) : 0);
+          const double gv = rt[D * PLANE + base + off];
+#pragma unroll
+          for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + D * NV + q] * gv;
+        }
+        todo = false;
+      }
+    }
+  }
+  if (cls >= 0)
+    for (int f = 0; f <= D; ++f) x[f * N + node] += omega * y[f];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t N, int64_t nirr,
+                                                              const int* __restrict__ irr_nodes,
+                                                              const double* __restrict__ Zirr,
+                                                              const double* __restrict__ r, double* __restrict__ x,
+                                                              double omega) {
+  constexpr int NV = PT<D>::NV, ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
+  const int lane = threadIdx.x & 63;
+  for (int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6); p < nirr; p += (int64_t)gridDim.x * 4) {
+    const int64_t node = irr_nodes[p];
+    int c[3];
+    node_coords<D>(node, n, c);
+    const double* __restrict__ Z = Zirr + p * (int64_t)(D + 1) * ZSP;
+    double acc[D + 1];
+    for (int f = 0; f <= D; ++f) acc[f] = 0;
+    for (int col = lane; col < ZS; col += 64) {
+      int field, o[3];
+      if (col < D * NV) {
+        field = col / NV;
+        const int v = col % NV;
+        o[0] = v % 5 - 2;
+        o[1] = (v / 5) % 5 - 2;
+        o[2] = D == 3 ? v / 25 - 2 : 0;
+      } else {
+        field = D;
+        const int q = col - D * NV;
+        o[0] = q % 3 - 1;
+        o[1] = (q / 3) % 3 - 1;
+        o[2] = D == 3 ? q / 9 - 1 : 0;
+      }
+      int cc[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
+      bool in = true;
+      for (int k = 0; k < D; ++k)
+        if (cc[k] < 0 || cc[k] > n) in = false;
+      const double gv = in ? r[field * N + node_index<D>(cc, n)] : 0.0;
+      for (int f = 0; f <= D; ++f) acc[f] += Z[f * ZSP + col] * gv;
+    }
+    for (int f = 0; f <= D; ++f) acc[f] = wave_sum(acc[f]);
+    if (lane <= D) {
+      double v = acc[0];
+      for (int f = 1; f <= D; ++f)
+        if (lane == f) v = acc[f];
+      x[lane * N + node] += omega * v;
+    }
+  }
+}
+
+template <int D>
+hipError_t k_apply_inverse(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
+  constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
+  if (L.n_classes > 0) {
+    const int64_t nt = (int64_t)((L.n + 1 + TX - 1) / TX) * ((L.n + 1 + TY - 1) / TY) *
+                       (D == 3 ? (L.n + 1 + TZ - 1) / TZ : 1);
+    apply_regular_kernel<D><<<dim3((unsigned)nt), dim3(256), 0, s>>>(L.n, L.N, L.node_class, L.Zcls, r, x,
+                                                                     c.prm.omega);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (L.n_irr > 0) {
+    int64_t nb = (L.n_irr + 3) / 4;
+    if (nb > 65536) nb = 65536;
+    apply_irregular_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.N, L.n_irr, L.irr_nodes, L.Zirr, r, x,
+                                                                       c.prm.omega);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fcg

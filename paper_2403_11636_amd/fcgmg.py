@@ -1,0 +1,269 @@
+"""Python binding of the fcgmg C-ABI library (include/fcgmg.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libfcgmg.so. PyTorch provides the
+device memory (FP64 CUDA/HIP tensors) and the stream. There is no CPU fallback: if the library
+is missing or no GPU is visible, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfcgmg.so")
+
+CACHE_INVERSE, CACHE_MATRIX, CACHE_NONE = 0, 1, 2
+POLICY_NAMES = {CACHE_INVERSE: "cache_inverse", CACHE_MATRIX: "cache_matrix", CACHE_NONE: "cache_none"}
+
+OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTS = [
+    "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
+    "fcgmg_residual", "fcgmg_smooth", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
+    "fcgmg_vcycle", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_destroy", "fcgmg_last_error",
+]
+
+
+class FcgmgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fcgmg error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n_cells", ctypes.c_int), ("n_levels", ctypes.c_int),
+        ("quad_depth", ctypes.c_int), ("cache_policy", ctypes.c_int), ("nu_pre", ctypes.c_int),
+        ("nu_post", ctypes.c_int), ("force", ctypes.c_int), ("bc", ctypes.c_int * 6),
+        ("eta", ctypes.c_double), ("alpha_fict", ctypes.c_double), ("nitsche_beta", ctypes.c_double),
+        ("omega", ctypes.c_double), ("ubar", ctypes.c_double),
+    ]
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n_cells_axis", "n_nodes", "n_cut_cells", "n_fict_cells", "n_classes", "n_irregular",
+        "irregular_cols", "cached_bytes")]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfcgmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with paper_2403_11636_amd/build.py")
+    # torch bundles its own HIP runtime (SONAME libamdhip64.so.7). Loading torch first makes the
+    # library's dependency resolve to that same runtime instead of a second copy from /opt/rocm,
+    # which would not see the device context that torch owns.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(path)
+    vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    L.fcgmg_setup_hierarchy.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.fcgmg_num_levels.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    L.fcgmg_num_dofs.argtypes = [vp, ctypes.c_int, i64p]
+    L.fcgmg_level_stats_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(LevelStats)]
+    L.fcgmg_rhs.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.fcgmg_residual.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.fcgmg_smooth.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    L.fcgmg_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fcgmg_prolongate_add.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.fcgmg_coarse_solve.argtypes = [vp, vp, vp, vp]
+    L.fcgmg_vcycle.argtypes = [vp, vp, vp, vp]
+    L.fcgmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, vp]
+    L.fcgmg_norm.argtypes = [vp, ctypes.c_int, vp, dp, vp]
+    L.fcgmg_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.fcgmg_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_int
+    L.fcgmg_destroy.restype = None
+    L.fcgmg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+_device_ready = False
+
+
+def _init_device():
+    """Make torch create the device context (and load its HIP runtime) before the library's first
+    HIP call, so that the library and torch share one runtime and one context."""
+    global _device_ready
+    if not _device_ready:
+        import torch
+        torch.cuda.init()
+        torch.empty(1, device="cuda")
+        torch.cuda.synchronize()
+        _device_ready = True
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FcgmgError(rc, load().fcgmg_last_error().decode())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, name: str, numel: int):
+    """Device pointer of a contiguous FP64 GPU tensor of exactly `numel` values (checked on the host
+    so that no kernel is ever handed a buffer shorter than the level it works on)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 GPU tensor")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} values, the level needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(prob, policy: int = CACHE_INVERSE) -> Params:
+    p = Params()
+    p.dim = prob.dim
+    p.n_cells = prob.n_cells
+    p.n_levels = prob.n_levels
+    p.quad_depth = prob.quad_depth
+    p.cache_policy = policy
+    p.nu_pre = prob.nu_pre
+    p.nu_post = prob.nu_post
+    p.force = prob.force
+    for k in range(6):
+        p.bc[k] = int(prob.bcs[k])
+    p.eta = prob.eta
+    p.alpha_fict = prob.alpha_fict
+    p.nitsche_beta = prob.nitsche_beta
+    p.omega = prob.omega
+    p.ubar = prob.ubar
+    return p
+
+
+class Hierarchy:
+    """Device-resident GMG hierarchy of one finite cell Stokes problem (fcgmg_setup_hierarchy)."""
+
+    def __init__(self, prob, policy: int = CACHE_INVERSE, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fcgmg needs a GPU; none is visible")
+        _init_device()
+        L = load()
+        self.prob = prob
+        self.policy = policy
+        self.dim = prob.dim
+        self._params = make_params(prob, policy)
+        balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
+        self._balls = balls
+        h = ctypes.c_void_p()
+        bp = balls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if balls.size else None
+        _check(L.fcgmg_setup_hierarchy(ctypes.byref(self._params), bp, balls.shape[0], _stream_ptr(stream),
+                                       ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int()
+        _check(L.fcgmg_num_levels(self.h, ctypes.byref(n)))
+        self.n_levels = n.value
+        self.fine = self.n_levels - 1
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcgmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ndofs(self, level: Optional[int] = None) -> int:
+        level = self.fine if level is None else level
+        n = ctypes.c_int64()
+        _check(load().fcgmg_num_dofs(self.h, level, ctypes.byref(n)))
+        return n.value
+
+    def stats(self, level: Optional[int] = None) -> dict:
+        level = self.fine if level is None else level
+        s = LevelStats()
+        _check(load().fcgmg_level_stats_get(self.h, level, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in LevelStats._fields_}
+
+    def device_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        _check(load().fcgmg_device_bytes(self.h, ctypes.byref(v)))
+        return v.value
+
+    def zeros(self, level: Optional[int] = None):
+        import torch
+        return torch.zeros(self.ndofs(level), dtype=torch.float64, device="cuda")
+
+    def rhs(self, level: Optional[int] = None, out=None, stream=None):
+        level = self.fine if level is None else level
+        b = self.zeros(level) if out is None else out
+        _check(load().fcgmg_rhs(self.h, level, _dptr(b, "b", self.ndofs(level)), _stream_ptr(stream)))
+        return b
+
+    def residual(self, x, b, level: Optional[int] = None, out=None, stream=None):
+        level = self.fine if level is None else level
+        n = self.ndofs(level)
+        r = self.zeros(level) if out is None else out
+        _check(load().fcgmg_residual(self.h, level, _dptr(x, "x", n), _dptr(b, "b", n), _dptr(r, "r", n),
+                                     _stream_ptr(stream)))
+        return r
+
+    def smooth(self, x, b, sweeps: int = 1, level: Optional[int] = None, stream=None):
+        level = self.fine if level is None else level
+        n = self.ndofs(level)
+        _check(load().fcgmg_smooth(self.h, level, _dptr(x, "x", n), _dptr(b, "b", n), sweeps, _stream_ptr(stream)))
+        return x
+
+    def restrict(self, r_fine, fine_level: Optional[int] = None, out=None, stream=None):
+        fine_level = self.fine if fine_level is None else fine_level
+        bc = self.zeros(fine_level - 1) if out is None else out
+        _check(load().fcgmg_restrict(self.h, fine_level, _dptr(r_fine, "r", self.ndofs(fine_level)),
+                                     _dptr(bc, "b_coarse", self.ndofs(fine_level - 1)),
+                                     _stream_ptr(stream)))
+        return bc
+
+    def prolongate_add(self, e_coarse, x_fine, fine_level: Optional[int] = None, stream=None):
+        fine_level = self.fine if fine_level is None else fine_level
+        _check(load().fcgmg_prolongate_add(self.h, fine_level, _dptr(e_coarse, "e", self.ndofs(fine_level - 1)),
+                                           _dptr(x_fine, "x", self.ndofs(fine_level)),
+                                           _stream_ptr(stream)))
+        return x_fine
+
+    def coarse_solve(self, b, out=None, stream=None):
+        x = self.zeros(0) if out is None else out
+        n = self.ndofs(0)
+        _check(load().fcgmg_coarse_solve(self.h, _dptr(b, "b", n), _dptr(x, "x", n), _stream_ptr(stream)))
+        return x
+
+    def vcycle(self, x, b, stream=None):
+        n = self.ndofs()
+        _check(load().fcgmg_vcycle(self.h, _dptr(x, "x", n), _dptr(b, "b", n), _stream_ptr(stream)))
+        return x
+
+    def norm(self, v, level: Optional[int] = None, stream=None) -> float:
+        level = self.fine if level is None else level
+        out = ctypes.c_double()
+        _check(load().fcgmg_norm(self.h, level, _dptr(v, "v", self.ndofs(level)), ctypes.byref(out),
+                                 _stream_ptr(stream)))
+        return out.value
+
+    def solve(self, b, x=None, rtol: float = 1e-8, max_iter: int = 100, stream=None, raise_on_noconv=True):
+        x = self.zeros() if x is None else x
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        hist = np.zeros(max_iter + 1)
+        n = self.ndofs()
+        rc = load().fcgmg_solve(self.h, _dptr(x, "x", n), _dptr(b, "b", n), rtol, max_iter, ctypes.byref(it),
+                                ctypes.byref(rel), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                _stream_ptr(stream))
+        if rc != OK and (rc != E_NOCONV or raise_on_noconv):
+            _check(rc)
+        return x, it.value, rel.value, hist[: it.value + 1], rc

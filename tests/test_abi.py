@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every entry point that include/fcgmg.h declares.
+
+No compute call is made here (this suite also runs without a GPU); only the host-side argument
+validation of fcgmg_setup_hierarchy, which returns before touching the device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2403_11636_amd import fcgmg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcgmg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcgmg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declarations_are_exported():
+    lib = fcgmg.load()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fcgmg.EXPORTS)
+
+
+def test_params_struct_matches_header():
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct {", src.index("FCGMG_E_NAN")):src.index("} fcgmg_params;")]
+    fields = re.findall(r"\b(?:int|double)\s+([a-z_]+)(?:\[\d\])?\s*;", body)
+    assert fields == [f for f, _ in fcgmg.Params._fields_]
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda p: setattr(p, "dim", 4), "dim"),
+    (lambda p: setattr(p, "n_cells", 30), "n_cells"),
+    (lambda p: setattr(p, "cache_policy", 7), "policy"),
+    (lambda p: setattr(p, "eta", -1.0), "eta"),
+    (lambda p: setattr(p, "quad_depth", 9), "quad_depth"),
+])
+def test_setup_rejects_bad_arguments_on_host(mutate, msg):
+    from paper_2403_11636_amd import inputs
+    lib = fcgmg.load()
+    p = fcgmg.make_params(inputs.config1(32, 3))
+    mutate(p)
+    h = ctypes.c_void_p()
+    rc = lib.fcgmg_setup_hierarchy(ctypes.byref(p), None, 0, None, ctypes.byref(h))
+    assert rc == fcgmg.E_ARG
+    assert msg in lib.fcgmg_last_error().decode()
+    assert not h.value
