@@ -1,0 +1,326 @@
+#!/usr/bin/env python
+"""Benchmark of the RAS-smoothed geometric multigrid for finite cell Stokes on one MI355X.
+
+Workload (default): the 2D finite cell Stokes problem on a 512 x 512 background grid of the unit
+square with 20 seeded non-overlapping disc obstacles (radii U[0.02, 0.06], alpha = 1e-8 inside),
+parabolic inflow left, do-nothing outflow right, no-slip top/bottom, Q1-Q1 stabilised, 7-level
+hierarchy, V(2,2) cycles with the restricted additive smoother (omega = 0.8) under the
+cache_inverse policy, FP64. Synthetic inputs stand in for the paper's channel-flow grids.
+
+A step is one V(2,2) cycle on the whole hierarchy (residuals, patch gathers, local solves,
+restricted scatters, restriction, prolongation, coarsest solve). The headline value is the RAS
+smoother throughput in fine-grid DoFs per second, counted as n_dof(finest) x (nu_pre + nu_post)
+fine-grid sweeps per step, divided by the measured step time; it therefore includes every coarse-
+level and transfer cost of the cycle. The same run also reports the fine-grid smoother alone, the
+GMG solve time to a 1e-8 relative residual with p50/p99 latencies, the dominant kernel against the
+HBM roofline, and the FP64 CPU oracle timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
+
+
+def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
+    """Bytes a kernel launch must move at minimum on one level (FP64 values, int32 indices).
+
+    residual:        read x, b; write r; cut-cell element data; one int per cell
+    apply_regular:   read r; one int per node; read+write x of the regular nodes; class rows
+    apply_irregular: the stored rows (d+1)|S_i| of every irregular patch; read+write x and read r
+                     of those nodes; one int per patch
+    patch_solve:     read r; read+write x (local blocks are built on chip or, for cache_matrix,
+                     read from the stored pattern values: added separately by the caller)
+    sweep_fused:     read x, b; write the new x; stored rows of the irregular patches; cut-cell
+                     element data; one int per node (patch class) and per cell (cell kind)
+    """
+    N = st["n_nodes"]
+    nf = d + 1
+    nel = (d + 1) * (1 << d) ** 2
+    ncells = st["n_cells_axis"] ** d
+    zs = d * 5 ** d + 3 ** d
+    nreg = N - st["n_irregular"]
+    if kind == "residual":
+        return 8.0 * 3 * nf * N + 8.0 * nel * st["n_cut_cells"] + 4.0 * ncells
+    if kind == "apply_regular":
+        return 8.0 * nf * N + 4.0 * N + 16.0 * nf * nreg + 8.0 * nf * zs * st["n_classes"]
+    if kind == "apply_irregular":
+        return 8.0 * nf * st["irregular_cols"] + 24.0 * nf * st["n_irregular"] + 4.0 * st["n_irregular"]
+    if kind == "patch_solve":
+        return 8.0 * 3 * nf * N
+    if kind == "sweep_fused":
+        return sweep_minimum_bytes(d, st) + 4.0 * N + 4.0 * ncells
+    if kind in ("restrict", "prolong"):
+        return 8.0 * nf * N * 1.25 if d == 2 else 8.0 * nf * N * 1.125
+    return 0.0
+
+
+def sweep_minimum_bytes(d: int, st: dict) -> float:
+    """Fused minimum of one cache_inverse sweep: read x, b, write x, stored rows of the irregular
+    patches, cut-cell element data."""
+    nf = d + 1
+    nel = (d + 1) * (1 << d) ** 2
+    return 8.0 * (3 * nf * st["n_nodes"] + nf * st["irregular_cols"] + nel * st["n_cut_cells"])
+
+
+def time_vcycles(torch, h, x, b, steps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        h.vcycle(x, b)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def time_sweeps(torch, h, x, b, count):
+    lat = []
+    for _ in range(count):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        h.smooth(x, b, 1)
+        e1.record()
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(z) for a, z in lat]
+
+
+def time_solves(torch, h, b, count, rtol=1e-8):
+    ms, its, rels = [], [], []
+    for _ in range(count):
+        x = h.zeros()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, it, rel, _, rc = h.solve(b, x=x, rtol=rtol, max_iter=200)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        its.append(it)
+        rels.append(rel)
+    return ms, its, rels
+
+
+def dominant_kernel(torch, h, x, b, steps, d):
+    """Profile `steps` V-cycles with the library's event timers (on the launch stream) and return
+    the kernel kind/level with the largest total time, with its average launch time."""
+    h.profile(True)
+    h.profile_reset()
+    for _ in range(steps):
+        h.vcycle(x, b)
+    torch.cuda.synchronize()
+    prof = h.profile_read()
+    h.profile(False)
+    (kind, lev), (tot, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+    total_all = sum(v[0] for v in prof.values())
+    avg_ms = tot / cnt
+    st = h.stats(lev)
+    nbytes = algorithmic_bytes(kind, d, st)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    table = {f"{k}@L{l}": {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches": v[1],
+                           "share": round(v[0] / total_all, 4)} for (k, l), v in sorted(prof.items())}
+    return {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": f"{kind}@L{lev}", "avg_launch_us": round(avg_ms * 1e3, 3),
+        "algorithmic_bytes_per_launch": int(nbytes), "time_share": round(tot / total_all, 4),
+    }, table
+
+
+def cpu_baseline(prob, steps=2):
+    """The FP64 oracle (as it stands) on the host cores: cache_inverse-form V(2,2) cycles on the same
+    problem. The oracle's inverse-row set-up runs first, untimed; it is most of the CPU work."""
+    from oracle.oracle import MODE_INVERSE, Oracle, max_threads
+    t0 = time.perf_counter()
+    o = Oracle(prob)
+    b = o.rhs()
+    x = o.vcycle(np.zeros_like(b), b, mode=MODE_INVERSE)  # builds the inverse rows on every level
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x = o.vcycle(x, b, mode=MODE_INVERSE)
+    dt = (time.perf_counter() - t0) / steps
+    nd = o.ndofs(o.fine)
+    return {
+        "value": round(nd * (prob.nu_pre + prob.nu_post) / dt, 1), "unit": "DOF/s", "cores": max_threads(),
+        "kind": "oracle",
+        "sample": f"{prob.name}: {steps} V({prob.nu_pre},{prob.nu_post}) cycles of the FP64 oracle in "
+                  f"cache_inverse form after its untimed {setup_s:.1f} s inverse-row set-up; "
+                  f"{dt * 1e3:.1f} ms per cycle",
+    }
+
+
+def policy_extras(torch, fcgmg, prob, sweeps=4):
+    out = {}
+    for pol in (fcgmg.CACHE_MATRIX, fcgmg.CACHE_NONE):
+        t0 = time.perf_counter()
+        h = fcgmg.Hierarchy(prob, pol)
+        setup = time.perf_counter() - t0
+        b = h.rhs()
+        x = h.zeros()
+        h.smooth(x, b, 1)
+        lat = time_sweeps(torch, h, x, b, sweeps)
+        ms = float(np.median(lat))
+        st = h.stats()
+        out[fcgmg.POLICY_NAMES[pol]] = {
+            "sweep_ms_p50": round(ms, 4), "smoother_dof_per_s": round(h.ndofs() / (ms * 1e-3), 1),
+            "cached_bytes_finest": st["cached_bytes"], "device_bytes": h.device_bytes(),
+            "setup_s": round(setup, 3)}
+        h.close()
+        log(f"  {fcgmg.POLICY_NAMES[pol]}: sweep {ms:.3f} ms")
+    return out
+
+
+def workload_extra(torch, fcgmg, prob, steps=5):
+    t0 = time.perf_counter()
+    h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
+    setup = time.perf_counter() - t0
+    b = h.rhs()
+    x = h.zeros()
+    h.vcycle(x, b)
+    ms, _ = time_vcycles(torch, h, x, b, steps)
+    lat = time_sweeps(torch, h, x, b, 10)
+    sw = float(np.median(lat))
+    st = h.stats()
+    nd = h.ndofs()
+    res = {
+        "workload": prob.name, "n_dof": nd, "setup_s": round(setup, 3), "vcycle_ms": round(ms, 4),
+        "value_dof_per_s": round(nd * (prob.nu_pre + prob.nu_post) / (ms * 1e-3), 1),
+        "smoother_dof_per_s": round(nd / (sw * 1e-3), 1), "sweep_ms_p50": round(sw, 4),
+        "sweep_min_bytes": int(sweep_minimum_bytes(prob.dim, st)),
+        "sweep_gbs_vs_min_bytes": round(sweep_minimum_bytes(prob.dim, st) / (sw * 1e-3) / 1e9, 1),
+        "n_irregular": st["n_irregular"], "n_cut_cells": st["n_cut_cells"], "device_bytes": h.device_bytes(),
+    }
+    h.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the policy / 3D / 4096^2 side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the multi-GPU (sharded) path is not part of this build; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2403_11636_amd import fcgmg, inputs
+
+    torch.cuda.set_device(0)
+    prob = inputs.config2(0)
+    d = prob.dim
+    log(f"setup {prob.name} (cache_inverse) ...")
+    t0 = time.perf_counter()
+    h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
+    setup_s = time.perf_counter() - t0
+    nd = h.ndofs()
+    b = h.rhs()
+    x = h.zeros()
+    for _ in range(args.warmup):
+        h.vcycle(x, b)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} V-cycles ...")
+    ms_step, wall = time_vcycles(torch, h, x, b, args.steps)
+    sweeps_per_step = prob.nu_pre + prob.nu_post
+    value = nd * sweeps_per_step / (ms_step * 1e-3)
+
+    log("fine-grid sweeps, solves, profile ...")
+    lat = time_sweeps(torch, h, x, b, 100)
+    sw50, sw99 = pct(lat, 50), pct(lat, 99)
+    solve_ms, its, rels = time_solves(torch, h, b, 20)
+    roof, table = dominant_kernel(torch, h, x, b, max(5, args.steps // 5), d)
+    st = h.stats()
+    sweep_min = sweep_minimum_bytes(d, st)
+
+    out = {
+        "metric": "RAS smoother DOF/s, GMG solve time to 1e-8 rel. residual; p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D finite cell Stokes, 512x512 background grid, 20 seeded discs r~U[0.02,0.06], "
+                        "alpha=1e-8, Q1-Q1 stabilised, inflow/do-nothing, 7-level GMG V(2,2), RAS smoother "
+                        "cache_inverse, omega=0.8",
+            "n_dof_finest": nd, "levels": prob.n_levels, "step": "one V(2,2) cycle",
+            "value_definition": "n_dof(finest) x 4 fine-grid sweeps per cycle / cycle time",
+            "parallelism": "1 GPU",
+        },
+        "smoother": {
+            "sweep_us_p50": round(sw50 * 1e3, 2), "sweep_us_p99": round(sw99 * 1e3, 2),
+            "fine_sweep_dof_per_s": round(nd / (sw50 * 1e-3), 1),
+            "sweep_min_bytes": int(sweep_min),
+            "sweep_gbs_vs_min_bytes": round(sweep_min / (sw50 * 1e-3) / 1e9, 1),
+        },
+        "solve": {
+            "rtol": 1e-8, "iterations": int(np.median(its)), "rel_res": float(np.max(rels)),
+            "ms_p50": round(pct(solve_ms, 50), 3), "ms_p99": round(pct(solve_ms, 99), 3), "count": len(solve_ms),
+            "setup_s": round(setup_s, 3),
+        },
+        "roofline": roof,
+        "kernels": table,
+        "wall_s_timed_region": round(wall, 4),
+    }
+    h.close()
+    if not args.no_extras:
+        log("policies ...")
+        out["policies"] = policy_extras(torch, fcgmg, prob)
+        out["policies"]["cache_inverse"] = {"sweep_ms_p50": round(sw50, 4),
+                                           "smoother_dof_per_s": round(nd / (sw50 * 1e-3), 1),
+                                           "cached_bytes_finest": st["cached_bytes"]}
+        log("3D 64^3 ...")
+        out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
+        log("2D 4096^2 ...")
+        big = inputs.config2(0, n_cells=4096, n_levels=10)
+        big.name = "2d_20discs_4096_seed0"
+        out["extra_2d_4096"] = workload_extra(torch, fcgmg, big)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

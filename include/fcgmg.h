@@ -141,6 +141,29 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
 /* ||v||_2 of a level vector, written to *out (host) after synchronising `stream`. */
 int fcgmg_norm(fcgmg_h h, int level, const double* v, double* out, void* stream);
 
+/* Kernel kinds for the event profiler. */
+enum {
+  FCGMG_K_RESIDUAL = 0,      /* r = b - L x                                                     */
+  FCGMG_K_APPLY_REGULAR = 1, /* cache_inverse: shared-row patches (LDS residual tile)            */
+  FCGMG_K_APPLY_IRREGULAR = 2, /* cache_inverse: individual rows streamed from HBM              */
+  FCGMG_K_PATCH_SOLVE = 3,   /* cache_matrix / cache_none: factorise + solve per patch           */
+  FCGMG_K_RESTRICT = 4,
+  FCGMG_K_PROLONG = 5,
+  FCGMG_K_COARSE = 6,        /* coarsest-grid solve                                              */
+  FCGMG_K_ZERO = 7,
+  FCGMG_K_SWEEP_FUSED = 8,   /* cache_inverse, 2D: residual + all patch corrections in one kernel */
+  FCGMG_K_TAIL = 9,          /* cache_inverse: the small coarse levels of a V-cycle in one kernel */
+  FCGMG_K_COUNT = 10
+};
+
+/* Event profiler (tracing): while enabled, every kernel launch of the handle is bracketed by a
+ * pair of HIP events on the launch stream. fcgmg_profile_read synchronises those events and returns
+ * the accumulated kernel time (ms) and launch count of one kind on one level since the last reset.
+ * Enabling adds two event records per launch; leave it off for production timing. */
+int fcgmg_profile_enable(fcgmg_h h, int on);
+int fcgmg_profile_reset(fcgmg_h h);
+int fcgmg_profile_read(fcgmg_h h, int kind, int level, double* total_ms, int64_t* launches);
+
 /* Device bytes held by the handle (all levels, all policy data). */
 int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
 

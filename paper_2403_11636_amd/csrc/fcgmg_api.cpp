@@ -53,6 +53,49 @@ int alloc_n(Ctx& c, T** p, size_t n) {
   return dev_alloc(c, reinterpret_cast<void**>(p), n * sizeof(T));
 }
 
+// Launch a kernel through `f` (returning hipError_t); with the profiler on, bracket it by events.
+template <class F>
+int launch(const Ctx& c, int kind, int level, hipStream_t s, F&& f) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.prof) {
+    for (hipEvent_t* e : {&e0, &e1}) {
+      if (!c.prof_pool.empty()) {
+        *e = c.prof_pool.back();
+        c.prof_pool.pop_back();
+      } else {
+        FCG_HIP(hipEventCreate(e));
+      }
+    }
+    FCG_HIP(hipEventRecord(e0, s));
+  }
+  const hipError_t err = f();
+  if (err != hipSuccess) return fail(FCGMG_E_HIP, std::string("kernel launch: ") + hipGetErrorString(err));
+  if (c.prof) {
+    FCG_HIP(hipEventRecord(e1, s));
+    c.prof_pending.push_back(Ctx::ProfRec{kind, level, e0, e1});
+  }
+  return FCGMG_OK;
+}
+
+int prof_collect(const Ctx& c) {
+  const int nl = (int)c.lev.size();
+  if (c.prof_ms.empty()) {
+    c.prof_ms.assign((size_t)FCGMG_K_COUNT * nl, 0.0);
+    c.prof_count.assign((size_t)FCGMG_K_COUNT * nl, 0);
+  }
+  for (const Ctx::ProfRec& r : c.prof_pending) {
+    FCG_HIP(hipEventSynchronize(r.stop));
+    float ms = 0;
+    FCG_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+    c.prof_ms[(size_t)r.kind * nl + r.level] += ms;
+    c.prof_count[(size_t)r.kind * nl + r.level] += 1;
+    c.prof_pool.push_back(r.start);
+    c.prof_pool.push_back(r.stop);
+  }
+  c.prof_pending.clear();
+  return FCGMG_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Reference element data of uncut cells and Nitsche face matrices (host, once per level).
 // ---------------------------------------------------------------------------------------------
@@ -131,9 +174,10 @@ void build_consts(const Ctx& c, Level& L) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Patch classification: a patch whose 6^d cell window (clipped to the grid) holds no cut cell
-// and only one kind of uncut cell has a block L_i determined by its distances to the walls
-// (clipped at 3) and that kind; such patches share one class. All others are individual.
+// Patch classification: a patch whose 6^d cell window lies inside the grid (at least 3 nodes from
+// every wall) and holds no cut cell and only one kind of uncut cell has the same block L_i as every
+// other such patch of that kind; these patches share one class (at most two classes per level:
+// physical and fictitious). All other patches (cut band, walls) keep individual blocks.
 // ---------------------------------------------------------------------------------------------
 template <int D>
 void classify_patches(const Level& L, const std::vector<signed char>& kinds, std::vector<int>& node_class,
@@ -179,15 +223,16 @@ void classify_patches(const Level& L, const std::vector<signed char>& kinds, std
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t tot = 1;
     int key = 0;
+    bool interior = true;
     for (int k = 0; k < D; ++k) {
       lo[k] = std::max(c[k] - 3, 0);
       hi[k] = std::min(c[k] + 2, n - 1);
       tot *= (hi[k] - lo[k] + 1);
-      key = key * 16 + std::min(c[k], 3) * 4 + std::min(n - c[k], 3);
+      interior = interior && c[k] >= 3 && n - c[k] >= 3;
     }
     const int64_t ncut = box_sum(sat_cut, lo, hi);
     const int64_t nfic = box_sum(sat_fic, lo, hi);
-    if (ncut == 0 && (nfic == 0 || nfic == tot)) {
+    if (interior && ncut == 0 && (nfic == 0 || nfic == tot)) {
       key = key * 2 + (nfic ? 1 : 0);
       auto it = key2cls.find(key);
       int cls;
@@ -239,6 +284,9 @@ bool dense_inverse(int n, std::vector<double>& A, std::vector<double>& Inv) {
 }
 
 constexpr int kCoarseMaxDofs = 6000;
+// LDS budget of the single-workgroup coarse V-cycle; 0 switches it off (it is not yet faster than
+// the per-level kernels on the measured workloads).
+constexpr size_t kTailLdsBytes = 0;
 constexpr int kRedBlocks = 512;
 
 template <int D>
@@ -281,6 +329,8 @@ int setup_impl(Ctx& c, hipStream_t s) {
       if ((rc = alloc_n(c, &L.x, nd))) return rc;
       if ((rc = alloc_n(c, &L.b, nd))) return rc;
     }
+    if (D == 2 && P.cache_policy == FCGMG_CACHE_INVERSE)
+      if ((rc = alloc_n(c, &L.xalt, nd))) return rc;
     // cells
     FCG_HIP(hipMallocAsync((void**)&kinds_d, L.ncells, s));
     FCG_HIP(k_classify_cells<D>(c, L, kinds_d, s));
@@ -364,6 +414,33 @@ int setup_impl(Ctx& c, hipStream_t s) {
       return fail(FCGMG_E_SINGULAR, "singular local block L_i of patch node " + std::to_string(errv) + " on level " +
                                         std::to_string(l));
   }
+  // Small coarse levels run as one single-workgroup kernel per V-cycle (cache_inverse only): the
+  // deepest levels below the finest whose x, b and r fit in the LDS of one workgroup.
+  if (P.cache_policy == FCGMG_CACHE_INVERSE) {
+    int top = -1;
+    size_t bytes = 0;
+    for (int l = 0; l < nlev - 1; ++l) {
+      const size_t lb = 3 * sizeof(double) * (D + 1) * (size_t)c.lev[l].N;
+      if (bytes + lb > kTailLdsBytes) break;
+      bytes += lb;
+      top = l;
+    }
+    if (D == 2 && top >= 1 && top < 6) {
+      std::vector<TailLevel> tl(top + 1);
+      int off = 0;
+      for (int l = 0; l <= top; ++l) {
+        const Level& L = c.lev[l];
+        tl[l] = TailLevel{L.consts, L.cell_info, L.cut_mats, L.node_class, L.Zcls, L.Zirr, L.irr_nodes, L.n_irr,
+                          L.x, L.b, L.r, L.n, off};
+        off += 3 * (D + 1) * (int)L.N;
+      }
+      if ((rc = alloc_n(c, &c.tail, tl.size()))) return rc;
+      FCG_HIP(hipMemcpyAsync(c.tail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
+      FCG_HIP(hipStreamSynchronize(s));
+      c.tail_top = top;
+      c.tail_lds_bytes = (size_t)off * sizeof(double);
+    }
+  }
   // coarsest level: dense operator, bordered when the constant pressure lies in the kernel
   {
     Level& L = c.lev[0];
@@ -408,43 +485,80 @@ int setup_impl(Ctx& c, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 template <int D>
 int residual_impl(const Ctx& c, int l, const double* x, const double* b, double* r, hipStream_t s) {
-  FCG_HIP(k_residual<D>(c, c.lev[l], x, b, r, s));
-  return FCGMG_OK;
+  return launch(c, FCGMG_K_RESIDUAL, l, s, [&] { return k_residual<D>(c, c.lev[l], x, b, r, s); });
 }
 
 template <int D>
 int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
   const Level& L = c.lev[l];
-  FCG_HIP(k_residual<D>(c, L, x, b, L.r, s));
+  int rc;
+  if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
   if (c.prm.cache_policy == FCGMG_CACHE_INVERSE) {
-    FCG_HIP(k_apply_inverse<D>(c, L, L.r, x, s));
-  } else {
-    FCG_HIP(k_patch_solve<D>(c, L, c.prm.cache_policy, L.r, x, s));
+    if (L.n_classes)
+      if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s, [&] { return k_apply_regular<D>(c, L, L.r, x, s); })))
+        return rc;
+    if (L.n_irr)
+      if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s, [&] { return k_apply_irregular<D>(c, L, L.r, x, s); })))
+        return rc;
+    return FCGMG_OK;
   }
+  return launch(c, FCGMG_K_PATCH_SOLVE, l, s,
+                [&] { return k_patch_solve<D>(c, L, c.prm.cache_policy, L.r, x, s); });
+}
+
+// `sweeps` sweeps on level l. 2D cache_inverse: pairs of fused sweeps ping-pong between x and the
+// level's second buffer (an odd first sweep runs unfused, in place); the arithmetic is identical.
+template <int D>
+int smooth_impl(const Ctx& c, int l, double* x, const double* b, int sweeps, hipStream_t s) {
+  const Level& L = c.lev[l];
+  int rc;
+  if (D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && L.xalt) {
+    int k = 0;
+    if (sweeps % 2 == 1) {
+      if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+      k = 1;
+    }
+    for (; k < sweeps; k += 2) {
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, x, b, L.xalt, s); })))
+        return rc;
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, L.xalt, b, x, s); })))
+        return rc;
+    }
+    return FCGMG_OK;
+  }
+  for (int i = 0; i < sweeps; ++i)
+    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
   return FCGMG_OK;
 }
 
 int coarse_impl(const Ctx& c, const double* b, double* x, hipStream_t s) {
-  FCG_HIP(k_dense_matvec(c.coarse_inv, c.coarse_n, b, x, s));
-  return FCGMG_OK;
+  return launch(c, FCGMG_K_COARSE, 0, s, [&] { return k_dense_matvec(c.coarse_inv, c.coarse_n, b, x, s); });
+}
+
+template <int D>
+int restrict_impl(const Ctx& c, int l, const double* rf, double* bc, hipStream_t s) {
+  return launch(c, FCGMG_K_RESTRICT, l, s, [&] { return k_restrict<D>(c, l, rf, bc, s); });
+}
+
+template <int D>
+int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t s) {
+  return launch(c, FCGMG_K_PROLONG, l, s, [&] { return k_prolong_add<D>(c, l, xc, xf, s); });
 }
 
 template <int D>
 int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
+  if (l == c.tail_top) return launch(c, FCGMG_K_TAIL, l, s, [&] { return k_tail_vcycle<D>(c, s); });
   if (l == 0) return coarse_impl(c, b, x, s);
   int rc;
-  for (int i = 0; i < c.prm.nu_pre; ++i)
-    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+  if ((rc = smooth_impl<D>(c, l, x, b, c.prm.nu_pre, s))) return rc;
   const Level& L = c.lev[l];
   const Level& C = c.lev[l - 1];
-  FCG_HIP(k_residual<D>(c, L, x, b, L.r, s));
-  FCG_HIP(k_restrict<D>(c, l, L.r, C.b, s));
-  FCG_HIP(k_zero(C.x, (D + 1) * C.N, s));
+  if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
+  if ((rc = restrict_impl<D>(c, l, L.r, C.b, s))) return rc;
+  if ((rc = launch(c, FCGMG_K_ZERO, l - 1, s, [&] { return k_zero(C.x, (D + 1) * C.N, s); }))) return rc;
   if ((rc = vcycle_impl<D>(c, l - 1, C.x, C.b, s))) return rc;
-  FCG_HIP(k_prolong_add<D>(c, l, C.x, x, s));
-  for (int i = 0; i < c.prm.nu_post; ++i)
-    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
-  return FCGMG_OK;
+  if ((rc = prolong_impl<D>(c, l, C.x, x, s))) return rc;
+  return smooth_impl<D>(c, l, x, b, c.prm.nu_post, s);
 }
 
 int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {
@@ -468,6 +582,12 @@ const char* fcgmg_last_error(void) { return g_err.c_str(); }
 
 void fcgmg_destroy(fcgmg_h h) {
   if (!h) return;
+  for (const Ctx::ProfRec& r : h->prof_pending) {
+    (void)hipEventSynchronize(r.stop);
+    h->prof_pool.push_back(r.start);
+    h->prof_pool.push_back(r.stop);
+  }
+  for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->red_host) (void)hipHostFree(h->red_host);
   delete h;
@@ -554,28 +674,19 @@ int fcgmg_residual(fcgmg_h h, int level, const double* x, const double* b, doubl
 int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream) {
   if (!valid_level(h, level) || !x || !b || sweeps < 0) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
   hipStream_t s = (hipStream_t)stream;
-  for (int i = 0; i < sweeps; ++i) {
-    const int rc = h->prm.dim == 2 ? sweep_impl<2>(*h, level, x, b, s) : sweep_impl<3>(*h, level, x, b, s);
-    if (rc) return rc;
-  }
-  return FCGMG_OK;
+  return h->prm.dim == 2 ? smooth_impl<2>(*h, level, x, b, sweeps, s) : smooth_impl<3>(*h, level, x, b, sweeps, s);
 }
 
 int fcgmg_restrict(fcgmg_h h, int fine_level, const double* rf, double* bc, void* stream) {
   if (!valid_level(h, fine_level) || fine_level < 1 || !rf || !bc) return fail(FCGMG_E_ARG, "bad level or pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = h->prm.dim == 2 ? k_restrict<2>(*h, fine_level, rf, bc, s) : k_restrict<3>(*h, fine_level, rf, bc, s);
-  if (e != hipSuccess) return fail(FCGMG_E_HIP, std::string("restrict: ") + hipGetErrorString(e));
-  return FCGMG_OK;
+  return h->prm.dim == 2 ? restrict_impl<2>(*h, fine_level, rf, bc, s) : restrict_impl<3>(*h, fine_level, rf, bc, s);
 }
 
 int fcgmg_prolongate_add(fcgmg_h h, int fine_level, const double* ec, double* xf, void* stream) {
   if (!valid_level(h, fine_level) || fine_level < 1 || !ec || !xf) return fail(FCGMG_E_ARG, "bad level or pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e =
-      h->prm.dim == 2 ? k_prolong_add<2>(*h, fine_level, ec, xf, s) : k_prolong_add<3>(*h, fine_level, ec, xf, s);
-  if (e != hipSuccess) return fail(FCGMG_E_HIP, std::string("prolongate: ") + hipGetErrorString(e));
-  return FCGMG_OK;
+  return h->prm.dim == 2 ? prolong_impl<2>(*h, fine_level, ec, xf, s) : prolong_impl<3>(*h, fine_level, ec, xf, s);
 }
 
 int fcgmg_coarse_solve(fcgmg_h h, const double* b, double* x, void* stream) {
@@ -627,6 +738,32 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
   }
   return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
                                   std::to_string(*rel_res) + ")");
+}
+
+int fcgmg_profile_enable(fcgmg_h h, int on) {
+  if (!h) return fail(FCGMG_E_ARG, "null handle");
+  h->prof = on != 0;
+  return FCGMG_OK;
+}
+
+int fcgmg_profile_reset(fcgmg_h h) {
+  if (!h) return fail(FCGMG_E_ARG, "null handle");
+  int rc = prof_collect(*h);
+  if (rc) return rc;
+  std::fill(h->prof_ms.begin(), h->prof_ms.end(), 0.0);
+  std::fill(h->prof_count.begin(), h->prof_count.end(), 0);
+  return FCGMG_OK;
+}
+
+int fcgmg_profile_read(fcgmg_h h, int kind, int level, double* total_ms, int64_t* launches) {
+  if (!valid_level(h, level) || kind < 0 || kind >= FCGMG_K_COUNT || !total_ms || !launches)
+    return fail(FCGMG_E_ARG, "bad handle, kind, level or pointer");
+  int rc = prof_collect(*h);
+  if (rc) return rc;
+  const size_t i = (size_t)kind * h->lev.size() + level;
+  *total_ms = h->prof_ms[i];
+  *launches = h->prof_count[i];
+  return FCGMG_OK;
 }
 
 int fcgmg_device_bytes(fcgmg_h h, size_t* bytes) {

@@ -78,11 +78,32 @@ struct Level {
   double* r = nullptr;        // residual scratch, (d+1) N
   double* x = nullptr;        // V-cycle iterate (levels below the finest)
   double* b = nullptr;        // V-cycle right-hand side (levels below the finest)
+  double* xalt = nullptr;     // second iterate buffer of the fused 2D sweep
   size_t cached_bytes = 0;
+};
+
+// Per-level data the single-workgroup V-cycle kernel reads (device resident).
+struct TailLevel {
+  const OpConsts* oc;
+  const int* cell_info;
+  const double* cut;
+  const int* node_class;
+  const double* Zcls;
+  const double* Zirr;
+  const int* irr_nodes;
+  int64_t n_irr;
+  double* x;
+  double* b;
+  double* r;
+  int n;
+  int lds;  // offset of this level's x, b, r in the tail kernel's LDS (doubles)
 };
 
 struct Ctx {
   fcgmg_params prm{};
+  int tail_top = -1;             // levels 0..tail_top run inside one single-workgroup kernel
+  TailLevel* tail = nullptr;     // device copy of the per-level table
+  size_t tail_lds_bytes = 0;
   std::vector<double> balls_h;
   double* balls = nullptr;
   std::vector<Level> lev;
@@ -96,6 +117,16 @@ struct Ctx {
   int n_pattern = 0;
   size_t bytes = 0;
   std::vector<void*> allocs;
+  // event profiler
+  struct ProfRec {
+    int kind, level;
+    hipEvent_t start, stop;
+  };
+  bool prof = false;
+  mutable std::vector<ProfRec> prof_pending;
+  mutable std::vector<hipEvent_t> prof_pool;
+  mutable std::vector<double> prof_ms;      // [kind * nlev + level]
+  mutable std::vector<int64_t> prof_count;
   Geom geom() const { return Geom{balls, (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
   Geom geom_host() const { return Geom{balls_h.data(), (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
 };
@@ -262,7 +293,12 @@ template <int D> hipError_t k_residual(const Ctx& c, const Level& L, const doubl
                                        hipStream_t s);
 template <int D> hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count,
                                                  double* Z, hipStream_t s);
-template <int D> hipError_t k_apply_inverse(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s);
+template <int D> hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s);
+template <int D> hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x,
+                                             hipStream_t s);
+template <int D> hipError_t k_tail_vcycle(const Ctx& c, hipStream_t s);
+hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                          hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,
                                           hipStream_t s);
 template <int D> hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int64_t count,

@@ -10,6 +10,10 @@
 
 namespace fcg {
 
+// Pointer into the constant address space: loads with a wavefront-uniform address from it are
+// issued as scalar loads into SGPRs.
+typedef __attribute__((address_space(4))) const double cdouble;
+
 namespace {
 
 constexpr int kMaxLocalBalls = 16;
@@ -224,87 +228,280 @@ hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s) {
 }
 
 // ================================================================================================
-// Residual r = b - L x (Eq. 12, 14): one thread per node, summing the element contributions of the
-// 2^d cells around it (uncut cells: reference matrices times alpha; cut cells: stored integrals;
-// Dirichlet walls: Nitsche face matrices). The stabilisation C has no alpha (Eq. 10).
+// Residual r = b - L x (Eq. 12, 14). Each node sums the element rows of the 2^d cells around it:
+// uncut cells use the reference matrices (read through uniform scalar loads) times alpha of the
+// cell, cut cells their stored integrals, Dirichlet walls the Nitsche face matrices; the
+// stabilisation C carries no alpha (Eq. 10). x comes from an LDS tile with a one-node halo.
 // ================================================================================================
 template <int D>
-__global__ void __launch_bounds__(256) residual_kernel(const OpConsts* __restrict__ oc, const int* __restrict__ cell_info,
-                                                      const double* __restrict__ cut, int64_t N,
-                                                      const double* __restrict__ x, const double* __restrict__ b,
-                                                      double* __restrict__ r) {
-  constexpr int NN = 1 << D;
+struct TileShape;
+template <>
+struct TileShape<2> {
+  static constexpr int TX = 32, TY = 8, TZ = 1;
+};
+template <>
+struct TileShape<3> {
+  static constexpr int TX = 8, TY = 8, TZ = 4;
+};
+
+// Tile of block `bid` in an nt[0] x nt[1] x nt[2] tile grid. Consecutive workgroups are dealt
+// round-robin to the 8 XCDs (each with its own L2); the remap gives every XCD a contiguous range of
+// tiles so that halo re-reads of neighbouring tiles hit the same L2. It is a bijection of the first
+// 8*floor(nb/8) blocks onto themselves; the last nb % 8 blocks keep their own tile.
+template <int D>
+__device__ __forceinline__ void tile_coords(int bid, const int* nt, int* t) {
+  const int nb = nt[0] * nt[1] * nt[2];
+  const int nb8 = nb - nb % 8;
+  int lin = bid;
+  if (bid < nb8) lin = (bid % 8) * (nb8 / 8) + bid / 8;
+  t[0] = lin % nt[0];
+  t[1] = (lin / nt[0]) % nt[1];
+  t[2] = lin / (nt[0] * nt[1]);
+}
+
+// Cut-cell integrals of a tile's cell region staged in LDS (up to MAXCUT cells; any further cut cell
+// of the region is read from global memory). The values, and so the arithmetic, are the same.
+template <int D, int MAXCUT, int NCELL>
+struct CutStage {
+  double buf[MAXCUT * PT<D>::NEL];
+  int slot[NCELL];
+  int cell[MAXCUT];
+  int count;
+};
+
+// cs: cell kinds of the region (LDS, already filled and synchronised). st.count must be 0.
+template <int D, int MAXCUT, int NCELL>
+__device__ __forceinline__ void stage_cuts(CutStage<D, MAXCUT, NCELL>& st, const int* cs,
+                                           const double* __restrict__ cut) {
   constexpr int NEL = PT<D>::NEL;
-  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int n = oc->n;
-  int c[3];
-  node_coords<D>(node, n, c);
-  double acc[D + 1];
-  for (int f = 0; f <= D; ++f) acc[f] = 0;
+  for (int e = threadIdx.x; e < NCELL; e += blockDim.x) {
+    const int v = cs[e];
+    int sl = -1;
+    if (v >= 0) {
+      const int k = atomicAdd(&st.count, 1);
+      if (k < MAXCUT) {
+        sl = k;
+        st.cell[k] = v;
+      }
+    }
+    st.slot[e] = sl;
+  }
+  __syncthreads();
+  const int nc = st.count < MAXCUT ? st.count : MAXCUT;
+  for (int i = threadIdx.x; i < nc * NEL; i += blockDim.x) st.buf[i] = cut[(int64_t)st.cell[i / NEL] * NEL + i % NEL];
+  __syncthreads();
+}
+
+// Reference element matrices of a level (uncut physical cell; fictitious cells scale K and B by
+// alpha_f), the stabilisation block and the Nitsche face matrices, packed for one dimension. The
+// kernels copy them into LDS once per workgroup: the node loops then read only LDS.
+template <int D>
+struct RefMats {
+  static constexpr int NN2 = (1 << D) * (1 << D);
+  static constexpr int oK = 0, oB = NN2, oC = NN2 * (1 + D), oFK = NN2 * (2 + D), oFB = NN2 * (2 + 3 * D);
+  static constexpr int TOT = NN2 * (2 + 5 * D);
+  double v[TOT];  // K | B_0..B_{D-1} | C | FK_0..FK_{2D-1} | FB_0..FB_{2D-1}
+  int dir[2 * D];
+};
+
+// Cooperative copy of the level constants into LDS (caller synchronises afterwards).
+template <int D>
+__device__ __forceinline__ void stage_refmats(const OpConsts* __restrict__ oc, RefMats<D>& rm) {
+  using R = RefMats<D>;
+  constexpr int NN2 = R::NN2;
+  for (int i = threadIdx.x; i < R::TOT; i += blockDim.x) {
+    double v;
+    if (i < R::oB)
+      v = oc->K[0][i];
+    else if (i < R::oC)
+      v = oc->B[0][(i - R::oB) / NN2][(i - R::oB) % NN2];
+    else if (i < R::oFK)
+      v = oc->C[i - R::oC];
+    else if (i < R::oFB)
+      v = oc->FK[(i - R::oFK) / NN2][(i - R::oFK) % NN2];
+    else
+      v = oc->FB[(i - R::oFB) / NN2][(i - R::oFB) % NN2];
+    rm.v[i] = v;
+  }
+  if (threadIdx.x < 2 * D) rm.dir[threadIdx.x] = oc->dirichlet[threadIdx.x];
+}
+
+// Accumulate L x at node c (coords) into acc[0..D]; xat(f, o) returns x_f at c + o (o in {-1,0,1}^D),
+// ci(cc) the kind/cut index of the in-grid cell with lower corner cc, cutp(cc, info) the address of a
+// cut cell's integrals.
+// UNR = false keeps the loop over the cells rolled (same order of operations, fewer registers).
+template <int D, bool UNR = true, class CI, class CP, class XA>
+__device__ __forceinline__ void node_apply(const RefMats<D>& rm, CI&& ci, CP&& cutp, double alpha_f, int n,
+                                           const int* c, XA&& xat, double* acc) {
+  constexpr int NN = 1 << D, NN2 = NN * NN;
+#pragma unroll(UNR ? NN : 1)
   for (int sc = 0; sc < NN; ++sc) {
     int cc[3] = {0, 0, 0};
     bool in = true;
     int a = 0;
+#pragma unroll
     for (int k = 0; k < D; ++k) {
       const int sk = (sc >> k) & 1;
       cc[k] = c[k] - 1 + sk;
-      if (cc[k] < 0 || cc[k] > n - 1) in = false;
+      in = in && cc[k] >= 0 && cc[k] <= n - 1;
       a |= (1 - sk) << k;
     }
     if (!in) continue;
-    const int info = cell_info[cell_index<D>(cc, n)];
-    const double* Kp;
-    const double* Bp;
-    int bstride;
-    if (info >= 0) {
-      Kp = cut + (int64_t)info * NEL;
-      Bp = Kp + NN * NN;
-      bstride = NN * NN;
-    } else {
-      const int kind = info == -1 ? 0 : 1;
-      Kp = oc->K[kind];
-      Bp = oc->B[kind][0];
-      bstride = 64;
-    }
+    const int info = ci(cc);
     double u[D + 1][NN];
+#pragma unroll
     for (int bn = 0; bn < NN; ++bn) {
-      int cb[3] = {cc[0] + (bn & 1), cc[1] + ((bn >> 1) & 1), D == 3 ? cc[2] + ((bn >> 2) & 1) : 0};
-      const int64_t j = node_index<D>(cb, n);
-      for (int f = 0; f <= D; ++f) u[f][bn] = x[f * N + j];
+      int o[3] = {0, 0, 0};
+#pragma unroll
+      for (int k = 0; k < D; ++k) o[k] = -1 + ((sc >> k) & 1) + ((bn >> k) & 1);
+#pragma unroll
+      for (int f = 0; f <= D; ++f) u[f][bn] = xat(f, o);
     }
-    for (int bn = 0; bn < NN; ++bn) {
-      const double kab = Kp[a * NN + bn];
-      const double cab = oc->C[a * NN + bn];
-      for (int f = 0; f < D; ++f) {
-        acc[f] += kab * u[f][bn] + Bp[f * bstride + a * NN + bn] * u[D][bn];
-        acc[D] += Bp[f * bstride + bn * NN + a] * u[f][bn];
+    if (info >= 0) {
+      const double* Kp = cutp(cc, info);
+      const double* Bp = Kp + NN * NN;
+#pragma unroll
+      for (int bn = 0; bn < NN; ++bn) {
+        const double kab = Kp[a * NN + bn];
+#pragma unroll
+        for (int f = 0; f < D; ++f) {
+          acc[f] += kab * u[f][bn] + Bp[f * NN * NN + a * NN + bn] * u[D][bn];
+          acc[D] += Bp[f * NN * NN + bn * NN + a] * u[f][bn];
+        }
       }
-      acc[D] += cab * u[D][bn];
+    } else {
+      const double al = info == -1 ? 1.0 : alpha_f;
+      double sk[D + 1];
+#pragma unroll
+      for (int f = 0; f <= D; ++f) sk[f] = 0;
+#pragma unroll
+      for (int bn = 0; bn < NN; ++bn) {
+        const double kab = rm.v[RefMats<D>::oK + a * NN + bn];
+#pragma unroll
+        for (int f = 0; f < D; ++f) {
+          sk[f] += kab * u[f][bn] + rm.v[RefMats<D>::oB + f * NN2 + a * NN + bn] * u[D][bn];
+          sk[D] += rm.v[RefMats<D>::oB + f * NN2 + bn * NN + a] * u[f][bn];
+        }
+      }
+#pragma unroll
+      for (int f = 0; f <= D; ++f) acc[f] += al * sk[f];
     }
-    // Nitsche terms of Dirichlet walls touched by this cell
+#pragma unroll
+    for (int bn = 0; bn < NN; ++bn) acc[D] += rm.v[RefMats<D>::oC + a * NN + bn] * u[D][bn];
+#pragma unroll
     for (int k = 0; k < D; ++k)
+#pragma unroll
       for (int sd = 0; sd < 2; ++sd) {
         const int face = 2 * k + sd;
-        if (!oc->dirichlet[face]) continue;
-        if (cc[k] != (sd ? n - 1 : 0)) continue;
-        const double* FK = oc->FK[face];
-        const double* FB = oc->FB[face];
+        if (!rm.dir[face] || cc[k] != (sd ? n - 1 : 0)) continue;
+#pragma unroll
         for (int bn = 0; bn < NN; ++bn) {
-          for (int f = 0; f < D; ++f) acc[f] += FK[a * NN + bn] * u[f][bn];
-          acc[k] += FB[a * NN + bn] * u[D][bn];
-          acc[D] += FB[bn * NN + a] * u[k][bn];
+          const double fk = rm.v[RefMats<D>::oFK + face * NN2 + a * NN + bn];
+#pragma unroll
+          for (int f = 0; f < D; ++f) acc[f] += fk * u[f][bn];
+          acc[k] += rm.v[RefMats<D>::oFB + face * NN2 + a * NN + bn] * u[D][bn];
+          acc[D] += rm.v[RefMats<D>::oFB + face * NN2 + bn * NN + a] * u[k][bn];
         }
       }
   }
-  for (int f = 0; f <= D; ++f) r[f * N + node] = b[f * N + node] - acc[f];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __restrict__ oc,
+                                                           const int* __restrict__ cell_info,
+                                                           const double* __restrict__ cut, double alpha_f, int ntx,
+                                                           int nty, int ntz, const double* __restrict__ x,
+                                                           const double* __restrict__ b, double* __restrict__ r) {
+  constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
+  constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
+  constexpr int CW = TX + 1, CH = TY + 1, CD = D == 3 ? TZ + 1 : 1, CP = CW * CH * CD;
+  constexpr int MAXCUT = D == 2 ? 32 : 1;
+  constexpr int NXL = ((D + 1) * XP + 255) / 256, NCL = (CP + 255) / 256;
+  __shared__ double xs[(D + 1) * XP];
+  __shared__ int cs[CP];
+  __shared__ CutStage<D, MAXCUT, CP> cst;
+  __shared__ RefMats<D> rm;
+  if (threadIdx.x == 0) cst.count = 0;
+  const int n = oc->n;
+  const int m = n + 1;
+  const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
+  const int nt[3] = {ntx, nty, ntz};
+  int t[3];
+  tile_coords<D>(blockIdx.x, nt, t);
+  const int o0 = t[0] * TX - 1, o1 = t[1] * TY - 1, o2 = D == 3 ? t[2] * TZ - 1 : 0;
+  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = D == 3 ? threadIdx.x / (TX * TY) : 0;
+  const int c[3] = {t[0] * TX + tx, t[1] * TY + ty, D == 3 ? t[2] * TZ + tz : 0};
+  const bool inside = c[0] < m && c[1] < m && (D == 2 || c[2] < m);
+  const int64_t node = D == 2 ? c[0] + (int64_t)m * c[1] : c[0] + (int64_t)m * (c[1] + (int64_t)m * c[2]);
+  // every global load of the tile is issued before the first LDS store
+  double bv[D + 1];
+#pragma unroll
+  for (int f = 0; f <= D; ++f) bv[f] = inside ? b[f * N + node] : 0.0;
+  double xv[NXL];
+#pragma unroll
+  for (int k = 0; k < NXL; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    const int f = e / XP, p = e % XP;
+    const int gx = o0 + p % XW, gy = o1 + (p / XW) % XH, gz = D == 3 ? o2 + p / (XW * XH) : 0;
+    const bool ok = e < (D + 1) * XP && gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m));
+    xv[k] = ok ? x[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))] : 0.0;
+  }
+  int cv[NCL];
+#pragma unroll
+  for (int k = 0; k < NCL; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    const int gx = o0 + e % CW, gy = o1 + (e / CW) % CH, gz = D == 3 ? o2 + e / (CW * CH) : 0;
+    const bool ok = e < CP && gx >= 0 && gx < n && gy >= 0 && gy < n && (D == 2 || (gz >= 0 && gz < n));
+    cv[k] = ok ? cell_info[D == 2 ? gx + n * gy : gx + n * (gy + n * gz)] : -1;
+  }
+  stage_refmats<D>(oc, rm);
+#pragma unroll
+  for (int k = 0; k < NXL; ++k)
+    if (threadIdx.x + 256 * k < (D + 1) * XP) xs[threadIdx.x + 256 * k] = xv[k];
+#pragma unroll
+  for (int k = 0; k < NCL; ++k)
+    if (threadIdx.x + 256 * k < CP) cs[threadIdx.x + 256 * k] = cv[k];
+  __syncthreads();
+  if (D == 2) stage_cuts<D, MAXCUT, CP>(cst, cs, cut);
+  if (!inside) return;
+  const int base = (tx + 1) + XW * ((ty + 1) + XH * (tz + 1) * (D == 3 ? 1 : 0));
+  double acc[D + 1];
+#pragma unroll
+  for (int f = 0; f <= D; ++f) acc[f] = 0;
+  node_apply<D>(rm,
+                [&](const int* cc) {
+                  return cs[(cc[0] - o0) + CW * ((cc[1] - o1) + (D == 3 ? CH * (cc[2] - o2) : 0))];
+                },
+                [&](const int* cc, int info) -> const double* {
+                  if (D == 2) {
+                    const int sl = cst.slot[(cc[0] - o0) + CW * (cc[1] - o1)];
+                    if (sl >= 0) return cst.buf + sl * PT<D>::NEL;
+                  }
+                  return cut + (int64_t)info * PT<D>::NEL;
+                },
+                alpha_f, n, c,
+                [&](int f, const int* o) {
+                  return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];
+                },
+                acc);
+#pragma unroll
+  for (int f = 0; f <= D; ++f) r[f * N + node] = bv[f] - acc[f];
+}
+
+template <int D>
+void tile_grid(int n, int* nt) {
+  nt[0] = (n + 1 + TileShape<D>::TX - 1) / TileShape<D>::TX;
+  nt[1] = (n + 1 + TileShape<D>::TY - 1) / TileShape<D>::TY;
+  nt[2] = D == 3 ? (n + 1 + TileShape<D>::TZ - 1) / TileShape<D>::TZ : 1;
 }
 
 template <int D>
 hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const double* b, double* r, hipStream_t s) {
-  const int bs = 256;
-  const int64_t nb = (L.N + bs - 1) / bs;
-  residual_kernel<D><<<dim3((unsigned)nb), dim3(bs), 0, s>>>(L.consts, L.cell_info, L.cut_mats, L.N, x, b, r);
+  int nt[3];
+  tile_grid<D>(L.n, nt);
+  const int nb = nt[0] * nt[1] * nt[2];
+  residual_tile_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.cell_info, L.cut_mats,
+                                                                    c.prm.alpha_fict, nt[0], nt[1], nt[2], x, b, r);
   return hipGetLastError();
 }
 
@@ -312,11 +509,11 @@ hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const doubl
 // Grid transfers (Eq. 13, one GPU: T = identity). P is the Q1 interpolation from level l-1 to l
 // (coarse node 2I coincides with fine node I); R = P^T. Gather form, one thread per output node.
 // ================================================================================================
+// b_c at coarse node `node` = sum of the fine residuals around fine node 2*node, weights 1/2 per
+// offset axis (R = P^T).
 template <int D>
-__global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ rf,
-                                double* __restrict__ bc) {
-  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (node >= Nc) return;
+__device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ rf,
+                                              double* __restrict__ bc, int64_t node) {
   int c[3];
   node_coords<D>(node, nc, c);
   double acc[D + 1];
@@ -341,11 +538,10 @@ __global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const do
   for (int f = 0; f <= D; ++f) bc[f * Nc + node] = acc[f];
 }
 
+// x_f at fine node `node` += Q1 interpolation of the coarse correction.
 template <int D>
-__global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
-                                   double* __restrict__ xf) {
-  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (node >= Nf) return;
+__device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
+                                             double* __restrict__ xf, int64_t node) {
   int c[3];
   node_coords<D>(node, nf, c);
   double acc[D + 1];
@@ -369,6 +565,20 @@ __global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const
     for (int f = 0; f <= D; ++f) acc[f] += w * xc[f * Nc + j];
   }
   for (int f = 0; f <= D; ++f) xf[f * Nf + node] += acc[f];
+}
+
+template <int D>
+__global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ rf,
+                                double* __restrict__ bc) {
+  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (node < Nc) restrict_node<D>(nf, Nf, nc, Nc, rf, bc, node);
+}
+
+template <int D>
+__global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
+                                   double* __restrict__ xf) {
+  const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (node < Nf) prolong_node<D>(nf, Nf, nc, Nc, xc, xf, node);
 }
 
 template <int D>
@@ -486,15 +696,18 @@ hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hip
 
 // x = A b with a dense row-major n x n matrix (coarsest-grid solve through the stored inverse):
 // one wavefront per row.
-__global__ void dense_matvec_kernel(const double* __restrict__ A, int n, const double* __restrict__ b,
-                                    double* __restrict__ x) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+__device__ __forceinline__ void dense_row(const double* __restrict__ A, int n, const double* __restrict__ b,
+                                          double* __restrict__ x, int row, int lane) {
   double s = 0;
   for (int j = lane; j < n; j += 64) s += A[(int64_t)row * n + j] * b[j];
   s = wave_sum(s);
   if (lane == 0) x[row] = s;
+}
+
+__global__ void dense_matvec_kernel(const double* __restrict__ A, int n, const double* __restrict__ b,
+                                    double* __restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row < n) dense_row(A, n, b, x, row, threadIdx.x & 63);
 }
 
 hipError_t k_dense_matvec(const double* A, int n, const double* b, double* x, hipStream_t s) {
@@ -552,6 +765,7 @@ hipError_t k_zero(double* v, int64_t n, hipStream_t s) {
 }  // namespace fcg
 
 #include "fcgmg_patch.inl"
+#include "fcgmg_tail.inl"
 
 namespace fcg {
 #define FCG_INST(D)                                                                                           \
@@ -565,10 +779,12 @@ namespace fcg {
   template hipError_t k_coarse_matrix<D>(const Ctx&, const Level&, double*, int, hipStream_t);                \
   template hipError_t k_patch_inverse_rows<D>(const Ctx&, const Level&, const int*, int64_t, double*,         \
                                               hipStream_t);                                                   \
-  template hipError_t k_apply_inverse<D>(const Ctx&, const Level&, const double*, double*, hipStream_t);      \
+  template hipError_t k_apply_regular<D>(const Ctx&, const Level&, const double*, double*, hipStream_t);      \
+  template hipError_t k_apply_irregular<D>(const Ctx&, const Level&, const double*, double*, hipStream_t);    \
   template hipError_t k_patch_solve<D>(const Ctx&, const Level&, int, const double*, double*, hipStream_t);  \
   template hipError_t k_store_matrices<D>(const Ctx&, const Level&, const int*, int64_t, double*,             \
                                           hipStream_t);                                                       \
+  template hipError_t k_tail_vcycle<D>(const Ctx&, hipStream_t);                                               \
   template int pattern_size<D>();                                                                             \
   template void pattern_entries<D>(std::vector<int>&);
 FCG_INST(2)

@@ -628,151 +628,384 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
 // ================================================================================================
 // cache_inverse application (Eq. 14-15 with the stored rows Z_i): y_f = Z_i[f,:] . R_i r,
 // x[i, f] += omega y_f.
-//   Regular patches: node tiles with the residual tile (+2 halo) in LDS; the class's rows are
-//   wavefront-uniform, so the loop over classes present in a wavefront reads them with scalar
-//   loads ("waterfall" over distinct classes).
+//   Regular patches: the class rows are wavefront-uniform and read with scalar loads; a
+//   "waterfall" loops over the distinct classes present in a wavefront. The residual comes from an
+//   LDS tile (two-node halo).
 //   Irregular patches: one wavefront per patch, lanes over the patch columns, rows streamed
 //   coalesced from HBM, reduction across the wavefront.
+// The fused 2D sweep kernel computes the residual tile itself (x with a three-node halo) and writes
+// the new iterate to a second buffer; it performs exactly the same arithmetic as the residual
+// kernel followed by the two apply kernels.
 // ================================================================================================
+
+// y[f] += Z[f,:] . g for a regular patch; rt(f, o) = r_f at the centre node + o. P is a pointer to
+// the rows in the constant address space (scalar loads) or the global one (per-lane loads).
+template <int D, bool UNR, class P, class RA>
+__device__ __forceinline__ void regular_rows(P Z, RA&& rt, double* y) {
+  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, ZSP = PT<D>::ZSP;
+#pragma unroll
+  for (int cmp = 0; cmp < D; ++cmp) {
+#pragma unroll(UNR ? NV : 5)
+    for (int v = 0; v < NV; ++v) {
+      const int o[3] = {v % 5 - 2, (v / 5) % 5 - 2, D == 3 ? v / 25 - 2 : 0};
+      const double gv = rt(cmp, o);
+#pragma unroll
+      for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + cmp * NV + v] * gv;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, D == 3 ? q / 9 - 1 : 0};
+    const double gv = rt(D, o);
+#pragma unroll
+    for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + D * NV + q] * gv;
+  }
+}
+
+// Regular patches of a wavefront: a waterfall over the classes present (at most two per level:
+// interior physical and interior fictitious), each applied with scalar loads of its rows. Lanes
+// with cls < 0 take no part.
+template <int D, bool UNR = true, class RA>
+__device__ __forceinline__ void regular_apply(const double* __restrict__ Zcls, int cls, RA&& rt, double* y) {
+  constexpr int ZSP = PT<D>::ZSP;
+  bool todo = cls >= 0;
+  while (__ballot(todo) != 0) {
+    if (todo) {
+      const int c0 = __builtin_amdgcn_readfirstlane(cls);
+      if (cls == c0) {
+        // read the lane value again inside the branch: the compiler would otherwise substitute the
+        // (equal, per-lane) cls for c0 and lose the scalar address
+        const int cu = __builtin_amdgcn_readfirstlane(cls);
+        regular_rows<D, UNR>((const cdouble*)(Zcls + (int64_t)cu * (D + 1) * ZSP), rt, y);
+        todo = false;
+      }
+    }
+  }
+}
+
+// Column j of a patch: field and offset of the node.
 template <int D>
-struct TileShape;
-template <>
-struct TileShape<2> {
-  static constexpr int TX = 32, TY = 8, TZ = 1;
-};
-template <>
-struct TileShape<3> {
-  static constexpr int TX = 8, TY = 8, TZ = 4;
-};
+__device__ __forceinline__ void patch_column(int col, int* field, int* o) {
+  constexpr int NV = PT<D>::NV;
+  if (col < D * NV) {
+    *field = col / NV;
+    const int v = col % NV;
+    o[0] = v % 5 - 2;
+    o[1] = (v / 5) % 5 - 2;
+    o[2] = D == 3 ? v / 25 - 2 : 0;
+  } else {
+    *field = D;
+    const int q = col - D * NV;
+    o[0] = q % 3 - 1;
+    o[1] = (q / 3) % 3 - 1;
+    o[2] = D == 3 ? q / 9 - 1 : 0;
+  }
+}
+
+// acc[f] = Z[f,:] . g for an irregular patch, computed by a group of 16 lanes (j16 = lane in the
+// group; columns j16, j16+16, ...); rg(field, o) = r at centre + o, or 0 outside the grid. Every
+// lane of the group returns the full sums. A wavefront holds 4 groups and each group takes two
+// patches at once (A, B), so the rows of 8 patches stream from HBM per wavefront and loop trip.
+// The arithmetic of each patch does not depend on which patch it is paired with.
+template <int D, class RGA, class RGB>
+__device__ __forceinline__ void irregular_pair(const double* __restrict__ ZA, const double* __restrict__ ZB,
+                                               bool has_b, int j16, RGA&& rga, RGB&& rgb, double* acca,
+                                               double* accb) {
+  constexpr int ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
+#pragma unroll
+  for (int f = 0; f <= D; ++f) acca[f] = accb[f] = 0;
+  const double* ZBs = has_b ? ZB : ZA;
+  // 2D: the four column steps are unrolled so that all row loads are in flight at once
+#pragma unroll(D == 2 ? 4 : 2)
+  for (int col = j16; col < ZS; col += 16) {
+    int field, o[3];
+    patch_column<D>(col, &field, o);
+    double za[D + 1], zb[D + 1];
+#pragma unroll
+    for (int f = 0; f <= D; ++f) {
+      za[f] = ZA[f * ZSP + col];
+      zb[f] = ZBs[f * ZSP + col];
+    }
+    const double ga = rga(field, o);
+    const double gb = has_b ? rgb(field, o) : 0.0;
+#pragma unroll
+    for (int f = 0; f <= D; ++f) {
+      acca[f] += za[f] * ga;
+      accb[f] += zb[f] * gb;
+    }
+  }
+#pragma unroll
+  for (int f = 0; f <= D; ++f)
+#pragma unroll
+    for (int msk = 8; msk >= 1; msk >>= 1) {
+      acca[f] += __shfl_xor(acca[f], msk, 16);
+      accb[f] += __shfl_xor(accb[f], msk, 16);
+    }
+}
 
 template <int D>
-__global__ void __launch_bounds__(256) apply_regular_kernel(int n, int64_t N, const int* __restrict__ node_class,
+__global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int nty, int ntz,
+                                                            const int* __restrict__ node_class,
                                                             const double* __restrict__ Zcls,
                                                             const double* __restrict__ r, double* __restrict__ x,
                                                             double omega) {
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int HX = TX + 4, HY = TY + 4, HZ = D == 3 ? TZ + 4 : 1;
   constexpr int PLANE = HX * HY * HZ;
-  constexpr int NV = PT<D>::NV, NP = PT<D>::NP, ZSP = PT<D>::ZSP;
   __shared__ double rt[(D + 1) * PLANE];
-  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = D == 3 ? threadIdx.x / (TX * TY) : 0;
-  const int ntx = (n + 1 + TX - 1) / TX, nty = (n + 1 + TY - 1) / TY;
-  const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = D == 3 ? blockIdx.x / (ntx * nty) : 0;
-  const int ox = bx * TX - 2, oy = by * TY - 2, oz = D == 3 ? bz * TZ - 2 : 0;
+  const int m = n + 1;
+  const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
+  const int nt[3] = {ntx, nty, ntz};
+  int t[3];
+  tile_coords<D>(blockIdx.x, nt, t);
+  const int ox = t[0] * TX - 2, oy = t[1] * TY - 2, oz = D == 3 ? t[2] * TZ - 2 : 0;
   for (int e = threadIdx.x; e < (D + 1) * PLANE; e += 256) {
     const int f = e / PLANE, p = e % PLANE;
     const int gx = ox + p % HX, gy = oy + (p / HX) % HY, gz = D == 3 ? oz + p / (HX * HY) : 0;
     double v = 0;
-    if (gx >= 0 && gx <= n && gy >= 0 && gy <= n && (D == 2 || (gz >= 0 && gz <= n))) {
-      const int64_t j = D == 2 ? gx + (int64_t)(n + 1) * gy : gx + (int64_t)(n + 1) * (gy + (int64_t)(n + 1) * gz);
-      v = r[f * N + j];
-    }
+    if (gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m)))
+      v = r[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))];
     rt[e] = v;
   }
   __syncthreads();
-  const int gx = bx * TX + tx, gy = by * TY + ty, gz = D == 3 ? bz * TZ + tz : 0;
-  const bool inside = gx <= n && gy <= n && (D == 2 || gz <= n);
-  const int64_t node = D == 2 ? gx + (int64_t)(n + 1) * gy : gx + (int64_t)(n + 1) * (gy + (int64_t)(n + 1) * gz);
+  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = D == 3 ? threadIdx.x / (TX * TY) : 0;
+  const int gx = t[0] * TX + tx, gy = t[1] * TY + ty, gz = D == 3 ? t[2] * TZ + tz : 0;
+  const bool inside = gx < m && gy < m && (D == 2 || gz < m);
+  const int64_t node = D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz);
   const int cls = inside ? node_class[node] : -1;
-  bool todo = cls >= 0;
-  double y[D + 1];
-  for (int f = 0; f <= D; ++f) y[f] = 0;
   const int base = tx + 2 + HX * (ty + 2 + (D == 3 ? HY * (tz + 2) : 0));
-  while (__ballot(todo) != 0) {
-    if (todo) {
-      const int c0 = __builtin_amdgcn_readfirstlane(cls);
-      if (cls == c0) {
-        const double* __restrict__ Z = Zcls + (int64_t)c0 * (D + 1) * ZSP;
+  double y[D + 1];
 #pragma unroll
-        for (int cmp = 0; cmp < D; ++cmp) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const int off = (v % 5 - 2) + HX * ((v / 5) % 5 - 2) + (D == 3 ? HX * HY * (v / 25 - 2) : 0);
-            const double gv = rt[cmp * PLANE + base + off];
-#pragma unroll
-            for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + cmp * NV + v] * gv;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          const int off = (q % 3 - 1) + HX * ((q / 3) % 3 - 1) + (D == 3 ? HX * HY * (q / 9 - 1) : 0);
-          const double gv = rt[D * PLANE + base + off];
-#pragma unroll
-          for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + D * NV + q] * gv;
-        }
-        todo = false;
-      }
-    }
-  }
+  for (int f = 0; f <= D; ++f) y[f] = 0;
+  regular_apply<D>(Zcls, cls, [&](int f, const int* o) {
+    return rt[f * PLANE + base + o[0] + HX * (o[1] + (D == 3 ? HY * o[2] : 0))];
+  }, y);
   if (cls >= 0)
+#pragma unroll
     for (int f = 0; f <= D; ++f) x[f * N + node] += omega * y[f];
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t N, int64_t nirr,
-                                                              const int* __restrict__ irr_nodes,
+__global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nirr, const int* __restrict__ irr_nodes,
                                                               const double* __restrict__ Zirr,
                                                               const double* __restrict__ r, double* __restrict__ x,
                                                               double omega) {
-  constexpr int NV = PT<D>::NV, ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
-  const int lane = threadIdx.x & 63;
-  for (int64_t p = blockIdx.x * 4 + (threadIdx.x >> 6); p < nirr; p += (int64_t)gridDim.x * 4) {
-    const int64_t node = irr_nodes[p];
-    int c[3];
-    node_coords<D>(node, n, c);
-    const double* __restrict__ Z = Zirr + p * (int64_t)(D + 1) * ZSP;
-    double acc[D + 1];
-    for (int f = 0; f <= D; ++f) acc[f] = 0;
-    for (int col = lane; col < ZS; col += 64) {
-      int field, o[3];
-      if (col < D * NV) {
-        field = col / NV;
-        const int v = col % NV;
-        o[0] = v % 5 - 2;
-        o[1] = (v / 5) % 5 - 2;
-        o[2] = D == 3 ? v / 25 - 2 : 0;
-      } else {
-        field = D;
-        const int q = col - D * NV;
-        o[0] = q % 3 - 1;
-        o[1] = (q / 3) % 3 - 1;
-        o[2] = D == 3 ? q / 9 - 1 : 0;
-      }
+  constexpr int ZSP = PT<D>::ZSP;
+  const int j16 = threadIdx.x & 15;
+  const int m = n + 1;
+  const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
+  const int64_t stride = (int64_t)gridDim.x * 32;
+  for (int64_t pa = blockIdx.x * 32 + (threadIdx.x >> 4); pa < nirr; pa += stride) {
+    const int64_t pb = pa + 16;
+    const bool has_b = pb < nirr;
+    const int na = irr_nodes[pa], nbn = has_b ? irr_nodes[pb] : na;
+    const int ca[3] = {na % m, (na / m) % m, D == 3 ? na / (m * m) : 0};
+    const int cb[3] = {nbn % m, (nbn / m) % m, D == 3 ? nbn / (m * m) : 0};
+    auto gather = [&](const int* c, int field, const int* o) {
       int cc[3] = {c[0] + o[0], c[1] + o[1], c[2] + o[2]};
       bool in = true;
-      for (int k = 0; k < D; ++k)
-        if (cc[k] < 0 || cc[k] > n) in = false;
-      const double gv = in ? r[field * N + node_index<D>(cc, n)] : 0.0;
-      for (int f = 0; f <= D; ++f) acc[f] += Z[f * ZSP + col] * gv;
-    }
-    for (int f = 0; f <= D; ++f) acc[f] = wave_sum(acc[f]);
-    if (lane <= D) {
-      double v = acc[0];
+      for (int k = 0; k < D; ++k) in = in && cc[k] >= 0 && cc[k] < m;
+      return in ? r[field * N + (D == 2 ? cc[0] + (int64_t)m * cc[1] : cc[0] + (int64_t)m * (cc[1] + (int64_t)m * cc[2]))]
+                : 0.0;
+    };
+    double acca[D + 1], accb[D + 1];
+    irregular_pair<D>(Zirr + pa * (int64_t)(D + 1) * ZSP, Zirr + (has_b ? pb : pa) * (int64_t)(D + 1) * ZSP, has_b,
+                      j16, [&](int f, const int* o) { return gather(ca, f, o); },
+                      [&](int f, const int* o) { return gather(cb, f, o); }, acca, accb);
+    if (j16 <= D) {
+      double va = acca[0], vb = accb[0];
+#pragma unroll
       for (int f = 1; f <= D; ++f)
-        if (lane == f) v = acc[f];
-      x[lane * N + node] += omega * v;
+        if (j16 == f) {
+          va = acca[f];
+          vb = accb[f];
+        }
+      x[j16 * N + na] += omega * va;
+      if (has_b) x[j16 * N + nbn] += omega * vb;
     }
   }
 }
 
+// Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes, one thread
+// per node. Large grids use 32 x 8 tiles (less halo work), small grids 16 x 4 (more workgroups in
+// flight); the arithmetic of every node is the same for both.
+template <int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 8))) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
+                                                           const int* __restrict__ cell_info,
+                                                           const double* __restrict__ cut, double alpha_f, int ntx,
+                                                           int nty, const int* __restrict__ node_class,
+                                                           const double* __restrict__ Zcls,
+                                                           const double* __restrict__ Zirr,
+                                                           const double* __restrict__ x_in,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ x_out, double omega) {
+  constexpr int NT = TX * TY;
+  constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
+  constexpr int RW = TX + 4, RH = TY + 4, RP = RW * RH;  // residual tile, halo 2
+  constexpr int ZSP = PT<2>::ZSP;
+  constexpr int CW = TX + 5, CH = TY + 5, CP = CW * CH;  // cells of the residual tile
+  constexpr int NRES = (RP + NT - 1) / NT;                // residual nodes per thread
+  __shared__ double xs[3 * XP];
+  __shared__ double rs[3 * RP];
+  __shared__ int cs[CP];
+  __shared__ int irr_tid[TX * TY], irr_pidx[TX * TY];
+  __shared__ int irr_cnt;
+  constexpr int MAXCUT = NT >= 256 ? 32 : 12;
+  __shared__ CutStage<2, MAXCUT, CP> cst;
+  __shared__ RefMats<2> rm;
+  if (threadIdx.x == 0) {
+    irr_cnt = 0;
+    cst.count = 0;
+  }
+  const int n = oc->n;
+  const int m = n + 1;
+  const int64_t N = (int64_t)m * m;
+  const int nt[3] = {ntx, nty, 1};
+  int t[3];
+  tile_coords<2>(blockIdx.x, nt, t);
+  const int bx = t[0] * TX, by = t[1] * TY;
+  // every global load that does not depend on another one is issued before the first LDS store:
+  // own patch class, b of the residual nodes, the x tile and the cell kinds of the tile
+  const int tx0 = threadIdx.x % TX, ty0 = threadIdx.x / TX;
+  const bool inside0 = bx + tx0 < m && by + ty0 < m;
+  const int cls = inside0 ? node_class[(bx + tx0) + (int64_t)m * (by + ty0)] : -1;
+  double bres[NRES][3];
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
+    const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) bres[k][f] = ok ? b[f * N + cx + (int64_t)m * cy] : 0.0;
+  }
+  constexpr int NXL = (3 * XP + NT - 1) / NT, NCL = (CP + NT - 1) / NT;
+  double xv[NXL];
+#pragma unroll
+  for (int k = 0; k < NXL; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int f = e / XP, p = e % XP;
+    const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
+    xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x_in[f * N + gx + (int64_t)m * gy] : 0.0;
+  }
+  int cv[NCL];
+#pragma unroll
+  for (int k = 0; k < NCL; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int gx = bx - 3 + e % CW, gy = by - 3 + e / CW;
+    cv[k] = (e < CP && gx >= 0 && gx < n && gy >= 0 && gy < n) ? cell_info[gx + n * gy] : -1;
+  }
+  stage_refmats<2>(oc, rm);
+#pragma unroll
+  for (int k = 0; k < NXL; ++k)
+    if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
+#pragma unroll
+  for (int k = 0; k < NCL; ++k)
+    if (threadIdx.x + NT * k < CP) cs[threadIdx.x + NT * k] = cv[k];
+  __syncthreads();
+  stage_cuts<2, MAXCUT, CP>(cst, cs, cut);
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) {
+    const int e = threadIdx.x + NT * k;
+    if (e >= RP) break;
+    const int px = e % RW, py = e / RW;
+    const int c[3] = {bx - 2 + px, by - 2 + py, 0};
+    double rv[3] = {0, 0, 0};
+    if (c[0] >= 0 && c[0] < m && c[1] >= 0 && c[1] < m) {
+      const int xb = (px + 1) + XW * (py + 1);
+      double acc[3] = {0, 0, 0};
+      node_apply<2>(
+          rm, [&](const int* cc) { return cs[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)]; },
+          [&](const int* cc, int info) -> const double* {
+            const int sl = cst.slot[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)];
+            return sl >= 0 ? cst.buf + sl * PT<2>::NEL : cut + (int64_t)info * PT<2>::NEL;
+          },
+          alpha_f, n, c, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; }, acc);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) rv[f] = bres[k][f] - acc[f];
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
+  }
+  __syncthreads();
+  const int tx = tx0, ty = ty0;
+  const bool inside = inside0;
+  const int64_t node = (bx + tx) + (int64_t)m * (by + ty);
+  const int rbase = (tx + 2) + RW * (ty + 2);
+  double y[3] = {0, 0, 0};
+  regular_apply<2>(Zcls, cls, [&](int f, const int* o) { return rs[f * RP + rbase + o[0] + RW * o[1]]; }, y);
+  if (cls >= 0) {
+    const int xb = (tx + 3) + XW * (ty + 3);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) x_out[f * N + node] = xs[f * XP + xb] + omega * y[f];
+  }
+  // irregular patches of the tile: collected in LDS, then 16 lane groups take them in turn
+  if (inside && cls < 0) {
+    const int k = atomicAdd(&irr_cnt, 1);
+    irr_tid[k] = threadIdx.x;
+    irr_pidx[k] = -cls - 1;
+  }
+  __syncthreads();
+  const int cnt = irr_cnt;
+  const int j16 = threadIdx.x & 15;
+  constexpr int NG = NT / 16;  // lane groups of the workgroup
+  for (int ea = threadIdx.x >> 4; ea < cnt; ea += 2 * NG) {
+    const int eb = ea + NG;
+    const bool has_b = eb < cnt;
+    const int ta = irr_tid[ea], tb = has_b ? irr_tid[eb] : ta;
+    const int rba = (ta % TX + 2) + RW * (ta / TX + 2), rbb = (tb % TX + 2) + RW * (tb / TX + 2);
+    double acca[3], accb[3];
+    irregular_pair<2>(Zirr + (int64_t)irr_pidx[ea] * 3 * ZSP, Zirr + (int64_t)irr_pidx[has_b ? eb : ea] * 3 * ZSP,
+                      has_b, j16, [&](int field, const int* o) { return rs[field * RP + rba + o[0] + RW * o[1]]; },
+                      [&](int field, const int* o) { return rs[field * RP + rbb + o[0] + RW * o[1]]; }, acca, accb);
+    if (j16 < 3) {
+      const double va = j16 == 0 ? acca[0] : (j16 == 1 ? acca[1] : acca[2]);
+      const double vb = j16 == 0 ? accb[0] : (j16 == 1 ? accb[1] : accb[2]);
+      x_out[j16 * N + (bx + ta % TX) + (int64_t)m * (by + ta / TX)] =
+          xs[j16 * XP + (ta % TX + 3) + XW * (ta / TX + 3)] + omega * va;
+      if (has_b)
+        x_out[j16 * N + (bx + tb % TX) + (int64_t)m * (by + tb / TX)] =
+            xs[j16 * XP + (tb % TX + 3) + XW * (tb / TX + 3)] + omega * vb;
+    }
+  }
+}
+
+// Levels with at least this many nodes use the 32 x 8 tile of the fused 2D sweep.
+constexpr int64_t kFusedBigTileNodes = 200000;
+
 template <int D>
-hipError_t k_apply_inverse(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
-  constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
-  if (L.n_classes > 0) {
-    const int64_t nt = (int64_t)((L.n + 1 + TX - 1) / TX) * ((L.n + 1 + TY - 1) / TY) *
-                       (D == 3 ? (L.n + 1 + TZ - 1) / TZ : 1);
-    apply_regular_kernel<D><<<dim3((unsigned)nt), dim3(256), 0, s>>>(L.n, L.N, L.node_class, L.Zcls, r, x,
-                                                                     c.prm.omega);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (L.n_irr > 0) {
-    int64_t nb = (L.n_irr + 3) / 4;
-    if (nb > 65536) nb = 65536;
-    apply_irregular_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.N, L.n_irr, L.irr_nodes, L.Zirr, r, x,
-                                                                       c.prm.omega);
-  }
+hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
+  if (L.n_classes == 0) return hipSuccess;
+  int nt[3];
+  tile_grid<D>(L.n, nt);
+  apply_regular_kernel<D><<<dim3((unsigned)(nt[0] * nt[1] * nt[2])), dim3(256), 0, s>>>(
+      L.n, nt[0], nt[1], nt[2], L.node_class, L.Zcls, r, x, c.prm.omega);
   return hipGetLastError();
+}
+
+template <int D>
+hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
+  if (L.n_irr == 0) return hipSuccess;
+  int64_t nb = (L.n_irr + 31) / 32;
+  if (nb > 65536) nb = 65536;
+  apply_irregular_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.n_irr, L.irr_nodes, L.Zirr, r, x,
+                                                                     c.prm.omega);
+  return hipGetLastError();
+}
+
+template <int TX, int TY>
+hipError_t launch_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                         hipStream_t s) {
+  const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
+  sweep_fused2_kernel<TX, TY><<<dim3((unsigned)(ntx * nty)), dim3(TX * TY), 0, s>>>(
+      L.consts, L.cell_info, L.cut_mats, c.prm.alpha_fict, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out,
+      c.prm.omega);
+  return hipGetLastError();
+}
+
+hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                          hipStream_t s) {
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8>(c, L, x_in, b, x_out, s);
+  return launch_fused2<16, 4>(c, L, x_in, b, x_out, s);
 }
 
 }  // namespace fcg

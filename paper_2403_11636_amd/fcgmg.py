@@ -24,7 +24,11 @@ EXPORTS = [
     "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
     "fcgmg_residual", "fcgmg_smooth", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
     "fcgmg_vcycle", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_destroy", "fcgmg_last_error",
+    "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
 ]
+
+KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
+                "zero", "sweep_fused", "tail"]
 
 
 class FcgmgError(RuntimeError):
@@ -80,6 +84,9 @@ def load(path: str = LIB_PATH):
     L.fcgmg_norm.argtypes = [vp, ctypes.c_int, vp, dp, vp]
     L.fcgmg_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.fcgmg_destroy.argtypes = [vp]
+    L.fcgmg_profile_enable.argtypes = [vp, ctypes.c_int]
+    L.fcgmg_profile_reset.argtypes = [vp]
+    L.fcgmg_profile_read.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, i64p]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int
     L.fcgmg_destroy.restype = None
@@ -192,6 +199,25 @@ class Hierarchy:
         s = LevelStats()
         _check(load().fcgmg_level_stats_get(self.h, level, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in LevelStats._fields_}
+
+    def profile(self, on: bool = True):
+        """Enable/disable the library's per-kernel event timers."""
+        _check(load().fcgmg_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(load().fcgmg_profile_reset(self.h))
+
+    def profile_read(self) -> dict:
+        """{(kind_name, level): (total_ms, launches)} for every kind/level with launches."""
+        out = {}
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        for k, name in enumerate(KERNEL_KINDS):
+            for lev in range(self.n_levels):
+                _check(load().fcgmg_profile_read(self.h, k, lev, ctypes.byref(ms), ctypes.byref(cnt)))
+                if cnt.value:
+                    out[(name, lev)] = (ms.value, cnt.value)
+        return out
 
     def device_bytes(self) -> int:
         v = ctypes.c_size_t()

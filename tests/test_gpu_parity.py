@@ -256,3 +256,38 @@ def test_config2_full_size_sampled():
 def test_config3_full_size_sampled():
     st = _sampled_sweep(inputs.config3(0), 0, 40)
     assert st["n_cut_cells"] > 1000
+
+
+@pytest.mark.parametrize("name", ["2d_16_l3_s0", "2d_40_l3_noslip", "c1_32_l3"])
+def test_fused_sweep_bitwise_equals_unfused(name):
+    # 2D cache_inverse: an even number of sweeps runs the fused kernel (ping-pong buffers), a single
+    # sweep runs residual + apply kernels in place; both perform the same arithmetic.
+    p, o, h = setup_case(name)
+    n = h.ndofs()
+    x = inputs.random_vector(n, 31)
+    b = inputs.random_vector(n, 32)
+    xf = dev(x)
+    h.smooth(xf, dev(b), 2)
+    xu = dev(x)
+    h.smooth(xu, dev(b), 1)
+    h.smooth(xu, dev(b), 1)
+    assert np.array_equal(host(xf), host(xu))
+    assert rel(host(xf), o.smooth(h.fine, x, b, 2, p.omega)) <= 1e-12
+
+
+def test_config2_fused_sweeps_sampled():
+    p = inputs.config2(0)
+    o = Oracle(p)
+    h = fcg().Hierarchy(p, 0)
+    n = h.ndofs()
+    N = o.nnodes(o.fine)
+    x = inputs.random_vector(n, 41)
+    b = inputs.random_vector(n, 42)
+    xg = dev(x)
+    h.smooth(xg, dev(b), 2)
+    x_gpu = host(xg)
+    x1 = o.smooth(o.fine, x, b, 1, p.omega)  # first sweep in full (cheap in 2D), second sampled
+    nodes = np.unique(np.r_[np.arange(0, N, 97), np.arange(N - 600, N)]).astype(np.int64)
+    ref = o.smooth_nodes(o.fine, x1, b, nodes, p.omega)
+    got = np.stack([x_gpu[f * N + nodes] for f in range(3)], axis=1)
+    assert rel(got, ref) <= 1e-12
