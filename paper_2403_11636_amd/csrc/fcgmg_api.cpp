@@ -140,6 +140,25 @@ void build_consts(const Ctx& c, Level& L) {
     for (int a = 0; a < NN; ++a)
       for (int b = 0; b < NN; ++b) oc.C[a * NN + b] = -(1.0 / eta) * (M[a * NN + b] - m[a] * m[b] / vol);
   }
+  // node stencils of uniform uncut neighbourhoods: sum of the element rows of the 2^d cells
+  for (int kind = 0; kind < 2; ++kind)
+    for (int sc = 0; sc < NN; ++sc) {
+      int a = 0;
+      for (int k = 0; k < D; ++k) a |= (1 - ((sc >> k) & 1)) << k;
+      for (int bn = 0; bn < NN; ++bn) {
+        int o = 0, mul = 1;
+        for (int k = 0; k < D; ++k) {
+          o += (((sc >> k) & 1) + ((bn >> k) & 1)) * mul;  // offset -1 + s + b shifted by +1
+          mul *= 3;
+        }
+        oc.SK[kind][o] += oc.K[kind][a * NN + bn];
+        for (int cc = 0; cc < D; ++cc) {
+          oc.SB[kind][cc][o] += oc.B[kind][cc][a * NN + bn];
+          oc.ST[kind][cc][o] += oc.B[kind][cc][bn * NN + a];
+        }
+        if (kind == 0) oc.SC[o] += oc.C[a * NN + bn];
+      }
+    }
   // Nitsche face terms: -(v, n.eta grad u) - (n.eta grad v, u) + (v, lambda u) per component and
   // (v, n p) + (n q, u) on each Dirichlet wall (2-point Gauss per tangential direction).
   for (int k = 0; k < D; ++k)

@@ -49,6 +49,13 @@ struct OpConsts {
   int dirichlet[6];
   int n;                // cells per axis
   double h, lam;
+  // Assembled node stencils of a node whose 2^d cells are uncut, of one kind and away from the
+  // walls, per kind, over the 3^d neighbour offsets: velocity-velocity (same component), velocity
+  // row c / pressure column, pressure row / velocity column c, pressure-pressure.
+  double SK[2][27];
+  double SB[2][3][27];
+  double ST[2][3][27];
+  double SC[27];
 };
 
 struct Geom {

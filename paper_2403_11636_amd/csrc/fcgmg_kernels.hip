@@ -259,48 +259,21 @@ __device__ __forceinline__ void tile_coords(int bid, const int* nt, int* t) {
   t[2] = lin / (nt[0] * nt[1]);
 }
 
-// Cut-cell integrals of a tile's cell region staged in LDS (up to MAXCUT cells; any further cut cell
-// of the region is read from global memory). The values, and so the arithmetic, are the same.
-template <int D, int MAXCUT, int NCELL>
-struct CutStage {
-  double buf[MAXCUT * PT<D>::NEL];
-  int slot[NCELL];
-  int cell[MAXCUT];
-  int count;
-};
-
-// cs: cell kinds of the region (LDS, already filled and synchronised). st.count must be 0.
-template <int D, int MAXCUT, int NCELL>
-__device__ __forceinline__ void stage_cuts(CutStage<D, MAXCUT, NCELL>& st, const int* cs,
-                                           const double* __restrict__ cut) {
-  constexpr int NEL = PT<D>::NEL;
-  for (int e = threadIdx.x; e < NCELL; e += blockDim.x) {
-    const int v = cs[e];
-    int sl = -1;
-    if (v >= 0) {
-      const int k = atomicAdd(&st.count, 1);
-      if (k < MAXCUT) {
-        sl = k;
-        st.cell[k] = v;
-      }
-    }
-    st.slot[e] = sl;
-  }
-  __syncthreads();
-  const int nc = st.count < MAXCUT ? st.count : MAXCUT;
-  for (int i = threadIdx.x; i < nc * NEL; i += blockDim.x) st.buf[i] = cut[(int64_t)st.cell[i / NEL] * NEL + i % NEL];
-  __syncthreads();
-}
-
 // Reference element matrices of a level (uncut physical cell; fictitious cells scale K and B by
 // alpha_f), the stabilisation block and the Nitsche face matrices, packed for one dimension. The
 // kernels copy them into LDS once per workgroup: the node loops then read only LDS.
 template <int D>
 struct RefMats {
   static constexpr int NN2 = (1 << D) * (1 << D);
+  static constexpr int NS = D == 2 ? 9 : 27;  // stencil offsets
   static constexpr int oK = 0, oB = NN2, oC = NN2 * (1 + D), oFK = NN2 * (2 + D), oFB = NN2 * (2 + 3 * D);
-  static constexpr int TOT = NN2 * (2 + 5 * D);
-  double v[TOT];  // K | B_0..B_{D-1} | C | FK_0..FK_{2D-1} | FB_0..FB_{2D-1}
+  static constexpr int oSK = NN2 * (2 + 5 * D);        // [kind][NS]
+  static constexpr int oSB = oSK + 2 * NS;             // [kind][D][NS]
+  static constexpr int oST = oSB + 2 * D * NS;         // [kind][D][NS]
+  static constexpr int oSC = oST + 2 * D * NS;         // [NS]
+  static constexpr int TOT = oSC + NS;
+  // K | B_0..B_{D-1} | C | FK_0..FK_{2D-1} | FB_0..FB_{2D-1} | node stencils
+  double v[TOT];
   int dir[2 * D];
 };
 
@@ -319,8 +292,16 @@ __device__ __forceinline__ void stage_refmats(const OpConsts* __restrict__ oc, R
       v = oc->C[i - R::oC];
     else if (i < R::oFB)
       v = oc->FK[(i - R::oFK) / NN2][(i - R::oFK) % NN2];
-    else
+    else if (i < R::oSK)
       v = oc->FB[(i - R::oFB) / NN2][(i - R::oFB) % NN2];
+    else if (i < R::oSB)
+      v = oc->SK[(i - R::oSK) / R::NS][(i - R::oSK) % R::NS];
+    else if (i < R::oST)
+      v = oc->SB[(i - R::oSB) / (D * R::NS)][((i - R::oSB) / R::NS) % D][(i - R::oSB) % R::NS];
+    else if (i < R::oSC)
+      v = oc->ST[(i - R::oST) / (D * R::NS)][((i - R::oST) / R::NS) % D][(i - R::oST) % R::NS];
+    else
+      v = oc->SC[i - R::oSC];
     rm.v[i] = v;
   }
   if (threadIdx.x < 2 * D) rm.dir[threadIdx.x] = oc->dirichlet[threadIdx.x];
@@ -334,6 +315,41 @@ template <int D, bool UNR = true, class CI, class CP, class XA>
 __device__ __forceinline__ void node_apply(const RefMats<D>& rm, CI&& ci, CP&& cutp, double alpha_f, int n,
                                            const int* c, XA&& xat, double* acc) {
   constexpr int NN = 1 << D, NN2 = NN * NN;
+  using R = RefMats<D>;
+  // Uniform neighbourhood (2^d uncut cells of one kind, no wall face among them): the assembled
+  // node stencil of that kind. Otherwise the element rows of the cells one by one.
+  bool uni = true;
+#pragma unroll
+  for (int k = 0; k < D; ++k) uni = uni && c[k] >= 2 && c[k] <= n - 2;
+  int kind0 = 0;
+  if (uni) {
+    int cc0[3] = {c[0] - 1, c[1] - 1, D == 3 ? c[2] - 1 : 0};
+    const int i0 = ci(cc0);
+#pragma unroll
+    for (int sc = 1; sc < NN; ++sc) {
+      int cs2[3] = {c[0] - 1 + (sc & 1), c[1] - 1 + ((sc >> 1) & 1), D == 3 ? c[2] - 1 + ((sc >> 2) & 1) : 0};
+      uni = uni && ci(cs2) == i0;
+    }
+    uni = uni && i0 < 0;
+    kind0 = i0 == -1 ? 0 : 1;
+  }
+  if (uni) {
+#pragma unroll(UNR ? R::NS : 3)
+    for (int o = 0; o < R::NS; ++o) {
+      const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, D == 3 ? o / 9 - 1 : 0};
+      double u[D + 1];
+#pragma unroll
+      for (int f = 0; f <= D; ++f) u[f] = xat(f, oo);
+      const double sk = rm.v[R::oSK + kind0 * R::NS + o];
+#pragma unroll
+      for (int f = 0; f < D; ++f) {
+        acc[f] += sk * u[f] + rm.v[R::oSB + (kind0 * D + f) * R::NS + o] * u[D];
+        acc[D] += rm.v[R::oST + (kind0 * D + f) * R::NS + o] * u[f];
+      }
+      acc[D] += rm.v[R::oSC + o] * u[D];
+    }
+    return;
+  }
 #pragma unroll(UNR ? NN : 1)
   for (int sc = 0; sc < NN; ++sc) {
     int cc[3] = {0, 0, 0};
@@ -415,13 +431,10 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
   constexpr int CW = TX + 1, CH = TY + 1, CD = D == 3 ? TZ + 1 : 1, CP = CW * CH * CD;
-  constexpr int MAXCUT = D == 2 ? 32 : 1;
   constexpr int NXL = ((D + 1) * XP + 255) / 256, NCL = (CP + 255) / 256;
   __shared__ double xs[(D + 1) * XP];
   __shared__ int cs[CP];
-  __shared__ CutStage<D, MAXCUT, CP> cst;
   __shared__ RefMats<D> rm;
-  if (threadIdx.x == 0) cst.count = 0;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
@@ -462,7 +475,6 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   for (int k = 0; k < NCL; ++k)
     if (threadIdx.x + 256 * k < CP) cs[threadIdx.x + 256 * k] = cv[k];
   __syncthreads();
-  if (D == 2) stage_cuts<D, MAXCUT, CP>(cst, cs, cut);
   if (!inside) return;
   const int base = (tx + 1) + XW * ((ty + 1) + XH * (tz + 1) * (D == 3 ? 1 : 0));
   double acc[D + 1];
@@ -472,13 +484,7 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
                 [&](const int* cc) {
                   return cs[(cc[0] - o0) + CW * ((cc[1] - o1) + (D == 3 ? CH * (cc[2] - o2) : 0))];
                 },
-                [&](const int* cc, int info) -> const double* {
-                  if (D == 2) {
-                    const int sl = cst.slot[(cc[0] - o0) + CW * (cc[1] - o1)];
-                    if (sl >= 0) return cst.buf + sl * PT<D>::NEL;
-                  }
-                  return cut + (int64_t)info * PT<D>::NEL;
-                },
+                [&](const int*, int info) -> const double* { return cut + (int64_t)info * PT<D>::NEL; },
                 alpha_f, n, c,
                 [&](int f, const int* o) {
                   return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];

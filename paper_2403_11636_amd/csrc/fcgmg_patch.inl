@@ -830,7 +830,7 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
 // per node. Large grids use 32 x 8 tiles (less halo work), small grids 16 x 4 (more workgroups in
 // flight); the arithmetic of every node is the same for both.
 template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2, 8))) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
+__global__ void __launch_bounds__(TX * TY) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
                                                            const int* __restrict__ cell_info,
                                                            const double* __restrict__ cut, double alpha_f, int ntx,
                                                            int nty, const int* __restrict__ node_class,
@@ -850,13 +850,8 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2,
   __shared__ int cs[CP];
   __shared__ int irr_tid[TX * TY], irr_pidx[TX * TY];
   __shared__ int irr_cnt;
-  constexpr int MAXCUT = NT >= 256 ? 32 : 12;
-  __shared__ CutStage<2, MAXCUT, CP> cst;
   __shared__ RefMats<2> rm;
-  if (threadIdx.x == 0) {
-    irr_cnt = 0;
-    cst.count = 0;
-  }
+  if (threadIdx.x == 0) irr_cnt = 0;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -864,20 +859,11 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2,
   int t[3];
   tile_coords<2>(blockIdx.x, nt, t);
   const int bx = t[0] * TX, by = t[1] * TY;
-  // every global load that does not depend on another one is issued before the first LDS store:
-  // own patch class, b of the residual nodes, the x tile and the cell kinds of the tile
+  // the global loads of the own patch class, the x tile and the cell kinds of the tile are issued
+  // before the first LDS store; b of a residual node is read next to its residual
   const int tx0 = threadIdx.x % TX, ty0 = threadIdx.x / TX;
   const bool inside0 = bx + tx0 < m && by + ty0 < m;
   const int cls = inside0 ? node_class[(bx + tx0) + (int64_t)m * (by + ty0)] : -1;
-  double bres[NRES][3];
-#pragma unroll
-  for (int k = 0; k < NRES; ++k) {
-    const int e = threadIdx.x + NT * k;
-    const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
-    const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) bres[k][f] = ok ? b[f * N + cx + (int64_t)m * cy] : 0.0;
-  }
   constexpr int NXL = (3 * XP + NT - 1) / NT, NCL = (CP + NT - 1) / NT;
   double xv[NXL];
 #pragma unroll
@@ -902,8 +888,7 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2,
   for (int k = 0; k < NCL; ++k)
     if (threadIdx.x + NT * k < CP) cs[threadIdx.x + NT * k] = cv[k];
   __syncthreads();
-  stage_cuts<2, MAXCUT, CP>(cst, cs, cut);
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
     if (e >= RP) break;
@@ -911,17 +896,23 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2,
     const int c[3] = {bx - 2 + px, by - 2 + py, 0};
     double rv[3] = {0, 0, 0};
     if (c[0] >= 0 && c[0] < m && c[1] >= 0 && c[1] < m) {
+      const int64_t g = c[0] + (int64_t)m * c[1];
+      double bres[3];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) bres[f] = b[f * N + g];
       const int xb = (px + 1) + XW * (py + 1);
       double acc[3] = {0, 0, 0};
+      // an offset the compiler cannot see through: keeps it from hoisting the level constants
+      // out of this loop into registers (they are read from LDS where they are used)
+      int ro = 0;
+      asm volatile("" : "+s"(ro));
+      const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
       node_apply<2>(
-          rm, [&](const int* cc) { return cs[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)]; },
-          [&](const int* cc, int info) -> const double* {
-            const int sl = cst.slot[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)];
-            return sl >= 0 ? cst.buf + sl * PT<2>::NEL : cut + (int64_t)info * PT<2>::NEL;
-          },
+          rmk, [&](const int* cc) { return cs[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)]; },
+          [&](const int*, int info) -> const double* { return cut + (int64_t)info * PT<2>::NEL; },
           alpha_f, n, c, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; }, acc);
 #pragma unroll
-      for (int f = 0; f < 3; ++f) rv[f] = bres[k][f] - acc[f];
+      for (int f = 0; f < 3; ++f) rv[f] = bres[f] - acc[f];
     }
 #pragma unroll
     for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
