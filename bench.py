@@ -16,11 +16,14 @@ GMG solve time to a 1e-8 relative residual with p50/p99 latencies, the dominant 
 HBM roofline, and the FP64 CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
-Prints one JSON line on stdout; progress goes to stderr.
+Prints one JSON line on stdout; progress goes to stderr. Two helper modes for hardware counter runs
+print a short JSON line instead: --cycles-only (the V-cycles alone) and --copy-calibration MIB (a plain
+device copy of known size, the reference for scaling FETCH_SIZE / WRITE_SIZE to bytes).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -148,10 +151,35 @@ def dominant_kernel(torch, h, x, b, steps, d):
                            "share": round(v[0] / total_all, 4)} for (k, l), v in sorted(prof.items())}
     return {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"{kind}@L{lev}"),
         "kernel": f"{kind}@L{lev}", "avg_launch_us": round(avg_ms * 1e3, 3),
         "algorithmic_bytes_per_launch": int(nbytes), "time_share": round(tot / total_all, 4),
     }, table
+
+
+def kernel_sources_sha256() -> str:
+    """Hash over the HIP/C++ sources of the library: counter figures taken on other sources are stale."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_11636_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    (profiles/hbm_traffic.json, scaled by a plain-copy calibration), or None when no figure exists
+    for it or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != kernel_sources_sha256():
+        return None
+    return int(rec["traffic_bytes"])
 
 
 def cpu_baseline(prob, steps=2):
@@ -229,6 +257,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the policy / 3D / 4096^2 side measurements")
+    ap.add_argument("--cycles-only", action="store_true",
+                    help="run warmup + steps V-cycles of the default workload and nothing else (for counter runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run only a plain device-to-device copy of MIB MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU (sharded) path is not part of this build; "
@@ -240,6 +272,15 @@ def main():
     from paper_2403_11636_amd import fcgmg, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "repeats": 5}), flush=True)
+        return
     prob = inputs.config2(0)
     d = prob.dim
     log(f"setup {prob.name} (cache_inverse) ...")
@@ -252,6 +293,13 @@ def main():
     for _ in range(args.warmup):
         h.vcycle(x, b)
     torch.cuda.synchronize()
+    if args.cycles_only:
+        for _ in range(args.steps):
+            h.vcycle(x, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": prob.name, "vcycles": args.warmup + args.steps, "n_dof": nd}), flush=True)
+        h.close()
+        return
     log(f"timing {args.steps} V-cycles ...")
     ms_step, wall = time_vcycles(torch, h, x, b, args.steps)
     sweeps_per_step = prob.nu_pre + prob.nu_post
