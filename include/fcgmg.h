@@ -152,8 +152,7 @@ enum {
   FCGMG_K_COARSE = 6,        /* coarsest-grid solve                                              */
   FCGMG_K_ZERO = 7,
   FCGMG_K_SWEEP_FUSED = 8,   /* cache_inverse, 2D: residual + all patch corrections in one kernel */
-  FCGMG_K_TAIL = 9,          /* cache_inverse: the small coarse levels of a V-cycle in one kernel */
-  FCGMG_K_COUNT = 10
+  FCGMG_K_COUNT = 9
 };
 
 /* Event profiler (tracing): while enabled, every kernel launch of the handle is bracketed by a

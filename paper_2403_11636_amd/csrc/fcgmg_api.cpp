@@ -190,6 +190,63 @@ void build_consts(const Ctx& c, Level& L) {
           }
       }
     }
+  using R = RefLayout<D>;
+  for (int i = 0; i < R::NN2; ++i) {
+    oc.pack[R::oK + i] = oc.K[0][i];
+    for (int cc = 0; cc < D; ++cc) oc.pack[R::oB + cc * R::NN2 + i] = oc.B[0][cc][i];
+    oc.pack[R::oC + i] = oc.C[i];
+    for (int f = 0; f < 2 * D; ++f) {
+      oc.pack[R::oFK + f * R::NN2 + i] = oc.FK[f][i];
+      oc.pack[R::oFB + f * R::NN2 + i] = oc.FB[f][i];
+    }
+  }
+  for (int o = 0; o < R::NS; ++o) {
+    for (int kind = 0; kind < 2; ++kind) {
+      oc.pack[R::oSK + kind * R::NS + o] = oc.SK[kind][o];
+      for (int cc = 0; cc < D; ++cc) {
+        oc.pack[R::oSB + (kind * D + cc) * R::NS + o] = oc.SB[kind][cc][o];
+        oc.pack[R::oST + (kind * D + cc) * R::NS + o] = oc.ST[kind][cc][o];
+      }
+    }
+    oc.pack[R::oSC + o] = oc.SC[o];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Operator code of every node (Level::node_op): a node at least 2 nodes from every wall whose 2^d
+// cells are uncut and of one kind uses that kind's reference stencil (-1 physical, -2 fictitious);
+// every other node gets a stored stencil, listed in `sten_nodes`.
+// ---------------------------------------------------------------------------------------------
+template <int D>
+void node_operator_codes(const Level& L, const std::vector<signed char>& kinds, std::vector<int>& op,
+                         std::vector<int>& sten_nodes) {
+  const int n = L.n;
+  const int64_t m = n + 1;
+  sten_nodes.clear();
+  for (int64_t node = 0; node < L.N; ++node) {
+    const int c[3] = {(int)(node % m), (int)((node / m) % m), D == 3 ? (int)(node / (m * m)) : 0};
+    bool uni = true;
+    for (int k = 0; k < D; ++k) uni = uni && c[k] >= 2 && c[k] <= n - 2;
+    int kind0 = -1;
+    if (uni) {
+      for (int sc = 0; sc < (1 << D) && uni; ++sc) {
+        int64_t cell = 0, mul = 1;
+        for (int k = 0; k < D; ++k) {
+          cell += (c[k] - 1 + ((sc >> k) & 1)) * mul;
+          mul *= n;
+        }
+        const int kd = kinds[cell];
+        if (sc == 0) kind0 = kd;
+        uni = kd != 2 && kd == kind0;
+      }
+    }
+    if (uni) {
+      op[node] = -1 - kind0;
+    } else {
+      op[node] = (int)sten_nodes.size();
+      sten_nodes.push_back((int)node);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -303,9 +360,6 @@ bool dense_inverse(int n, std::vector<double>& A, std::vector<double>& Inv) {
 }
 
 constexpr int kCoarseMaxDofs = 6000;
-// LDS budget of the single-workgroup coarse V-cycle; 0 switches it off (it is not yet faster than
-// the per-level kernels on the measured workloads).
-constexpr size_t kTailLdsBytes = 0;
 constexpr int kRedBlocks = 512;
 
 template <int D>
@@ -381,6 +435,21 @@ int setup_impl(Ctx& c, hipStream_t s) {
     build_consts<D>(c, L);
     if ((rc = alloc_n(c, &L.consts, 1))) return rc;
     FCG_HIP(hipMemcpyAsync(L.consts, &L.consts_h, sizeof(OpConsts), hipMemcpyHostToDevice, s));
+    // operator rows: the reference stencil of a uniform neighbourhood, else an assembled one
+    std::vector<int> op(L.N), sten_nodes;
+    node_operator_codes<D>(L, kinds, op, sten_nodes);
+    L.n_nsten = (int64_t)sten_nodes.size();
+    if ((rc = alloc_n(c, &L.node_op, L.N))) return rc;
+    FCG_HIP(hipMemcpyAsync(L.node_op, op.data(), L.N * sizeof(int), hipMemcpyHostToDevice, s));
+    if (L.n_nsten) {
+      if ((rc = alloc_n(c, &L.nsten, (size_t)L.n_nsten * PT<D>::NSTEN))) return rc;
+      int* sn_d = nullptr;
+      FCG_HIP(hipMallocAsync((void**)&sn_d, L.n_nsten * sizeof(int), s));
+      FCG_HIP(hipMemcpyAsync(sn_d, sten_nodes.data(), L.n_nsten * sizeof(int), hipMemcpyHostToDevice, s));
+      FCG_HIP(k_node_stencils<D>(c, L, sn_d, s));
+      FCG_HIP(hipFreeAsync(sn_d, s));
+    }
+    FCG_HIP(hipStreamSynchronize(s));  // op and sten_nodes must outlive the copies
     // patches
     std::vector<int> ncls, reps, irr;
     classify_patches<D>(L, kinds, ncls, reps, irr);
@@ -432,33 +501,6 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if (errv != INT_MAX)
       return fail(FCGMG_E_SINGULAR, "singular local block L_i of patch node " + std::to_string(errv) + " on level " +
                                         std::to_string(l));
-  }
-  // Small coarse levels run as one single-workgroup kernel per V-cycle (cache_inverse only): the
-  // deepest levels below the finest whose x, b and r fit in the LDS of one workgroup.
-  if (P.cache_policy == FCGMG_CACHE_INVERSE) {
-    int top = -1;
-    size_t bytes = 0;
-    for (int l = 0; l < nlev - 1; ++l) {
-      const size_t lb = 3 * sizeof(double) * (D + 1) * (size_t)c.lev[l].N;
-      if (bytes + lb > kTailLdsBytes) break;
-      bytes += lb;
-      top = l;
-    }
-    if (D == 2 && top >= 1 && top < 6) {
-      std::vector<TailLevel> tl(top + 1);
-      int off = 0;
-      for (int l = 0; l <= top; ++l) {
-        const Level& L = c.lev[l];
-        tl[l] = TailLevel{L.consts, L.cell_info, L.cut_mats, L.node_class, L.Zcls, L.Zirr, L.irr_nodes, L.n_irr,
-                          L.x, L.b, L.r, L.n, off};
-        off += 3 * (D + 1) * (int)L.N;
-      }
-      if ((rc = alloc_n(c, &c.tail, tl.size()))) return rc;
-      FCG_HIP(hipMemcpyAsync(c.tail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
-      FCG_HIP(hipStreamSynchronize(s));
-      c.tail_top = top;
-      c.tail_lds_bytes = (size_t)off * sizeof(double);
-    }
   }
   // coarsest level: dense operator, bordered when the constant pressure lies in the kernel
   {
@@ -566,7 +608,6 @@ int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t 
 
 template <int D>
 int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
-  if (l == c.tail_top) return launch(c, FCGMG_K_TAIL, l, s, [&] { return k_tail_vcycle<D>(c, s); });
   if (l == 0) return coarse_impl(c, b, x, s);
   int rc;
   if ((rc = smooth_impl<D>(c, l, x, b, c.prm.nu_pre, s))) return rc;

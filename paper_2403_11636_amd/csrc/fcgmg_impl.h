@@ -37,6 +37,26 @@ struct PT {
   static constexpr int NEL = (D + 1) * NN * NN;       // stored entries of one cut cell (K, B_c)
   static constexpr int THREADS = D == 2 ? 64 : 256;   // block size of the patch kernels
   static constexpr int NST = D == 2 ? 9 : 27;         // node stencil offsets (3^d)
+  static constexpr int NSTEN = (2 * D + 2) * NST;     // stored stencil of one node (see node_op)
+};
+
+// Layout of the level constants as the residual kernels stage them into LDS: the reference
+// matrices of a physical uncut cell (a fictitious uncut cell is alpha_f times them), C, the Nitsche
+// face matrices of the 2d faces and the node stencils of uniform neighbourhoods.
+template <int D>
+struct RefLayout {
+  static constexpr int NN2 = (1 << D) * (1 << D);
+  static constexpr int NS = D == 2 ? 9 : 27;             // stencil offsets
+  static constexpr int oK = 0;                           // K            [NN2]
+  static constexpr int oB = NN2;                         // B_c          [D][NN2]
+  static constexpr int oC = NN2 * (1 + D);               // C            [NN2]
+  static constexpr int oFK = NN2 * (2 + D);              // FK_face      [2D][NN2]
+  static constexpr int oFB = NN2 * (2 + 3 * D);          // FB_face      [2D][NN2]
+  static constexpr int oSK = NN2 * (2 + 5 * D);          // SK           [kind][NS]
+  static constexpr int oSB = oSK + 2 * NS;               // SB           [kind][D][NS]
+  static constexpr int oST = oSB + 2 * D * NS;           // ST           [kind][D][NS]
+  static constexpr int oSC = oST + 2 * D * NS;           // SC           [NS]
+  static constexpr int TOT = oSC + NS;
 };
 
 // Per-level operator constants (device resident, read through uniform loads).
@@ -56,6 +76,7 @@ struct OpConsts {
   double SB[2][3][27];
   double ST[2][3][27];
   double SC[27];
+  double pack[RefLayout<3>::TOT];  // the entries above in RefLayout<d> order
 };
 
 struct Geom {
@@ -73,6 +94,14 @@ struct Level {
   double* cut_mats = nullptr; // n_cut x NEL: K (NN x NN) then B_c (NN x NN) for c < d
   int64_t n_cut = 0, n_fict = 0;
   int* node_class = nullptr;  // >=0 regular class id, <0: -(irregular index)-1
+  // Operator row of each node: -1 / -2 when its 2^d cells are uncut, all physical / all fictitious
+  // and it is at least 2 nodes from every wall (the level's reference stencil applies), otherwise
+  // the index of its assembled stencil in nsten: NSTEN doubles [j][o] over the 3^d neighbour
+  // offsets o, j = 0 velocity-velocity (every component), 1..d velocity c / pressure, d+1..2d
+  // pressure / velocity c, 2d+1 pressure-pressure.
+  int* node_op = nullptr;
+  double* nsten = nullptr;
+  int64_t n_nsten = 0;
   int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
   int* irr_nodes = nullptr;   // centre node of each irregular patch
   int* class_rep = nullptr;   // representative node of each class
@@ -89,28 +118,8 @@ struct Level {
   size_t cached_bytes = 0;
 };
 
-// Per-level data the single-workgroup V-cycle kernel reads (device resident).
-struct TailLevel {
-  const OpConsts* oc;
-  const int* cell_info;
-  const double* cut;
-  const int* node_class;
-  const double* Zcls;
-  const double* Zirr;
-  const int* irr_nodes;
-  int64_t n_irr;
-  double* x;
-  double* b;
-  double* r;
-  int n;
-  int lds;  // offset of this level's x, b, r in the tail kernel's LDS (doubles)
-};
-
 struct Ctx {
   fcgmg_params prm{};
-  int tail_top = -1;             // levels 0..tail_top run inside one single-workgroup kernel
-  TailLevel* tail = nullptr;     // device copy of the per-level table
-  size_t tail_lds_bytes = 0;
   std::vector<double> balls_h;
   double* balls = nullptr;
   std::vector<Level> lev;
@@ -295,6 +304,7 @@ __host__ __device__ inline void wall_data(int code, double ubar, int k, int s, c
 // ------------------------------------------------------------------------------------------------
 template <int D> hipError_t k_classify_cells(const Ctx& c, Level& L, signed char* kinds, hipStream_t s);
 template <int D> hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStream_t s);
+template <int D> hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipStream_t s);
 template <int D> hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s);
 template <int D> hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const double* b, double* r,
                                        hipStream_t s);
@@ -303,7 +313,6 @@ template <int D> hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, c
 template <int D> hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s);
 template <int D> hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x,
                                              hipStream_t s);
-template <int D> hipError_t k_tail_vcycle(const Ctx& c, hipStream_t s);
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                           hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,

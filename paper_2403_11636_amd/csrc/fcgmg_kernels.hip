@@ -263,93 +263,40 @@ __device__ __forceinline__ void tile_coords(int bid, const int* nt, int* t) {
 // alpha_f), the stabilisation block and the Nitsche face matrices, packed for one dimension. The
 // kernels copy them into LDS once per workgroup: the node loops then read only LDS.
 template <int D>
-struct RefMats {
-  static constexpr int NN2 = (1 << D) * (1 << D);
-  static constexpr int NS = D == 2 ? 9 : 27;  // stencil offsets
-  static constexpr int oK = 0, oB = NN2, oC = NN2 * (1 + D), oFK = NN2 * (2 + D), oFB = NN2 * (2 + 3 * D);
-  static constexpr int oSK = NN2 * (2 + 5 * D);        // [kind][NS]
-  static constexpr int oSB = oSK + 2 * NS;             // [kind][D][NS]
-  static constexpr int oST = oSB + 2 * D * NS;         // [kind][D][NS]
-  static constexpr int oSC = oST + 2 * D * NS;         // [NS]
-  static constexpr int TOT = oSC + NS;
-  // K | B_0..B_{D-1} | C | FK_0..FK_{2D-1} | FB_0..FB_{2D-1} | node stencils
-  double v[TOT];
+struct RefMats : RefLayout<D> {
+  double v[RefLayout<D>::TOT];
   int dir[2 * D];
 };
 
-// Cooperative copy of the level constants into LDS (caller synchronises afterwards).
-template <int D>
+// Cooperative copy of the level constants into LDS by a workgroup of NT threads: every load is
+// issued before the first store (caller synchronises afterwards).
+template <int D, int NT>
 __device__ __forceinline__ void stage_refmats(const OpConsts* __restrict__ oc, RefMats<D>& rm) {
-  using R = RefMats<D>;
-  constexpr int NN2 = R::NN2;
-  for (int i = threadIdx.x; i < R::TOT; i += blockDim.x) {
-    double v;
-    if (i < R::oB)
-      v = oc->K[0][i];
-    else if (i < R::oC)
-      v = oc->B[0][(i - R::oB) / NN2][(i - R::oB) % NN2];
-    else if (i < R::oFK)
-      v = oc->C[i - R::oC];
-    else if (i < R::oFB)
-      v = oc->FK[(i - R::oFK) / NN2][(i - R::oFK) % NN2];
-    else if (i < R::oSK)
-      v = oc->FB[(i - R::oFB) / NN2][(i - R::oFB) % NN2];
-    else if (i < R::oSB)
-      v = oc->SK[(i - R::oSK) / R::NS][(i - R::oSK) % R::NS];
-    else if (i < R::oST)
-      v = oc->SB[(i - R::oSB) / (D * R::NS)][((i - R::oSB) / R::NS) % D][(i - R::oSB) % R::NS];
-    else if (i < R::oSC)
-      v = oc->ST[(i - R::oST) / (D * R::NS)][((i - R::oST) / R::NS) % D][(i - R::oST) % R::NS];
-    else
-      v = oc->SC[i - R::oSC];
-    rm.v[i] = v;
+  constexpr int TOT = RefLayout<D>::TOT, NK = (TOT + NT - 1) / NT;
+  double v[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + NT * k;
+    v[k] = i < TOT ? oc->pack[i] : 0.0;
   }
-  if (threadIdx.x < 2 * D) rm.dir[threadIdx.x] = oc->dirichlet[threadIdx.x];
+  const int dv = threadIdx.x < 2 * D ? oc->dirichlet[threadIdx.x] : 0;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int i = threadIdx.x + NT * k;
+    if (i < TOT) rm.v[i] = v[k];
+  }
+  if (threadIdx.x < 2 * D) rm.dir[threadIdx.x] = dv;
 }
 
-// Accumulate L x at node c (coords) into acc[0..D]; xat(f, o) returns x_f at c + o (o in {-1,0,1}^D),
-// ci(cc) the kind/cut index of the in-grid cell with lower corner cc, cutp(cc, info) the address of a
-// cut cell's integrals.
+// Accumulate L x at node c (coords) into acc[0..D] cell by cell from the element matrices (Eq. 9-11):
+// xat(f, o) returns x_f at c + o (o in {-1,0,1}^D), ci(cc) the kind/cut index of the in-grid cell
+// with lower corner cc, cutp(cc, info) the address of a cut cell's integrals. The residual kernels
+// apply the node stencils this assembles (node_stencil_kernel); set-up code applies it directly.
 // UNR = false keeps the loop over the cells rolled (same order of operations, fewer registers).
 template <int D, bool UNR = true, class CI, class CP, class XA>
 __device__ __forceinline__ void node_apply(const RefMats<D>& rm, CI&& ci, CP&& cutp, double alpha_f, int n,
                                            const int* c, XA&& xat, double* acc) {
   constexpr int NN = 1 << D, NN2 = NN * NN;
-  using R = RefMats<D>;
-  // Uniform neighbourhood (2^d uncut cells of one kind, no wall face among them): the assembled
-  // node stencil of that kind. Otherwise the element rows of the cells one by one.
-  bool uni = true;
-#pragma unroll
-  for (int k = 0; k < D; ++k) uni = uni && c[k] >= 2 && c[k] <= n - 2;
-  int kind0 = 0;
-  if (uni) {
-    int cc0[3] = {c[0] - 1, c[1] - 1, D == 3 ? c[2] - 1 : 0};
-    const int i0 = ci(cc0);
-#pragma unroll
-    for (int sc = 1; sc < NN; ++sc) {
-      int cs2[3] = {c[0] - 1 + (sc & 1), c[1] - 1 + ((sc >> 1) & 1), D == 3 ? c[2] - 1 + ((sc >> 2) & 1) : 0};
-      uni = uni && ci(cs2) == i0;
-    }
-    uni = uni && i0 < 0;
-    kind0 = i0 == -1 ? 0 : 1;
-  }
-  if (uni) {
-#pragma unroll(UNR ? R::NS : 3)
-    for (int o = 0; o < R::NS; ++o) {
-      const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, D == 3 ? o / 9 - 1 : 0};
-      double u[D + 1];
-#pragma unroll
-      for (int f = 0; f <= D; ++f) u[f] = xat(f, oo);
-      const double sk = rm.v[R::oSK + kind0 * R::NS + o];
-#pragma unroll
-      for (int f = 0; f < D; ++f) {
-        acc[f] += sk * u[f] + rm.v[R::oSB + (kind0 * D + f) * R::NS + o] * u[D];
-        acc[D] += rm.v[R::oST + (kind0 * D + f) * R::NS + o] * u[f];
-      }
-      acc[D] += rm.v[R::oSC + o] * u[D];
-    }
-    return;
-  }
 #pragma unroll(UNR ? NN : 1)
   for (int sc = 0; sc < NN; ++sc) {
     int cc[3] = {0, 0, 0};
@@ -422,18 +369,115 @@ __device__ __forceinline__ void node_apply(const RefMats<D>& rm, CI&& ci, CP&& c
   }
 }
 
+// acc[f] += sum over the 3^d offsets o of the node stencil applied to x around the node; cf(j, o) is
+// the coefficient of block j (layout of Level::nsten), xat(f, o) the value x_f at the node + o.
+template <int D, bool UNR, class CF, class XA>
+__device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, double* acc) {
+  constexpr int NS = PT<D>::NST;
+#pragma unroll(UNR ? NS : 3)
+  for (int o = 0; o < NS; ++o) {
+    const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, D == 3 ? o / 9 - 1 : 0};
+    double u[D + 1];
+#pragma unroll
+    for (int f = 0; f <= D; ++f) u[f] = xat(f, oo);
+    const double sk = cf(0, o);
+#pragma unroll
+    for (int f = 0; f < D; ++f) {
+      acc[f] += sk * u[f] + cf(1 + f, o) * u[D];
+      acc[D] += cf(1 + D + f, o) * u[f];
+    }
+    acc[D] += cf(1 + 2 * D, o) * u[D];
+  }
+}
+
+// Row of L at a node with operator code op (Level::node_op): the level's reference stencil of a
+// uniform neighbourhood (staged in rm) or the node's own assembled stencil in nsten.
+template <int D, bool UNR = true, class XA>
+__device__ __forceinline__ void node_row_apply(const RefMats<D>& rm, int op, const double* __restrict__ nsten,
+                                               XA&& xat, double* acc) {
+  using R = RefLayout<D>;
+  constexpr int NS = PT<D>::NST;
+  if (op < 0) {
+    const int kind = -op - 1;
+    stencil_apply<D, UNR>(
+        [&](int j, int o) {
+          if (j == 0) return rm.v[R::oSK + kind * NS + o];
+          if (j <= D) return rm.v[R::oSB + (kind * D + j - 1) * NS + o];
+          if (j <= 2 * D) return rm.v[R::oST + (kind * D + j - 1 - D) * NS + o];
+          return rm.v[R::oSC + o];
+        },
+        xat, acc);
+  } else {
+    // the stored row streams from memory: the loop over offsets stays partly rolled so that its
+    // loads do not all occupy registers at once
+    const double* p = nsten + (int64_t)op * PT<D>::NSTEN;
+    stencil_apply<D, false>([&](int j, int o) { return p[j * NS + o]; }, xat, acc);
+  }
+}
+
+// Set-up: assembled stencils of the listed nodes. One wavefront per node; lane (o, g) applies the
+// element rows to the unit vector of field g at offset o, which yields column (o, g) of the row.
+template <int D>
+__global__ void __launch_bounds__(256) node_stencil_kernel(const OpConsts* __restrict__ oc,
+                                                          const int* __restrict__ cell_info,
+                                                          const double* __restrict__ cut, double alpha_f,
+                                                          const int* __restrict__ nodes, int64_t count,
+                                                          double* __restrict__ nsten) {
+  constexpr int NS = PT<D>::NST;
+  __shared__ RefMats<D> rm;
+  stage_refmats<D, 256>(oc, rm);
+  __syncthreads();
+  const int64_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n = oc->n;
+  for (int col = lane; col < NS * (D + 1) && k < count; col += 64) {
+    const int o = col % NS, g = col / NS;
+    const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, D == 3 ? o / 9 - 1 : 0};
+    int c[3];
+    node_coords<D>(nodes[k], n, c);
+    double acc[D + 1];
+#pragma unroll
+    for (int f = 0; f <= D; ++f) acc[f] = 0;
+    node_apply<D, false>(
+        rm, [&](const int* cc) { return cell_info[D == 2 ? cc[0] + n * cc[1] : cc[0] + n * (cc[1] + n * cc[2])]; },
+        [&](const int*, int info) -> const double* { return cut + (int64_t)info * PT<D>::NEL; }, alpha_f, n, c,
+        [&](int f, const int* q) {
+          bool hit = f == g;
+#pragma unroll
+          for (int a = 0; a < D; ++a) hit = hit && q[a] == oo[a];
+          return hit ? 1.0 : 0.0;
+        },
+        acc);
+    double* p = nsten + k * PT<D>::NSTEN;
+    if (g < D) {
+      if (g == 0) p[o] = acc[0];
+      p[(1 + D + g) * NS + o] = acc[D];
+    } else {
+#pragma unroll
+      for (int f = 0; f < D; ++f) p[(1 + f) * NS + o] = acc[f];
+      p[(1 + 2 * D) * NS + o] = acc[D];
+    }
+  }
+}
+
+template <int D>
+hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipStream_t s) {
+  if (L.n_nsten == 0) return hipSuccess;
+  node_stencil_kernel<D><<<dim3((unsigned)((L.n_nsten + 3) / 4)), dim3(256), 0, s>>>(
+      L.consts, L.cell_info, L.cut_mats, c.prm.alpha_fict, nodes, L.n_nsten, L.nsten);
+  return hipGetLastError();
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __restrict__ oc,
-                                                           const int* __restrict__ cell_info,
-                                                           const double* __restrict__ cut, double alpha_f, int ntx,
-                                                           int nty, int ntz, const double* __restrict__ x,
+                                                           const int* __restrict__ node_op,
+                                                           const double* __restrict__ nsten, int ntx, int nty,
+                                                           int ntz, const double* __restrict__ x,
                                                            const double* __restrict__ b, double* __restrict__ r) {
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
-  constexpr int CW = TX + 1, CH = TY + 1, CD = D == 3 ? TZ + 1 : 1, CP = CW * CH * CD;
-  constexpr int NXL = ((D + 1) * XP + 255) / 256, NCL = (CP + 255) / 256;
+  constexpr int NXL = ((D + 1) * XP + 255) / 256;
   __shared__ double xs[(D + 1) * XP];
-  __shared__ int cs[CP];
   __shared__ RefMats<D> rm;
   const int n = oc->n;
   const int m = n + 1;
@@ -450,6 +494,7 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   double bv[D + 1];
 #pragma unroll
   for (int f = 0; f <= D; ++f) bv[f] = inside ? b[f * N + node] : 0.0;
+  const int op = inside ? node_op[node] : -1;
   double xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
@@ -459,37 +504,21 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
     const bool ok = e < (D + 1) * XP && gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m));
     xv[k] = ok ? x[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))] : 0.0;
   }
-  int cv[NCL];
-#pragma unroll
-  for (int k = 0; k < NCL; ++k) {
-    const int e = threadIdx.x + 256 * k;
-    const int gx = o0 + e % CW, gy = o1 + (e / CW) % CH, gz = D == 3 ? o2 + e / (CW * CH) : 0;
-    const bool ok = e < CP && gx >= 0 && gx < n && gy >= 0 && gy < n && (D == 2 || (gz >= 0 && gz < n));
-    cv[k] = ok ? cell_info[D == 2 ? gx + n * gy : gx + n * (gy + n * gz)] : -1;
-  }
-  stage_refmats<D>(oc, rm);
+  stage_refmats<D, 256>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + 256 * k < (D + 1) * XP) xs[threadIdx.x + 256 * k] = xv[k];
-#pragma unroll
-  for (int k = 0; k < NCL; ++k)
-    if (threadIdx.x + 256 * k < CP) cs[threadIdx.x + 256 * k] = cv[k];
   __syncthreads();
   if (!inside) return;
   const int base = (tx + 1) + XW * ((ty + 1) + XH * (tz + 1) * (D == 3 ? 1 : 0));
   double acc[D + 1];
 #pragma unroll
   for (int f = 0; f <= D; ++f) acc[f] = 0;
-  node_apply<D>(rm,
-                [&](const int* cc) {
-                  return cs[(cc[0] - o0) + CW * ((cc[1] - o1) + (D == 3 ? CH * (cc[2] - o2) : 0))];
-                },
-                [&](const int*, int info) -> const double* { return cut + (int64_t)info * PT<D>::NEL; },
-                alpha_f, n, c,
-                [&](int f, const int* o) {
-                  return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];
-                },
-                acc);
+  node_row_apply<D>(rm, op, nsten,
+                    [&](int f, const int* o) {
+                      return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];
+                    },
+                    acc);
 #pragma unroll
   for (int f = 0; f <= D; ++f) r[f * N + node] = bv[f] - acc[f];
 }
@@ -506,8 +535,8 @@ hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const doubl
   int nt[3];
   tile_grid<D>(L.n, nt);
   const int nb = nt[0] * nt[1] * nt[2];
-  residual_tile_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.cell_info, L.cut_mats,
-                                                                    c.prm.alpha_fict, nt[0], nt[1], nt[2], x, b, r);
+  residual_tile_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.node_op, L.nsten, nt[0], nt[1],
+                                                                    nt[2], x, b, r);
   return hipGetLastError();
 }
 
@@ -771,7 +800,6 @@ hipError_t k_zero(double* v, int64_t n, hipStream_t s) {
 }  // namespace fcg
 
 #include "fcgmg_patch.inl"
-#include "fcgmg_tail.inl"
 
 namespace fcg {
 #define FCG_INST(D)                                                                                           \
@@ -780,6 +808,7 @@ namespace fcg {
   template hipError_t k_rhs<D>(const Ctx&, const Level&, double*, hipStream_t);                               \
   template hipError_t k_residual<D>(const Ctx&, const Level&, const double*, const double*, double*,           \
                                     hipStream_t);                                                             \
+  template hipError_t k_node_stencils<D>(const Ctx&, const Level&, const int*, hipStream_t);                  \
   template hipError_t k_restrict<D>(const Ctx&, int, const double*, double*, hipStream_t);                    \
   template hipError_t k_prolong_add<D>(const Ctx&, int, const double*, double*, hipStream_t);                 \
   template hipError_t k_coarse_matrix<D>(const Ctx&, const Level&, double*, int, hipStream_t);                \
@@ -790,7 +819,6 @@ namespace fcg {
   template hipError_t k_patch_solve<D>(const Ctx&, const Level&, int, const double*, double*, hipStream_t);  \
   template hipError_t k_store_matrices<D>(const Ctx&, const Level&, const int*, int64_t, double*,             \
                                           hipStream_t);                                                       \
-  template hipError_t k_tail_vcycle<D>(const Ctx&, hipStream_t);                                               \
   template int pattern_size<D>();                                                                             \
   template void pattern_entries<D>(std::vector<int>&);
 FCG_INST(2)

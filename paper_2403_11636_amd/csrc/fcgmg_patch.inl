@@ -826,28 +826,28 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
   }
 }
 
-// Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes, one thread
-// per node. Large grids use 32 x 8 tiles (less halo work), small grids 16 x 4 (more workgroups in
-// flight); the arithmetic of every node is the same for both.
-template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
-                                                           const int* __restrict__ cell_info,
-                                                           const double* __restrict__ cut, double alpha_f, int ntx,
-                                                           int nty, const int* __restrict__ node_class,
-                                                           const double* __restrict__ Zcls,
-                                                           const double* __restrict__ Zirr,
-                                                           const double* __restrict__ x_in,
-                                                           const double* __restrict__ b,
-                                                           double* __restrict__ x_out, double omega) {
-  constexpr int NT = TX * TY;
+// Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes by NT >= TX TY
+// threads; thread t < TX TY owns node t of the tile. Large grids use 32 x 8 tiles with one thread per
+// node (less halo work); small grids, whose sweep time is the latency of one workgroup, use small
+// tiles with four times as many threads (shorter residual and individual-patch loops per thread).
+// The arithmetic of every node is the same for all shapes.
+template <int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
+                                                          const int* __restrict__ node_op,
+                                                          const double* __restrict__ nsten, int ntx, int nty,
+                                                          const int* __restrict__ node_class,
+                                                          const double* __restrict__ Zcls,
+                                                          const double* __restrict__ Zirr,
+                                                          const double* __restrict__ x_in,
+                                                          const double* __restrict__ b,
+                                                          double* __restrict__ x_out, double omega) {
+  static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
   constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
   constexpr int RW = TX + 4, RH = TY + 4, RP = RW * RH;  // residual tile, halo 2
   constexpr int ZSP = PT<2>::ZSP;
-  constexpr int CW = TX + 5, CH = TY + 5, CP = CW * CH;  // cells of the residual tile
   constexpr int NRES = (RP + NT - 1) / NT;                // residual nodes per thread
   __shared__ double xs[3 * XP];
   __shared__ double rs[3 * RP];
-  __shared__ int cs[CP];
   __shared__ int irr_tid[TX * TY], irr_pidx[TX * TY];
   __shared__ int irr_cnt;
   __shared__ RefMats<2> rm;
@@ -859,12 +859,12 @@ __global__ void __launch_bounds__(TX * TY) sweep_fused2_kernel(const OpConsts* _
   int t[3];
   tile_coords<2>(blockIdx.x, nt, t);
   const int bx = t[0] * TX, by = t[1] * TY;
-  // the global loads of the own patch class, the x tile and the cell kinds of the tile are issued
-  // before the first LDS store; b of a residual node is read next to its residual
+  // every global load that depends on no other one is issued before the first LDS store: the own
+  // patch class, the x tile, and the operator code and b of this thread's residual nodes
   const int tx0 = threadIdx.x % TX, ty0 = threadIdx.x / TX;
-  const bool inside0 = bx + tx0 < m && by + ty0 < m;
+  const bool inside0 = threadIdx.x < TX * TY && bx + tx0 < m && by + ty0 < m;
   const int cls = inside0 ? node_class[(bx + tx0) + (int64_t)m * (by + ty0)] : -1;
-  constexpr int NXL = (3 * XP + NT - 1) / NT, NCL = (CP + NT - 1) / NT;
+  constexpr int NXL = (3 * XP + NT - 1) / NT;
   double xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
@@ -873,49 +873,46 @@ __global__ void __launch_bounds__(TX * TY) sweep_fused2_kernel(const OpConsts* _
     const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
     xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x_in[f * N + gx + (int64_t)m * gy] : 0.0;
   }
-  int cv[NCL];
+  int opv[NRES];
+  double bv[NRES][3];
 #pragma unroll
-  for (int k = 0; k < NCL; ++k) {
+  for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
-    const int gx = bx - 3 + e % CW, gy = by - 3 + e / CW;
-    cv[k] = (e < CP && gx >= 0 && gx < n && gy >= 0 && gy < n) ? cell_info[gx + n * gy] : -1;
+    const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
+    const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
+    const int64_t g = cx + (int64_t)m * cy;
+    opv[k] = ok ? node_op[g] : -1;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : 0.0;
   }
-  stage_refmats<2>(oc, rm);
+  stage_refmats<2, NT>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
-#pragma unroll
-  for (int k = 0; k < NCL; ++k)
-    if (threadIdx.x + NT * k < CP) cs[threadIdx.x + NT * k] = cv[k];
   __syncthreads();
-#pragma unroll 1
+#pragma unroll
   for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
-    if (e >= RP) break;
-    const int px = e % RW, py = e / RW;
-    const int c[3] = {bx - 2 + px, by - 2 + py, 0};
-    double rv[3] = {0, 0, 0};
-    if (c[0] >= 0 && c[0] < m && c[1] >= 0 && c[1] < m) {
-      const int64_t g = c[0] + (int64_t)m * c[1];
-      double bres[3];
+    if (e < RP) {
+      const int px = e % RW, py = e / RW;
+      const int cx = bx - 2 + px, cy = by - 2 + py;
+      double rv[3] = {0, 0, 0};
+      if (cx >= 0 && cx < m && cy >= 0 && cy < m) {
+        const int xb = (px + 1) + XW * (py + 1);
+        double acc[3] = {0, 0, 0};
+        // an offset the compiler cannot see through: keeps it from holding the level constants of
+        // several residual nodes in registers at once (they are read from LDS where they are used)
+        int ro = 0;
+        asm volatile("" : "+s"(ro));
+        const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
+        node_row_apply<2>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+                          acc);
 #pragma unroll
-      for (int f = 0; f < 3; ++f) bres[f] = b[f * N + g];
-      const int xb = (px + 1) + XW * (py + 1);
-      double acc[3] = {0, 0, 0};
-      // an offset the compiler cannot see through: keeps it from hoisting the level constants
-      // out of this loop into registers (they are read from LDS where they are used)
-      int ro = 0;
-      asm volatile("" : "+s"(ro));
-      const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
-      node_apply<2>(
-          rmk, [&](const int* cc) { return cs[(cc[0] - bx + 3) + CW * (cc[1] - by + 3)]; },
-          [&](const int*, int info) -> const double* { return cut + (int64_t)info * PT<2>::NEL; },
-          alpha_f, n, c, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; }, acc);
+        for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
+      }
 #pragma unroll
-      for (int f = 0; f < 3; ++f) rv[f] = bres[f] - acc[f];
+      for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
     }
-#pragma unroll
-    for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
   }
   __syncthreads();
   const int tx = tx0, ty = ty0;
@@ -960,8 +957,10 @@ __global__ void __launch_bounds__(TX * TY) sweep_fused2_kernel(const OpConsts* _
   }
 }
 
-// Levels with at least this many nodes use the 32 x 8 tile of the fused 2D sweep.
+// Tile shapes of the fused 2D sweep by level size (nodes): 32 x 8 tiles by 256 threads from
+// kFusedBigTileNodes on, 8 x 4 by 128 from kFusedMidTileNodes on, 4 x 4 by 128 below.
 constexpr int64_t kFusedBigTileNodes = 200000;
+constexpr int64_t kFusedMidTileNodes = 30000;
 
 template <int D>
 hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
@@ -983,20 +982,20 @@ hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, doub
   return hipGetLastError();
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int NT>
 hipError_t launch_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                          hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
-  sweep_fused2_kernel<TX, TY><<<dim3((unsigned)(ntx * nty)), dim3(TX * TY), 0, s>>>(
-      L.consts, L.cell_info, L.cut_mats, c.prm.alpha_fict, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out,
-      c.prm.omega);
+  sweep_fused2_kernel<TX, TY, NT><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
+      L.consts, L.node_op, L.nsten, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega);
   return hipGetLastError();
 }
 
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                           hipStream_t s) {
-  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8>(c, L, x_in, b, x_out, s);
-  return launch_fused2<16, 4>(c, L, x_in, b, x_out, s);
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8, 256>(c, L, x_in, b, x_out, s);
+  if (L.N >= kFusedMidTileNodes) return launch_fused2<8, 4, 128>(c, L, x_in, b, x_out, s);
+  return launch_fused2<4, 4, 128>(c, L, x_in, b, x_out, s);
 }
 
 }  // namespace fcg

@@ -28,7 +28,7 @@ EXPORTS = [
 ]
 
 KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
-                "zero", "sweep_fused", "tail"]
+                "zero", "sweep_fused"]
 
 
 class FcgmgError(RuntimeError):
