@@ -152,7 +152,8 @@ enum {
   FCGMG_K_COARSE = 6,        /* coarsest-grid solve                                              */
   FCGMG_K_ZERO = 7,
   FCGMG_K_SWEEP_FUSED = 8,   /* cache_inverse, 2D: residual + all patch corrections in one kernel */
-  FCGMG_K_COUNT = 9
+  FCGMG_K_RESIDUAL_RESTRICT = 9, /* 2D V-cycle: fine residual and its restriction in one kernel    */
+  FCGMG_K_COUNT = 10
 };
 
 /* Event profiler (tracing): while enabled, every kernel launch of the handle is bracketed by a

@@ -550,6 +550,9 @@ int residual_impl(const Ctx& c, int l, const double* x, const double* b, double*
 }
 
 template <int D>
+int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t s);
+
+template <int D>
 int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
   const Level& L = c.lev[l];
   int rc;
@@ -569,20 +572,35 @@ int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
 
 // `sweeps` sweeps on level l. 2D cache_inverse: pairs of fused sweeps ping-pong between x and the
 // level's second buffer (an odd first sweep runs unfused, in place); the arithmetic is identical.
+// `mode` describes x on entry: 0 as given; 1 zero (contents undefined, not read); 2 still to be
+// corrected by the prolongation of the coarse vector xc. The fused pair applies modes 1 and 2 while
+// loading; otherwise x is zeroed or corrected first.
 template <int D>
-int smooth_impl(const Ctx& c, int l, double* x, const double* b, int sweeps, hipStream_t s) {
+int smooth_impl(const Ctx& c, int l, double* x, const double* b, int sweeps, hipStream_t s, int mode = 0,
+                const double* xc = nullptr) {
   const Level& L = c.lev[l];
   int rc;
-  if (D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && L.xalt) {
+  const bool fused = D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && L.xalt;
+  if (mode != 0 && (!fused || sweeps % 2 == 1 || sweeps == 0)) {
+    if (mode == 1)
+      rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero(x, (D + 1) * L.N, s); });
+    else
+      rc = prolong_impl<D>(c, l, xc, x, s);
+    if (rc) return rc;
+    mode = 0;
+  }
+  if (fused) {
     int k = 0;
     if (sweeps % 2 == 1) {
       if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
       k = 1;
     }
     for (; k < sweeps; k += 2) {
-      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, x, b, L.xalt, s); })))
+      const int md = k == 0 ? mode : 0;
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s,
+                       [&] { return k_sweep_fused2(c, L, x, b, L.xalt, md, md == 2 ? xc : nullptr, s); })))
         return rc;
-      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, L.xalt, b, x, s); })))
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, L.xalt, b, x, 0, nullptr, s); })))
         return rc;
     }
     return FCGMG_OK;
@@ -606,19 +624,25 @@ int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t 
   return launch(c, FCGMG_K_PROLONG, l, s, [&] { return k_prolong_add<D>(c, l, xc, xf, s); });
 }
 
+// One V-cycle on level l (Sec. 3): pre-smoothing, restriction of the residual, the cycle on level
+// l-1 from a zero initial guess, prolongation of its result, post-smoothing. `x_zero`: x holds zero
+// on entry (its contents are not read). The coarsest solve writes every entry of its x.
 template <int D>
-int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
+int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s, bool x_zero = false) {
   if (l == 0) return coarse_impl(c, b, x, s);
   int rc;
-  if ((rc = smooth_impl<D>(c, l, x, b, c.prm.nu_pre, s))) return rc;
+  if ((rc = smooth_impl<D>(c, l, x, b, c.prm.nu_pre, s, x_zero ? 1 : 0))) return rc;
   const Level& L = c.lev[l];
   const Level& C = c.lev[l - 1];
-  if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
-  if ((rc = restrict_impl<D>(c, l, L.r, C.b, s))) return rc;
-  if ((rc = launch(c, FCGMG_K_ZERO, l - 1, s, [&] { return k_zero(C.x, (D + 1) * C.N, s); }))) return rc;
-  if ((rc = vcycle_impl<D>(c, l - 1, C.x, C.b, s))) return rc;
-  if ((rc = prolong_impl<D>(c, l, C.x, x, s))) return rc;
-  return smooth_impl<D>(c, l, x, b, c.prm.nu_post, s);
+  if (D == 2) {
+    if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s, [&] { return k_residual_restrict2(c, L, x, b, C.b, s); })))
+      return rc;
+  } else {
+    if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
+    if ((rc = restrict_impl<D>(c, l, L.r, C.b, s))) return rc;
+  }
+  if ((rc = vcycle_impl<D>(c, l - 1, C.x, C.b, s, true))) return rc;
+  return smooth_impl<D>(c, l, x, b, c.prm.nu_post, s, 2, C.x);
 }
 
 int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {

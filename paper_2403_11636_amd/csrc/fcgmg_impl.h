@@ -314,7 +314,9 @@ template <int D> hipError_t k_apply_regular(const Ctx& c, const Level& L, const 
 template <int D> hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x,
                                              hipStream_t s);
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                          hipStream_t s);
+                          int mode, const double* xc, hipStream_t s);
+hipError_t k_residual_restrict2(const Ctx& c, const Level& F, const double* x, const double* b, double* bc,
+                                hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,
                                           hipStream_t s);
 template <int D> hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int64_t count,

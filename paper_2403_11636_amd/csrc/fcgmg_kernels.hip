@@ -573,14 +573,11 @@ __device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_
   for (int f = 0; f <= D; ++f) bc[f * Nc + node] = acc[f];
 }
 
-// x_f at fine node `node` += Q1 interpolation of the coarse correction.
+// Q1 interpolation of field f of the coarse vector xc at the fine node with coordinates c.
 template <int D>
-__device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
-                                             double* __restrict__ xf, int64_t node) {
-  int c[3];
-  node_coords<D>(node, nf, c);
-  double acc[D + 1];
-  for (int f = 0; f <= D; ++f) acc[f] = 0;
+__device__ __forceinline__ double prolong_value(int nc, int64_t Nc, const double* __restrict__ xc, const int* c,
+                                                int f) {
+  double acc = 0;
   for (int t = 0; t < (1 << D); ++t) {
     int cc[3] = {0, 0, 0};
     double w = 1;
@@ -596,10 +593,18 @@ __device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t
       }
     }
     if (!valid) continue;
-    const int64_t j = node_index<D>(cc, nc);
-    for (int f = 0; f <= D; ++f) acc[f] += w * xc[f * Nc + j];
+    acc += w * xc[f * Nc + node_index<D>(cc, nc)];
   }
-  for (int f = 0; f <= D; ++f) xf[f * Nf + node] += acc[f];
+  return acc;
+}
+
+// x_f at fine node `node` += Q1 interpolation of the coarse correction.
+template <int D>
+__device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
+                                             double* __restrict__ xf, int64_t node) {
+  int c[3];
+  node_coords<D>(node, nf, c);
+  for (int f = 0; f <= D; ++f) xf[f * Nf + node] += prolong_value<D>(nc, Nc, xc, c, f);
 }
 
 template <int D>

@@ -831,6 +831,9 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
 // node (less halo work); small grids, whose sweep time is the latency of one workgroup, use small
 // tiles with four times as many threads (shorter residual and individual-patch loops per thread).
 // The arithmetic of every node is the same for all shapes.
+// mode 0: x_in as given; mode 1: x_in is zero (not read; the first sweep on a coarse level);
+// mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
+// V-cycle applied as the x tile is loaded, as prolong_add would apply it).
 template <int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
                                                           const int* __restrict__ node_op,
@@ -840,7 +843,8 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
                                                           const double* __restrict__ Zirr,
                                                           const double* __restrict__ x_in,
                                                           const double* __restrict__ b,
-                                                          double* __restrict__ x_out, double omega) {
+                                                          double* __restrict__ x_out, double omega, int mode,
+                                                          const double* __restrict__ xc) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
   constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
   constexpr int RW = TX + 4, RH = TY + 4, RP = RW * RH;  // residual tile, halo 2
@@ -871,7 +875,15 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
     const int e = threadIdx.x + NT * k;
     const int f = e / XP, p = e % XP;
     const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
-    xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x_in[f * N + gx + (int64_t)m * gy] : 0.0;
+    double v = 0.0;
+    if (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) {
+      if (mode != 1) v = x_in[f * N + gx + (int64_t)m * gy];
+      if (mode == 2) {
+        const int cg[3] = {gx, gy, 0};
+        v += prolong_value<2>(n >> 1, (int64_t)((n >> 1) + 1) * ((n >> 1) + 1), xc, cg, f);
+      }
+    }
+    xv[k] = v;
   }
   int opv[NRES];
   double bv[NRES][3];
@@ -984,18 +996,130 @@ hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, doub
 
 template <int TX, int TY, int NT>
 hipError_t launch_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                         hipStream_t s) {
+                         int mode, const double* xc, hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
   sweep_fused2_kernel<TX, TY, NT><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
-      L.consts, L.node_op, L.nsten, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega);
+      L.consts, L.node_op, L.nsten, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega, mode, xc);
   return hipGetLastError();
 }
 
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                          hipStream_t s) {
-  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8, 256>(c, L, x_in, b, x_out, s);
-  if (L.N >= kFusedMidTileNodes) return launch_fused2<8, 4, 128>(c, L, x_in, b, x_out, s);
-  return launch_fused2<4, 4, 128>(c, L, x_in, b, x_out, s);
+                          int mode, const double* xc, hipStream_t s) {
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8, 256>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.N >= kFusedMidTileNodes) return launch_fused2<8, 4, 128>(c, L, x_in, b, x_out, mode, xc, s);
+  return launch_fused2<4, 4, 128>(c, L, x_in, b, x_out, mode, xc, s);
+}
+
+// Residual and restriction in one pass (2D, V-cycle): b_c = P^T (b - L x) for a TXC x TYC tile of
+// coarse nodes. The fine residual of the (2 TXC + 1) x (2 TYC + 1) nodes the tile gathers from is
+// computed into LDS from an x tile with halo 1; arithmetic and summation order are those of the
+// residual and restriction kernels.
+template <int TXC, int TYC, int NT>
+__global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* __restrict__ oc,
+                                                                const int* __restrict__ node_op,
+                                                                const double* __restrict__ nsten, int ntx, int nty,
+                                                                const double* __restrict__ x,
+                                                                const double* __restrict__ b,
+                                                                double* __restrict__ bc) {
+  static_assert(NT >= TXC * TYC && NT % 64 == 0, "one thread per coarse node at least");
+  constexpr int RW = 2 * TXC + 1, RH = 2 * TYC + 1, RP = RW * RH;  // fine residual region
+  constexpr int XW = RW + 2, XH = RH + 2, XP = XW * XH;            // x region, halo 1
+  constexpr int NRES = (RP + NT - 1) / NT, NXL = (3 * XP + NT - 1) / NT;
+  __shared__ double xs[3 * XP];
+  __shared__ double rs[3 * RP];
+  __shared__ RefMats<2> rm;
+  const int n = oc->n;
+  const int m = n + 1;
+  const int64_t N = (int64_t)m * m;
+  const int mc = (n >> 1) + 1;
+  const int64_t Nc = (int64_t)mc * mc;
+  const int nt[3] = {ntx, nty, 1};
+  int t[3];
+  tile_coords<2>(blockIdx.x, nt, t);
+  const int cx0 = t[0] * TXC, cy0 = t[1] * TYC;
+  const int fx0 = 2 * cx0 - 1, fy0 = 2 * cy0 - 1;  // fine coordinates of residual-region entry 0
+  double xv[NXL];
+#pragma unroll
+  for (int k = 0; k < NXL; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int f = e / XP, p = e % XP;
+    const int gx = fx0 - 1 + p % XW, gy = fy0 - 1 + p / XW;
+    xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x[f * N + gx + (int64_t)m * gy] : 0.0;
+  }
+  int opv[NRES];
+  double bv[NRES][3];
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) {
+    const int e = threadIdx.x + NT * k;
+    const int gx = fx0 + e % RW, gy = fy0 + e / RW;
+    const bool ok = e < RP && gx >= 0 && gx < m && gy >= 0 && gy < m;
+    const int64_t g = gx + (int64_t)m * gy;
+    opv[k] = ok ? node_op[g] : -1;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : 0.0;
+  }
+  stage_refmats<2, NT>(oc, rm);
+#pragma unroll
+  for (int k = 0; k < NXL; ++k)
+    if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) {
+    const int e = threadIdx.x + NT * k;
+    if (e < RP) {
+      const int px = e % RW, py = e / RW;
+      const int gx = fx0 + px, gy = fy0 + py;
+      double rv[3] = {0, 0, 0};
+      if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
+        const int xb = (px + 1) + XW * (py + 1);
+        double acc[3] = {0, 0, 0};
+        int ro = 0;  // opaque offset: no hoisting of the level constants (see the fused sweep)
+        asm volatile("" : "+s"(ro));
+        const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
+        node_row_apply<2>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+                          acc);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
+      }
+#pragma unroll
+      for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x >= TXC * TYC) return;
+  const int cx = cx0 + threadIdx.x % TXC, cy = cy0 + threadIdx.x / TXC;
+  if (cx >= mc || cy >= mc) return;
+  double acc[3] = {0, 0, 0};
+  for (int o = 0; o < 9; ++o) {
+    const int ox = o % 3 - 1, oy = o / 3 - 1;
+    const int gx = 2 * cx + ox, gy = 2 * cy + oy;
+    if (gx < 0 || gx > n || gy < 0 || gy > n) continue;
+    double w = 1;
+    if (ox != 0) w *= 0.5;
+    if (oy != 0) w *= 0.5;
+    const int e = (gx - fx0) + RW * (gy - fy0);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) acc[f] += w * rs[f * RP + e];
+  }
+  const int64_t cn = cx + (int64_t)mc * cy;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) bc[f * Nc + cn] = acc[f];
+}
+
+template <int TXC, int TYC, int NT>
+hipError_t launch_residual_restrict2(const Level& F, const double* x, const double* b, double* bc, hipStream_t s) {
+  const int mc = (F.n >> 1) + 1;
+  const int ntx = (mc + TXC - 1) / TXC, nty = (mc + TYC - 1) / TYC;
+  residual_restrict2_kernel<TXC, TYC, NT><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
+      F.consts, F.node_op, F.nsten, ntx, nty, x, b, bc);
+  return hipGetLastError();
+}
+
+hipError_t k_residual_restrict2(const Ctx&, const Level& F, const double* x, const double* b, double* bc,
+                                hipStream_t s) {
+  if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256>(F, x, b, bc, s);
+  if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128>(F, x, b, bc, s);
+  return launch_residual_restrict2<4, 4, 128>(F, x, b, bc, s);
 }
 
 }  // namespace fcg

@@ -28,7 +28,7 @@ EXPORTS = [
 ]
 
 KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
-                "zero", "sweep_fused"]
+                "zero", "sweep_fused", "residual_restrict"]
 
 
 class FcgmgError(RuntimeError):

@@ -291,3 +291,32 @@ def test_config2_fused_sweeps_sampled():
     ref = o.smooth_nodes(o.fine, x1, b, nodes, p.omega)
     got = np.stack([x_gpu[f * N + nodes] for f in range(3)], axis=1)
     assert rel(got, ref) <= 1e-12
+
+
+def _composed_vcycle(h, p, level, x, b):
+    """The V-cycle spelled out with the library's single-step calls (Sec. 3)."""
+    if level == 0:
+        h.coarse_solve(b, out=x)
+        return
+    h.smooth(x, b, p.nu_pre, level=level)
+    r = h.residual(x, b, level=level)
+    bc = h.restrict(r, level)
+    xc = h.zeros(level - 1)
+    _composed_vcycle(h, p, level - 1, xc, bc)
+    h.prolongate_add(xc, x, level)
+    h.smooth(x, b, p.nu_post, level=level)
+
+
+@pytest.mark.parametrize("name", ["2d_16_l3_s0", "c1_32_l3", "2d_40_l3_noslip", "3d_8_l2_s0"])
+def test_vcycle_bitwise_equals_composed_steps(name):
+    # The V-cycle folds the zero initial guess of coarse levels, the prolongation and (2D) the
+    # residual + restriction into fewer kernels; the arithmetic must be that of the single steps.
+    p, o, h = setup_case(name)
+    n = h.ndofs()
+    x = inputs.random_vector(n, 51)
+    b = inputs.random_vector(n, 52)
+    xv = dev(x)
+    h.vcycle(xv, dev(b))
+    xs = dev(x)
+    _composed_vcycle(h, p, h.fine, xs, dev(b))
+    assert np.array_equal(host(xv), host(xs))
