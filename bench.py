@@ -49,23 +49,28 @@ def pct(v, q):
 def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
     """Bytes a kernel launch must move at minimum on one level (FP64 values, int32 indices).
 
-    residual:        read x, b; write r; cut-cell element data; one int per cell
-    apply_regular:   read r; one int per node; read+write x of the regular nodes; class rows
-    apply_irregular: the stored rows (d+1)|S_i| of every irregular patch; read+write x and read r
-                     of those nodes; one int per patch
-    patch_solve:     read r; read+write x (local blocks are built on chip or, for cache_matrix,
-                     read from the stored pattern values: added separately by the caller)
-    sweep_fused:     read x, b; write the new x; stored rows of the irregular patches; cut-cell
-                     element data; one int per node (patch class) and per cell (cell kind)
+    residual:          read x, b; write r; stored operator rows of the non-uniform nodes; one int
+                       per node (operator code)
+    residual_restrict: read x, b; write the coarse b; stored operator rows; one int per node
+    apply_regular:     read r; one int per node; read+write x of the regular nodes; class rows
+    apply_irregular:   the stored rows (d+1)|S_i| of every irregular patch; read+write x and read r
+                       of those nodes; one int per patch
+    patch_solve:       read r; read+write x (local blocks are built on chip or, for cache_matrix,
+                       read from the stored pattern values: added separately by the caller)
+    sweep_fused:       read x, b; write the new x; stored rows of the irregular patches; stored
+                       operator rows; two ints per node (patch class, operator code)
     """
     N = st["n_nodes"]
     nf = d + 1
-    nel = (d + 1) * (1 << d) ** 2
-    ncells = st["n_cells_axis"] ** d
+    nsten = (2 * d + 2) * 3 ** d
     zs = d * 5 ** d + 3 ** d
     nreg = N - st["n_irregular"]
+    rows = 8.0 * nsten * st["n_stencils"]
     if kind == "residual":
-        return 8.0 * 3 * nf * N + 8.0 * nel * st["n_cut_cells"] + 4.0 * ncells
+        return 8.0 * 3 * nf * N + rows + 4.0 * N
+    if kind == "residual_restrict":
+        nc = st["n_cells_axis"] // 2
+        return 8.0 * 2 * nf * N + 8.0 * nf * (nc + 1) ** d + rows + 4.0 * N
     if kind == "apply_regular":
         return 8.0 * nf * N + 4.0 * N + 16.0 * nf * nreg + 8.0 * nf * zs * st["n_classes"]
     if kind == "apply_irregular":
@@ -73,7 +78,7 @@ def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
     if kind == "patch_solve":
         return 8.0 * 3 * nf * N
     if kind == "sweep_fused":
-        return sweep_minimum_bytes(d, st) + 4.0 * N + 4.0 * ncells
+        return sweep_minimum_bytes(d, st) + 8.0 * N
     if kind in ("restrict", "prolong"):
         return 8.0 * nf * N * 1.25 if d == 2 else 8.0 * nf * N * 1.125
     return 0.0
@@ -81,10 +86,10 @@ def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
 
 def sweep_minimum_bytes(d: int, st: dict) -> float:
     """Fused minimum of one cache_inverse sweep: read x, b, write x, stored rows of the irregular
-    patches, cut-cell element data."""
+    patches, stored operator rows of the non-uniform nodes (FP64)."""
     nf = d + 1
-    nel = (d + 1) * (1 << d) ** 2
-    return 8.0 * (3 * nf * st["n_nodes"] + nf * st["irregular_cols"] + nel * st["n_cut_cells"])
+    nsten = (2 * d + 2) * 3 ** d
+    return 8.0 * (3 * nf * st["n_nodes"] + nf * st["irregular_cols"] + nsten * st["n_stencils"])
 
 
 def time_vcycles(torch, h, x, b, steps):
@@ -182,18 +187,21 @@ def measured_traffic(kernel_key: str):
     return int(rec["traffic_bytes"])
 
 
-def cpu_baseline(prob, steps=2):
+def cpu_baseline(prob, budget_s=10.0):
     """The FP64 oracle (as it stands) on the host cores: cache_inverse-form V(2,2) cycles on the same
-    problem. The oracle's inverse-row set-up runs first, untimed; it is most of the CPU work."""
+    problem, repeated until about `budget_s` seconds of cycles have run. The oracle's inverse-row
+    set-up runs first, untimed."""
     from oracle.oracle import MODE_INVERSE, Oracle, max_threads
     t0 = time.perf_counter()
     o = Oracle(prob)
     b = o.rhs()
     x = o.vcycle(np.zeros_like(b), b, mode=MODE_INVERSE)  # builds the inverse rows on every level
     setup_s = time.perf_counter() - t0
+    steps = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    while steps < 2 or time.perf_counter() - t0 < budget_s:
         x = o.vcycle(x, b, mode=MODE_INVERSE)
+        steps += 1
     dt = (time.perf_counter() - t0) / steps
     nd = o.ndofs(o.fine)
     return {

@@ -86,6 +86,7 @@ typedef struct {
   int64_t n_irregular;    /* patches with an individual local block                             */
   int64_t irregular_cols; /* sum of |S_i| over irregular patches                                */
   int64_t cached_bytes;   /* device bytes of policy-cached patch data on this level             */
+  int64_t n_stencils;     /* nodes whose operator row is stored (not a uniform neighbourhood)    */
 } fcgmg_level_stats;
 
 /* Build the hierarchy of Algorithm 1 (uniform case: every level fully coarsened), classify cells,

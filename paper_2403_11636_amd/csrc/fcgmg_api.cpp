@@ -737,6 +737,7 @@ int fcgmg_level_stats_get(fcgmg_h h, int level, fcgmg_level_stats* o) {
   o->n_irregular = L.n_irr;
   o->irregular_cols = L.irr_cols;
   o->cached_bytes = (int64_t)L.cached_bytes;
+  o->n_stencils = L.n_nsten;
   return FCGMG_OK;
 }
 

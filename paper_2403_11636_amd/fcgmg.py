@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n_cells_axis", "n_nodes", "n_cut_cells", "n_fict_cells", "n_classes", "n_irregular",
-        "irregular_cols", "cached_bytes")]
+        "irregular_cols", "cached_bytes", "n_stencils")]
 
 
 _lib = None

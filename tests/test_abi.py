@@ -37,6 +37,21 @@ def test_params_struct_matches_header():
     assert fields == [f for f, _ in fcgmg.Params._fields_]
 
 
+def test_level_stats_struct_matches_header():
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct {", src.index("} fcgmg_params;")):src.index("} fcgmg_level_stats;")]
+    fields = re.findall(r"\bint64_t\s+([a-z_]+)\s*;", body)
+    assert fields == [f for f, _ in fcgmg.LevelStats._fields_]
+
+
+def test_kernel_kinds_match_header():
+    src = open(HEADER).read()
+    kinds = re.findall(r"FCGMG_K_([A-Z_]+)\s*=\s*(\d+)", src)
+    named = {int(v): k.lower() for k, v in kinds if k != "COUNT"}
+    count = int(dict(kinds)["COUNT"])
+    assert [named[i] for i in range(count)] == fcgmg.KERNEL_KINDS
+
+
 @pytest.mark.parametrize("mutate,msg", [
     (lambda p: setattr(p, "dim", 4), "dim"),
     (lambda p: setattr(p, "n_cells", 30), "n_cells"),
