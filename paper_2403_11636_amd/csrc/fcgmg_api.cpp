@@ -451,7 +451,7 @@ int setup_impl(Ctx& c, hipStream_t s) {
     }
     FCG_HIP(hipStreamSynchronize(s));  // op and sten_nodes must outlive the copies
     // patches
-    std::vector<int> ncls, reps, irr;
+    std::vector<int> ncls, reps, irr, extra;
     classify_patches<D>(L, kinds, ncls, reps, irr);
     L.n_classes = (int64_t)reps.size();
     L.n_irr = (int64_t)irr.size();
@@ -474,6 +474,14 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if (L.n_irr) {
       if ((rc = alloc_n(c, &L.irr_nodes, L.n_irr))) return rc;
       FCG_HIP(hipMemcpyAsync(L.irr_nodes, irr.data(), L.n_irr * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    if (D == 2 && P.cache_policy == FCGMG_CACHE_INVERSE) {
+      plan_fused2(L, ncls, extra);
+      L.n_fused_extra = (int)extra.size();
+      if (L.n_fused_extra) {
+        if ((rc = alloc_n(c, &L.fused_extra, extra.size()))) return rc;
+        FCG_HIP(hipMemcpyAsync(L.fused_extra, extra.data(), extra.size() * sizeof(int), hipMemcpyHostToDevice, s));
+      }
     }
     // the host vectors above must outlive the asynchronous copies
     FCG_HIP(hipStreamSynchronize(s));

@@ -102,6 +102,8 @@ struct Level {
   int* node_op = nullptr;
   double* nsten = nullptr;
   int64_t n_nsten = 0;
+  int* fused_extra = nullptr;  // 2D cache_inverse: extra workgroups of heavy tiles (plan_fused2)
+  int n_fused_extra = 0;
   int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
   int* irr_nodes = nullptr;   // centre node of each irregular patch
   int* class_rep = nullptr;   // representative node of each class
@@ -315,6 +317,7 @@ template <int D> hipError_t k_apply_irregular(const Ctx& c, const Level& L, cons
                                              hipStream_t s);
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                           int mode, const double* xc, hipStream_t s);
+void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra);
 hipError_t k_residual_restrict2(const Ctx& c, const Level& F, const double* x, const double* b, double* bc,
                                 hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,

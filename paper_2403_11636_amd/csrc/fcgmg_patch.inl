@@ -834,10 +834,12 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
 // mode 0: x_in as given; mode 1: x_in is zero (not read; the first sweep on a coarse level);
 // mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
 // V-cycle applied as the x tile is loaded, as prolong_add would apply it).
-template <int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __restrict__ oc,
+template <int TX, int TY, int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) sweep_fused2_kernel(
+    const OpConsts* __restrict__ oc,
                                                           const int* __restrict__ node_op,
                                                           const double* __restrict__ nsten, int ntx, int nty,
+                                                          const int* __restrict__ extra,
                                                           const int* __restrict__ node_class,
                                                           const double* __restrict__ Zcls,
                                                           const double* __restrict__ Zirr,
@@ -852,17 +854,29 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
   constexpr int NRES = (RP + NT - 1) / NT;                // residual nodes per thread
   __shared__ double xs[3 * XP];
   __shared__ double rs[3 * RP];
-  __shared__ int irr_tid[TX * TY], irr_pidx[TX * TY];
-  __shared__ int irr_cnt;
+  constexpr int NWO = (TX * TY + 63) / 64;               // wavefronts that own tile nodes
+  constexpr int NG = NT / 16;                             // 16-lane groups of the workgroup
+  constexpr int CAP = 4 * NG;                             // individual patches per part (two trips)
+  __shared__ int irr_tid[NWO * 64], irr_pidx[NWO * 64];
+  __shared__ int irr_wcnt[NWO];
   __shared__ RefMats<2> rm;
-  if (threadIdx.x == 0) irr_cnt = 0;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
-  const int nt[3] = {ntx, nty, 1};
-  int t[3];
-  tile_coords<2>(blockIdx.x, nt, t);
-  const int bx = t[0] * TX, by = t[1] * TY;
+  // Workgroups 0 .. ntx*nty-1 are part 0 of every tile (XCD-aware order); further workgroups are
+  // extra parts of tiles with more than CAP individual patches (code tile * 4 + part, set-up).
+  int tile_lin, part = 0;
+  if ((int)blockIdx.x < ntx * nty) {
+    const int nt[3] = {ntx, nty, 1};
+    int t[3];
+    tile_coords<2>(blockIdx.x, nt, t);
+    tile_lin = t[0] + ntx * t[1];
+  } else {
+    const int code = extra[blockIdx.x - ntx * nty];
+    tile_lin = code >> 2;
+    part = code & 3;
+  }
+  const int bx = (tile_lin % ntx) * TX, by = (tile_lin / ntx) * TY;
   // every global load that depends on no other one is issued before the first LDS store: the own
   // patch class, the x tile, and the operator code and b of this thread's residual nodes
   const int tx0 = threadIdx.x % TX, ty0 = threadIdx.x / TX;
@@ -886,16 +900,12 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
     xv[k] = v;
   }
   int opv[NRES];
-  double bv[NRES][3];
 #pragma unroll
   for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
     const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
     const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
-    const int64_t g = cx + (int64_t)m * cy;
-    opv[k] = ok ? node_op[g] : -1;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : 0.0;
+    opv[k] = ok ? node_op[cx + (int64_t)m * cy] : -1;
   }
   stage_refmats<2, NT>(oc, rm);
 #pragma unroll
@@ -910,6 +920,10 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
       const int cx = bx - 2 + px, cy = by - 2 + py;
       double rv[3] = {0, 0, 0};
       if (cx >= 0 && cx < m && cy >= 0 && cy < m) {
+        const int64_t g = cx + (int64_t)m * cy;
+        double bv[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) bv[f] = b[f * N + g];
         const int xb = (px + 1) + XW * (py + 1);
         double acc[3] = {0, 0, 0};
         // an offset the compiler cannot see through: keeps it from holding the level constants of
@@ -920,7 +934,7 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
         node_row_apply<2>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                           acc);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
+        for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
       }
 #pragma unroll
       for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
@@ -932,29 +946,48 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
   const int64_t node = (bx + tx) + (int64_t)m * (by + ty);
   const int rbase = (tx + 2) + RW * (ty + 2);
   double y[3] = {0, 0, 0};
-  regular_apply<2>(Zcls, cls, [&](int f, const int* o) { return rs[f * RP + rbase + o[0] + RW * o[1]]; }, y);
-  if (cls >= 0) {
+  const int cls_reg = part == 0 ? cls : -1;  // regular patches belong to part 0
+  regular_apply<2>(Zcls, cls_reg, [&](int f, const int* o) { return rs[f * RP + rbase + o[0] + RW * o[1]]; }, y);
+  if (cls_reg >= 0) {
     const int xb = (tx + 3) + XW * (ty + 3);
 #pragma unroll
     for (int f = 0; f < 3; ++f) x_out[f * N + node] = xs[f * XP + xb] + omega * y[f];
   }
-  // irregular patches of the tile: collected in LDS, then 16 lane groups take them in turn
-  if (inside && cls < 0) {
-    const int k = atomicAdd(&irr_cnt, 1);
-    irr_tid[k] = threadIdx.x;
-    irr_pidx[k] = -cls - 1;
+  // Individual patches of the tile, listed in LDS in node order (one segment per wavefront, so
+  // every part of a tile sees the same list); part p takes entries [p CAP, (p + 1) CAP), which 16
+  // lane groups process two patches at a time.
+  if (threadIdx.x < NWO * 64) {
+    const bool irr = inside && cls < 0;
+    const unsigned long long mask = __ballot(irr);
+    const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+    if (irr) {
+      irr_tid[(threadIdx.x & ~63) + pos] = threadIdx.x;
+      irr_pidx[(threadIdx.x & ~63) + pos] = -cls - 1;
+    }
+    if ((threadIdx.x & 63) == 0) irr_wcnt[threadIdx.x >> 6] = __popcll(mask);
   }
   __syncthreads();
-  const int cnt = irr_cnt;
+  int pre[NWO + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int w = 0; w < NWO; ++w) pre[w + 1] = pre[w] + irr_wcnt[w];
+  const int cnt = pre[NWO];
+  auto slot = [&](int e) {
+    int w = 0;
+#pragma unroll
+    for (int k = 1; k < NWO; ++k) w += e >= pre[k] ? 1 : 0;
+    return w * 64 + e - pre[w];
+  };
+  const int lo = part * CAP, hi = min(cnt, lo + CAP);
   const int j16 = threadIdx.x & 15;
-  constexpr int NG = NT / 16;  // lane groups of the workgroup
-  for (int ea = threadIdx.x >> 4; ea < cnt; ea += 2 * NG) {
+  for (int ea = lo + (threadIdx.x >> 4); ea < hi; ea += 2 * NG) {
     const int eb = ea + NG;
-    const bool has_b = eb < cnt;
-    const int ta = irr_tid[ea], tb = has_b ? irr_tid[eb] : ta;
+    const bool has_b = eb < hi;
+    const int sa = slot(ea), sb = has_b ? slot(eb) : sa;
+    const int ta = irr_tid[sa], tb = irr_tid[sb];
     const int rba = (ta % TX + 2) + RW * (ta / TX + 2), rbb = (tb % TX + 2) + RW * (tb / TX + 2);
     double acca[3], accb[3];
-    irregular_pair<2>(Zirr + (int64_t)irr_pidx[ea] * 3 * ZSP, Zirr + (int64_t)irr_pidx[has_b ? eb : ea] * 3 * ZSP,
+    irregular_pair<2>(Zirr + (int64_t)irr_pidx[sa] * 3 * ZSP, Zirr + (int64_t)irr_pidx[sb] * 3 * ZSP,
                       has_b, j16, [&](int field, const int* o) { return rs[field * RP + rba + o[0] + RW * o[1]]; },
                       [&](int field, const int* o) { return rs[field * RP + rbb + o[0] + RW * o[1]]; }, acca, accb);
     if (j16 < 3) {
@@ -973,6 +1006,34 @@ __global__ void __launch_bounds__(NT) sweep_fused2_kernel(const OpConsts* __rest
 // kFusedBigTileNodes on, 8 x 4 by 128 from kFusedMidTileNodes on, 4 x 4 by 128 below.
 constexpr int64_t kFusedBigTileNodes = 200000;
 constexpr int64_t kFusedMidTileNodes = 30000;
+struct Fused2Shape {
+  int tx, ty, nt;
+};
+constexpr Fused2Shape kFusedBig{32, 8, 256}, kFusedMid{8, 4, 128}, kFusedSmall{4, 4, 128};
+Fused2Shape fused2_shape(int64_t N) {
+  return N >= kFusedBigTileNodes ? kFusedBig : (N >= kFusedMidTileNodes ? kFusedMid : kFusedSmall);
+}
+
+// Extra workgroups of the fused 2D sweep: tiles whose individual patches exceed one part (two
+// trips of all 16-lane groups) get parts 1, 2, ... (code tile * 4 + part), appended after the
+// part-0 workgroups of all tiles.
+void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra) {
+  const Fused2Shape sh = fused2_shape(L.N);
+  const int m = L.n + 1;
+  const int ntx = (m + sh.tx - 1) / sh.tx, nty = (m + sh.ty - 1) / sh.ty;
+  const int cap = 4 * (sh.nt / 16);
+  extra.clear();
+  for (int ty = 0; ty < nty; ++ty)
+    for (int tx = 0; tx < ntx; ++tx) {
+      int cnt = 0;
+      for (int j = 0; j < sh.ty; ++j)
+        for (int i = 0; i < sh.tx; ++i) {
+          const int x = tx * sh.tx + i, y = ty * sh.ty + j;
+          if (x < m && y < m && node_class[x + (int64_t)m * y] < 0) ++cnt;
+        }
+      for (int p = 1; p * cap < cnt; ++p) extra.push_back((tx + ntx * ty) * 4 + p);
+    }
+}
 
 template <int D>
 hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
@@ -994,20 +1055,21 @@ hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, doub
   return hipGetLastError();
 }
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, int WPE>
 hipError_t launch_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                          int mode, const double* xc, hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
-  sweep_fused2_kernel<TX, TY, NT><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
-      L.consts, L.node_op, L.nsten, ntx, nty, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega, mode, xc);
+  sweep_fused2_kernel<TX, TY, NT, WPE><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(
+      L.consts, L.node_op, L.nsten, ntx, nty, L.fused_extra, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega, mode, xc);
   return hipGetLastError();
 }
 
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                           int mode, const double* xc, hipStream_t s) {
-  if (L.N >= kFusedBigTileNodes) return launch_fused2<32, 8, 256>(c, L, x_in, b, x_out, mode, xc, s);
-  if (L.N >= kFusedMidTileNodes) return launch_fused2<8, 4, 128>(c, L, x_in, b, x_out, mode, xc, s);
-  return launch_fused2<4, 4, 128>(c, L, x_in, b, x_out, mode, xc, s);
+  constexpr Fused2Shape B = kFusedBig, M = kFusedMid, S = kFusedSmall;
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, 5>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, 5>(c, L, x_in, b, x_out, mode, xc, s);
+  return launch_fused2<S.tx, S.ty, S.nt, 4>(c, L, x_in, b, x_out, mode, xc, s);
 }
 
 // Residual and restriction in one pass (2D, V-cycle): b_c = P^T (b - L x) for a TXC x TYC tile of

@@ -320,3 +320,20 @@ def test_vcycle_bitwise_equals_composed_steps(name):
     xs = dev(x)
     _composed_vcycle(h, p, h.fine, xs, dev(b))
     assert np.array_equal(host(xv), host(xs))
+
+
+def test_config2_fused_bitwise_equals_unfused():
+    # 512^2 level: 32 x 8 tiles, the cut-band tiles split into several workgroups (parts); the
+    # fused pair must still equal two unfused sweeps bit for bit.
+    p = inputs.config2(0)
+    h = fcg().Hierarchy(p, 0)
+    n = h.ndofs()
+    x = inputs.random_vector(n, 61)
+    b = inputs.random_vector(n, 62)
+    xf = dev(x)
+    h.smooth(xf, dev(b), 2)
+    xu = dev(x)
+    h.smooth(xu, dev(b), 1)
+    h.smooth(xu, dev(b), 1)
+    assert np.array_equal(host(xf), host(xu))
+    h.close()
