@@ -75,7 +75,15 @@ typedef struct {
   double nitsche_beta; /* Nitsche parameter: lambda = beta * eta / h_l                         */
   double omega;      /* damping, omega_i = omega * I in Eq. (15)                                */
   double ubar;       /* inflow amplitude, Eq. (16)                                             */
+  int precision;     /* FCGMG_PREC_*: arithmetic of fcgmg_solve's V-cycles                       */
 } fcgmg_params;
+
+/* Precision of fcgmg_solve. FP64: every operation in FP64. MIXED (cache_inverse only): set-up,
+ * including every patch factorisation, stays FP64; the inverse rows, stored stencils and coarse
+ * inverse are then rounded to FP32, and each V-cycle runs in FP32 on the residual equation
+ * A e = r. The outer loop is FP64 iterative refinement: r = b - A x in FP64, e from one FP32
+ * V-cycle with a zero guess, x += e. The single-step calls (smooth, vcycle, ...) stay FP64. */
+enum { FCGMG_PREC_FP64 = 0, FCGMG_PREC_MIXED = 1 };
 
 typedef struct {
   int64_t n_cells_axis;   /* n_l                                                                */
@@ -132,8 +140,14 @@ int fcgmg_coarse_solve(fcgmg_h h, const double* b, double* x, void* stream);
  * coarse correction from a zero guess, prolongation, nu_post sweeps. x updated in place. */
 int fcgmg_vcycle(fcgmg_h h, double* x, const double* b, void* stream);
 
+/* Mixed precision only: e = V(0, r), one V-cycle in FP32 on the residual equation of the finest
+ * level from a zero guess. r (read) and e (written) are FP64 device vectors of the finest level;
+ * r is rounded to FP32 on entry, e widened on exit. E_ARG when the hierarchy is not MIXED. */
+int fcgmg_vcycle_fp32(fcgmg_h h, const double* r, double* e, void* stream);
+
 /* Standalone GMG (Sec. 4): V-cycles until ||b - L x||_2 <= rtol ||b - L x0||_2 (Euclidean norm
- * over all DoFs) or max_iter cycles. Synchronises `stream` once per cycle to read the norm.
+ * over all DoFs) or max_iter cycles; with FCGMG_PREC_MIXED, FP64 iterative refinement around FP32
+ * V-cycles (see FCGMG_PREC_*). Synchronises `stream` once per cycle to read the norm.
  * *iters, *rel_res receive the cycle count and final ratio (also on E_NOCONV / E_NAN).
  * res_hist (optional HOST array of max_iter+1 doubles) receives the residual norms. */
 int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter, int* iters,

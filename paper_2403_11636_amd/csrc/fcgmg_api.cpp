@@ -13,6 +13,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fcgmg_impl.h"
@@ -493,6 +494,21 @@ int setup_impl(Ctx& c, hipStream_t s) {
       L.cached_bytes = (L.n_classes + L.n_irr) * row * sizeof(double);
       FCG_HIP(k_patch_inverse_rows<D>(c, L, L.class_rep, L.n_classes, L.Zcls, s));
       FCG_HIP(k_patch_inverse_rows<D>(c, L, L.irr_nodes, L.n_irr, L.Zirr, s));
+      if (P.precision == FCGMG_PREC_MIXED) {
+        // FP32 copies, rounded from the FP64 factorisations
+        const int64_t nd32 = (D + 1) * L.N;
+        if ((rc = alloc_n(c, &L.Zcls32, L.n_classes * row))) return rc;
+        if ((rc = alloc_n(c, &L.Zirr32, L.n_irr * row))) return rc;
+        if ((rc = alloc_n(c, &L.nsten32, (size_t)L.n_nsten * PT<D>::NSTEN))) return rc;
+        if ((rc = alloc_n(c, &L.r32, nd32))) return rc;
+        if ((rc = alloc_n(c, &L.x32, nd32))) return rc;
+        if ((rc = alloc_n(c, &L.b32, nd32))) return rc;
+        if (D == 2)
+          if ((rc = alloc_n(c, &L.xalt32, nd32))) return rc;
+        FCG_HIP(k_round_to_float(L.Zcls, L.Zcls32, (int64_t)(L.n_classes * row), s));
+        FCG_HIP(k_round_to_float(L.Zirr, L.Zirr32, (int64_t)(L.n_irr * row), s));
+        FCG_HIP(k_round_to_float(L.nsten, L.nsten32, L.n_nsten * PT<D>::NSTEN, s));
+      }
     } else if (P.cache_policy == FCGMG_CACHE_MATRIX) {
       if ((rc = alloc_n(c, &L.Mcls, L.n_classes * (size_t)c.n_pattern))) return rc;
       if ((rc = alloc_n(c, &L.Mirr, L.n_irr * (size_t)c.n_pattern))) return rc;
@@ -544,6 +560,10 @@ int setup_impl(Ctx& c, hipStream_t s) {
     c.coarse_n = nd;
     if ((rc = alloc_n(c, &c.coarse_inv, Ic.size()))) return rc;
     FCG_HIP(hipMemcpyAsync(c.coarse_inv, Ic.data(), Ic.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (P.precision == FCGMG_PREC_MIXED) {
+      if ((rc = alloc_n(c, &c.coarse_inv32, Ic.size()))) return rc;
+      FCG_HIP(k_round_to_float(c.coarse_inv, c.coarse_inv32, (int64_t)Ic.size(), s));
+    }
     FCG_HIP(hipStreamSynchronize(s));
   }
   return FCGMG_OK;
@@ -552,30 +572,36 @@ int setup_impl(Ctx& c, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 // Operations (dimension-dispatched).
 // ---------------------------------------------------------------------------------------------
-template <int D>
-int residual_impl(const Ctx& c, int l, const double* x, const double* b, double* r, hipStream_t s) {
-  return launch(c, FCGMG_K_RESIDUAL, l, s, [&] { return k_residual<D>(c, c.lev[l], x, b, r, s); });
+// T is the value type of the vectors: double for the FP64 operations, float for the V-cycle of the
+// mixed-precision solve (cache_inverse only).
+template <int D, class T = double>
+int residual_impl(const Ctx& c, int l, const T* x, const T* b, T* r, hipStream_t s) {
+  return launch(c, FCGMG_K_RESIDUAL, l, s, [&] { return k_residual<D, T>(c, c.lev[l], x, b, r, s); });
 }
 
-template <int D>
-int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t s);
+template <int D, class T = double>
+int prolong_impl(const Ctx& c, int l, const T* xc, T* xf, hipStream_t s) {
+  return launch(c, FCGMG_K_PROLONG, l, s, [&] { return k_prolong_add<D, T>(c, l, xc, xf, s); });
+}
 
-template <int D>
-int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
+template <int D, class T = double>
+int sweep_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s) {
   const Level& L = c.lev[l];
+  T* r = LV<T>::r(L);
   int rc;
-  if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
+  if ((rc = residual_impl<D, T>(c, l, x, b, r, s))) return rc;
   if (c.prm.cache_policy == FCGMG_CACHE_INVERSE) {
     if (L.n_classes)
-      if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s, [&] { return k_apply_regular<D>(c, L, L.r, x, s); })))
+      if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s, [&] { return k_apply_regular<D, T>(c, L, r, x, s); })))
         return rc;
     if (L.n_irr)
-      if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s, [&] { return k_apply_irregular<D>(c, L, L.r, x, s); })))
+      if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s, [&] { return k_apply_irregular<D, T>(c, L, r, x, s); })))
         return rc;
     return FCGMG_OK;
   }
-  return launch(c, FCGMG_K_PATCH_SOLVE, l, s,
-                [&] { return k_patch_solve<D>(c, L, c.prm.cache_policy, L.r, x, s); });
+  if constexpr (std::is_same<T, double>::value)
+    return launch(c, FCGMG_K_PATCH_SOLVE, l, s, [&] { return k_patch_solve<D>(c, L, c.prm.cache_policy, r, x, s); });
+  return fail(FCGMG_E_ARG, "the FP32 cycle needs the cache_inverse policy");
 }
 
 // `sweeps` sweeps on level l. 2D cache_inverse: pairs of fused sweeps ping-pong between x and the
@@ -583,74 +609,95 @@ int sweep_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s) {
 // `mode` describes x on entry: 0 as given; 1 zero (contents undefined, not read); 2 still to be
 // corrected by the prolongation of the coarse vector xc. The fused pair applies modes 1 and 2 while
 // loading; otherwise x is zeroed or corrected first.
-template <int D>
-int smooth_impl(const Ctx& c, int l, double* x, const double* b, int sweeps, hipStream_t s, int mode = 0,
-                const double* xc = nullptr) {
+template <int D, class T = double>
+int smooth_impl(const Ctx& c, int l, T* x, const T* b, int sweeps, hipStream_t s, int mode = 0,
+                const T* xc = nullptr) {
   const Level& L = c.lev[l];
+  T* xalt = LV<T>::xalt(L);
   int rc;
-  const bool fused = D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && L.xalt;
+  const bool fused = D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && xalt;
   if (mode != 0 && (!fused || sweeps % 2 == 1 || sweeps == 0)) {
     if (mode == 1)
-      rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero(x, (D + 1) * L.N, s); });
+      rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<T>(x, (D + 1) * L.N, s); });
     else
-      rc = prolong_impl<D>(c, l, xc, x, s);
+      rc = prolong_impl<D, T>(c, l, xc, x, s);
     if (rc) return rc;
     mode = 0;
   }
   if (fused) {
     int k = 0;
     if (sweeps % 2 == 1) {
-      if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+      if ((rc = sweep_impl<D, T>(c, l, x, b, s))) return rc;
       k = 1;
     }
     for (; k < sweeps; k += 2) {
       const int md = k == 0 ? mode : 0;
-      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s,
-                       [&] { return k_sweep_fused2(c, L, x, b, L.xalt, md, md == 2 ? xc : nullptr, s); })))
+      const T* xcm = md == 2 ? xc : nullptr;
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2<T>(c, L, x, b, xalt, md, xcm, s); })))
         return rc;
-      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s, [&] { return k_sweep_fused2(c, L, L.xalt, b, x, 0, nullptr, s); })))
+      if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s,
+                       [&] { return k_sweep_fused2<T>(c, L, xalt, b, x, 0, (const T*)nullptr, s); })))
         return rc;
     }
     return FCGMG_OK;
   }
   for (int i = 0; i < sweeps; ++i)
-    if ((rc = sweep_impl<D>(c, l, x, b, s))) return rc;
+    if ((rc = sweep_impl<D, T>(c, l, x, b, s))) return rc;
   return FCGMG_OK;
 }
 
-int coarse_impl(const Ctx& c, const double* b, double* x, hipStream_t s) {
-  return launch(c, FCGMG_K_COARSE, 0, s, [&] { return k_dense_matvec(c.coarse_inv, c.coarse_n, b, x, s); });
+template <class T = double>
+int coarse_impl(const Ctx& c, const T* b, T* x, hipStream_t s) {
+  const T* inv;
+  if constexpr (std::is_same<T, double>::value)
+    inv = c.coarse_inv;
+  else
+    inv = c.coarse_inv32;
+  return launch(c, FCGMG_K_COARSE, 0, s, [&] { return k_dense_matvec<T>(inv, c.coarse_n, b, x, s); });
 }
 
-template <int D>
-int restrict_impl(const Ctx& c, int l, const double* rf, double* bc, hipStream_t s) {
-  return launch(c, FCGMG_K_RESTRICT, l, s, [&] { return k_restrict<D>(c, l, rf, bc, s); });
-}
-
-template <int D>
-int prolong_impl(const Ctx& c, int l, const double* xc, double* xf, hipStream_t s) {
-  return launch(c, FCGMG_K_PROLONG, l, s, [&] { return k_prolong_add<D>(c, l, xc, xf, s); });
+template <int D, class T = double>
+int restrict_impl(const Ctx& c, int l, const T* rf, T* bc, hipStream_t s) {
+  return launch(c, FCGMG_K_RESTRICT, l, s, [&] { return k_restrict<D, T>(c, l, rf, bc, s); });
 }
 
 // One V-cycle on level l (Sec. 3): pre-smoothing, restriction of the residual, the cycle on level
 // l-1 from a zero initial guess, prolongation of its result, post-smoothing. `x_zero`: x holds zero
 // on entry (its contents are not read). The coarsest solve writes every entry of its x.
-template <int D>
-int vcycle_impl(const Ctx& c, int l, double* x, const double* b, hipStream_t s, bool x_zero = false) {
-  if (l == 0) return coarse_impl(c, b, x, s);
+template <int D, class T = double>
+int vcycle_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s, bool x_zero = false) {
+  if (l == 0) return coarse_impl<T>(c, b, x, s);
   int rc;
-  if ((rc = smooth_impl<D>(c, l, x, b, c.prm.nu_pre, s, x_zero ? 1 : 0))) return rc;
+  if ((rc = smooth_impl<D, T>(c, l, x, b, c.prm.nu_pre, s, x_zero ? 1 : 0))) return rc;
   const Level& L = c.lev[l];
   const Level& C = c.lev[l - 1];
+  T* cx = LV<T>::x(C);
+  T* cb = LV<T>::b(C);
   if (D == 2) {
-    if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s, [&] { return k_residual_restrict2(c, L, x, b, C.b, s); })))
+    if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s, [&] { return k_residual_restrict2<T>(c, L, x, b, cb, s); })))
       return rc;
   } else {
-    if ((rc = residual_impl<D>(c, l, x, b, L.r, s))) return rc;
-    if ((rc = restrict_impl<D>(c, l, L.r, C.b, s))) return rc;
+    T* r = LV<T>::r(L);
+    if ((rc = residual_impl<D, T>(c, l, x, b, r, s))) return rc;
+    if ((rc = restrict_impl<D, T>(c, l, r, cb, s))) return rc;
   }
-  if ((rc = vcycle_impl<D>(c, l - 1, C.x, C.b, s, true))) return rc;
-  return smooth_impl<D>(c, l, x, b, c.prm.nu_post, s, 2, C.x);
+  if ((rc = vcycle_impl<D, T>(c, l - 1, cx, cb, s, true))) return rc;
+  return smooth_impl<D, T>(c, l, x, b, c.prm.nu_post, s, 2, cx);
+}
+
+// x += V32(0, r): the FP32 V-cycle on the residual equation of the finest level from a zero guess
+// (mixed precision). r is rounded into the finest level's FP32 right-hand side, the correction
+// widened and added to the FP64 x.
+template <int D>
+int correction_fp32_impl(const Ctx& c, const double* r, double* x, hipStream_t s) {
+  const int top = (int)c.lev.size() - 1;
+  const Level& L = c.lev[top];
+  const int64_t nd = (D + 1) * L.N;
+  FCG_HIP(k_round_to_float(r, L.b32, nd, s));
+  int rc;
+  if ((rc = vcycle_impl<D, float>(c, top, L.x32, L.b32, s, true))) return rc;
+  FCG_HIP(k_add_float(L.x32, x, nd, s));
+  return FCGMG_OK;
 }
 
 int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {
@@ -698,6 +745,10 @@ int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_ba
     return fail(FCGMG_E_ARG, "grid too large for 32-bit node indices");
   if (P.quad_depth < 0 || P.quad_depth > 7) return fail(FCGMG_E_ARG, "quad_depth must be in [0,7]");
   if (P.cache_policy < 0 || P.cache_policy > 2) return fail(FCGMG_E_ARG, "unknown cache policy");
+  if (P.precision != FCGMG_PREC_FP64 && P.precision != FCGMG_PREC_MIXED)
+    return fail(FCGMG_E_ARG, "unknown precision");
+  if (P.precision == FCGMG_PREC_MIXED && P.cache_policy != FCGMG_CACHE_INVERSE)
+    return fail(FCGMG_E_ARG, "mixed precision needs the cache_inverse policy");
   if (!(P.eta > 0) || !(P.alpha_fict >= 0) || !(P.nitsche_beta > 0) || !std::isfinite(P.omega))
     return fail(FCGMG_E_ARG, "eta, nitsche_beta must be > 0, alpha_fict >= 0, omega finite");
   if (P.nu_pre < 0 || P.nu_post < 0) return fail(FCGMG_E_ARG, "negative smoothing steps");
@@ -794,6 +845,15 @@ int fcgmg_vcycle(fcgmg_h h, double* x, const double* b, void* stream) {
   return h->prm.dim == 2 ? vcycle_impl<2>(*h, top, x, b, s) : vcycle_impl<3>(*h, top, x, b, s);
 }
 
+int fcgmg_vcycle_fp32(fcgmg_h h, const double* r, double* e, void* stream) {
+  if (!h || !r || !e) return fail(FCGMG_E_ARG, "null argument");
+  if (h->prm.precision != FCGMG_PREC_MIXED) return fail(FCGMG_E_ARG, "hierarchy not set up for mixed precision");
+  hipStream_t s = (hipStream_t)stream;
+  const Level& L = h->lev.back();
+  FCG_HIP(k_zero<double>(e, (h->prm.dim + 1) * L.N, s));
+  return h->prm.dim == 2 ? correction_fp32_impl<2>(*h, r, e, s) : correction_fp32_impl<3>(*h, r, e, s);
+}
+
 int fcgmg_norm(fcgmg_h h, int level, const double* v, double* out, void* stream) {
   if (!valid_level(h, level) || !v || !out) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
   return norm_impl(*h, v, (h->prm.dim + 1) * h->lev[level].N, out, (hipStream_t)stream);
@@ -817,8 +877,13 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
   if (res_hist) res_hist[0] = r0;
   if (!std::isfinite(r0)) return fail(FCGMG_E_NAN, "non-finite initial residual");
   if (r0 == 0.0) return FCGMG_OK;
+  const bool mixed = h->prm.precision == FCGMG_PREC_MIXED;
   for (int it = 1; it <= max_iter; ++it) {
-    if ((rc = fcgmg_vcycle(h, x, b, stream))) return rc;
+    if (mixed)  // FP64 iterative refinement: L.r holds b - L x of the current iterate
+      rc = h->prm.dim == 2 ? correction_fp32_impl<2>(*h, L.r, x, s) : correction_fp32_impl<3>(*h, L.r, x, s);
+    else
+      rc = fcgmg_vcycle(h, x, b, stream);
+    if (rc) return rc;
     if ((rc = h->prm.dim == 2 ? residual_impl<2>(*h, top, x, b, L.r, s) : residual_impl<3>(*h, top, x, b, L.r, s)))
       return rc;
     double rn;

@@ -118,6 +118,39 @@ struct Level {
   double* b = nullptr;        // V-cycle right-hand side (levels below the finest)
   double* xalt = nullptr;     // second iterate buffer of the fused 2D sweep
   size_t cached_bytes = 0;
+  // FP32 copies for the mixed-precision V-cycle (cache_inverse, FCGMG_PREC_MIXED): inverse rows and
+  // stored stencils rounded from the FP64 set-up, and the level vectors of the FP32 cycle
+  float* Zcls32 = nullptr;
+  float* Zirr32 = nullptr;
+  float* nsten32 = nullptr;
+  float* r32 = nullptr;
+  float* x32 = nullptr;
+  float* b32 = nullptr;
+  float* xalt32 = nullptr;
+};
+
+// The level data a kernel of value type T reads and writes.
+template <class T>
+struct LV;
+template <>
+struct LV<double> {
+  static const double* Zcls(const Level& L) { return L.Zcls; }
+  static const double* Zirr(const Level& L) { return L.Zirr; }
+  static const double* nsten(const Level& L) { return L.nsten; }
+  static double* r(const Level& L) { return L.r; }
+  static double* x(const Level& L) { return L.x; }
+  static double* b(const Level& L) { return L.b; }
+  static double* xalt(const Level& L) { return L.xalt; }
+};
+template <>
+struct LV<float> {
+  static const float* Zcls(const Level& L) { return L.Zcls32; }
+  static const float* Zirr(const Level& L) { return L.Zirr32; }
+  static const float* nsten(const Level& L) { return L.nsten32; }
+  static float* r(const Level& L) { return L.r32; }
+  static float* x(const Level& L) { return L.x32; }
+  static float* b(const Level& L) { return L.b32; }
+  static float* xalt(const Level& L) { return L.xalt32; }
 };
 
 struct Ctx {
@@ -126,6 +159,7 @@ struct Ctx {
   double* balls = nullptr;
   std::vector<Level> lev;
   double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (ndof x ndof)
+  float* coarse_inv32 = nullptr; // its FP32 rounding (mixed precision)
   int coarse_n = 0;
   bool bordered = false;
   double* red = nullptr;         // reduction scratch
@@ -308,29 +342,38 @@ template <int D> hipError_t k_classify_cells(const Ctx& c, Level& L, signed char
 template <int D> hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStream_t s);
 template <int D> hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipStream_t s);
 template <int D> hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s);
-template <int D> hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const double* b, double* r,
-                                       hipStream_t s);
+template <int D, class T>
+hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s);
 template <int D> hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count,
                                                  double* Z, hipStream_t s);
-template <int D> hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s);
-template <int D> hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x,
-                                             hipStream_t s);
-hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                          int mode, const double* xc, hipStream_t s);
+template <int D, class T>
+hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
+template <int D, class T>
+hipError_t k_apply_irregular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
+template <class T>
+hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
+                          hipStream_t s);
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra);
-hipError_t k_residual_restrict2(const Ctx& c, const Level& F, const double* x, const double* b, double* bc,
-                                hipStream_t s);
+template <class T>
+hipError_t k_residual_restrict2(const Ctx& c, const Level& F, const T* x, const T* b, T* bc, hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,
                                           hipStream_t s);
 template <int D> hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int64_t count,
                                              double* M, hipStream_t s);
 template <int D> hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hipStream_t s);
-template <int D> hipError_t k_restrict(const Ctx& c, int fine, const double* rf, double* bc, hipStream_t s);
-template <int D> hipError_t k_prolong_add(const Ctx& c, int fine, const double* xc, double* xf, hipStream_t s);
-hipError_t k_dense_matvec(const double* A, int n, const double* b, double* x, hipStream_t s);
+template <int D, class T>
+hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s);
+template <int D, class T>
+hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s);
+template <class T>
+hipError_t k_dense_matvec(const T* A, int n, const T* b, T* x, hipStream_t s);
 hipError_t k_sumsq(const double* v, int64_t n, double* partial, int nblocks, hipStream_t s);
 hipError_t k_finish_sumsq(const double* partial, int nblocks, double* out, hipStream_t s);
-hipError_t k_zero(double* v, int64_t n, hipStream_t s);
+template <class T>
+hipError_t k_zero(T* v, int64_t n, hipStream_t s);
+// dst = (float) src / dst += (double) src, n values
+hipError_t k_round_to_float(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t k_add_float(const float* src, double* dst, int64_t n, hipStream_t s);
 template <int D> int pattern_size();
 template <int D> void pattern_entries(std::vector<int>& enc);
 

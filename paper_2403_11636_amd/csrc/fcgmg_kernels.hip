@@ -10,15 +10,17 @@
 
 namespace fcg {
 
-// Pointer into the constant address space: loads with a wavefront-uniform address from it are
-// issued as scalar loads into SGPRs.
-typedef __attribute__((address_space(4))) const double cdouble;
+// Value in the constant address space: loads with a wavefront-uniform address from it are issued
+// as scalar loads into SGPRs.
+template <class T>
+using cconst = __attribute__((address_space(4))) const T;
 
 namespace {
 
 constexpr int kMaxLocalBalls = 16;
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
   return v;
 }
@@ -262,22 +264,22 @@ __device__ __forceinline__ void tile_coords(int bid, const int* nt, int* t) {
 // Reference element matrices of a level (uncut physical cell; fictitious cells scale K and B by
 // alpha_f), the stabilisation block and the Nitsche face matrices, packed for one dimension. The
 // kernels copy them into LDS once per workgroup: the node loops then read only LDS.
-template <int D>
+template <int D, class T = double>
 struct RefMats : RefLayout<D> {
-  double v[RefLayout<D>::TOT];
+  T v[RefLayout<D>::TOT];
   int dir[2 * D];
 };
 
-// Cooperative copy of the level constants into LDS by a workgroup of NT threads: every load is
-// issued before the first store (caller synchronises afterwards).
-template <int D, int NT>
-__device__ __forceinline__ void stage_refmats(const OpConsts* __restrict__ oc, RefMats<D>& rm) {
+// Cooperative copy of the level constants into LDS by a workgroup of NT threads, rounded to T:
+// every load is issued before the first store (caller synchronises afterwards).
+template <int D, int NT, class T>
+__device__ __forceinline__ void stage_refmats(const OpConsts* __restrict__ oc, RefMats<D, T>& rm) {
   constexpr int TOT = RefLayout<D>::TOT, NK = (TOT + NT - 1) / NT;
-  double v[NK];
+  T v[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
     const int i = threadIdx.x + NT * k;
-    v[k] = i < TOT ? oc->pack[i] : 0.0;
+    v[k] = i < TOT ? (T)oc->pack[i] : T(0);
   }
   const int dv = threadIdx.x < 2 * D ? oc->dirichlet[threadIdx.x] : 0;
 #pragma unroll
@@ -371,16 +373,16 @@ __device__ __forceinline__ void node_apply(const RefMats<D>& rm, CI&& ci, CP&& c
 
 // acc[f] += sum over the 3^d offsets o of the node stencil applied to x around the node; cf(j, o) is
 // the coefficient of block j (layout of Level::nsten), xat(f, o) the value x_f at the node + o.
-template <int D, bool UNR, class CF, class XA>
-__device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, double* acc) {
+template <int D, bool UNR, class T, class CF, class XA>
+__device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, T* acc) {
   constexpr int NS = PT<D>::NST;
 #pragma unroll(UNR ? NS : 3)
   for (int o = 0; o < NS; ++o) {
     const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, D == 3 ? o / 9 - 1 : 0};
-    double u[D + 1];
+    T u[D + 1];
 #pragma unroll
     for (int f = 0; f <= D; ++f) u[f] = xat(f, oo);
-    const double sk = cf(0, o);
+    const T sk = cf(0, o);
 #pragma unroll
     for (int f = 0; f < D; ++f) {
       acc[f] += sk * u[f] + cf(1 + f, o) * u[D];
@@ -392,14 +394,14 @@ __device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, double* acc) {
 
 // Row of L at a node with operator code op (Level::node_op): the level's reference stencil of a
 // uniform neighbourhood (staged in rm) or the node's own assembled stencil in nsten.
-template <int D, bool UNR = true, class XA>
-__device__ __forceinline__ void node_row_apply(const RefMats<D>& rm, int op, const double* __restrict__ nsten,
-                                               XA&& xat, double* acc) {
+template <int D, bool UNR = true, class T, class XA>
+__device__ __forceinline__ void node_row_apply(const RefMats<D, T>& rm, int op, const T* __restrict__ nsten,
+                                               XA&& xat, T* acc) {
   using R = RefLayout<D>;
   constexpr int NS = PT<D>::NST;
   if (op < 0) {
     const int kind = -op - 1;
-    stencil_apply<D, UNR>(
+    stencil_apply<D, UNR, T>(
         [&](int j, int o) {
           if (j == 0) return rm.v[R::oSK + kind * NS + o];
           if (j <= D) return rm.v[R::oSB + (kind * D + j - 1) * NS + o];
@@ -410,8 +412,8 @@ __device__ __forceinline__ void node_row_apply(const RefMats<D>& rm, int op, con
   } else {
     // the stored row streams from memory: the loop over offsets stays partly rolled so that its
     // loads do not all occupy registers at once
-    const double* p = nsten + (int64_t)op * PT<D>::NSTEN;
-    stencil_apply<D, false>([&](int j, int o) { return p[j * NS + o]; }, xat, acc);
+    const T* p = nsten + (int64_t)op * PT<D>::NSTEN;
+    stencil_apply<D, false, T>([&](int j, int o) { return p[j * NS + o]; }, xat, acc);
   }
 }
 
@@ -425,7 +427,7 @@ __global__ void __launch_bounds__(256) node_stencil_kernel(const OpConsts* __res
                                                           double* __restrict__ nsten) {
   constexpr int NS = PT<D>::NST;
   __shared__ RefMats<D> rm;
-  stage_refmats<D, 256>(oc, rm);
+  stage_refmats<D, 256, double>(oc, rm);
   __syncthreads();
   const int64_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -468,17 +470,17 @@ hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipSt
   return hipGetLastError();
 }
 
-template <int D>
+template <int D, class T>
 __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __restrict__ oc,
                                                            const int* __restrict__ node_op,
-                                                           const double* __restrict__ nsten, int ntx, int nty,
-                                                           int ntz, const double* __restrict__ x,
-                                                           const double* __restrict__ b, double* __restrict__ r) {
+                                                           const T* __restrict__ nsten, int ntx, int nty, int ntz,
+                                                           const T* __restrict__ x, const T* __restrict__ b,
+                                                           T* __restrict__ r) {
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
   constexpr int NXL = ((D + 1) * XP + 255) / 256;
-  __shared__ double xs[(D + 1) * XP];
-  __shared__ RefMats<D> rm;
+  __shared__ T xs[(D + 1) * XP];
+  __shared__ RefMats<D, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
@@ -491,30 +493,30 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   const bool inside = c[0] < m && c[1] < m && (D == 2 || c[2] < m);
   const int64_t node = D == 2 ? c[0] + (int64_t)m * c[1] : c[0] + (int64_t)m * (c[1] + (int64_t)m * c[2]);
   // every global load of the tile is issued before the first LDS store
-  double bv[D + 1];
+  T bv[D + 1];
 #pragma unroll
-  for (int f = 0; f <= D; ++f) bv[f] = inside ? b[f * N + node] : 0.0;
+  for (int f = 0; f <= D; ++f) bv[f] = inside ? b[f * N + node] : T(0);
   const int op = inside ? node_op[node] : -1;
-  double xv[NXL];
+  T xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
     const int e = threadIdx.x + 256 * k;
     const int f = e / XP, p = e % XP;
     const int gx = o0 + p % XW, gy = o1 + (p / XW) % XH, gz = D == 3 ? o2 + p / (XW * XH) : 0;
     const bool ok = e < (D + 1) * XP && gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m));
-    xv[k] = ok ? x[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))] : 0.0;
+    xv[k] = ok ? x[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))] : T(0);
   }
-  stage_refmats<D, 256>(oc, rm);
+  stage_refmats<D, 256, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + 256 * k < (D + 1) * XP) xs[threadIdx.x + 256 * k] = xv[k];
   __syncthreads();
   if (!inside) return;
   const int base = (tx + 1) + XW * ((ty + 1) + XH * (tz + 1) * (D == 3 ? 1 : 0));
-  double acc[D + 1];
+  T acc[D + 1];
 #pragma unroll
   for (int f = 0; f <= D; ++f) acc[f] = 0;
-  node_row_apply<D>(rm, op, nsten,
+  node_row_apply<D, true, T>(rm, op, nsten,
                     [&](int f, const int* o) {
                       return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];
                     },
@@ -530,13 +532,13 @@ void tile_grid(int n, int* nt) {
   nt[2] = D == 3 ? (n + 1 + TileShape<D>::TZ - 1) / TileShape<D>::TZ : 1;
 }
 
-template <int D>
-hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const double* b, double* r, hipStream_t s) {
+template <int D, class T>
+hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s) {
   int nt[3];
   tile_grid<D>(L.n, nt);
   const int nb = nt[0] * nt[1] * nt[2];
-  residual_tile_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.node_op, L.nsten, nt[0], nt[1],
-                                                                    nt[2], x, b, r);
+  residual_tile_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.node_op, LV<T>::nsten(L), nt[0],
+                                                                       nt[1], nt[2], x, b, r);
   return hipGetLastError();
 }
 
@@ -546,17 +548,17 @@ hipError_t k_residual(const Ctx& c, const Level& L, const double* x, const doubl
 // ================================================================================================
 // b_c at coarse node `node` = sum of the fine residuals around fine node 2*node, weights 1/2 per
 // offset axis (R = P^T).
-template <int D>
-__device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ rf,
-                                              double* __restrict__ bc, int64_t node) {
+template <int D, class T>
+__device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ rf,
+                                              T* __restrict__ bc, int64_t node) {
   int c[3];
   node_coords<D>(node, nc, c);
-  double acc[D + 1];
+  T acc[D + 1];
   for (int f = 0; f <= D; ++f) acc[f] = 0;
   constexpr int NO = D == 2 ? 9 : 27;
   for (int o = 0; o < NO; ++o) {
     int fc[3] = {0, 0, 0};
-    double w = 1;
+    T w = 1;
     bool in = true;
     int t = o;
     for (int k = 0; k < D; ++k) {
@@ -574,13 +576,12 @@ __device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_
 }
 
 // Q1 interpolation of field f of the coarse vector xc at the fine node with coordinates c.
-template <int D>
-__device__ __forceinline__ double prolong_value(int nc, int64_t Nc, const double* __restrict__ xc, const int* c,
-                                                int f) {
-  double acc = 0;
+template <int D, class T>
+__device__ __forceinline__ T prolong_value(int nc, int64_t Nc, const T* __restrict__ xc, const int* c, int f) {
+  T acc = 0;
   for (int t = 0; t < (1 << D); ++t) {
     int cc[3] = {0, 0, 0};
-    double w = 1;
+    T w = 1;
     bool valid = true;
     for (int k = 0; k < D; ++k) {
       const int bit = (t >> k) & 1;
@@ -599,43 +600,43 @@ __device__ __forceinline__ double prolong_value(int nc, int64_t Nc, const double
 }
 
 // x_f at fine node `node` += Q1 interpolation of the coarse correction.
-template <int D>
-__device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
-                                             double* __restrict__ xf, int64_t node) {
+template <int D, class T>
+__device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ xc,
+                                             T* __restrict__ xf, int64_t node) {
   int c[3];
   node_coords<D>(node, nf, c);
-  for (int f = 0; f <= D; ++f) xf[f * Nf + node] += prolong_value<D>(nc, Nc, xc, c, f);
+  for (int f = 0; f <= D; ++f) xf[f * Nf + node] += prolong_value<D, T>(nc, Nc, xc, c, f);
 }
 
-template <int D>
-__global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ rf,
-                                double* __restrict__ bc) {
+template <int D, class T>
+__global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ rf,
+                                T* __restrict__ bc) {
   const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (node < Nc) restrict_node<D>(nf, Nf, nc, Nc, rf, bc, node);
+  if (node < Nc) restrict_node<D, T>(nf, Nf, nc, Nc, rf, bc, node);
 }
 
-template <int D>
-__global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const double* __restrict__ xc,
-                                   double* __restrict__ xf) {
+template <int D, class T>
+__global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ xc,
+                                   T* __restrict__ xf) {
   const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (node < Nf) prolong_node<D>(nf, Nf, nc, Nc, xc, xf, node);
+  if (node < Nf) prolong_node<D, T>(nf, Nf, nc, Nc, xc, xf, node);
 }
 
-template <int D>
-hipError_t k_restrict(const Ctx& c, int fine, const double* rf, double* bc, hipStream_t s) {
+template <int D, class T>
+hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s) {
   const Level& F = c.lev[fine];
   const Level& C = c.lev[fine - 1];
   const int bs = 256;
-  restrict_kernel<D><<<dim3((unsigned)((C.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, rf, bc);
+  restrict_kernel<D, T><<<dim3((unsigned)((C.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, rf, bc);
   return hipGetLastError();
 }
 
-template <int D>
-hipError_t k_prolong_add(const Ctx& c, int fine, const double* xc, double* xf, hipStream_t s) {
+template <int D, class T>
+hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s) {
   const Level& F = c.lev[fine];
   const Level& C = c.lev[fine - 1];
   const int bs = 256;
-  prolong_add_kernel<D><<<dim3((unsigned)((F.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, xc, xf);
+  prolong_add_kernel<D, T><<<dim3((unsigned)((F.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, xc, xf);
   return hipGetLastError();
 }
 
@@ -736,22 +737,24 @@ hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hip
 
 // x = A b with a dense row-major n x n matrix (coarsest-grid solve through the stored inverse):
 // one wavefront per row.
-__device__ __forceinline__ void dense_row(const double* __restrict__ A, int n, const double* __restrict__ b,
-                                          double* __restrict__ x, int row, int lane) {
-  double s = 0;
+template <class T>
+__device__ __forceinline__ void dense_row(const T* __restrict__ A, int n, const T* __restrict__ b, T* __restrict__ x,
+                                          int row, int lane) {
+  T s = 0;
   for (int j = lane; j < n; j += 64) s += A[(int64_t)row * n + j] * b[j];
   s = wave_sum(s);
   if (lane == 0) x[row] = s;
 }
 
-__global__ void dense_matvec_kernel(const double* __restrict__ A, int n, const double* __restrict__ b,
-                                    double* __restrict__ x) {
+template <class T>
+__global__ void dense_matvec_kernel(const T* __restrict__ A, int n, const T* __restrict__ b, T* __restrict__ x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row < n) dense_row(A, n, b, x, row, threadIdx.x & 63);
 }
 
-hipError_t k_dense_matvec(const double* A, int n, const double* b, double* x, hipStream_t s) {
-  dense_matvec_kernel<<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(A, n, b, x);
+template <class T>
+hipError_t k_dense_matvec(const T* A, int n, const T* b, T* x, hipStream_t s) {
+  dense_matvec_kernel<T><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(A, n, b, x);
   return hipGetLastError();
 }
 
@@ -789,16 +792,44 @@ hipError_t k_finish_sumsq(const double* partial, int nblocks, double* out, hipSt
   return hipGetLastError();
 }
 
-__global__ void zero_kernel(double* v, int64_t n) {
+template <class T>
+__global__ void zero_kernel(T* v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = 0.0;
+    v[i] = T(0);
 }
 
-hipError_t k_zero(double* v, int64_t n, hipStream_t s) {
+static unsigned stream_blocks(int64_t n) {
   int64_t nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
-  zero_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(v, n);
+  return (unsigned)nb;
+}
+
+template <class T>
+hipError_t k_zero(T* v, int64_t n, hipStream_t s) {
+  zero_kernel<T><<<dim3(stream_blocks(n)), dim3(256), 0, s>>>(v, n);
+  return hipGetLastError();
+}
+
+// Precision conversions of the mixed-precision solve: the FP64 residual rounded to FP32 for the FP32
+// V-cycle, and its FP32 correction added to the FP64 iterate.
+__global__ void round_to_float_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+__global__ void add_float_kernel(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += (double)src[i];
+}
+
+hipError_t k_round_to_float(const double* src, float* dst, int64_t n, hipStream_t s) {
+  round_to_float_kernel<<<dim3(stream_blocks(n)), dim3(256), 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t k_add_float(const float* src, double* dst, int64_t n, hipStream_t s) {
+  add_float_kernel<<<dim3(stream_blocks(n)), dim3(256), 0, s>>>(src, dst, n);
   return hipGetLastError();
 }
 
@@ -811,16 +842,23 @@ namespace fcg {
   template hipError_t k_classify_cells<D>(const Ctx&, Level&, signed char*, hipStream_t);                     \
   template hipError_t k_cut_matrices<D>(const Ctx&, Level&, const int*, hipStream_t);                         \
   template hipError_t k_rhs<D>(const Ctx&, const Level&, double*, hipStream_t);                               \
-  template hipError_t k_residual<D>(const Ctx&, const Level&, const double*, const double*, double*,           \
-                                    hipStream_t);                                                             \
+  template hipError_t k_residual<D, double>(const Ctx&, const Level&, const double*, const double*, double*,   \
+                                            hipStream_t);                                                     \
+  template hipError_t k_residual<D, float>(const Ctx&, const Level&, const float*, const float*, float*,       \
+                                           hipStream_t);                                                      \
   template hipError_t k_node_stencils<D>(const Ctx&, const Level&, const int*, hipStream_t);                  \
-  template hipError_t k_restrict<D>(const Ctx&, int, const double*, double*, hipStream_t);                    \
-  template hipError_t k_prolong_add<D>(const Ctx&, int, const double*, double*, hipStream_t);                 \
+  template hipError_t k_restrict<D, double>(const Ctx&, int, const double*, double*, hipStream_t);            \
+  template hipError_t k_restrict<D, float>(const Ctx&, int, const float*, float*, hipStream_t);               \
+  template hipError_t k_prolong_add<D, double>(const Ctx&, int, const double*, double*, hipStream_t);         \
+  template hipError_t k_prolong_add<D, float>(const Ctx&, int, const float*, float*, hipStream_t);            \
   template hipError_t k_coarse_matrix<D>(const Ctx&, const Level&, double*, int, hipStream_t);                \
   template hipError_t k_patch_inverse_rows<D>(const Ctx&, const Level&, const int*, int64_t, double*,         \
                                               hipStream_t);                                                   \
-  template hipError_t k_apply_regular<D>(const Ctx&, const Level&, const double*, double*, hipStream_t);      \
-  template hipError_t k_apply_irregular<D>(const Ctx&, const Level&, const double*, double*, hipStream_t);    \
+  template hipError_t k_apply_regular<D, double>(const Ctx&, const Level&, const double*, double*, hipStream_t); \
+  template hipError_t k_apply_regular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t);  \
+  template hipError_t k_apply_irregular<D, double>(const Ctx&, const Level&, const double*, double*,          \
+                                                   hipStream_t);                                              \
+  template hipError_t k_apply_irregular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t); \
   template hipError_t k_patch_solve<D>(const Ctx&, const Level&, int, const double*, double*, hipStream_t);  \
   template hipError_t k_store_matrices<D>(const Ctx&, const Level&, const int*, int64_t, double*,             \
                                           hipStream_t);                                                       \
@@ -829,4 +867,13 @@ namespace fcg {
 FCG_INST(2)
 FCG_INST(3)
 #undef FCG_INST
+#define FCG_INST_T(T)                                                                                         \
+  template hipError_t k_sweep_fused2<T>(const Ctx&, const Level&, const T*, const T*, T*, int, const T*,       \
+                                        hipStream_t);                                                         \
+  template hipError_t k_residual_restrict2<T>(const Ctx&, const Level&, const T*, const T*, T*, hipStream_t);   \
+  template hipError_t k_dense_matvec<T>(const T*, int, const T*, T*, hipStream_t);                            \
+  template hipError_t k_zero<T>(T*, int64_t, hipStream_t);
+FCG_INST_T(double)
+FCG_INST_T(float)
+#undef FCG_INST_T
 }  // namespace fcg

@@ -640,15 +640,15 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
 
 // y[f] += Z[f,:] . g for a regular patch; rt(f, o) = r_f at the centre node + o. P is a pointer to
 // the rows in the constant address space (scalar loads) or the global one (per-lane loads).
-template <int D, bool UNR, class P, class RA>
-__device__ __forceinline__ void regular_rows(P Z, RA&& rt, double* y) {
+template <int D, bool UNR, class T, class P, class RA>
+__device__ __forceinline__ void regular_rows(P Z, RA&& rt, T* y) {
   constexpr int NV = PT<D>::NV, NP = PT<D>::NP, ZSP = PT<D>::ZSP;
 #pragma unroll
   for (int cmp = 0; cmp < D; ++cmp) {
 #pragma unroll(UNR ? NV : 5)
     for (int v = 0; v < NV; ++v) {
       const int o[3] = {v % 5 - 2, (v / 5) % 5 - 2, D == 3 ? v / 25 - 2 : 0};
-      const double gv = rt(cmp, o);
+      const T gv = rt(cmp, o);
 #pragma unroll
       for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + cmp * NV + v] * gv;
     }
@@ -656,7 +656,7 @@ __device__ __forceinline__ void regular_rows(P Z, RA&& rt, double* y) {
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     const int o[3] = {q % 3 - 1, (q / 3) % 3 - 1, D == 3 ? q / 9 - 1 : 0};
-    const double gv = rt(D, o);
+    const T gv = rt(D, o);
 #pragma unroll
     for (int f = 0; f <= D; ++f) y[f] += Z[f * ZSP + D * NV + q] * gv;
   }
@@ -665,8 +665,8 @@ __device__ __forceinline__ void regular_rows(P Z, RA&& rt, double* y) {
 // Regular patches of a wavefront: a waterfall over the classes present (at most two per level:
 // interior physical and interior fictitious), each applied with scalar loads of its rows. Lanes
 // with cls < 0 take no part.
-template <int D, bool UNR = true, class RA>
-__device__ __forceinline__ void regular_apply(const double* __restrict__ Zcls, int cls, RA&& rt, double* y) {
+template <int D, bool UNR = true, class T, class RA>
+__device__ __forceinline__ void regular_apply(const T* __restrict__ Zcls, int cls, RA&& rt, T* y) {
   constexpr int ZSP = PT<D>::ZSP;
   bool todo = cls >= 0;
   while (__ballot(todo) != 0) {
@@ -676,7 +676,7 @@ __device__ __forceinline__ void regular_apply(const double* __restrict__ Zcls, i
         // read the lane value again inside the branch: the compiler would otherwise substitute the
         // (equal, per-lane) cls for c0 and lose the scalar address
         const int cu = __builtin_amdgcn_readfirstlane(cls);
-        regular_rows<D, UNR>((const cdouble*)(Zcls + (int64_t)cu * (D + 1) * ZSP), rt, y);
+        regular_rows<D, UNR, T>((cconst<T>*)(Zcls + (int64_t)cu * (D + 1) * ZSP), rt, y);
         todo = false;
       }
     }
@@ -707,27 +707,27 @@ __device__ __forceinline__ void patch_column(int col, int* field, int* o) {
 // lane of the group returns the full sums. A wavefront holds 4 groups and each group takes two
 // patches at once (A, B), so the rows of 8 patches stream from HBM per wavefront and loop trip.
 // The arithmetic of each patch does not depend on which patch it is paired with.
-template <int D, class RGA, class RGB>
-__device__ __forceinline__ void irregular_pair(const double* __restrict__ ZA, const double* __restrict__ ZB,
-                                               bool has_b, int j16, RGA&& rga, RGB&& rgb, double* acca,
-                                               double* accb) {
+template <int D, class T, class RGA, class RGB>
+__device__ __forceinline__ void irregular_pair(const T* __restrict__ ZA, const T* __restrict__ ZB,
+                                               bool has_b, int j16, RGA&& rga, RGB&& rgb, T* acca,
+                                               T* accb) {
   constexpr int ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
 #pragma unroll
   for (int f = 0; f <= D; ++f) acca[f] = accb[f] = 0;
-  const double* ZBs = has_b ? ZB : ZA;
+  const T* ZBs = has_b ? ZB : ZA;
   // 2D: the four column steps are unrolled so that all row loads are in flight at once
 #pragma unroll(D == 2 ? 4 : 2)
   for (int col = j16; col < ZS; col += 16) {
     int field, o[3];
     patch_column<D>(col, &field, o);
-    double za[D + 1], zb[D + 1];
+    T za[D + 1], zb[D + 1];
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
       za[f] = ZA[f * ZSP + col];
       zb[f] = ZBs[f * ZSP + col];
     }
-    const double ga = rga(field, o);
-    const double gb = has_b ? rgb(field, o) : 0.0;
+    const T ga = rga(field, o);
+    const T gb = has_b ? rgb(field, o) : T(0);
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
       acca[f] += za[f] * ga;
@@ -743,16 +743,16 @@ __device__ __forceinline__ void irregular_pair(const double* __restrict__ ZA, co
     }
 }
 
-template <int D>
+template <int D, class T>
 __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int nty, int ntz,
                                                             const int* __restrict__ node_class,
-                                                            const double* __restrict__ Zcls,
-                                                            const double* __restrict__ r, double* __restrict__ x,
-                                                            double omega) {
+                                                            const T* __restrict__ Zcls,
+                                                            const T* __restrict__ r, T* __restrict__ x,
+                                                            T omega) {
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int HX = TX + 4, HY = TY + 4, HZ = D == 3 ? TZ + 4 : 1;
   constexpr int PLANE = HX * HY * HZ;
-  __shared__ double rt[(D + 1) * PLANE];
+  __shared__ T rt[(D + 1) * PLANE];
   const int m = n + 1;
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
   const int nt[3] = {ntx, nty, ntz};
@@ -762,7 +762,7 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
   for (int e = threadIdx.x; e < (D + 1) * PLANE; e += 256) {
     const int f = e / PLANE, p = e % PLANE;
     const int gx = ox + p % HX, gy = oy + (p / HX) % HY, gz = D == 3 ? oz + p / (HX * HY) : 0;
-    double v = 0;
+    T v = 0;
     if (gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m)))
       v = r[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))];
     rt[e] = v;
@@ -774,10 +774,10 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
   const int64_t node = D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz);
   const int cls = inside ? node_class[node] : -1;
   const int base = tx + 2 + HX * (ty + 2 + (D == 3 ? HY * (tz + 2) : 0));
-  double y[D + 1];
+  T y[D + 1];
 #pragma unroll
   for (int f = 0; f <= D; ++f) y[f] = 0;
-  regular_apply<D>(Zcls, cls, [&](int f, const int* o) {
+  regular_apply<D, true, T>(Zcls, cls, [&](int f, const int* o) {
     return rt[f * PLANE + base + o[0] + HX * (o[1] + (D == 3 ? HY * o[2] : 0))];
   }, y);
   if (cls >= 0)
@@ -785,11 +785,11 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
     for (int f = 0; f <= D; ++f) x[f * N + node] += omega * y[f];
 }
 
-template <int D>
+template <int D, class T>
 __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nirr, const int* __restrict__ irr_nodes,
-                                                              const double* __restrict__ Zirr,
-                                                              const double* __restrict__ r, double* __restrict__ x,
-                                                              double omega) {
+                                                              const T* __restrict__ Zirr,
+                                                              const T* __restrict__ r, T* __restrict__ x,
+                                                              T omega) {
   constexpr int ZSP = PT<D>::ZSP;
   const int j16 = threadIdx.x & 15;
   const int m = n + 1;
@@ -806,14 +806,14 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
       bool in = true;
       for (int k = 0; k < D; ++k) in = in && cc[k] >= 0 && cc[k] < m;
       return in ? r[field * N + (D == 2 ? cc[0] + (int64_t)m * cc[1] : cc[0] + (int64_t)m * (cc[1] + (int64_t)m * cc[2]))]
-                : 0.0;
+                : T(0);
     };
-    double acca[D + 1], accb[D + 1];
-    irregular_pair<D>(Zirr + pa * (int64_t)(D + 1) * ZSP, Zirr + (has_b ? pb : pa) * (int64_t)(D + 1) * ZSP, has_b,
+    T acca[D + 1], accb[D + 1];
+    irregular_pair<D, T>(Zirr + pa * (int64_t)(D + 1) * ZSP, Zirr + (has_b ? pb : pa) * (int64_t)(D + 1) * ZSP, has_b,
                       j16, [&](int f, const int* o) { return gather(ca, f, o); },
                       [&](int f, const int* o) { return gather(cb, f, o); }, acca, accb);
     if (j16 <= D) {
-      double va = acca[0], vb = accb[0];
+      T va = acca[0], vb = accb[0];
 #pragma unroll
       for (int f = 1; f <= D; ++f)
         if (j16 == f) {
@@ -834,32 +834,32 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
 // mode 0: x_in as given; mode 1: x_in is zero (not read; the first sweep on a coarse level);
 // mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
 // V-cycle applied as the x tile is loaded, as prolong_add would apply it).
-template <int TX, int TY, int NT, int WPE>
+template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) sweep_fused2_kernel(
     const OpConsts* __restrict__ oc,
                                                           const int* __restrict__ node_op,
-                                                          const double* __restrict__ nsten, int ntx, int nty,
+                                                          const T* __restrict__ nsten, int ntx, int nty,
                                                           const int* __restrict__ extra,
                                                           const int* __restrict__ node_class,
-                                                          const double* __restrict__ Zcls,
-                                                          const double* __restrict__ Zirr,
-                                                          const double* __restrict__ x_in,
-                                                          const double* __restrict__ b,
-                                                          double* __restrict__ x_out, double omega, int mode,
-                                                          const double* __restrict__ xc) {
+                                                          const T* __restrict__ Zcls,
+                                                          const T* __restrict__ Zirr,
+                                                          const T* __restrict__ x_in,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ x_out, T omega, int mode,
+                                                          const T* __restrict__ xc) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
   constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
   constexpr int RW = TX + 4, RH = TY + 4, RP = RW * RH;  // residual tile, halo 2
   constexpr int ZSP = PT<2>::ZSP;
   constexpr int NRES = (RP + NT - 1) / NT;                // residual nodes per thread
-  __shared__ double xs[3 * XP];
-  __shared__ double rs[3 * RP];
+  __shared__ T xs[3 * XP];
+  __shared__ T rs[3 * RP];
   constexpr int NWO = (TX * TY + 63) / 64;               // wavefronts that own tile nodes
   constexpr int NG = NT / 16;                             // 16-lane groups of the workgroup
   constexpr int CAP = 4 * NG;                             // individual patches per part (two trips)
   __shared__ int irr_tid[NWO * 64], irr_pidx[NWO * 64];
   __shared__ int irr_wcnt[NWO];
-  __shared__ RefMats<2> rm;
+  __shared__ RefMats<2, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -883,18 +883,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
   const bool inside0 = threadIdx.x < TX * TY && bx + tx0 < m && by + ty0 < m;
   const int cls = inside0 ? node_class[(bx + tx0) + (int64_t)m * (by + ty0)] : -1;
   constexpr int NXL = (3 * XP + NT - 1) / NT;
-  double xv[NXL];
+  T xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
     const int e = threadIdx.x + NT * k;
     const int f = e / XP, p = e % XP;
     const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
-    double v = 0.0;
+    T v = 0;
     if (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) {
       if (mode != 1) v = x_in[f * N + gx + (int64_t)m * gy];
       if (mode == 2) {
         const int cg[3] = {gx, gy, 0};
-        v += prolong_value<2>(n >> 1, (int64_t)((n >> 1) + 1) * ((n >> 1) + 1), xc, cg, f);
+        v += prolong_value<2, T>(n >> 1, (int64_t)((n >> 1) + 1) * ((n >> 1) + 1), xc, cg, f);
       }
     }
     xv[k] = v;
@@ -907,7 +907,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
     opv[k] = ok ? node_op[cx + (int64_t)m * cy] : -1;
   }
-  stage_refmats<2, NT>(oc, rm);
+  stage_refmats<2, NT, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
@@ -918,20 +918,20 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     if (e < RP) {
       const int px = e % RW, py = e / RW;
       const int cx = bx - 2 + px, cy = by - 2 + py;
-      double rv[3] = {0, 0, 0};
+      T rv[3] = {0, 0, 0};
       if (cx >= 0 && cx < m && cy >= 0 && cy < m) {
         const int64_t g = cx + (int64_t)m * cy;
-        double bv[3];
+        T bv[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) bv[f] = b[f * N + g];
         const int xb = (px + 1) + XW * (py + 1);
-        double acc[3] = {0, 0, 0};
+        T acc[3] = {0, 0, 0};
         // an offset the compiler cannot see through: keeps it from holding the level constants of
         // several residual nodes in registers at once (they are read from LDS where they are used)
         int ro = 0;
         asm volatile("" : "+s"(ro));
-        const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
-        node_row_apply<2>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+        const RefMats<2, T>& rmk = *reinterpret_cast<const RefMats<2, T>*>(reinterpret_cast<const char*>(&rm) + ro);
+        node_row_apply<2, true, T>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                           acc);
 #pragma unroll
         for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
@@ -945,9 +945,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
   const bool inside = inside0;
   const int64_t node = (bx + tx) + (int64_t)m * (by + ty);
   const int rbase = (tx + 2) + RW * (ty + 2);
-  double y[3] = {0, 0, 0};
+  T y[3] = {0, 0, 0};
   const int cls_reg = part == 0 ? cls : -1;  // regular patches belong to part 0
-  regular_apply<2>(Zcls, cls_reg, [&](int f, const int* o) { return rs[f * RP + rbase + o[0] + RW * o[1]]; }, y);
+  regular_apply<2, true, T>(Zcls, cls_reg, [&](int f, const int* o) { return rs[f * RP + rbase + o[0] + RW * o[1]]; }, y);
   if (cls_reg >= 0) {
     const int xb = (tx + 3) + XW * (ty + 3);
 #pragma unroll
@@ -986,13 +986,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     const int sa = slot(ea), sb = has_b ? slot(eb) : sa;
     const int ta = irr_tid[sa], tb = irr_tid[sb];
     const int rba = (ta % TX + 2) + RW * (ta / TX + 2), rbb = (tb % TX + 2) + RW * (tb / TX + 2);
-    double acca[3], accb[3];
-    irregular_pair<2>(Zirr + (int64_t)irr_pidx[sa] * 3 * ZSP, Zirr + (int64_t)irr_pidx[sb] * 3 * ZSP,
+    T acca[3], accb[3];
+    irregular_pair<2, T>(Zirr + (int64_t)irr_pidx[sa] * 3 * ZSP, Zirr + (int64_t)irr_pidx[sb] * 3 * ZSP,
                       has_b, j16, [&](int field, const int* o) { return rs[field * RP + rba + o[0] + RW * o[1]]; },
                       [&](int field, const int* o) { return rs[field * RP + rbb + o[0] + RW * o[1]]; }, acca, accb);
     if (j16 < 3) {
-      const double va = j16 == 0 ? acca[0] : (j16 == 1 ? acca[1] : acca[2]);
-      const double vb = j16 == 0 ? accb[0] : (j16 == 1 ? accb[1] : accb[2]);
+      const T va = j16 == 0 ? acca[0] : (j16 == 1 ? acca[1] : acca[2]);
+      const T vb = j16 == 0 ? accb[0] : (j16 == 1 ? accb[1] : accb[2]);
       x_out[j16 * N + (bx + ta % TX) + (int64_t)m * (by + ta / TX)] =
           xs[j16 * XP + (ta % TX + 3) + XW * (ta / TX + 3)] + omega * va;
       if (has_b)
@@ -1035,61 +1035,63 @@ void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector
     }
 }
 
-template <int D>
-hipError_t k_apply_regular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
+template <int D, class T>
+hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s) {
   if (L.n_classes == 0) return hipSuccess;
   int nt[3];
   tile_grid<D>(L.n, nt);
-  apply_regular_kernel<D><<<dim3((unsigned)(nt[0] * nt[1] * nt[2])), dim3(256), 0, s>>>(
-      L.n, nt[0], nt[1], nt[2], L.node_class, L.Zcls, r, x, c.prm.omega);
+  apply_regular_kernel<D, T><<<dim3((unsigned)(nt[0] * nt[1] * nt[2])), dim3(256), 0, s>>>(
+      L.n, nt[0], nt[1], nt[2], L.node_class, LV<T>::Zcls(L), r, x, (T)c.prm.omega);
   return hipGetLastError();
 }
 
-template <int D>
-hipError_t k_apply_irregular(const Ctx& c, const Level& L, const double* r, double* x, hipStream_t s) {
+template <int D, class T>
+hipError_t k_apply_irregular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s) {
   if (L.n_irr == 0) return hipSuccess;
   int64_t nb = (L.n_irr + 31) / 32;
   if (nb > 65536) nb = 65536;
-  apply_irregular_kernel<D><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.n_irr, L.irr_nodes, L.Zirr, r, x,
-                                                                     c.prm.omega);
+  apply_irregular_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.n_irr, L.irr_nodes, LV<T>::Zirr(L),
+                                                                        r, x, (T)c.prm.omega);
   return hipGetLastError();
 }
 
-template <int TX, int TY, int NT, int WPE>
-hipError_t launch_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                         int mode, const double* xc, hipStream_t s) {
+template <int TX, int TY, int NT, int WPE, class T>
+hipError_t launch_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out,
+                         int mode, const T* xc, hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
-  sweep_fused2_kernel<TX, TY, NT, WPE><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(
-      L.consts, L.node_op, L.nsten, ntx, nty, L.fused_extra, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, c.prm.omega, mode, xc);
+  sweep_fused2_kernel<TX, TY, NT, WPE, T><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(
+      L.consts, L.node_op, LV<T>::nsten(L), ntx, nty, L.fused_extra, L.node_class, LV<T>::Zcls(L), LV<T>::Zirr(L), x_in,
+      b, x_out, (T)c.prm.omega, mode, xc);
   return hipGetLastError();
 }
 
-hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
-                          int mode, const double* xc, hipStream_t s) {
+template <class T>
+hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
+                          hipStream_t s) {
   constexpr Fused2Shape B = kFusedBig, M = kFusedMid, S = kFusedSmall;
-  if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, 5>(c, L, x_in, b, x_out, mode, xc, s);
-  if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, 5>(c, L, x_in, b, x_out, mode, xc, s);
-  return launch_fused2<S.tx, S.ty, S.nt, 4>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, 5, T>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, 5, T>(c, L, x_in, b, x_out, mode, xc, s);
+  return launch_fused2<S.tx, S.ty, S.nt, 4, T>(c, L, x_in, b, x_out, mode, xc, s);
 }
 
 // Residual and restriction in one pass (2D, V-cycle): b_c = P^T (b - L x) for a TXC x TYC tile of
 // coarse nodes. The fine residual of the (2 TXC + 1) x (2 TYC + 1) nodes the tile gathers from is
 // computed into LDS from an x tile with halo 1; arithmetic and summation order are those of the
 // residual and restriction kernels.
-template <int TXC, int TYC, int NT>
+template <int TXC, int TYC, int NT, class T>
 __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* __restrict__ oc,
                                                                 const int* __restrict__ node_op,
-                                                                const double* __restrict__ nsten, int ntx, int nty,
-                                                                const double* __restrict__ x,
-                                                                const double* __restrict__ b,
-                                                                double* __restrict__ bc) {
+                                                                const T* __restrict__ nsten, int ntx, int nty,
+                                                                const T* __restrict__ x,
+                                                                const T* __restrict__ b,
+                                                                T* __restrict__ bc) {
   static_assert(NT >= TXC * TYC && NT % 64 == 0, "one thread per coarse node at least");
   constexpr int RW = 2 * TXC + 1, RH = 2 * TYC + 1, RP = RW * RH;  // fine residual region
   constexpr int XW = RW + 2, XH = RH + 2, XP = XW * XH;            // x region, halo 1
   constexpr int NRES = (RP + NT - 1) / NT, NXL = (3 * XP + NT - 1) / NT;
-  __shared__ double xs[3 * XP];
-  __shared__ double rs[3 * RP];
-  __shared__ RefMats<2> rm;
+  __shared__ T xs[3 * XP];
+  __shared__ T rs[3 * RP];
+  __shared__ RefMats<2, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -1100,16 +1102,16 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
   tile_coords<2>(blockIdx.x, nt, t);
   const int cx0 = t[0] * TXC, cy0 = t[1] * TYC;
   const int fx0 = 2 * cx0 - 1, fy0 = 2 * cy0 - 1;  // fine coordinates of residual-region entry 0
-  double xv[NXL];
+  T xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
     const int e = threadIdx.x + NT * k;
     const int f = e / XP, p = e % XP;
     const int gx = fx0 - 1 + p % XW, gy = fy0 - 1 + p / XW;
-    xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x[f * N + gx + (int64_t)m * gy] : 0.0;
+    xv[k] = (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) ? x[f * N + gx + (int64_t)m * gy] : T(0);
   }
   int opv[NRES];
-  double bv[NRES][3];
+  T bv[NRES][3];
 #pragma unroll
   for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
@@ -1118,9 +1120,9 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
     const int64_t g = gx + (int64_t)m * gy;
     opv[k] = ok ? node_op[g] : -1;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : 0.0;
+    for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : T(0);
   }
-  stage_refmats<2, NT>(oc, rm);
+  stage_refmats<2, NT, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
@@ -1131,14 +1133,14 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
     if (e < RP) {
       const int px = e % RW, py = e / RW;
       const int gx = fx0 + px, gy = fy0 + py;
-      double rv[3] = {0, 0, 0};
+      T rv[3] = {0, 0, 0};
       if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
         const int xb = (px + 1) + XW * (py + 1);
-        double acc[3] = {0, 0, 0};
+        T acc[3] = {0, 0, 0};
         int ro = 0;  // opaque offset: no hoisting of the level constants (see the fused sweep)
         asm volatile("" : "+s"(ro));
-        const RefMats<2>& rmk = *reinterpret_cast<const RefMats<2>*>(reinterpret_cast<const char*>(&rm) + ro);
-        node_row_apply<2>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+        const RefMats<2, T>& rmk = *reinterpret_cast<const RefMats<2, T>*>(reinterpret_cast<const char*>(&rm) + ro);
+        node_row_apply<2, true, T>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                           acc);
 #pragma unroll
         for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
@@ -1151,12 +1153,12 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
   if (threadIdx.x >= TXC * TYC) return;
   const int cx = cx0 + threadIdx.x % TXC, cy = cy0 + threadIdx.x / TXC;
   if (cx >= mc || cy >= mc) return;
-  double acc[3] = {0, 0, 0};
+  T acc[3] = {0, 0, 0};
   for (int o = 0; o < 9; ++o) {
     const int ox = o % 3 - 1, oy = o / 3 - 1;
     const int gx = 2 * cx + ox, gy = 2 * cy + oy;
     if (gx < 0 || gx > n || gy < 0 || gy > n) continue;
-    double w = 1;
+    T w = 1;
     if (ox != 0) w *= 0.5;
     if (oy != 0) w *= 0.5;
     const int e = (gx - fx0) + RW * (gy - fy0);
@@ -1168,20 +1170,20 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
   for (int f = 0; f < 3; ++f) bc[f * Nc + cn] = acc[f];
 }
 
-template <int TXC, int TYC, int NT>
-hipError_t launch_residual_restrict2(const Level& F, const double* x, const double* b, double* bc, hipStream_t s) {
+template <int TXC, int TYC, int NT, class T>
+hipError_t launch_residual_restrict2(const Level& F, const T* x, const T* b, T* bc, hipStream_t s) {
   const int mc = (F.n >> 1) + 1;
   const int ntx = (mc + TXC - 1) / TXC, nty = (mc + TYC - 1) / TYC;
-  residual_restrict2_kernel<TXC, TYC, NT><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
-      F.consts, F.node_op, F.nsten, ntx, nty, x, b, bc);
+  residual_restrict2_kernel<TXC, TYC, NT, T><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
+      F.consts, F.node_op, LV<T>::nsten(F), ntx, nty, x, b, bc);
   return hipGetLastError();
 }
 
-hipError_t k_residual_restrict2(const Ctx&, const Level& F, const double* x, const double* b, double* bc,
-                                hipStream_t s) {
-  if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256>(F, x, b, bc, s);
-  if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128>(F, x, b, bc, s);
-  return launch_residual_restrict2<4, 4, 128>(F, x, b, bc, s);
+template <class T>
+hipError_t k_residual_restrict2(const Ctx&, const Level& F, const T* x, const T* b, T* bc, hipStream_t s) {
+  if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256, T>(F, x, b, bc, s);
+  if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128, T>(F, x, b, bc, s);
+  return launch_residual_restrict2<4, 4, 128, T>(F, x, b, bc, s);
 }
 
 }  // namespace fcg

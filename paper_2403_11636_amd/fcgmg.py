@@ -17,13 +17,14 @@ LIB_PATH = os.path.join(PKG, "libfcgmg.so")
 
 CACHE_INVERSE, CACHE_MATRIX, CACHE_NONE = 0, 1, 2
 POLICY_NAMES = {CACHE_INVERSE: "cache_inverse", CACHE_MATRIX: "cache_matrix", CACHE_NONE: "cache_none"}
+PREC_FP64, PREC_MIXED = 0, 1
 
 OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTS = [
     "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
     "fcgmg_residual", "fcgmg_smooth", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
-    "fcgmg_vcycle", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_destroy", "fcgmg_last_error",
+    "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
 ]
 
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
         ("quad_depth", ctypes.c_int), ("cache_policy", ctypes.c_int), ("nu_pre", ctypes.c_int),
         ("nu_post", ctypes.c_int), ("force", ctypes.c_int), ("bc", ctypes.c_int * 6),
         ("eta", ctypes.c_double), ("alpha_fict", ctypes.c_double), ("nitsche_beta", ctypes.c_double),
-        ("omega", ctypes.c_double), ("ubar", ctypes.c_double),
+        ("omega", ctypes.c_double), ("ubar", ctypes.c_double), ("precision", ctypes.c_int),
     ]
 
 
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_prolongate_add.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fcgmg_coarse_solve.argtypes = [vp, vp, vp, vp]
     L.fcgmg_vcycle.argtypes = [vp, vp, vp, vp]
+    L.fcgmg_vcycle_fp32.argtypes = [vp, vp, vp, vp]
     L.fcgmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, vp]
     L.fcgmg_norm.argtypes = [vp, ctypes.c_int, vp, dp, vp]
     L.fcgmg_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -132,7 +134,7 @@ def _dptr(t, name: str, numel: int):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_params(prob, policy: int = CACHE_INVERSE) -> Params:
+def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -> Params:
     p = Params()
     p.dim = prob.dim
     p.n_cells = prob.n_cells
@@ -149,13 +151,14 @@ def make_params(prob, policy: int = CACHE_INVERSE) -> Params:
     p.nitsche_beta = prob.nitsche_beta
     p.omega = prob.omega
     p.ubar = prob.ubar
+    p.precision = precision
     return p
 
 
 class Hierarchy:
     """Device-resident GMG hierarchy of one finite cell Stokes problem (fcgmg_setup_hierarchy)."""
 
-    def __init__(self, prob, policy: int = CACHE_INVERSE, stream=None):
+    def __init__(self, prob, policy: int = CACHE_INVERSE, stream=None, precision: int = PREC_FP64):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fcgmg needs a GPU; none is visible")
@@ -164,7 +167,8 @@ class Hierarchy:
         self.prob = prob
         self.policy = policy
         self.dim = prob.dim
-        self._params = make_params(prob, policy)
+        self.precision = precision
+        self._params = make_params(prob, policy, precision)
         balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
         self._balls = balls
         h = ctypes.c_void_p()
@@ -273,6 +277,13 @@ class Hierarchy:
         n = self.ndofs()
         _check(load().fcgmg_vcycle(self.h, _dptr(x, "x", n), _dptr(b, "b", n), _stream_ptr(stream)))
         return x
+
+    def vcycle_fp32(self, r, out=None, stream=None):
+        """e = V(0, r) by one FP32 V-cycle (mixed-precision hierarchies); r, e FP64 finest-level."""
+        n = self.ndofs()
+        e = self.zeros() if out is None else out
+        _check(load().fcgmg_vcycle_fp32(self.h, _dptr(r, "r", n), _dptr(e, "e", n), _stream_ptr(stream)))
+        return e
 
     def norm(self, v, level: Optional[int] = None, stream=None) -> float:
         level = self.fine if level is None else level

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "fcgmg.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fcgmg_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(fcgmg_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declarations_are_exported():
@@ -58,6 +58,8 @@ def test_kernel_kinds_match_header():
     (lambda p: setattr(p, "cache_policy", 7), "policy"),
     (lambda p: setattr(p, "eta", -1.0), "eta"),
     (lambda p: setattr(p, "quad_depth", 9), "quad_depth"),
+    (lambda p: setattr(p, "precision", 5), "precision"),
+    (lambda p: (setattr(p, "precision", 1), setattr(p, "cache_policy", 1)), "mixed precision"),
 ])
 def test_setup_rejects_bad_arguments_on_host(mutate, msg):
     from paper_2403_11636_amd import inputs
