@@ -234,6 +234,45 @@ def policy_extras(torch, fcgmg, prob, sweeps=4):
     return out
 
 
+def precision_extra(torch, fcgmg, prob, solves=5):
+    """FP64 solve against the mixed-precision solve (FP32 V-cycles inside FP64 iterative refinement)
+    on one workload: time to 1e-8, cycles, the FP32 cycle alone, and the distance of the mixed
+    iterate from the FP64 one."""
+    out = {"workload": prob.name}
+    xs = {}
+    for prec, tag in ((fcgmg.PREC_FP64, "fp64"), (fcgmg.PREC_MIXED, "mixed")):
+        h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE, precision=prec)
+        b = h.rhs()
+        h.solve(b, rtol=1e-8, max_iter=200)
+        ms, its, rels = time_solves(torch, h, b, solves)
+        x, _, _, _, _ = h.solve(b, rtol=1e-8, max_iter=200)
+        xs[tag] = x.cpu().numpy()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        if prec == fcgmg.PREC_MIXED:
+            e = h.zeros()
+            h.vcycle_fp32(b, out=e)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(10):
+                h.vcycle_fp32(b, out=e)
+            e1.record()
+        else:
+            xx = h.zeros()
+            e0.record()
+            for _ in range(10):
+                h.vcycle(xx, b)
+            e1.record()
+        torch.cuda.synchronize()
+        out[tag] = {"solve_ms_p50": round(pct(ms, 50), 3), "solve_ms_p99": round(pct(ms, 99), 3),
+                    "cycles": int(np.median(its)), "rel_res": float(np.max(rels)),
+                    "cycle_us": round(e0.elapsed_time(e1) / 10 * 1e3, 1), "device_bytes": h.device_bytes()}
+        h.close()
+    out["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    out["speedup"] = round(out["fp64"]["solve_ms_p50"] / out["mixed"]["solve_ms_p50"], 3)
+    return out
+
+
 def workload_extra(torch, fcgmg, prob, steps=5):
     t0 = time.perf_counter()
     h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
@@ -366,6 +405,8 @@ def main():
                                            "cached_bytes_finest": st["cached_bytes"]}
         log("3D 64^3 ...")
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
+        log("precision: FP64 vs mixed ...")
+        out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]
         log("2D 4096^2 ...")
         big = inputs.config2(0, n_cells=4096, n_levels=10)
         big.name = "2d_20discs_4096_seed0"

@@ -182,6 +182,55 @@ int fcgmg_profile_read(fcgmg_h h, int kind, int level, double* total_ms, int64_t
 /* Device bytes held by the handle (all levels, all policy data). */
 int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
 
+/* Device bytes fcgmg_setup_hierarchy would hold for these arguments (equal to fcgmg_device_bytes
+ * after that set-up), computed on the host without touching the device: the cell kinds by the same
+ * ball-box test, then the sizes of every level's vectors, operator data and policy cache (Sec.
+ * 3.1.2: cache_inverse > cache_matrix > cache_none in general). For admission by memory footprint.
+ * Cost: one pass over the cells of every level. Errors: E_ARG as set-up. */
+int fcgmg_footprint_bytes(const fcgmg_params* prm, const double* balls, int n_balls, size_t* bytes);
+
+/* ---- Solve server: concurrent solves with device-resident hierarchies ------------------------
+ * Worker threads (one HIP stream each) take requests in arrival order. A request runs on a resident
+ * hierarchy of the same problem when one is idle; otherwise it is admitted once its footprint
+ * (fcgmg_footprint_bytes plus its right-hand side) fits the memory budget, after evicting idle
+ * hierarchies least recently used first. With cache_policy = -1 the server picks the fastest policy
+ * of Sec. 3.1.2 that fits (cache_inverse, then cache_matrix, then cache_none). A request that can
+ * never fit completes with E_NOMEM. Each solve is fcgmg_solve from x = 0 on the problem's own
+ * right-hand side (fcgmg_rhs), so its result does not depend on what else runs. */
+typedef struct fcgmg_server* fcgmg_server_h;
+
+typedef struct {
+  int workers;         /* concurrent solves, 1..16                                                */
+  int max_iter;        /* cycle limit of every solve                                              */
+  int64_t hbm_budget;  /* device bytes for resident hierarchies; 0: 80% of the free memory         */
+} fcgmg_server_params;
+
+typedef struct {
+  int status;          /* FCGMG_OK or the error of the request (E_NOMEM: never fits the budget)     */
+  int policy;          /* cache policy it ran with                                                */
+  int iters;           /* V-cycles                                                                */
+  int cache_hit;       /* 1: ran on a resident hierarchy                                          */
+  double rel_res;      /* final relative residual                                                 */
+  double t_queue_ms;   /* submit to start                                                         */
+  double t_setup_ms;   /* hierarchy set-up (0 on a hit)                                           */
+  double t_solve_ms;   /* solve, including the final stream synchronisation                       */
+  double t_total_ms;   /* submit to completion                                                    */
+  int64_t footprint;   /* device bytes of its hierarchy and right-hand side                       */
+} fcgmg_request_result;
+
+int fcgmg_server_create(const fcgmg_server_params* sp, fcgmg_server_h* out);
+/* Queue a solve of the problem (prm, balls as for fcgmg_setup_hierarchy; prm->cache_policy may be
+ * -1). x_out: caller-owned device buffer of (d+1)(n_cells+1)^d doubles, written before the request
+ * completes; it must stay valid until fcgmg_server_wait returns for *request_id. */
+int fcgmg_server_submit(fcgmg_server_h srv, const fcgmg_params* prm, const double* balls, int n_balls,
+                        double rtol, double* x_out, int64_t* request_id);
+/* Block until the request completes; fills *res and forgets the id. */
+int fcgmg_server_wait(fcgmg_server_h srv, int64_t request_id, fcgmg_request_result* res);
+/* Device bytes and number of hierarchies currently resident. */
+int fcgmg_server_resident_bytes(fcgmg_server_h srv, int64_t* bytes, int* hierarchies);
+/* Finish queued requests, join the workers, free every resident hierarchy. */
+int fcgmg_server_destroy(fcgmg_server_h srv);
+
 /* Release every device buffer of the handle. NULL is accepted. */
 void fcgmg_destroy(fcgmg_h h);
 

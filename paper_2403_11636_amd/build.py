@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfcgmg.so")
 
-SOURCES = ["fcgmg_kernels.hip", "fcgmg_api.cpp"]
+SOURCES = ["fcgmg_kernels.hip", "fcgmg_api.cpp", "fcgmg_serve.cpp"]
 HEADERS = ["fcgmg_impl.h", "fcgmg_patch.inl"]
 
 
@@ -44,7 +44,7 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         if p.wait() != 0:
             raise RuntimeError("compilation failed: " + " ".join(cmd))
     tmp = LIB + ".tmp"
-    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

@@ -700,6 +700,70 @@ int correction_fp32_impl(const Ctx& c, const double* r, double* x, hipStream_t s
   return FCGMG_OK;
 }
 
+// Device bytes that setup_impl would allocate, from the same host-side planning (cell kinds by the
+// exact ball-box test on the host, operator codes, patch classes, fused-sweep plan). Temporaries
+// freed during set-up are not counted.
+template <int D>
+size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
+  const int nlev = P.n_levels;
+  const bool inverse = P.cache_policy == FCGMG_CACHE_INVERSE;
+  const bool mixed = P.precision == FCGMG_PREC_MIXED;
+  size_t bytes = sizeof(int) + balls.size() * sizeof(double) + (kRedBlocks + 1) * sizeof(double);
+  size_t n_pattern = 0;
+  if (P.cache_policy == FCGMG_CACHE_MATRIX) {
+    std::vector<int> enc;
+    pattern_entries<D>(enc);
+    n_pattern = enc.size();
+    bytes += n_pattern * sizeof(int);
+  }
+  const Geom g{balls.data(), (int)balls.size() / 4, P.quad_depth, P.alpha_fict};
+  int64_t nd0 = 0;
+  for (int l = 0; l < nlev; ++l) {
+    Level L;
+    L.n = P.n_cells >> (nlev - 1 - l);
+    L.h = 1.0 / L.n;
+    L.N = 1;
+    L.ncells = 1;
+    for (int k = 0; k < D; ++k) {
+      L.N *= (L.n + 1);
+      L.ncells *= L.n;
+    }
+    const size_t nd = (size_t)(D + 1) * L.N;
+    if (l == 0) nd0 = (int64_t)nd;
+    bytes += nd * sizeof(double) * (l < nlev - 1 ? 3 : 1);
+    if (D == 2 && inverse) bytes += nd * sizeof(double);
+    std::vector<signed char> kinds(L.ncells);
+    int64_t n_cut = 0;
+    for (int64_t cell = 0; cell < L.ncells; ++cell) {
+      const double lo[3] = {(double)(cell % L.n) * L.h, (double)((cell / L.n) % L.n) * L.h,
+                            D == 3 ? (double)(cell / ((int64_t)L.n * L.n)) * L.h : 0.0};
+      kinds[cell] = (signed char)box_kind<D>(g, lo, L.h);
+      if (kinds[cell] == 2) ++n_cut;
+    }
+    bytes += L.ncells * sizeof(int) + (size_t)n_cut * PT<D>::NEL * sizeof(double) + sizeof(OpConsts);
+    std::vector<int> op(L.N), sten, ncls, reps, irr, extra;
+    node_operator_codes<D>(L, kinds, op, sten);
+    bytes += L.N * sizeof(int) + sten.size() * PT<D>::NSTEN * sizeof(double);
+    classify_patches<D>(L, kinds, ncls, reps, irr);
+    bytes += (L.N + reps.size() + irr.size()) * sizeof(int);
+    const size_t npatch = reps.size() + irr.size();
+    if (D == 2 && inverse) {
+      plan_fused2(L, ncls, extra);
+      bytes += extra.size() * sizeof(int);
+    }
+    if (inverse) {
+      const size_t row = (size_t)(D + 1) * PT<D>::ZSP;
+      bytes += npatch * row * sizeof(double);
+      if (mixed)
+        bytes += (npatch * row + sten.size() * PT<D>::NSTEN + nd * (D == 2 ? 4 : 3)) * sizeof(float);
+    } else if (P.cache_policy == FCGMG_CACHE_MATRIX) {
+      bytes += npatch * n_pattern * sizeof(double);
+    }
+  }
+  bytes += (size_t)nd0 * nd0 * (sizeof(double) + (mixed ? sizeof(float) : 0));
+  return bytes;
+}
+
 int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {
   FCG_HIP(k_sumsq(v, n, c.red, kRedBlocks, s));
   FCG_HIP(k_finish_sumsq(c.red, kRedBlocks, c.red + kRedBlocks, s));
@@ -715,28 +779,11 @@ bool valid_level(const Ctx* c, int l) { return c && l >= 0 && l < (int)c->lev.si
 
 struct fcgmg_ctx : public Ctx {};
 
-extern "C" {
+int fcg::set_error(int code, const std::string& msg) { return fail(code, msg); }
 
-const char* fcgmg_last_error(void) { return g_err.c_str(); }
-
-void fcgmg_destroy(fcgmg_h h) {
-  if (!h) return;
-  for (const Ctx::ProfRec& r : h->prof_pending) {
-    (void)hipEventSynchronize(r.stop);
-    h->prof_pool.push_back(r.start);
-    h->prof_pool.push_back(r.stop);
-  }
-  for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
-  for (void* p : h->allocs) (void)hipFree(p);
-  if (h->red_host) (void)hipHostFree(h->red_host);
-  delete h;
-}
-
-int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_balls, void* stream, fcgmg_h* out) {
-  g_err.clear();
-  if (!prm || !out) return fail(FCGMG_E_ARG, "null argument");
-  *out = nullptr;
-  const fcgmg_params& P = *prm;
+// Argument checks shared by set-up and the footprint estimate.
+static int validate_params(const fcgmg_params& prm, const double* balls, int n_balls) {
+  const fcgmg_params& P = prm;
   if (P.dim != 2 && P.dim != 3) return fail(FCGMG_E_ARG, "dim must be 2 or 3");
   if (P.n_levels < 1 || P.n_levels > 20) return fail(FCGMG_E_ARG, "n_levels out of range");
   if (P.n_cells < 1 || ((P.n_cells >> (P.n_levels - 1)) << (P.n_levels - 1)) != P.n_cells)
@@ -757,6 +804,43 @@ int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_ba
   if (n_balls < 0 || (n_balls > 0 && !balls)) return fail(FCGMG_E_ARG, "bad obstacle list");
   for (int i = 0; i < n_balls; ++i)
     if (!(balls[4 * i + 3] > 0)) return fail(FCGMG_E_ARG, "obstacle radius must be > 0");
+  return FCGMG_OK;
+}
+
+extern "C" {
+
+const char* fcgmg_last_error(void) { return g_err.c_str(); }
+
+void fcgmg_destroy(fcgmg_h h) {
+  if (!h) return;
+  for (const Ctx::ProfRec& r : h->prof_pending) {
+    (void)hipEventSynchronize(r.stop);
+    h->prof_pool.push_back(r.start);
+    h->prof_pool.push_back(r.stop);
+  }
+  for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->red_host) (void)hipHostFree(h->red_host);
+  delete h;
+}
+
+int fcgmg_footprint_bytes(const fcgmg_params* prm, const double* balls, int n_balls, size_t* bytes) {
+  g_err.clear();
+  if (!prm || !bytes) return fail(FCGMG_E_ARG, "null argument");
+  int rc;
+  if ((rc = validate_params(*prm, balls, n_balls))) return rc;
+  const std::vector<double> bh(balls, balls + 4 * (size_t)n_balls);
+  *bytes = prm->dim == 2 ? footprint_impl<2>(*prm, bh) : footprint_impl<3>(*prm, bh);
+  return FCGMG_OK;
+}
+
+int fcgmg_setup_hierarchy(const fcgmg_params* prm, const double* balls, int n_balls, void* stream, fcgmg_h* out) {
+  g_err.clear();
+  if (!prm || !out) return fail(FCGMG_E_ARG, "null argument");
+  *out = nullptr;
+  int rc0;
+  if ((rc0 = validate_params(*prm, balls, n_balls))) return rc0;
+  const fcgmg_params& P = *prm;
   fcgmg_ctx* c = new fcgmg_ctx();
   c->prm = P;
   c->balls_h.assign(balls, balls + 4 * (size_t)n_balls);

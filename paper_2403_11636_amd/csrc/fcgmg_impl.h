@@ -354,6 +354,8 @@ template <class T>
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
                           hipStream_t s);
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra);
+// Set the calling thread's error message (fcgmg_last_error) and return `code`.
+int set_error(int code, const std::string& msg);
 template <class T>
 hipError_t k_residual_restrict2(const Ctx& c, const Level& F, const T* x, const T* b, T* bc, hipStream_t s);
 template <int D> hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x,

@@ -24,8 +24,10 @@ OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, 
 EXPORTS = [
     "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
     "fcgmg_residual", "fcgmg_smooth", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
-    "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_destroy", "fcgmg_last_error",
+    "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
+    "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
+    "fcgmg_server_destroy",
 ]
 
 KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
@@ -46,6 +48,17 @@ class Params(ctypes.Structure):
         ("eta", ctypes.c_double), ("alpha_fict", ctypes.c_double), ("nitsche_beta", ctypes.c_double),
         ("omega", ctypes.c_double), ("ubar", ctypes.c_double), ("precision", ctypes.c_int),
     ]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int), ("max_iter", ctypes.c_int), ("hbm_budget", ctypes.c_int64)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("policy", ctypes.c_int), ("iters", ctypes.c_int),
+                ("cache_hit", ctypes.c_int), ("rel_res", ctypes.c_double), ("t_queue_ms", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("footprint", ctypes.c_int64)]
 
 
 class LevelStats(ctypes.Structure):
@@ -85,6 +98,12 @@ def load(path: str = LIB_PATH):
     L.fcgmg_solve.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, vp]
     L.fcgmg_norm.argtypes = [vp, ctypes.c_int, vp, dp, vp]
     L.fcgmg_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.fcgmg_server_create.argtypes = [ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
+    L.fcgmg_server_submit.argtypes = [vp, ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.c_double, vp, i64p]
+    L.fcgmg_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(RequestResult)]
+    L.fcgmg_server_resident_bytes.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int)]
+    L.fcgmg_server_destroy.argtypes = [vp]
+    L.fcgmg_footprint_bytes.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.fcgmg_destroy.argtypes = [vp]
     L.fcgmg_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fcgmg_profile_reset.argtypes = [vp]
@@ -153,6 +172,17 @@ def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -
     p.ubar = prob.ubar
     p.precision = precision
     return p
+
+
+def footprint_bytes(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -> int:
+    """Device bytes a Hierarchy of `prob` would hold (fcgmg_footprint_bytes; host-only, no GPU)."""
+    L = load()
+    prm = make_params(prob, policy, precision)
+    balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
+    bp = balls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if balls.size else None
+    out = ctypes.c_size_t()
+    _check(L.fcgmg_footprint_bytes(ctypes.byref(prm), bp, balls.shape[0], ctypes.byref(out)))
+    return out.value
 
 
 class Hierarchy:
@@ -304,3 +334,57 @@ class Hierarchy:
         if rc != OK and (rc != E_NOCONV or raise_on_noconv):
             _check(rc)
         return x, it.value, rel.value, hist[: it.value + 1], rc
+
+
+class Server:
+    """Solve server (fcgmg_server_*): concurrent solves on device-resident hierarchies, admitted by
+    device-memory footprint. submit() queues a problem and returns an id; wait(id) returns the
+    solution tensor and the request's result fields."""
+
+    def __init__(self, workers: int = 4, hbm_budget: int = 0, max_iter: int = 200):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("fcgmg needs a GPU; none is visible")
+        _init_device()
+        L = load()
+        sp = ServerParams(workers, max_iter, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(L.fcgmg_server_create(ctypes.byref(sp), ctypes.byref(h)))
+        self.h = h
+        self._out = {}
+
+    def submit(self, prob, policy: int = -1, precision: int = PREC_FP64, rtol: float = 1e-8) -> int:
+        import torch
+        prm = make_params(prob, policy, precision)
+        balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
+        bp = balls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if balls.size else None
+        n = (prob.dim + 1) * (prob.n_cells + 1) ** prob.dim
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        rid = ctypes.c_int64()
+        _check(load().fcgmg_server_submit(self.h, ctypes.byref(prm), bp, balls.shape[0], rtol,
+                                          ctypes.c_void_p(x.data_ptr()), ctypes.byref(rid)))
+        self._out[rid.value] = x
+        return rid.value
+
+    def wait(self, rid: int):
+        res = RequestResult()
+        _check(load().fcgmg_server_wait(self.h, rid, ctypes.byref(res)))
+        x = self._out.pop(rid)
+        return x, {k: getattr(res, k) for k, _ in RequestResult._fields_}
+
+    def resident(self):
+        b = ctypes.c_int64()
+        n = ctypes.c_int()
+        _check(load().fcgmg_server_resident_bytes(self.h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcgmg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -71,3 +71,16 @@ def test_setup_rejects_bad_arguments_on_host(mutate, msg):
     assert rc == fcgmg.E_ARG
     assert msg in lib.fcgmg_last_error().decode()
     assert not h.value
+
+
+def test_footprint_orders_policies_on_host():
+    # fcgmg_footprint_bytes runs on the host only. On a uniform background grid the shared classes make
+    # cache_inverse smaller than cache_matrix, and cache_none smallest (Sec. 3.1.2 orders the three
+    # by memory the same way for cache_matrix and cache_none); the mixed FP32 copies add to FP64.
+    from paper_2403_11636_amd import inputs
+    for prob in (inputs.config1(32, 3), inputs.config2(0), inputs.config3(0)):
+        inv, mat, none = (fcgmg.footprint_bytes(prob, pol) for pol in (fcgmg.CACHE_INVERSE, fcgmg.CACHE_MATRIX,
+                                                                       fcgmg.CACHE_NONE))
+        mixed = fcgmg.footprint_bytes(prob, fcgmg.CACHE_INVERSE, fcgmg.PREC_MIXED)
+        assert none < inv < mat
+        assert inv < mixed < 2 * inv

@@ -337,3 +337,25 @@ def test_config2_fused_bitwise_equals_unfused():
     h.smooth(xu, dev(b), 1)
     assert np.array_equal(host(xf), host(xu))
     h.close()
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("name", ["2d_16_l3_s0", "c1_32_l3", "3d_12_l2_s3"])
+def test_footprint_equals_device_bytes(name, policy):
+    f = fcg()
+    p = SMALL[name]()
+    h = f.Hierarchy(p, policy)
+    assert f.footprint_bytes(p, policy) == h.device_bytes()
+    h.close()
+    if policy == 0:
+        hm = f.Hierarchy(p, policy, precision=f.PREC_MIXED)
+        assert f.footprint_bytes(p, policy, f.PREC_MIXED) == hm.device_bytes()
+        hm.close()
+
+
+def test_footprint_equals_device_bytes_full_size():
+    f = fcg()
+    for p in (inputs.config2(0), inputs.config3(0)):
+        h = f.Hierarchy(p, 0)
+        assert f.footprint_bytes(p, 0) == h.device_bytes()
+        h.close()
