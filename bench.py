@@ -273,6 +273,49 @@ def precision_extra(torch, fcgmg, prob, solves=5):
     return out
 
 
+def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0):
+    """Solve server under a Poisson arrival stream: requests drawn uniformly from a pool of seeded
+    obstacle problems (2D 128^2..1024^2 with 20 discs, 3D 32^3..96^3 with 40 spheres; alpha 1e-8;
+    FP64 or mixed precision per problem), tolerance 1e-8. Cold start: every hierarchy is set up by
+    its first request. Latency is submit to completion."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for n, lv in ((128, 5), (256, 6), (512, 7), (1024, 8)):
+        for sd in (0, 1):
+            pool.append((inputs.config2(sd, n_cells=n, n_levels=lv), fcgmg.PREC_MIXED if sd else fcgmg.PREC_FP64))
+    for n, lv in ((32, 4), (48, 4), (64, 5), (96, 5)):
+        pool.append((inputs.config3(0, n_cells=n, n_levels=lv), fcgmg.PREC_MIXED))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    picks = rng.integers(0, len(pool), n_req)
+    srv = fcgmg.Server(workers=workers)
+    t0 = time.perf_counter()
+    ids = []
+    for k in range(n_req):
+        delay = t0 + arrivals[k] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        p, prec = pool[picks[k]]
+        ids.append(srv.submit(p, precision=prec))
+    res = [srv.wait(i)[1] for i in ids]
+    wall = time.perf_counter() - t0
+    resident, n_res = srv.resident()
+    srv.close()
+    ok = [r for r in res if r["status"] == fcgmg.OK]
+    lat = [r["t_total_ms"] for r in ok]
+    solve = [r["t_solve_ms"] for r in ok]
+    return {
+        "requests": n_req, "arrival_rate_per_s": rate, "workers": workers, "pool": len(pool),
+        "completed": len(ok), "throughput_req_per_s": round(len(ok) / wall, 2),
+        "latency_ms_p50": round(pct(lat, 50), 2), "latency_ms_p99": round(pct(lat, 99), 2),
+        "solve_ms_p50": round(pct(solve, 50), 2), "solve_ms_p99": round(pct(solve, 99), 2),
+        "setup_ms_total": round(float(sum(r["t_setup_ms"] for r in ok)), 1),
+        "cache_hits": int(sum(r["cache_hit"] for r in ok)),
+        "max_rel_res": float(max(r["rel_res"] for r in ok)),
+        "policies": {fcgmg.POLICY_NAMES[k]: int(sum(r["policy"] == k for r in ok)) for k in (0, 1, 2)},
+        "resident_bytes_end": resident, "resident_hierarchies_end": n_res, "wall_s": round(wall, 2),
+    }
+
+
 def workload_extra(torch, fcgmg, prob, steps=5):
     t0 = time.perf_counter()
     h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
@@ -407,6 +450,8 @@ def main():
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
         log("precision: FP64 vs mixed ...")
         out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]
+        log("serving ...")
+        out["serving"] = serving_extra(fcgmg, inputs)
         log("2D 4096^2 ...")
         big = inputs.config2(0, n_cells=4096, n_levels=10)
         big.name = "2d_20discs_4096_seed0"

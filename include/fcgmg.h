@@ -76,7 +76,17 @@ typedef struct {
   double omega;      /* damping, omega_i = omega * I in Eq. (15)                                */
   double ubar;       /* inflow amplitude, Eq. (16)                                             */
   int precision;     /* FCGMG_PREC_*: arithmetic of fcgmg_solve's V-cycles                       */
+  int solver;        /* FCGMG_SOLVER_*: outer iteration of fcgmg_solve                            */
+  int krylov_restart; /* FGMRES restart length m, 1..63 (ignored by FCGMG_SOLVER_GMG)              */
 } fcgmg_params;
+
+/* Outer iteration of fcgmg_solve. GMG: the standalone multigrid of Sec. 4, x <- V(x, b) until the
+ * stopping test. FGMRES: flexible GMRES(m) in FP64 with one V-cycle from a zero guess as the right
+ * preconditioner (FP32 cycle under FCGMG_PREC_MIXED), classical Gram-Schmidt applied twice, the
+ * Arnoldi residual estimate as stopping test and the true residual checked at every restart; GMG
+ * used as a Krylov preconditioner, which also converges where the standalone cycle does not. The
+ * set-up holds 2m + 2 extra finest-level vectors. Iteration counts are V-cycles in both cases. */
+enum { FCGMG_SOLVER_GMG = 0, FCGMG_SOLVER_FGMRES = 1 };
 
 /* Precision of fcgmg_solve. FP64: every operation in FP64. MIXED (cache_inverse only): set-up,
  * including every patch factorisation, stays FP64; the inverse rows, stored stencils and coarse

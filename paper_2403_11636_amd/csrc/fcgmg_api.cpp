@@ -564,6 +564,17 @@ int setup_impl(Ctx& c, hipStream_t s) {
       if ((rc = alloc_n(c, &c.coarse_inv32, Ic.size()))) return rc;
       FCG_HIP(k_round_to_float(c.coarse_inv, c.coarse_inv32, (int64_t)Ic.size(), s));
     }
+    FCG_HIP(hipStreamSynchronize(s));  // Ic must outlive the copy
+  }
+  if (P.solver == FCGMG_SOLVER_FGMRES) {
+    const size_t nd = (size_t)(D + 1) * c.lev[nlev - 1].N, m = P.krylov_restart;
+    if ((rc = alloc_n(c, &c.kv, (m + 1) * nd))) return rc;
+    if ((rc = alloc_n(c, &c.kz, m * nd))) return rc;
+    if ((rc = alloc_n(c, &c.kw, nd))) return rc;
+    if ((rc = alloc_n(c, &c.kzero, nd))) return rc;
+    if ((rc = alloc_n(c, &c.kpart, (size_t)kKrylovPartials))) return rc;
+    if ((rc = alloc_n(c, &c.kh, (size_t)128))) return rc;
+    FCG_HIP(k_zero<double>(c.kzero, (int64_t)nd, s));
     FCG_HIP(hipStreamSynchronize(s));
   }
   return FCGMG_OK;
@@ -761,7 +772,121 @@ size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
     }
   }
   bytes += (size_t)nd0 * nd0 * (sizeof(double) + (mixed ? sizeof(float) : 0));
+  if (P.solver == FCGMG_SOLVER_FGMRES) {
+    int64_t N = 1;
+    for (int k = 0; k < D; ++k) N *= P.n_cells + 1;
+    bytes += ((size_t)(2 * P.krylov_restart + 3) * (D + 1) * N + kKrylovPartials + 128) * sizeof(double);
+  }
   return bytes;
+}
+
+int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s);
+
+// z = M^{-1} v: one V-cycle on the residual equation from a zero guess, FP64 or (mixed) FP32.
+template <int D>
+int precond_impl(const Ctx& c, const double* v, double* z, hipStream_t s) {
+  const int top = (int)c.lev.size() - 1;
+  if (c.prm.precision == FCGMG_PREC_MIXED) {
+    FCG_HIP(k_zero<double>(z, (D + 1) * c.lev[top].N, s));
+    return correction_fp32_impl<D>(c, v, z, s);
+  }
+  return vcycle_impl<D>(c, top, z, v, s, true);
+}
+
+// Flexible GMRES(m) with right preconditioning (Saad's FGMRES): Arnoldi on A M^{-1} with the
+// preconditioned directions z_j kept, classical Gram-Schmidt twice per step (one device
+// reduction each), Givens rotations and the small least-squares problem on the host. Stops when
+// the Arnoldi estimate of ||b - A x|| reaches rtol * r0; the true residual is recomputed at every
+// restart and decides. hist[k] is the estimate after k preconditioner applications.
+template <int D>
+int fgmres_impl(const Ctx& c, double* x, const double* b, double rtol, int max_iter, int* iters, double* rel_res,
+                double* hist, hipStream_t s) {
+  const int top = (int)c.lev.size() - 1;
+  const int64_t nd = (D + 1) * c.lev[top].N;
+  const int m = c.prm.krylov_restart;
+  int rc;
+  auto Vv = [&](int i) { return c.kv + (int64_t)i * nd; };
+  auto Zv = [&](int i) { return c.kz + (int64_t)i * nd; };
+  double r0, beta;
+  if ((rc = residual_impl<D>(c, top, x, b, Vv(0), s))) return rc;
+  if ((rc = norm_impl(c, Vv(0), nd, &r0, s))) return rc;
+  if (hist) hist[0] = r0;
+  *iters = 0;
+  *rel_res = 0;
+  if (!std::isfinite(r0)) return fail(FCGMG_E_NAN, "non-finite initial residual");
+  if (r0 == 0.0) return FCGMG_OK;
+  beta = r0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+  int its = 0;
+  for (;;) {
+    FCG_HIP(k_scale_copy(Vv(0), 1.0 / beta, Vv(0), nd, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    bool done = false;
+    for (int j = 0; j < m && its < max_iter; ++j) {
+      if ((rc = precond_impl<D>(c, Vv(j), Zv(j), s))) return rc;
+      // w = A z_j = -(0 - A z_j)
+      if ((rc = residual_impl<D>(c, top, Zv(j), c.kzero, c.kw, s))) return rc;
+      // first pass: h = V^T (A z) = -V^T w; w <- A z - V h = -w - V h
+      FCG_HIP(k_multi_dot(c.kv, nd, j + 1, c.kw, nd, -1.0, c.kpart, c.kh, s));
+      FCG_HIP(k_multi_axpy(c.kw, -1.0, c.kv, nd, j + 1, c.kh, nd, s));
+      FCG_HIP(hipMemcpyAsync(h.data(), c.kh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      // second pass: h2 = V^T w; w <- w - V h2
+      FCG_HIP(k_multi_dot(c.kv, nd, j + 1, c.kw, nd, 1.0, c.kpart, c.kh + 64, s));
+      FCG_HIP(k_multi_axpy(c.kw, 1.0, c.kv, nd, j + 1, c.kh + 64, nd, s));
+      FCG_HIP(hipMemcpyAsync(h2.data(), c.kh + 64, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      double hn;
+      if ((rc = norm_impl(c, c.kw, nd, &hn, s))) return rc;  // synchronises: h, h2 are on the host
+      ++its;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+      H[(size_t)(j + 1) * m + j] = hn;
+      if (!std::isfinite(hn)) return fail(FCGMG_E_NAN, "non-finite Arnoldi vector at cycle " + std::to_string(its));
+      if (hn > 0) FCG_HIP(k_scale_copy(c.kw, 1.0 / hn, Vv(j + 1), nd, s));
+      // apply the previous rotations to column j, then a new one that zeroes H[j+1][j]
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      const double rr = std::hypot(a, bb);
+      cs[j] = rr > 0 ? a / rr : 1.0;
+      sn[j] = rr > 0 ? bb / rr : 0.0;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      const double est = std::fabs(g[j + 1]);
+      if (hist) hist[its] = est;
+      *iters = its;
+      *rel_res = est / r0;
+      if (est <= rtol * r0 || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // x += Z y with H(0:k, 0:k) y = g(0:k)
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i) y[i] = -y[i];  // multi_axpy subtracts
+    FCG_HIP(hipMemcpyAsync(c.kh, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    FCG_HIP(k_multi_axpy(x, 1.0, c.kz, nd, k, c.kh, nd, s));
+    if ((rc = residual_impl<D>(c, top, x, b, Vv(0), s))) return rc;
+    if ((rc = norm_impl(c, Vv(0), nd, &beta, s))) return rc;  // synchronises: y may be reused
+    *rel_res = beta / r0;
+    if (hist) hist[its] = beta;
+    if (!std::isfinite(beta)) return fail(FCGMG_E_NAN, "non-finite residual at cycle " + std::to_string(its));
+    if (beta <= rtol * r0) return FCGMG_OK;
+    if (its >= max_iter)
+      return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
+                                      std::to_string(*rel_res) + ")");
+    (void)done;  // the estimate converged but the true residual did not: restart
+  }
 }
 
 int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t s) {
@@ -796,6 +921,9 @@ static int validate_params(const fcgmg_params& prm, const double* balls, int n_b
     return fail(FCGMG_E_ARG, "unknown precision");
   if (P.precision == FCGMG_PREC_MIXED && P.cache_policy != FCGMG_CACHE_INVERSE)
     return fail(FCGMG_E_ARG, "mixed precision needs the cache_inverse policy");
+  if (P.solver != FCGMG_SOLVER_GMG && P.solver != FCGMG_SOLVER_FGMRES) return fail(FCGMG_E_ARG, "unknown solver");
+  if (P.solver == FCGMG_SOLVER_FGMRES && (P.krylov_restart < 1 || P.krylov_restart > 63))
+    return fail(FCGMG_E_ARG, "krylov_restart must be in [1,63]");
   if (!(P.eta > 0) || !(P.alpha_fict >= 0) || !(P.nitsche_beta > 0) || !std::isfinite(P.omega))
     return fail(FCGMG_E_ARG, "eta, nitsche_beta must be > 0, alpha_fict >= 0, omega finite");
   if (P.nu_pre < 0 || P.nu_post < 0) return fail(FCGMG_E_ARG, "negative smoothing steps");
@@ -948,6 +1076,9 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
   if (!h || !x || !b || !iters || !rel_res || max_iter < 0 || !(rtol >= 0))
     return fail(FCGMG_E_ARG, "bad argument");
   hipStream_t s = (hipStream_t)stream;
+  if (h->prm.solver == FCGMG_SOLVER_FGMRES)
+    return h->prm.dim == 2 ? fgmres_impl<2>(*h, x, b, rtol, max_iter, iters, rel_res, res_hist, s)
+                           : fgmres_impl<3>(*h, x, b, rtol, max_iter, iters, rel_res, res_hist, s);
   const int top = (int)h->lev.size() - 1;
   const Level& L = h->lev[top];
   const int64_t nd = (h->prm.dim + 1) * L.N;

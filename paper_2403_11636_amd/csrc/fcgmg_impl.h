@@ -160,6 +160,14 @@ struct Ctx {
   std::vector<Level> lev;
   double* coarse_inv = nullptr;  // dense inverse of the coarsest operator (ndof x ndof)
   float* coarse_inv32 = nullptr; // its FP32 rounding (mixed precision)
+  // FGMRES (solver == FCGMG_SOLVER_FGMRES): basis V (m+1 vectors), preconditioned Z (m), work w,
+  // zero vector, inner-product partials and coefficients; all finest-level FP64
+  double* kv = nullptr;
+  double* kz = nullptr;
+  double* kw = nullptr;
+  double* kzero = nullptr;
+  double* kpart = nullptr;
+  double* kh = nullptr;
   int coarse_n = 0;
   bool bordered = false;
   double* red = nullptr;         // reduction scratch
@@ -376,6 +384,14 @@ hipError_t k_zero(T* v, int64_t n, hipStream_t s);
 // dst = (float) src / dst += (double) src, n values
 hipError_t k_round_to_float(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t k_add_float(const float* src, double* dst, int64_t n, hipStream_t s);
+// FGMRES vector kernels (FP64): h[i] = s * V_i . w for i < j (part: kKrylovPartials scratch);
+// w = s * w - sum_i h[i] V_i; v = a * w. V_i = V + i * ld.
+constexpr int kKrylovPartials = 256 * 64;
+hipError_t k_multi_dot(const double* V, int64_t ld, int j, const double* w, int64_t n, double s, double* part,
+                       double* h, hipStream_t st);
+hipError_t k_multi_axpy(double* w, double s, const double* V, int64_t ld, int j, const double* h, int64_t n,
+                        hipStream_t st);
+hipError_t k_scale_copy(const double* w, double a, double* v, int64_t n, hipStream_t st);
 template <int D> int pattern_size();
 template <int D> void pattern_entries(std::vector<int>& enc);
 

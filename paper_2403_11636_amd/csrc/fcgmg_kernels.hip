@@ -792,17 +792,83 @@ hipError_t k_finish_sumsq(const double* partial, int nblocks, double* out, hipSt
   return hipGetLastError();
 }
 
-template <class T>
-__global__ void zero_kernel(T* v, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = T(0);
-}
-
 static unsigned stream_blocks(int64_t n) {
   int64_t nb = (n + 255) / 256;
   if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   return (unsigned)nb;
+}
+
+// ================================================================================================
+// Krylov (FGMRES) vector kernels, FP64: block inner products against j basis vectors at once and
+// the matching combined update. Fixed grid and summation order (deterministic).
+// ================================================================================================
+constexpr int kKrylovBlocks = 256;
+
+// part[blk * j + i] = s * sum over this block's slice of V_i . w, for i < j (V_i = V + i * ld)
+__global__ void __launch_bounds__(256) multi_dot_kernel(const double* __restrict__ V, int64_t ld, int j,
+                                                        const double* __restrict__ w, int64_t n, double s,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[4];
+  for (int i = 0; i < j; ++i) {
+    const double* vi = V + i * ld;
+    double acc = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+      acc += vi[k] * w[k];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x * j + i] = s * (sh[0] + sh[1] + sh[2] + sh[3]);
+    __syncthreads();
+  }
+}
+
+// h[i] = sum over blocks of part[blk * j + i]
+__global__ void multi_dot_finish_kernel(const double* __restrict__ part, int nb, int j, double* __restrict__ h) {
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    double acc = 0;
+    for (int blk = 0; blk < nb; ++blk) acc += part[blk * j + i];
+    h[i] = acc;
+  }
+}
+
+// w = s * w - sum_{i < j} h[i] V_i
+__global__ void multi_axpy_kernel(double* __restrict__ w, double s, const double* __restrict__ V, int64_t ld, int j,
+                                  const double* __restrict__ h, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double acc = s * w[k];
+    for (int i = 0; i < j; ++i) acc -= h[i] * V[i * ld + k];
+    w[k] = acc;
+  }
+}
+
+__global__ void scale_copy_kernel(const double* __restrict__ w, double a, double* __restrict__ v, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    v[k] = a * w[k];
+}
+
+hipError_t k_multi_dot(const double* V, int64_t ld, int j, const double* w, int64_t n, double s, double* part,
+                       double* h, hipStream_t st) {
+  multi_dot_kernel<<<dim3(kKrylovBlocks), dim3(256), 0, st>>>(V, ld, j, w, n, s, part);
+  multi_dot_finish_kernel<<<dim3(1), dim3(64), 0, st>>>(part, kKrylovBlocks, j, h);
+  return hipGetLastError();
+}
+
+hipError_t k_multi_axpy(double* w, double s, const double* V, int64_t ld, int j, const double* h, int64_t n,
+                        hipStream_t st) {
+  multi_axpy_kernel<<<dim3(stream_blocks(n)), dim3(256), 0, st>>>(w, s, V, ld, j, h, n);
+  return hipGetLastError();
+}
+
+hipError_t k_scale_copy(const double* w, double a, double* v, int64_t n, hipStream_t st) {
+  scale_copy_kernel<<<dim3(stream_blocks(n)), dim3(256), 0, st>>>(w, a, v, n);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void zero_kernel(T* v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = T(0);
 }
 
 template <class T>

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libfcgmg.so")
 CACHE_INVERSE, CACHE_MATRIX, CACHE_NONE = 0, 1, 2
 POLICY_NAMES = {CACHE_INVERSE: "cache_inverse", CACHE_MATRIX: "cache_matrix", CACHE_NONE: "cache_none"}
 PREC_FP64, PREC_MIXED = 0, 1
+SOLVER_GMG, SOLVER_FGMRES = 0, 1
 
 OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, -6
 
@@ -47,6 +48,7 @@ class Params(ctypes.Structure):
         ("nu_post", ctypes.c_int), ("force", ctypes.c_int), ("bc", ctypes.c_int * 6),
         ("eta", ctypes.c_double), ("alpha_fict", ctypes.c_double), ("nitsche_beta", ctypes.c_double),
         ("omega", ctypes.c_double), ("ubar", ctypes.c_double), ("precision", ctypes.c_int),
+        ("solver", ctypes.c_int), ("krylov_restart", ctypes.c_int),
     ]
 
 
@@ -153,7 +155,8 @@ def _dptr(t, name: str, numel: int):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -> Params:
+def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64, solver: int = SOLVER_GMG,
+                krylov_restart: int = 30) -> Params:
     p = Params()
     p.dim = prob.dim
     p.n_cells = prob.n_cells
@@ -171,13 +174,16 @@ def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -
     p.omega = prob.omega
     p.ubar = prob.ubar
     p.precision = precision
+    p.solver = solver
+    p.krylov_restart = krylov_restart
     return p
 
 
-def footprint_bytes(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64) -> int:
+def footprint_bytes(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64, solver: int = SOLVER_GMG,
+                    krylov_restart: int = 30) -> int:
     """Device bytes a Hierarchy of `prob` would hold (fcgmg_footprint_bytes; host-only, no GPU)."""
     L = load()
-    prm = make_params(prob, policy, precision)
+    prm = make_params(prob, policy, precision, solver, krylov_restart)
     balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
     bp = balls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if balls.size else None
     out = ctypes.c_size_t()
@@ -188,7 +194,8 @@ def footprint_bytes(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP6
 class Hierarchy:
     """Device-resident GMG hierarchy of one finite cell Stokes problem (fcgmg_setup_hierarchy)."""
 
-    def __init__(self, prob, policy: int = CACHE_INVERSE, stream=None, precision: int = PREC_FP64):
+    def __init__(self, prob, policy: int = CACHE_INVERSE, stream=None, precision: int = PREC_FP64,
+                 solver: int = SOLVER_GMG, krylov_restart: int = 30):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fcgmg needs a GPU; none is visible")
@@ -198,7 +205,8 @@ class Hierarchy:
         self.policy = policy
         self.dim = prob.dim
         self.precision = precision
-        self._params = make_params(prob, policy, precision)
+        self.solver = solver
+        self._params = make_params(prob, policy, precision, solver, krylov_restart)
         balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
         self._balls = balls
         h = ctypes.c_void_p()
@@ -353,9 +361,10 @@ class Server:
         self.h = h
         self._out = {}
 
-    def submit(self, prob, policy: int = -1, precision: int = PREC_FP64, rtol: float = 1e-8) -> int:
+    def submit(self, prob, policy: int = -1, precision: int = PREC_FP64, rtol: float = 1e-8,
+               solver: int = SOLVER_GMG, krylov_restart: int = 30) -> int:
         import torch
-        prm = make_params(prob, policy, precision)
+        prm = make_params(prob, policy, precision, solver, krylov_restart)
         balls = np.ascontiguousarray(np.asarray(prob.balls, dtype=np.float64).reshape(-1, 4))
         bp = balls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if balls.size else None
         n = (prob.dim + 1) * (prob.n_cells + 1) ** prob.dim

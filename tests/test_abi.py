@@ -59,6 +59,8 @@ def test_kernel_kinds_match_header():
     (lambda p: setattr(p, "eta", -1.0), "eta"),
     (lambda p: setattr(p, "quad_depth", 9), "quad_depth"),
     (lambda p: setattr(p, "precision", 5), "precision"),
+    (lambda p: setattr(p, "solver", 3), "solver"),
+    (lambda p: (setattr(p, "solver", 1), setattr(p, "krylov_restart", 64)), "krylov_restart"),
     (lambda p: (setattr(p, "precision", 1), setattr(p, "cache_policy", 1)), "mixed precision"),
 ])
 def test_setup_rejects_bad_arguments_on_host(mutate, msg):
