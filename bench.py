@@ -235,18 +235,25 @@ def policy_extras(torch, fcgmg, prob, sweeps=4):
 
 
 def precision_extra(torch, fcgmg, prob, solves=5):
-    """FP64 solve against the mixed-precision solve (FP32 V-cycles inside FP64 iterative refinement)
-    on one workload: time to 1e-8, cycles, the FP32 cycle alone, and the distance of the mixed
-    iterate from the FP64 one."""
+    """Time to 1e-8 on one workload for the standalone FP64 GMG, the mixed-precision GMG (FP32 V-cycles
+    inside FP64 iterative refinement) and FGMRES(30) preconditioned by one FP64 or FP32 V-cycle:
+    cycles, the cycle alone, and the distance of each iterate from the FP64 GMG one."""
     out = {"workload": prob.name}
     xs = {}
-    for prec, tag in ((fcgmg.PREC_FP64, "fp64"), (fcgmg.PREC_MIXED, "mixed")):
-        h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE, precision=prec)
+    for prec, solver, tag in ((fcgmg.PREC_FP64, fcgmg.SOLVER_GMG, "fp64"), (fcgmg.PREC_MIXED, fcgmg.SOLVER_GMG, "mixed"),
+                              (fcgmg.PREC_FP64, fcgmg.SOLVER_FGMRES, "fgmres_fp64"),
+                              (fcgmg.PREC_MIXED, fcgmg.SOLVER_FGMRES, "fgmres_mixed")):
+        h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE, precision=prec, solver=solver)
         b = h.rhs()
         h.solve(b, rtol=1e-8, max_iter=200)
         ms, its, rels = time_solves(torch, h, b, solves)
         x, _, _, _, _ = h.solve(b, rtol=1e-8, max_iter=200)
         xs[tag] = x.cpu().numpy()
+        if solver == fcgmg.SOLVER_FGMRES:
+            out[tag] = {"solve_ms_p50": round(pct(ms, 50), 3), "solve_ms_p99": round(pct(ms, 99), 3),
+                        "cycles": int(np.median(its)), "rel_res": float(np.max(rels)), "device_bytes": h.device_bytes()}
+            h.close()
+            continue
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         if prec == fcgmg.PREC_MIXED:
@@ -268,16 +275,17 @@ def precision_extra(torch, fcgmg, prob, solves=5):
                     "cycles": int(np.median(its)), "rel_res": float(np.max(rels)),
                     "cycle_us": round(e0.elapsed_time(e1) / 10 * 1e3, 1), "device_bytes": h.device_bytes()}
         h.close()
-    out["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(xs["mixed"] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
-    out["speedup"] = round(out["fp64"]["solve_ms_p50"] / out["mixed"]["solve_ms_p50"], 3)
+    for tag in ("mixed", "fgmres_fp64", "fgmres_mixed"):
+        out[tag]["rel_diff_vs_fp64_gmg"] = float(np.linalg.norm(xs[tag] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+        out[tag]["speedup_vs_fp64_gmg"] = round(out["fp64"]["solve_ms_p50"] / out[tag]["solve_ms_p50"], 3)
     return out
 
 
 def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0):
     """Solve server under a Poisson arrival stream: requests drawn uniformly from a pool of seeded
     obstacle problems (2D 128^2..1024^2 with 20 discs, 3D 32^3..96^3 with 40 spheres; alpha 1e-8;
-    FP64 or mixed precision per problem), tolerance 1e-8. Cold start: every hierarchy is set up by
-    its first request. Latency is submit to completion."""
+    FP64 or mixed precision per problem), FGMRES(30) preconditioned by the V-cycle, tolerance 1e-8.
+    Cold start: every hierarchy is set up by its first request. Latency is submit to completion."""
     rng = np.random.default_rng(seed)
     pool = []
     for n, lv in ((128, 5), (256, 6), (512, 7), (1024, 8)):
@@ -295,7 +303,7 @@ def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0):
         if delay > 0:
             time.sleep(delay)
         p, prec = pool[picks[k]]
-        ids.append(srv.submit(p, precision=prec))
+        ids.append(srv.submit(p, precision=prec, solver=fcgmg.SOLVER_FGMRES))
     res = [srv.wait(i)[1] for i in ids]
     wall = time.perf_counter() - t0
     resident, n_res = srv.resident()
