@@ -393,23 +393,36 @@ __device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, T* acc) {
 }
 
 // Row of L at a node with operator code op (Level::node_op): the level's reference stencil of a
-// uniform neighbourhood (staged in rm) or the node's own assembled stencil in nsten.
+// uniform neighbourhood, or the node's own assembled stencil in nsten. The reference stencils are
+// read from the packed level constants (oc->pack, FP64, rounded to T) with scalar loads: the lanes
+// with a reference stencil are taken kind by kind (a waterfall over the at most two kinds present
+// in the wavefront), so every coefficient address is wavefront-uniform.
 template <int D, bool UNR = true, class T, class XA>
-__device__ __forceinline__ void node_row_apply(const RefMats<D, T>& rm, int op, const T* __restrict__ nsten,
+__device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, int op, const T* __restrict__ nsten,
                                                XA&& xat, T* acc) {
   using R = RefLayout<D>;
   constexpr int NS = PT<D>::NST;
-  if (op < 0) {
-    const int kind = -op - 1;
-    stencil_apply<D, UNR, T>(
-        [&](int j, int o) {
-          if (j == 0) return rm.v[R::oSK + kind * NS + o];
-          if (j <= D) return rm.v[R::oSB + (kind * D + j - 1) * NS + o];
-          if (j <= 2 * D) return rm.v[R::oST + (kind * D + j - 1 - D) * NS + o];
-          return rm.v[R::oSC + o];
-        },
-        xat, acc);
-  } else {
+  bool todo = op < 0;
+  while (__ballot(todo) != 0) {
+    if (todo) {
+      const int k0 = __builtin_amdgcn_readfirstlane(-op - 1);
+      if (-op - 1 == k0) {
+        // read the lane value again inside the branch, so that the compiler keeps a scalar kind
+        const int ku = __builtin_amdgcn_readfirstlane(-op - 1);
+        cconst<double>* P = (cconst<double>*)pack;
+        stencil_apply<D, UNR, T>(
+            [&](int j, int o) -> T {
+              if (j == 0) return (T)P[R::oSK + ku * NS + o];
+              if (j <= D) return (T)P[R::oSB + (ku * D + j - 1) * NS + o];
+              if (j <= 2 * D) return (T)P[R::oST + (ku * D + j - 1 - D) * NS + o];
+              return (T)P[R::oSC + o];
+            },
+            xat, acc);
+        todo = false;
+      }
+    }
+  }
+  if (op >= 0) {
     // the stored row streams from memory: the loop over offsets stays partly rolled so that its
     // loads do not all occupy registers at once
     const T* p = nsten + (int64_t)op * PT<D>::NSTEN;
@@ -480,7 +493,6 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
   constexpr int NXL = ((D + 1) * XP + 255) / 256;
   __shared__ T xs[(D + 1) * XP];
-  __shared__ RefMats<D, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
@@ -506,7 +518,6 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
     const bool ok = e < (D + 1) * XP && gx >= 0 && gx < m && gy >= 0 && gy < m && (D == 2 || (gz >= 0 && gz < m));
     xv[k] = ok ? x[f * N + (D == 2 ? gx + (int64_t)m * gy : gx + (int64_t)m * (gy + (int64_t)m * gz))] : T(0);
   }
-  stage_refmats<D, 256, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + 256 * k < (D + 1) * XP) xs[threadIdx.x + 256 * k] = xv[k];
@@ -516,7 +527,7 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   T acc[D + 1];
 #pragma unroll
   for (int f = 0; f <= D; ++f) acc[f] = 0;
-  node_row_apply<D, true, T>(rm, op, nsten,
+  node_row_apply<D, true, T>(oc->pack, op, nsten,
                     [&](int f, const int* o) {
                       return xs[f * XP + base + o[0] + XW * (o[1] + (D == 3 ? XH * o[2] : 0))];
                     },

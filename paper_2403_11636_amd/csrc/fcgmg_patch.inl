@@ -859,7 +859,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
   constexpr int CAP = 4 * NG;                             // individual patches per part (two trips)
   __shared__ int irr_tid[NWO * 64], irr_pidx[NWO * 64];
   __shared__ int irr_wcnt[NWO];
-  __shared__ RefMats<2, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -907,7 +906,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
     opv[k] = ok ? node_op[cx + (int64_t)m * cy] : -1;
   }
-  stage_refmats<2, NT, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
@@ -926,12 +924,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
         for (int f = 0; f < 3; ++f) bv[f] = b[f * N + g];
         const int xb = (px + 1) + XW * (py + 1);
         T acc[3] = {0, 0, 0};
-        // an offset the compiler cannot see through: keeps it from holding the level constants of
-        // several residual nodes in registers at once (they are read from LDS where they are used)
-        int ro = 0;
-        asm volatile("" : "+s"(ro));
-        const RefMats<2, T>& rmk = *reinterpret_cast<const RefMats<2, T>*>(reinterpret_cast<const char*>(&rm) + ro);
-        node_row_apply<2, true, T>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+        node_row_apply<2, true, T>(oc->pack, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                           acc);
 #pragma unroll
         for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
@@ -1091,7 +1084,6 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
   constexpr int NRES = (RP + NT - 1) / NT, NXL = (3 * XP + NT - 1) / NT;
   __shared__ T xs[3 * XP];
   __shared__ T rs[3 * RP];
-  __shared__ RefMats<2, T> rm;
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -1122,7 +1114,6 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
 #pragma unroll
     for (int f = 0; f < 3; ++f) bv[k][f] = ok ? b[f * N + g] : T(0);
   }
-  stage_refmats<2, NT, T>(oc, rm);
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
@@ -1137,10 +1128,7 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
       if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
         const int xb = (px + 1) + XW * (py + 1);
         T acc[3] = {0, 0, 0};
-        int ro = 0;  // opaque offset: no hoisting of the level constants (see the fused sweep)
-        asm volatile("" : "+s"(ro));
-        const RefMats<2, T>& rmk = *reinterpret_cast<const RefMats<2, T>*>(reinterpret_cast<const char*>(&rm) + ro);
-        node_row_apply<2, true, T>(rmk, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+        node_row_apply<2, true, T>(oc->pack, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                           acc);
 #pragma unroll
         for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
