@@ -103,6 +103,20 @@ def config3(seed: int = 0, n_cells: int = 64, n_levels: int = 5) -> Problem:
                    name=f"3d_40spheres_{n_cells}_seed{seed}")
 
 
+def batch_problem(seed: int) -> Problem:
+    """One problem of the batching workload: 2D, n = 32 m cells per axis with m ~ U{2..8} (64..256),
+    6 levels (coarsest 2..8 cells), 1..12 seeded discs r ~ U[0.02, 0.06], alpha_f in
+    {1e-6, 1e-8, 1e-10}, inflow left, do-nothing right, no-slip top/bottom."""
+    rng = np.random.default_rng(1000 + seed)
+    n_cells = 32 * int(rng.integers(2, 9))
+    n_balls = int(rng.integers(1, 13))
+    alpha = float((1e-6, 1e-8, 1e-10)[int(rng.integers(0, 3))])
+    balls = place_balls(rng, 2, n_balls, 0.02, 0.06)
+    return Problem(dim=2, n_cells=n_cells, n_levels=6, balls=balls, alpha_fict=alpha,
+                   bcs=(INFLOW, NEUMANN, NOSLIP, NOSLIP, NOSLIP, NOSLIP),
+                   name=f"2d_batch_{n_cells}_{n_balls}discs_seed{seed}")
+
+
 def small_problem(dim: int, n_cells: int, n_levels: int, seed: int, n_balls: int = 2,
                   rmin: float = 0.08, rmax: float = 0.18, bcs=None, alpha_fict: float = 1e-8,
                   force: int = 1) -> Problem:
