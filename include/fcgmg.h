@@ -199,6 +199,25 @@ int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
  * Cost: one pass over the cells of every level. Errors: E_ARG as set-up. */
 int fcgmg_footprint_bytes(const fcgmg_params* prm, const double* balls, int n_balls, size_t* bytes);
 
+/* ---- Batched cycles: many independent 2D problems per launch ---------------------------------
+ * The hierarchies (2D, cache_inverse, FP64, equal even nu_pre and nu_post >= 2, each at most once)
+ * stay owned by the caller and must outlive the batch. Every step of the V-cycle of Sec. 3 runs as
+ * one launch over all problems taking part: depth d of the cycle works on level n_levels - 1 - d of
+ * each problem, and the coarsest solves of all problems share one launch. Each problem's result is
+ * bitwise the one of fcgmg_vcycle on its own. x, b: HOST arrays of `count` device pointers to the
+ * finest-level vectors of the problems, in the order of hs. */
+typedef struct fcgmg_batch* fcgmg_batch_h;
+int fcgmg_batch_create(const fcgmg_h* hs, int count, fcgmg_batch_h* out);
+/* One V-cycle on every problem; x updated in place. */
+int fcgmg_batch_vcycle(fcgmg_batch_h bt, double* const* x, const double* const* b, void* stream);
+/* Standalone GMG on every problem (as fcgmg_solve with the GMG solver), with the residual norms of
+ * all problems from one launch and one synchronisation per cycle; a problem leaves the batch when it
+ * meets its stopping test. iters, rel_res: HOST arrays of `count`. E_NOCONV if any problem did not
+ * converge in max_iter cycles (the others are converged and their x final). */
+int fcgmg_batch_solve(fcgmg_batch_h bt, double* const* x, const double* const* b, double rtol, int max_iter,
+                      int* iters, double* rel_res, void* stream);
+int fcgmg_batch_destroy(fcgmg_batch_h bt);
+
 /* ---- Solve server: concurrent solves with device-resident hierarchies ------------------------
  * Worker threads (one HIP stream each) take requests in arrival order. A request runs on a resident
  * hierarchy of the same problem when one is idle; otherwise it is admitted once its footprint

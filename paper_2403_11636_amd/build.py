@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfcgmg.so")
 
-SOURCES = ["fcgmg_kernels.hip", "fcgmg_api.cpp", "fcgmg_serve.cpp"]
+SOURCES = ["fcgmg_kernels.hip", "fcgmg_api.cpp", "fcgmg_serve.cpp", "fcgmg_batch.cpp"]
 HEADERS = ["fcgmg_impl.h", "fcgmg_patch.inl"]
 
 

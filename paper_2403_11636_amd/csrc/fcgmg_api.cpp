@@ -902,7 +902,6 @@ bool valid_level(const Ctx* c, int l) { return c && l >= 0 && l < (int)c->lev.si
 
 }  // namespace
 
-struct fcgmg_ctx : public Ctx {};
 
 int fcg::set_error(int code, const std::string& msg) { return fail(code, msg); }
 

@@ -129,6 +129,58 @@ struct Level {
   float* xalt32 = nullptr;
 };
 
+// One fused 2D sweep over one level (the kernel's arguments; a batched launch takes an array).
+template <class T>
+struct Fused2Job {
+  const OpConsts* oc;
+  const int* node_op;
+  const T* nsten;
+  const int* extra;       // extra parts of split tiles (plan_fused2), or null
+  const int* node_class;
+  const T* Zcls;
+  const T* Zirr;
+  const T* x_in;
+  const T* b;
+  T* x_out;
+  const T* xc;            // coarse vector of mode 2
+  T omega;
+  int ntx, nty, mode;
+  int block0;             // first workgroup of the job in a batched launch
+};
+
+// One fused residual + restriction (2D), fine level F to F-1.
+template <class T>
+struct RR2Job {
+  const OpConsts* oc;
+  const int* node_op;
+  const T* nsten;
+  const T* x;
+  const T* b;
+  T* bc;
+  int ntx, nty;
+  int block0;
+};
+
+// One dense matvec x = A b of a coarsest level in a batched launch (4 rows per workgroup).
+struct DenseJob {
+  const double* A;
+  const double* b;
+  double* x;
+  int n;
+  int block0;
+};
+
+// ||b - L x||^2 of one 2D problem in a batched launch: workgroups block0 .. block0 + nblocks - 1.
+struct NormJob {
+  const OpConsts* oc;
+  const int* node_op;
+  const double* nsten;
+  const double* x;
+  const double* b;
+  int ntx, nty;
+  int block0, nblocks;
+};
+
 // The level data a kernel of value type T reads and writes.
 template <class T>
 struct LV;
@@ -362,6 +414,19 @@ template <class T>
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
                           hipStream_t s);
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra);
+// Batched launches over independent 2D problems (one tile shape for all jobs)
+int batch_fused2_blocks(const Level& L);
+Fused2Job<double> batch_fused2_job(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                                   int mode, const double* xc);
+int batch_rr2_blocks(const Level& F);
+RR2Job<double> batch_rr2_job(const Level& F, const double* x, const double* b, double* bc);
+hipError_t k_batch_fused2(const Fused2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s);
+hipError_t k_batch_rr2(const RR2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s);
+hipError_t k_batch_dense(const DenseJob* jobs, const int* block_job, int nblocks, hipStream_t s);
+int batch_norm_blocks(const Level& L);
+NormJob batch_norm_job(const Level& L, const double* x, const double* b);
+hipError_t k_batch_sumsq(const NormJob* jobs, int njobs, const int* block_job, int nblocks, double* part, double* out,
+                         hipStream_t s);
 // Set the calling thread's error message (fcgmg_last_error) and return `code`.
 int set_error(int code, const std::string& msg);
 template <class T>
@@ -396,3 +461,6 @@ template <int D> int pattern_size();
 template <int D> void pattern_entries(std::vector<int>& enc);
 
 }  // namespace fcg
+
+// The library handle (fcgmg_h) is the context of one hierarchy.
+struct fcgmg_ctx : public fcg::Ctx {};

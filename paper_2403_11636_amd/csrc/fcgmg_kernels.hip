@@ -536,6 +536,96 @@ __global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __re
   for (int f = 0; f <= D; ++f) r[f * N + node] = bv[f] - acc[f];
 }
 
+// Batched ||b - L x||^2 over independent 2D problems: one 32 x 8 tile per workgroup (the residual
+// arithmetic of residual_tile_kernel), its partial sum written to part[block]; then one workgroup
+// per job adds its partials in a fixed order.
+__global__ void __launch_bounds__(256) residual_sumsq2_batch_kernel(const NormJob* __restrict__ jobs,
+                                                                    const int* __restrict__ block_job,
+                                                                    double* __restrict__ part) {
+  constexpr int TX = TileShape<2>::TX, TY = TileShape<2>::TY;
+  constexpr int XW = TX + 2, XH = TY + 2, XP = XW * XH;
+  constexpr int NXL = (3 * XP + 255) / 256;
+  __shared__ double xs[3 * XP];
+  __shared__ double sh[4];
+  const NormJob J = jobs[block_job[blockIdx.x]];
+  const int bid = (int)blockIdx.x - J.block0;
+  const int n = J.oc->n;
+  const int m = n + 1;
+  const int64_t N = (int64_t)m * m;
+  const int nt[3] = {J.ntx, J.nty, 1};
+  int t[3];
+  tile_coords<2>(bid, nt, t);
+  const int o0 = t[0] * TX - 1, o1 = t[1] * TY - 1;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int c[3] = {t[0] * TX + tx, t[1] * TY + ty, 0};
+  const bool inside = c[0] < m && c[1] < m;
+  const int64_t node = c[0] + (int64_t)m * c[1];
+  double bv[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) bv[f] = inside ? J.b[f * N + node] : 0.0;
+  const int op = inside ? J.node_op[node] : -1;
+  double xv[NXL];
+#pragma unroll
+  for (int k = 0; k < NXL; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    const int f = e / XP, p = e % XP;
+    const int gx = o0 + p % XW, gy = o1 + p / XW;
+    const bool ok = e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m;
+    xv[k] = ok ? J.x[f * N + gx + (int64_t)m * gy] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < NXL; ++k)
+    if (threadIdx.x + 256 * k < 3 * XP) xs[threadIdx.x + 256 * k] = xv[k];
+  __syncthreads();
+  double ss = 0;
+  if (inside) {
+    const int base = (tx + 1) + XW * (ty + 1);
+    double acc[3] = {0, 0, 0};
+    node_row_apply<2, true, double>(J.oc->pack, op, J.nsten,
+                                    [&](int f, const int* o) { return xs[f * XP + base + o[0] + XW * o[1]]; }, acc);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const double r = bv[f] - acc[f];
+      ss += r * r;
+    }
+  }
+  ss = wave_sum(ss);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void finish_batch_sumsq_kernel(const NormJob* __restrict__ jobs, const double* __restrict__ part,
+                                          double* __restrict__ out) {
+  const NormJob J = jobs[blockIdx.x];
+  __shared__ double sh[4];
+  double s = 0;
+  for (int i = threadIdx.x; i < J.nblocks; i += blockDim.x) s += part[J.block0 + i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+int batch_norm_blocks(const Level& L) {
+  const int m = L.n + 1;
+  return ((m + TileShape<2>::TX - 1) / TileShape<2>::TX) * ((m + TileShape<2>::TY - 1) / TileShape<2>::TY);
+}
+
+NormJob batch_norm_job(const Level& L, const double* x, const double* b) {
+  const int m = L.n + 1;
+  return NormJob{L.consts, L.node_op, L.nsten, x, b, (m + TileShape<2>::TX - 1) / TileShape<2>::TX,
+                 (m + TileShape<2>::TY - 1) / TileShape<2>::TY, 0, 0};
+}
+
+hipError_t k_batch_sumsq(const NormJob* jobs, int njobs, const int* block_job, int nblocks, double* part, double* out,
+                         hipStream_t s) {
+  if (njobs == 0) return hipSuccess;
+  residual_sumsq2_batch_kernel<<<dim3((unsigned)nblocks), dim3(256), 0, s>>>(jobs, block_job, part);
+  finish_batch_sumsq_kernel<<<dim3((unsigned)njobs), dim3(256), 0, s>>>(jobs, part, out);
+  return hipGetLastError();
+}
+
 template <int D>
 void tile_grid(int n, int* nt) {
   nt[0] = (n + 1 + TileShape<D>::TX - 1) / TileShape<D>::TX;
@@ -761,6 +851,18 @@ template <class T>
 __global__ void dense_matvec_kernel(const T* __restrict__ A, int n, const T* __restrict__ b, T* __restrict__ x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row < n) dense_row(A, n, b, x, row, threadIdx.x & 63);
+}
+
+__global__ void dense_matvec_batch_kernel(const DenseJob* __restrict__ jobs, const int* __restrict__ block_job) {
+  const DenseJob J = jobs[block_job[blockIdx.x]];
+  const int row = ((int)blockIdx.x - J.block0) * 4 + (threadIdx.x >> 6);
+  if (row < J.n) dense_row(J.A, J.n, J.b, J.x, row, threadIdx.x & 63);
+}
+
+hipError_t k_batch_dense(const DenseJob* jobs, const int* block_job, int nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  dense_matvec_batch_kernel<<<dim3((unsigned)nblocks), dim3(256), 0, s>>>(jobs, block_job);
+  return hipGetLastError();
 }
 
 template <class T>

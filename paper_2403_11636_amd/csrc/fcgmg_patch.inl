@@ -834,20 +834,22 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
 // mode 0: x_in as given; mode 1: x_in is zero (not read; the first sweep on a coarse level);
 // mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
 // V-cycle applied as the x tile is loaded, as prolong_add would apply it).
-template <int TX, int TY, int NT, int WPE, class T>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) sweep_fused2_kernel(
-    const OpConsts* __restrict__ oc,
-                                                          const int* __restrict__ node_op,
-                                                          const T* __restrict__ nsten, int ntx, int nty,
-                                                          const int* __restrict__ extra,
-                                                          const int* __restrict__ node_class,
-                                                          const T* __restrict__ Zcls,
-                                                          const T* __restrict__ Zirr,
-                                                          const T* __restrict__ x_in,
-                                                          const T* __restrict__ b,
-                                                          T* __restrict__ x_out, T omega, int mode,
-                                                          const T* __restrict__ xc) {
+template <int TX, int TY, int NT, class T>
+__device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
+  const OpConsts* __restrict__ oc = J.oc;
+  const int* __restrict__ node_op = J.node_op;
+  const T* __restrict__ nsten = J.nsten;
+  const int* __restrict__ extra = J.extra;
+  const int* __restrict__ node_class = J.node_class;
+  const T* __restrict__ Zcls = J.Zcls;
+  const T* __restrict__ Zirr = J.Zirr;
+  const T* __restrict__ x_in = J.x_in;
+  const T* __restrict__ b = J.b;
+  T* __restrict__ x_out = J.x_out;
+  const T* __restrict__ xc = J.xc;
+  const T omega = J.omega;
+  const int ntx = J.ntx, nty = J.nty, mode = J.mode;
   constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
   constexpr int RW = TX + 4, RH = TY + 4, RP = RW * RH;  // residual tile, halo 2
   constexpr int ZSP = PT<2>::ZSP;
@@ -865,13 +867,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
   // Workgroups 0 .. ntx*nty-1 are part 0 of every tile (XCD-aware order); further workgroups are
   // extra parts of tiles with more than CAP individual patches (code tile * 4 + part, set-up).
   int tile_lin, part = 0;
-  if ((int)blockIdx.x < ntx * nty) {
+  if (bid < ntx * nty) {
     const int nt[3] = {ntx, nty, 1};
     int t[3];
-    tile_coords<2>(blockIdx.x, nt, t);
+    tile_coords<2>(bid, nt, t);
     tile_lin = t[0] + ntx * t[1];
   } else {
-    const int code = extra[blockIdx.x - ntx * nty];
+    const int code = extra[bid - ntx * nty];
     tile_lin = code >> 2;
     part = code & 3;
   }
@@ -995,6 +997,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)
   }
 }
 
+template <int TX, int TY, int NT, int WPE, class T>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+sweep_fused2_kernel(Fused2Job<T> J) {
+  fused2_body<TX, TY, NT, T>(J, (int)blockIdx.x);
+}
+
+// Batched form: the workgroups of several jobs (levels of independent problems) in one launch;
+// block_job maps a workgroup to its job, whose workgroups start at job.block0.
+template <int TX, int TY, int NT, int WPE, class T>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+sweep_fused2_batch_kernel(const Fused2Job<T>* __restrict__ jobs, const int* __restrict__ block_job) {
+  const Fused2Job<T> J = jobs[block_job[blockIdx.x]];
+  fused2_body<TX, TY, NT, T>(J, (int)blockIdx.x - J.block0);
+}
+
 // Tile shapes of the fused 2D sweep by level size (nodes): 32 x 8 tiles by 256 threads from
 // kFusedBigTileNodes on, 8 x 4 by 128 from kFusedMidTileNodes on, 4 x 4 by 128 below.
 constexpr int64_t kFusedBigTileNodes = 200000;
@@ -1052,9 +1069,10 @@ template <int TX, int TY, int NT, int WPE, class T>
 hipError_t launch_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out,
                          int mode, const T* xc, hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
-  sweep_fused2_kernel<TX, TY, NT, WPE, T><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(
-      L.consts, L.node_op, LV<T>::nsten(L), ntx, nty, L.fused_extra, L.node_class, LV<T>::Zcls(L), LV<T>::Zirr(L), x_in,
-      b, x_out, (T)c.prm.omega, mode, xc);
+  const Fused2Job<T> J{L.consts, L.node_op,   LV<T>::nsten(L), L.fused_extra, L.node_class, LV<T>::Zcls(L),
+                       LV<T>::Zirr(L), x_in,   b,               x_out,         xc,           (T)c.prm.omega,
+                       ntx,            nty,    mode,            0};
+  sweep_fused2_kernel<TX, TY, NT, WPE, T><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(J);
   return hipGetLastError();
 }
 
@@ -1072,13 +1090,15 @@ hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* 
 // computed into LDS from an x tile with halo 1; arithmetic and summation order are those of the
 // residual and restriction kernels.
 template <int TXC, int TYC, int NT, class T>
-__global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* __restrict__ oc,
-                                                                const int* __restrict__ node_op,
-                                                                const T* __restrict__ nsten, int ntx, int nty,
-                                                                const T* __restrict__ x,
-                                                                const T* __restrict__ b,
-                                                                T* __restrict__ bc) {
+__device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int bid) {
   static_assert(NT >= TXC * TYC && NT % 64 == 0, "one thread per coarse node at least");
+  const OpConsts* __restrict__ oc = J.oc;
+  const int* __restrict__ node_op = J.node_op;
+  const T* __restrict__ nsten = J.nsten;
+  const T* __restrict__ x = J.x;
+  const T* __restrict__ b = J.b;
+  T* __restrict__ bc = J.bc;
+  const int ntx = J.ntx, nty = J.nty;
   constexpr int RW = 2 * TXC + 1, RH = 2 * TYC + 1, RP = RW * RH;  // fine residual region
   constexpr int XW = RW + 2, XH = RH + 2, XP = XW * XH;            // x region, halo 1
   constexpr int NRES = (RP + NT - 1) / NT, NXL = (3 * XP + NT - 1) / NT;
@@ -1091,7 +1111,7 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
   const int64_t Nc = (int64_t)mc * mc;
   const int nt[3] = {ntx, nty, 1};
   int t[3];
-  tile_coords<2>(blockIdx.x, nt, t);
+  tile_coords<2>(bid, nt, t);
   const int cx0 = t[0] * TXC, cy0 = t[1] * TYC;
   const int fx0 = 2 * cx0 - 1, fy0 = 2 * cy0 - 1;  // fine coordinates of residual-region entry 0
   T xv[NXL];
@@ -1159,11 +1179,23 @@ __global__ void __launch_bounds__(NT) residual_restrict2_kernel(const OpConsts* 
 }
 
 template <int TXC, int TYC, int NT, class T>
+__global__ void __launch_bounds__(NT) residual_restrict2_kernel(RR2Job<T> J) {
+  residual_restrict2_body<TXC, TYC, NT, T>(J, (int)blockIdx.x);
+}
+
+template <int TXC, int TYC, int NT, class T>
+__global__ void __launch_bounds__(NT) residual_restrict2_batch_kernel(const RR2Job<T>* __restrict__ jobs,
+                                                                      const int* __restrict__ block_job) {
+  const RR2Job<T> J = jobs[block_job[blockIdx.x]];
+  residual_restrict2_body<TXC, TYC, NT, T>(J, (int)blockIdx.x - J.block0);
+}
+
+template <int TXC, int TYC, int NT, class T>
 hipError_t launch_residual_restrict2(const Level& F, const T* x, const T* b, T* bc, hipStream_t s) {
   const int mc = (F.n >> 1) + 1;
   const int ntx = (mc + TXC - 1) / TXC, nty = (mc + TYC - 1) / TYC;
-  residual_restrict2_kernel<TXC, TYC, NT, T><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(
-      F.consts, F.node_op, LV<T>::nsten(F), ntx, nty, x, b, bc);
+  const RR2Job<T> J{F.consts, F.node_op, LV<T>::nsten(F), x, b, bc, ntx, nty, 0};
+  residual_restrict2_kernel<TXC, TYC, NT, T><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(J);
   return hipGetLastError();
 }
 
@@ -1172,6 +1204,50 @@ hipError_t k_residual_restrict2(const Ctx&, const Level& F, const T* x, const T*
   if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256, T>(F, x, b, bc, s);
   if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128, T>(F, x, b, bc, s);
   return launch_residual_restrict2<4, 4, 128, T>(F, x, b, bc, s);
+}
+
+// ---- batched launches (independent 2D problems, one launch per V-cycle step) -------------------
+// One tile shape for every job of a batched launch: 8 x 4 tiles by 128 threads (the arithmetic of a
+// node does not depend on the shape, so the results equal those of the single-problem launches).
+constexpr int kBatchTX = 8, kBatchTY = 4, kBatchNT = 128;
+
+int batch_fused2_blocks(const Level& L) {
+  const int m = L.n + 1;
+  return ((m + kBatchTX - 1) / kBatchTX) * ((m + kBatchTY - 1) / kBatchTY);
+}
+
+Fused2Job<double> batch_fused2_job(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                                   int mode, const double* xc) {
+  const int m = L.n + 1;
+  // at most TX*TY individual patches per tile = 4 * NT / 16 per part: no extra parts at this shape
+  static_assert(kBatchTX * kBatchTY <= 4 * (kBatchNT / 16), "batched tiles must not need extra parts");
+  return Fused2Job<double>{L.consts, L.node_op, L.nsten, nullptr, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc,
+                           c.prm.omega, (m + kBatchTX - 1) / kBatchTX, (m + kBatchTY - 1) / kBatchTY, mode, 0};
+}
+
+int batch_rr2_blocks(const Level& F) {
+  const int mc = (F.n >> 1) + 1;
+  return ((mc + kBatchTX - 1) / kBatchTX) * ((mc + kBatchTY - 1) / kBatchTY);
+}
+
+RR2Job<double> batch_rr2_job(const Level& F, const double* x, const double* b, double* bc) {
+  const int mc = (F.n >> 1) + 1;
+  return RR2Job<double>{F.consts, F.node_op, F.nsten, x, b, bc, (mc + kBatchTX - 1) / kBatchTX,
+                        (mc + kBatchTY - 1) / kBatchTY, 0};
+}
+
+hipError_t k_batch_fused2(const Fused2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  sweep_fused2_batch_kernel<kBatchTX, kBatchTY, kBatchNT, 5, double><<<dim3((unsigned)nblocks), dim3(kBatchNT), 0, s>>>(
+      jobs, block_job);
+  return hipGetLastError();
+}
+
+hipError_t k_batch_rr2(const RR2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  residual_restrict2_batch_kernel<kBatchTX, kBatchTY, kBatchNT, double>
+      <<<dim3((unsigned)nblocks), dim3(kBatchNT), 0, s>>>(jobs, block_job);
+  return hipGetLastError();
 }
 
 }  // namespace fcg

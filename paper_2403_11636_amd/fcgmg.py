@@ -28,7 +28,8 @@ EXPORTS = [
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
-    "fcgmg_server_destroy",
+    "fcgmg_server_destroy", "fcgmg_batch_create", "fcgmg_batch_vcycle", "fcgmg_batch_solve",
+    "fcgmg_batch_destroy",
 ]
 
 KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
@@ -105,6 +106,11 @@ def load(path: str = LIB_PATH):
     L.fcgmg_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(RequestResult)]
     L.fcgmg_server_resident_bytes.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int)]
     L.fcgmg_server_destroy.argtypes = [vp]
+    L.fcgmg_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
+    L.fcgmg_batch_vcycle.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.fcgmg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), dp, vp]
+    L.fcgmg_batch_destroy.argtypes = [vp]
     L.fcgmg_footprint_bytes.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.fcgmg_destroy.argtypes = [vp]
     L.fcgmg_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -390,6 +396,47 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             load().fcgmg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Batched V-cycles over independent 2D hierarchies (fcgmg_batch_*): one launch per cycle step for
+    all problems. The hierarchies stay owned by the caller."""
+
+    def __init__(self, hierarchies):
+        L = load()
+        self.hs = list(hierarchies)
+        arr = (ctypes.c_void_p * len(self.hs))(*[h.h.value for h in self.hs])
+        h = ctypes.c_void_p()
+        _check(L.fcgmg_batch_create(arr, len(self.hs), ctypes.byref(h)))
+        self.h = h
+
+    def _ptrs(self, vecs, name):
+        assert len(vecs) == len(self.hs)
+        return (ctypes.c_void_p * len(vecs))(*[_dptr(v, name, h.ndofs()).value for v, h in zip(vecs, self.hs)])
+
+    def vcycle(self, xs, bs, stream=None):
+        _check(load().fcgmg_batch_vcycle(self.h, self._ptrs(xs, "x"), self._ptrs(bs, "b"), _stream_ptr(stream)))
+        return xs
+
+    def solve(self, bs, xs=None, rtol: float = 1e-8, max_iter: int = 100, stream=None):
+        xs = [h.zeros() for h in self.hs] if xs is None else xs
+        n = len(self.hs)
+        its = (ctypes.c_int * n)()
+        rel = np.zeros(n)
+        rc = load().fcgmg_batch_solve(self.h, self._ptrs(xs, "x"), self._ptrs(bs, "b"), rtol, max_iter, its,
+                                      rel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream_ptr(stream))
+        return xs, list(its), rel, rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().fcgmg_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):
