@@ -328,9 +328,11 @@ def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0):
 
 def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
     """Batching workload: 256 independent 2D problems of uneven sizes (64^2..256^2, 1..12 discs,
-    alpha_f in {1e-6, 1e-8, 1e-10}), each solved to 1e-8 by FGMRES(30) with the FP64 V-cycle. Their
-    hierarchies are set up first (untimed); then all solves run one after another on one stream and,
-    separately, through the solve server's concurrent workers on resident hierarchies."""
+    alpha_f in {1e-6, 1e-8, 1e-10}). Hierarchies are set up first (untimed). Measured: FGMRES(30)
+    solves to 1e-8 one after another on one stream and through the solve server's concurrent
+    workers; one V-cycle of all 256 problems one after another and as one batched cycle (one launch
+    per cycle step); the batched standalone GMG solve (at most 60 cycles; the problems on which the
+    standalone cycle does not converge are counted, not solved)."""
     probs = [inputs.batch_problem(k) for k in range(n_prob)]
     ndof = sum((p.dim + 1) * (p.n_cells + 1) ** p.dim for p in probs)
     # sequential: one stream, resident hierarchies
@@ -346,6 +348,37 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
     t_seq = time.perf_counter() - t0
     for h in hs:
         h.close()
+    # batched: one launch per V-cycle step for all 256 problems (standalone GMG cycles)
+    hs = [fcgmg.Hierarchy(p, fcgmg.CACHE_INVERSE) for p in probs]
+    bs = [h.rhs() for h in hs]
+    xs = [h.zeros() for h in hs]
+    for h, x, b in zip(hs, xs, bs):
+        h.vcycle(x, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        for h, x, b in zip(hs, xs, bs):
+            h.vcycle(x, b)
+    torch.cuda.synchronize()
+    t_cyc_seq = (time.perf_counter() - t0) / 5
+    bt = fcgmg.Batch(hs)
+    bt.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        bt.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    t_cyc_bat = (time.perf_counter() - t0) / 5
+    xs = [h.zeros() for h in hs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, bits, brel, brc = bt.solve(bs, xs=xs, rtol=1e-8, max_iter=60)
+    torch.cuda.synchronize()
+    t_bsolve = time.perf_counter() - t0
+    bt.close()
+    for h in hs:
+        h.close()
+    conv = [i for i, r in enumerate(brel) if r <= 1e-8]
     # server: warm pass sets the hierarchies up, the timed pass hits them
     srv = fcgmg.Server(workers=workers)
     for rid in [srv.submit(p, policy=fcgmg.CACHE_INVERSE, solver=fcgmg.SOLVER_FGMRES) for p in probs]:
@@ -363,6 +396,11 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
         "server_workers": workers, "server_s": round(t_srv, 3), "server_problems_per_s": round(n_prob / t_srv, 1),
         "server_completed": ok, "server_cache_hits": int(sum(r["cache_hit"] for r in res)),
         "speedup": round(t_seq / t_srv, 3),
+        "vcycle_all_sequential_ms": round(t_cyc_seq * 1e3, 3), "vcycle_all_batched_ms": round(t_cyc_bat * 1e3, 3),
+        "batched_vcycle_dof_per_s": round(ndof * 4 / t_cyc_bat, 1),
+        "batched_vcycle_speedup": round(t_cyc_seq / t_cyc_bat, 2),
+        "batched_gmg_solve_s": round(t_bsolve, 3), "batched_gmg_converged": len(conv),
+        "batched_gmg_cycles_median": int(np.median([bits[i] for i in conv])) if conv else None,
     }
 
 
