@@ -151,6 +151,21 @@ def dominant_kernel(torch, h, x, b, steps, d):
     (kind, lev), (tot, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
     total_all = sum(v[0] for v in prof.values())
     avg_ms = tot / cnt
+    timing = "per-launch events of the library profiler"
+    if kind == "sweep_fused" and lev == h.fine:
+        # the fine-level fused sweep alone: 50 smoother calls of two fused launches each between one
+        # pair of events on the launch stream (no per-launch events in the timed region)
+        h.smooth(x, b, 2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(50):
+            h.smooth(x, b, 2)
+        e1.record()
+        torch.cuda.synchronize()
+        avg_ms = e0.elapsed_time(e1) / 100
+        timing = "100 back-to-back launches between two events"
     st = h.stats(lev)
     nbytes = algorithmic_bytes(kind, d, st)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
@@ -159,7 +174,7 @@ def dominant_kernel(torch, h, x, b, steps, d):
     return {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"{kind}@L{lev}"),
-        "kernel": f"{kind}@L{lev}", "avg_launch_us": round(avg_ms * 1e3, 3),
+        "kernel": f"{kind}@L{lev}", "avg_launch_us": round(avg_ms * 1e3, 3), "avg_launch_timing": timing,
         "algorithmic_bytes_per_launch": int(nbytes), "time_share": round(tot / total_all, 4),
     }, table
 
