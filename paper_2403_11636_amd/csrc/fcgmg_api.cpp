@@ -573,7 +573,8 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if ((rc = alloc_n(c, &c.kw, nd))) return rc;
     if ((rc = alloc_n(c, &c.kzero, nd))) return rc;
     if ((rc = alloc_n(c, &c.kpart, (size_t)kKrylovPartials))) return rc;
-    if ((rc = alloc_n(c, &c.kh, (size_t)128))) return rc;
+    if ((rc = alloc_n(c, &c.kh, (size_t)192))) return rc;
+    FCG_HIP(hipHostMalloc((void**)&c.kh_host, 192 * sizeof(double), hipHostMallocDefault));
     FCG_HIP(k_zero<double>(c.kzero, (int64_t)nd, s));
     FCG_HIP(hipStreamSynchronize(s));
   }
@@ -775,7 +776,7 @@ size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
   if (P.solver == FCGMG_SOLVER_FGMRES) {
     int64_t N = 1;
     for (int k = 0; k < D; ++k) N *= P.n_cells + 1;
-    bytes += ((size_t)(2 * P.krylov_restart + 3) * (D + 1) * N + kKrylovPartials + 128) * sizeof(double);
+    bytes += ((size_t)(2 * P.krylov_restart + 3) * (D + 1) * N + kKrylovPartials + 192) * sizeof(double);
   }
   return bytes;
 }
@@ -831,13 +832,15 @@ int fgmres_impl(const Ctx& c, double* x, const double* b, double rtol, int max_i
       // first pass: h = V^T (A z) = -V^T w; w <- A z - V h = -w - V h
       FCG_HIP(k_multi_dot(c.kv, nd, j + 1, c.kw, nd, -1.0, c.kpart, c.kh, s));
       FCG_HIP(k_multi_axpy(c.kw, -1.0, c.kv, nd, j + 1, c.kh, nd, s));
-      FCG_HIP(hipMemcpyAsync(h.data(), c.kh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      FCG_HIP(hipMemcpyAsync(c.kh_host, c.kh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       // second pass: h2 = V^T w; w <- w - V h2
       FCG_HIP(k_multi_dot(c.kv, nd, j + 1, c.kw, nd, 1.0, c.kpart, c.kh + 64, s));
       FCG_HIP(k_multi_axpy(c.kw, 1.0, c.kv, nd, j + 1, c.kh + 64, nd, s));
-      FCG_HIP(hipMemcpyAsync(h2.data(), c.kh + 64, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      FCG_HIP(hipMemcpyAsync(c.kh_host + 64, c.kh + 64, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       double hn;
       if ((rc = norm_impl(c, c.kw, nd, &hn, s))) return rc;  // synchronises: h, h2 are on the host
+      std::copy(c.kh_host, c.kh_host + j + 1, h.begin());
+      std::copy(c.kh_host + 64, c.kh_host + 64 + j + 1, h2.begin());
       ++its;
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
       H[(size_t)(j + 1) * m + j] = hn;
@@ -873,8 +876,8 @@ int fgmres_impl(const Ctx& c, double* x, const double* b, double rtol, int max_i
       for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
       y[i] = acc / H[(size_t)i * m + i];
     }
-    for (int i = 0; i < k; ++i) y[i] = -y[i];  // multi_axpy subtracts
-    FCG_HIP(hipMemcpyAsync(c.kh, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    for (int i = 0; i < k; ++i) c.kh_host[128 + i] = -y[i];  // multi_axpy subtracts
+    FCG_HIP(hipMemcpyAsync(c.kh, c.kh_host + 128, k * sizeof(double), hipMemcpyHostToDevice, s));
     FCG_HIP(k_multi_axpy(x, 1.0, c.kz, nd, k, c.kh, nd, s));
     if ((rc = residual_impl<D>(c, top, x, b, Vv(0), s))) return rc;
     if ((rc = norm_impl(c, Vv(0), nd, &beta, s))) return rc;  // synchronises: y may be reused
@@ -948,6 +951,7 @@ void fcgmg_destroy(fcgmg_h h) {
   for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->red_host) (void)hipHostFree(h->red_host);
+  if (h->kh_host) (void)hipHostFree(h->kh_host);
   delete h;
 }
 

@@ -220,6 +220,7 @@ struct Ctx {
   double* kzero = nullptr;
   double* kpart = nullptr;
   double* kh = nullptr;
+  double* kh_host = nullptr;     // pinned host copy of kh (coefficients h, h2 and y)
   int coarse_n = 0;
   bool bordered = false;
   double* red = nullptr;         // reduction scratch

@@ -918,20 +918,33 @@ static unsigned stream_blocks(int64_t n) {
 // ================================================================================================
 constexpr int kKrylovBlocks = 256;
 
-// part[blk * j + i] = s * sum over this block's slice of V_i . w, for i < j (V_i = V + i * ld)
+// part[blk * j + i] = s * sum over this block's slice of V_i . w, for i < j (V_i = V + i * ld):
+// w is read once per chunk of up to 16 basis vectors, each thread keeping 16 running sums.
+constexpr int kDotChunk = 16;
 __global__ void __launch_bounds__(256) multi_dot_kernel(const double* __restrict__ V, int64_t ld, int j,
                                                         const double* __restrict__ w, int64_t n, double s,
                                                         double* __restrict__ part) {
-  __shared__ double sh[4];
-  for (int i = 0; i < j; ++i) {
-    const double* vi = V + i * ld;
-    double acc = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-      acc += vi[k] * w[k];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __shared__ double sh[4][kDotChunk];
+  for (int i0 = 0; i0 < j; i0 += kDotChunk) {
+    const int cnt = min(kDotChunk, j - i0);
+    double acc[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) acc[q] = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; ++q)
+        if (q < cnt) acc[q] += V[(i0 + q) * ld + k] * wk;
+    }
+#pragma unroll
+    for (int q = 0; q < kDotChunk; ++q) {
+      const double v = wave_sum(acc[q]);
+      if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x * j + i] = s * (sh[0] + sh[1] + sh[2] + sh[3]);
+    if (threadIdx.x < cnt)
+      part[blockIdx.x * j + i0 + threadIdx.x] =
+          s * (sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x]);
     __syncthreads();
   }
 }
