@@ -392,14 +392,88 @@ __device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, T* acc) {
   }
 }
 
-// Row of L at a node with operator code op (Level::node_op): the level's reference stencil of a
-// uniform neighbourhood, or the node's own assembled stencil in nsten. The reference stencils are
-// read from the packed level constants (oc->pack, FP64, rounded to T) with scalar loads: the lanes
-// with a reference stencil are taken kind by kind (a waterfall over the at most two kinds present
-// in the wavefront), so every coefficient address is wavefront-uniform.
+// Stored 2D stencil (layout of Level::nsten at p): the six coefficients of offset o, and the terms
+//   t_f = SK_o u_f(o) + SB_f,o p(o) (f < 2),  t_2 = ST_0,o u_0(o) + ST_1,o u_1(o) + SC_o p(o)
+// with u = x at the node + o. The fused multiply-adds are explicit, and contraction is off here
+// and in the sums of the terms below, so that every form of the row sum rounds alike in every
+// kernel.
+template <class T>
+__device__ __forceinline__ void stored_coefs2(const T* __restrict__ p, int o, T* c) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) c[j] = p[j * 9 + o];
+}
+
+template <class T>
+__device__ __forceinline__ void stored_terms2(const T* c, T u0, T u1, T u2, T* t) {
+#pragma clang fp contract(off)
+  t[0] = fma(c[0], u0, c[1] * u2);
+  t[1] = fma(c[0], u1, c[2] * u2);
+  t[2] = fma(c[5], u2, fma(c[4], u1, c[3] * u0));
+}
+
+// Marks the values as used here: loads issued before are all in flight together, since the
+// scheduler cannot move them past this point to shorten register lifetimes.
+template <class T, int K>
+__device__ __forceinline__ void in_flight_together(T (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) asm volatile("" : "+v"(v[k]));
+}
+
+// Row of a stored 2D stencil at p, one lane: the offset terms summed in the order of a butterfly
+// over 16 lanes (lane = offset, lanes 9..15 empty; partners at distance 8, 4, 2, 1):
+//   R(l, 8) = t_l + t_(l+8),  R(l, s) = R(l, 2s) + R(l+s, 2s),  row = R(0, 1)
+//   = (((t0 + t8) + t4) + (t2 + t6)) + ((t1 + t5) + (t3 + t7)),
+// so that the 8-lane form (stored_rows_group2), which starts from R(l, 8), gives the same bits. The
+// coefficients load in three batches of three offsets.
+template <class T, class XA>
+__device__ __forceinline__ void stored_row2(const T* __restrict__ p, XA&& xat, T* row) {
+#pragma clang fp contract(off)
+  auto terms = [&](const T* c, int o, T* t) {
+    const int oo[3] = {o % 3 - 1, o / 3 - 1, 0};
+    stored_terms2<T>(c, xat(0, oo), xat(1, oo), xat(2, oo), t);
+  };
+  T c[18], ta[3], tb[3], tc[3], A[3], L[3], R[3];
+  // offsets 0, 8, 4: A = (t0 + t8) + t4
+  stored_coefs2<T>(p, 0, c);
+  stored_coefs2<T>(p, 8, c + 6);
+  stored_coefs2<T>(p, 4, c + 12);
+  in_flight_together(c);
+  terms(c, 0, ta);
+  terms(c + 6, 8, tb);
+  terms(c + 12, 4, tc);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) A[f] = (ta[f] + tb[f]) + tc[f];
+  // offsets 2, 6, 1: L = A + (t2 + t6); t1 kept
+  stored_coefs2<T>(p, 2, c);
+  stored_coefs2<T>(p, 6, c + 6);
+  stored_coefs2<T>(p, 1, c + 12);
+  in_flight_together(c);
+  terms(c, 2, ta);
+  terms(c + 6, 6, tb);
+  terms(c + 12, 1, tc);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) L[f] = A[f] + (ta[f] + tb[f]);
+  // offsets 5, 3, 7: R = (t1 + t5) + (t3 + t7)
+  stored_coefs2<T>(p, 5, c);
+  stored_coefs2<T>(p, 3, c + 6);
+  stored_coefs2<T>(p, 7, c + 12);
+  in_flight_together(c);
+  terms(c, 5, ta);
+  terms(c + 6, 3, tb);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) R[f] = tc[f] + ta[f];
+  terms(c + 12, 7, ta);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) row[f] = L[f] + (R[f] + (tb[f] + ta[f]));
+}
+
+// Reference-stencil part of a row of L at a node with operator code op (Level::node_op): lanes
+// with op < 0 apply the level's reference stencil of their kind, read from the packed level
+// constants (oc->pack, FP64, rounded to T) with scalar loads. The lanes are taken kind by kind (a
+// waterfall over the at most two kinds present in the wavefront), so every coefficient address is
+// wavefront-uniform. Lanes with op >= 0 are left to stored_row_apply.
 template <int D, bool UNR = true, class T, class XA>
-__device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, int op, const T* __restrict__ nsten,
-                                               XA&& xat, T* acc) {
+__device__ __forceinline__ void ref_row_apply(const double* __restrict__ pack, int op, XA&& xat, T* acc) {
   using R = RefLayout<D>;
   constexpr int NS = PT<D>::NST;
   bool todo = op < 0;
@@ -422,11 +496,168 @@ __device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, 
       }
     }
   }
-  if (op >= 0) {
-    // the stored row streams from memory: the loop over offsets stays partly rolled so that its
-    // loads do not all occupy registers at once
-    const T* p = nsten + (int64_t)op * PT<D>::NSTEN;
-    stencil_apply<D, false, T>([&](int j, int o) { return p[j * NS + o]; }, xat, acc);
+}
+
+// Stored-stencil row (op >= 0), one lane: 2D sums the offset terms in the butterfly order of
+// stored_row2; 3D runs the offsets in sequence, partly rolled so that the loads of the row do not
+// all occupy registers at once.
+template <int D, class T, class XA>
+__device__ __forceinline__ void stored_row_apply(int op, const T* __restrict__ nsten, XA&& xat, T* acc) {
+#pragma clang fp contract(off)
+  const T* p = nsten + (int64_t)op * PT<D>::NSTEN;
+  if constexpr (D == 2) {
+    T t[3];
+    stored_row2<T>(p, xat, t);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) acc[f] += t[f];
+  } else {
+    stencil_apply<D, false, T>([&](int j, int o) { return p[j * PT<D>::NST + o]; }, xat, acc);
+  }
+}
+
+// Row of L at a node with operator code op: the level's reference stencil of a uniform
+// neighbourhood (op < 0), or the node's own assembled stencil in nsten (op >= 0).
+template <int D, bool UNR = true, class T, class XA>
+__device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, int op, const T* __restrict__ nsten,
+                                               XA&& xat, T* acc) {
+  ref_row_apply<D, UNR, T>(pack, op, xat, acc);
+  if (op >= 0) stored_row_apply<D, T>(op, nsten, xat, acc);
+}
+
+// Stored-stencil nodes of a 2D residual region in LDS (tile kernels): each wavefront compacts, per
+// round k of its residual nodes, the entries with op >= 0 into its own segment (k, wavefront) of the
+// list, in node order; cnt holds the length of every segment.
+template <int NT, int NRES>
+struct StoredList2 {
+  static constexpr int NW = NT / 64, NSEG = NRES * NW;
+  short e[NSEG * 64];
+  int op[NSEG * 64];
+  int cnt[NSEG];
+};
+
+template <int NT, int NRES>
+__device__ __forceinline__ void stored_list_add(StoredList2<NT, NRES>& sl, int k, int e, int op) {
+  constexpr int NW = NT / 64;
+  const bool st = op >= 0;
+  const unsigned long long msk = __ballot(st);
+  const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0));
+  const int seg = k * NW + (int)(threadIdx.x >> 6);
+  if (st) {
+    sl.e[seg * 64 + pos] = (short)e;
+    sl.op[seg * 64 + pos] = op;
+  }
+  if ((threadIdx.x & 63) == 0) sl.cnt[seg] = __popcll(msk);
+}
+
+// Partial sum R(j + OFF, S) of the butterfly order of stored_row2, for S >= LPN (the offsets of one
+// lane j < LPN: j, j + LPN, ...; lane 0 also offset 8); term(k, t) gives the terms of offset j + k LPN
+// (k < 8 / LPN), term(8 / LPN, t) those of offset 8.
+template <int OFF, int S, int LPN, class T, class TF>
+__device__ __forceinline__ void lane_tree2(int j, TF&& term, T* out) {
+#pragma clang fp contract(off)
+  if constexpr (S == 8) {
+    term(OFF / LPN, out);
+    if constexpr (OFF == 0) {
+      if (j == 0) {
+        T t8[3];
+        term(8 / LPN, t8);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) out[f] = out[f] + t8[f];
+      }
+    }
+  } else {
+    T a[3], b[3];
+    lane_tree2<OFF, 2 * S, LPN, T>(j, term, a);
+    lane_tree2<OFF + S, 2 * S, LPN, T>(j, term, b);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) out[f] = a[f] + b[f];
+  }
+}
+
+// rs[f RP + e] = b_f - (L x)_f for every listed node, LPN lanes per node (LPN = 8, 4 or 2): lane j
+// takes offsets j, j + LPN, ... below 8 and lane 0 also offset 8; each lane forms its partial sum
+// R(j, LPN) of the butterfly order of stored_row2 (lane_tree2), then a butterfly over the LPN lanes
+// completes it, so the bits equal those of the per-lane form. The six coefficients of offset 8 are
+// loaded by lanes k mod LPN and gathered by shuffles. The loads of the first trip (one node per
+// group of LPN lanes) are issued before `between` runs (the reference-stencil residuals of the
+// tile) and used after it, so that their latency is hidden behind that work; further trips follow.
+// Entry e of the region (row width RW) is grid node (ox + e % RW, oy + e / RW) of the level (m
+// nodes per axis, field stride N); x comes from the LDS tile xs (row width XW, field stride XP) at
+// index (e % RW + 1) + XW (e / RW + 1).
+template <int NT, int NRES, int RW, int RP, int XW, int XP, int LPN, class T, class BF>
+__device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& sl, const T* __restrict__ nsten,
+                                                   const T* __restrict__ b, int64_t N, int m, int ox, int oy,
+                                                   const T* xs, T* rs, BF&& between) {
+#pragma clang fp contract(off)
+  static_assert(LPN == 8 || LPN == 4 || LPN == 2, "lanes per node");
+  constexpr int NSEG = StoredList2<NT, NRES>::NSEG, NG = NT / LPN;
+  constexpr int NO = 8 / LPN;                  // offsets below 8 per lane
+  constexpr int N8 = (6 + LPN - 1) / LPN;      // coefficients of offset 8 per lane
+  constexpr int NC = 6 * NO + N8;
+  constexpr int NF = (3 + LPN - 1) / LPN;      // fields written per lane (j, j + LPN, ... < 3)
+  int pre[NSEG + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int s = 0; s < NSEG; ++s) pre[s + 1] = pre[s] + sl.cnt[s];
+  const int cnt = pre[NSEG];
+  const int j = threadIdx.x & (LPN - 1), g = (int)(threadIdx.x / LPN);
+  auto slot = [&](int t) {
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < NSEG; ++k) s += t >= pre[k] ? 1 : 0;
+    return s * 64 + t - pre[s];
+  };
+  // loads of entry t: the six coefficients of offsets j + k LPN, coefficients j + i LPN of offset 8,
+  // b of fields j + i LPN
+  auto issue = [&](int t, T* c, T* bl, int& e) {
+    const int sidx = slot(t);
+    e = sl.e[sidx];
+    const T* p = nsten + (int64_t)sl.op[sidx] * PT<2>::NSTEN;
+    const int64_t g = (ox + e % RW) + (int64_t)m * (oy + e / RW);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int f = j + i * LPN;
+      bl[i] = b[(f < 3 ? f : 0) * N + g];
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) stored_coefs2<T>(p, j + k * LPN, c + 6 * k);
+#pragma unroll
+    for (int i = 0; i < N8; ++i) {
+      const int q = j + i * LPN;
+      c[6 * NO + i] = p[(q < 6 ? q : 5) * 9 + 8];
+    }
+  };
+  auto finish = [&](const T* c, const T* bl, int e) {
+    const int xb = (e % RW + 1) + XW * (e / RW + 1);
+    T c8[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) c8[q] = __shfl(c[6 * NO + q / LPN], q % LPN, LPN);
+    auto term = [&](int k, T* t) {
+      const int o = k < NO ? j + k * LPN : 8;
+      const int xo = xb + (o % 3 - 1) + XW * (o / 3 - 1);
+      stored_terms2<T>(k < NO ? c + 6 * k : c8, xs[xo], xs[XP + xo], xs[2 * XP + xo], t);
+    };
+    T v[3];
+    lane_tree2<0, LPN, LPN, T>(j, term, v);
+#pragma unroll
+    for (int msk = LPN / 2; msk >= 1; msk >>= 1)
+#pragma unroll
+      for (int f = 0; f < 3; ++f) v[f] = v[f] + __shfl_xor(v[f], msk, LPN);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const int f = j + i * LPN;
+      if (f < 3) rs[f * RP + e] = bl[i] - (f == 0 ? v[0] : (f == 1 ? v[1] : v[2]));
+    }
+  };
+  T c[NC], bl[NF];
+  int e = 0;
+  const bool first = g < cnt;
+  if (first) issue(g, c, bl, e);
+  between();
+  if (first) finish(c, bl, e);
+  for (int t = g + NG; t < cnt; t += NG) {
+    issue(t, c, bl, e);
+    finish(c, bl, e);
   }
 }
 
@@ -484,7 +715,7 @@ hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipSt
 }
 
 template <int D, class T>
-__global__ void __launch_bounds__(256) residual_tile_kernel(const OpConsts* __restrict__ oc,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) residual_tile_kernel(const OpConsts* __restrict__ oc,
                                                            const int* __restrict__ node_op,
                                                            const T* __restrict__ nsten, int ntx, int nty, int ntz,
                                                            const T* __restrict__ x, const T* __restrict__ b,
@@ -676,9 +907,11 @@ __device__ __forceinline__ void restrict_node(int nf, int64_t Nf, int nc, int64_
   for (int f = 0; f <= D; ++f) bc[f * Nc + node] = acc[f];
 }
 
-// Q1 interpolation of field f of the coarse vector xc at the fine node with coordinates c.
-template <int D, class T>
-__device__ __forceinline__ T prolong_value(int nc, int64_t Nc, const T* __restrict__ xc, const int* c, int f) {
+// Q1 interpolation at the fine node with coordinates c of the coarse values xat(cc) (cc: coarse
+// node coordinates): the coarse nodes of the enclosing coarse cell face, edge or vertex, in a fixed
+// order, weighted by 1/2 per odd coordinate.
+template <int D, class T, class CA>
+__device__ __forceinline__ T prolong_sum(const int* c, CA&& xat) {
   T acc = 0;
   for (int t = 0; t < (1 << D); ++t) {
     int cc[3] = {0, 0, 0};
@@ -695,9 +928,15 @@ __device__ __forceinline__ T prolong_value(int nc, int64_t Nc, const T* __restri
       }
     }
     if (!valid) continue;
-    acc += w * xc[f * Nc + node_index<D>(cc, nc)];
+    acc += w * xat(cc);
   }
   return acc;
+}
+
+// Q1 interpolation of field f of the coarse vector xc at the fine node with coordinates c.
+template <int D, class T>
+__device__ __forceinline__ T prolong_value(int nc, int64_t Nc, const T* __restrict__ xc, const int* c, int f) {
+  return prolong_sum<D, T>(c, [&](const int* cc) { return xc[f * Nc + node_index<D>(cc, nc)]; });
 }
 
 // x_f at fine node `node` += Q1 interpolation of the coarse correction.

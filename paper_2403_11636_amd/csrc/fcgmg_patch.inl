@@ -856,6 +856,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   constexpr int NRES = (RP + NT - 1) / NT;                // residual nodes per thread
   __shared__ T xs[3 * XP];
   __shared__ T rs[3 * RP];
+  __shared__ StoredList2<NT, NRES> sl;                    // residual nodes with a stored stencil
   constexpr int NWO = (TX * TY + 63) / 64;               // wavefronts that own tile nodes
   constexpr int NG = NT / 16;                             // 16-lane groups of the workgroup
   constexpr int CAP = 4 * NG;                             // individual patches per part (two trips)
@@ -890,51 +891,83 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
     const int e = threadIdx.x + NT * k;
     const int f = e / XP, p = e % XP;
     const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
-    T v = 0;
-    if (e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m) {
-      if (mode != 1) v = x_in[f * N + gx + (int64_t)m * gy];
-      if (mode == 2) {
-        const int cg[3] = {gx, gy, 0};
-        v += prolong_value<2, T>(n >> 1, (int64_t)((n >> 1) + 1) * ((n >> 1) + 1), xc, cg, f);
-      }
-    }
-    xv[k] = v;
+    const bool ok = e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m;
+    xv[k] = (ok && mode != 1) ? x_in[f * N + gx + (int64_t)m * gy] : T(0);
   }
+  // mode 2: the coarse nodes the x tile interpolates from (CW x CH from coarse node (cx0, cy0)),
+  // loaded with the x tile and staged in the residual buffer, which is free until the residual
+  constexpr int CW = XW / 2 + 2, CH = XH / 2 + 2, CP = CW * CH;
+  constexpr int NCL = (3 * CP + NT - 1) / NT;
+  static_assert(CP <= RP, "the coarse tile fits in the residual buffer");
+  const int nc = n >> 1, mc = nc + 1;
+  const int64_t Nc = (int64_t)mc * mc;
+  const int cx0 = (bx - 3) >> 1, cy0 = (by - 3) >> 1;
+  T cv[NCL];
+  if (mode == 2)
+#pragma unroll
+    for (int k = 0; k < NCL; ++k) {
+      const int e = threadIdx.x + NT * k;
+      const int f = e / CP, p = e % CP;
+      const int gx = cx0 + p % CW, gy = cy0 + p / CW;
+      cv[k] = (e < 3 * CP && gx >= 0 && gx < mc && gy >= 0 && gy < mc) ? xc[f * Nc + gx + (int64_t)mc * gy] : T(0);
+    }
   int opv[NRES];
+  T bvv[NRES][3];
 #pragma unroll
   for (int k = 0; k < NRES; ++k) {
     const int e = threadIdx.x + NT * k;
     const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
     const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
-    opv[k] = ok ? node_op[cx + (int64_t)m * cy] : -1;
+    const int64_t g = cx + (int64_t)m * cy;
+    opv[k] = ok ? node_op[g] : -1;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) bvv[k][f] = ok ? b[f * N + g] : T(0);
+  }
+  if (mode == 2) {
+#pragma unroll
+    for (int k = 0; k < NCL; ++k)
+      if (threadIdx.x + NT * k < 3 * CP) rs[threadIdx.x + NT * k] = cv[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NXL; ++k) {
+      const int e = threadIdx.x + NT * k;
+      const int f = e / XP, p = e % XP;
+      const int c[3] = {bx - 3 + p % XW, by - 3 + p / XW, 0};
+      if (e < 3 * XP && c[0] >= 0 && c[0] < m && c[1] >= 0 && c[1] < m)
+        xv[k] += prolong_sum<2, T>(c, [&](const int* cc) { return rs[f * CP + (cc[0] - cx0) + CW * (cc[1] - cy0)]; });
+    }
   }
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
+  // nodes with a stored stencil are listed; groups of lanes compute their residuals
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, threadIdx.x + NT * k, opv[k]);
   __syncthreads();
+  // residuals: nodes with a reference stencil per thread, while the stored rows load
+  constexpr int LPN = TX * TY >= 256 ? 8 : (TX * TY >= 32 ? 4 : 2);  // lanes per stored row
+  stored_rows_group2<NT, NRES, RW, RP, XW, XP, LPN, T>(sl, nsten, b, N, m, bx - 2, by - 2, xs, rs, [&] {
 #pragma unroll
-  for (int k = 0; k < NRES; ++k) {
-    const int e = threadIdx.x + NT * k;
-    if (e < RP) {
-      const int px = e % RW, py = e / RW;
-      const int cx = bx - 2 + px, cy = by - 2 + py;
-      T rv[3] = {0, 0, 0};
-      if (cx >= 0 && cx < m && cy >= 0 && cy < m) {
-        const int64_t g = cx + (int64_t)m * cy;
-        T bv[3];
+    for (int k = 0; k < NRES; ++k) {
+      const int e = threadIdx.x + NT * k;
+      if (e < RP && opv[k] < 0) {
+        const int px = e % RW, py = e / RW;
+        const int cx = bx - 2 + px, cy = by - 2 + py;
+        T rv[3] = {0, 0, 0};
+        if (cx >= 0 && cx < m && cy >= 0 && cy < m) {
+          const T* bv = bvv[k];
+          const int xb = (px + 1) + XW * (py + 1);
+          T acc[3] = {0, 0, 0};
+          ref_row_apply<2, true, T>(oc->pack, opv[k],
+                                    [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; }, acc);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) bv[f] = b[f * N + g];
-        const int xb = (px + 1) + XW * (py + 1);
-        T acc[3] = {0, 0, 0};
-        node_row_apply<2, true, T>(oc->pack, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
-                          acc);
+          for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
+        }
 #pragma unroll
-        for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
+        for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
       }
-#pragma unroll
-      for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
     }
-  }
+  });
   __syncthreads();
   const int tx = tx0, ty = ty0;
   const bool inside = inside0;
@@ -1104,6 +1137,7 @@ __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int 
   constexpr int NRES = (RP + NT - 1) / NT, NXL = (3 * XP + NT - 1) / NT;
   __shared__ T xs[3 * XP];
   __shared__ T rs[3 * RP];
+  __shared__ StoredList2<NT, NRES> sl;  // residual nodes with a stored stencil
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
@@ -1137,26 +1171,33 @@ __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int 
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
+  // nodes with a stored stencil are listed; groups of lanes compute their residuals
+#pragma unroll
+  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, threadIdx.x + NT * k, opv[k]);
   __syncthreads();
+  // residuals: nodes with a reference stencil per thread, while the stored rows load
+  constexpr int LPN = TXC * TYC >= 128 ? 8 : 2;  // lanes per stored row
+  stored_rows_group2<NT, NRES, RW, RP, XW, XP, LPN, T>(sl, nsten, b, N, m, fx0, fy0, xs, rs, [&] {
 #pragma unroll
-  for (int k = 0; k < NRES; ++k) {
-    const int e = threadIdx.x + NT * k;
-    if (e < RP) {
-      const int px = e % RW, py = e / RW;
-      const int gx = fx0 + px, gy = fy0 + py;
-      T rv[3] = {0, 0, 0};
-      if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
-        const int xb = (px + 1) + XW * (py + 1);
-        T acc[3] = {0, 0, 0};
-        node_row_apply<2, true, T>(oc->pack, opv[k], nsten, [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
-                          acc);
+    for (int k = 0; k < NRES; ++k) {
+      const int e = threadIdx.x + NT * k;
+      if (e < RP && opv[k] < 0) {
+        const int px = e % RW, py = e / RW;
+        const int gx = fx0 + px, gy = fy0 + py;
+        T rv[3] = {0, 0, 0};
+        if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
+          const int xb = (px + 1) + XW * (py + 1);
+          T acc[3] = {0, 0, 0};
+          ref_row_apply<2, true, T>(oc->pack, opv[k], [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+                                    acc);
 #pragma unroll
-        for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
+          for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
       }
-#pragma unroll
-      for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
     }
-  }
+  });
   __syncthreads();
   if (threadIdx.x >= TXC * TYC) return;
   const int cx = cx0 + threadIdx.x % TXC, cy = cy0 + threadIdx.x / TXC;
