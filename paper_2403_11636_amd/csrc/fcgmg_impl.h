@@ -136,6 +136,7 @@ struct Fused2Job {
   const int* node_op;
   const T* nsten;
   const int* extra;       // extra parts of split tiles (plan_fused2), or null
+  int n_extra;            // their count: workgroups 0 .. n_extra-1
   const int* node_class;
   const T* Zcls;
   const T* Zirr;

@@ -580,7 +580,8 @@ __device__ __forceinline__ void lane_tree2(int j, TF&& term, T* out) {
 // completes it, so the bits equal those of the per-lane form. The six coefficients of offset 8 are
 // loaded by lanes k mod LPN and gathered by shuffles. The loads of the first trip (one node per
 // group of LPN lanes) are issued before `between` runs (the reference-stencil residuals of the
-// tile) and used after it, so that their latency is hidden behind that work; further trips follow.
+// tile) and used after it, so that their latency is hidden behind that work. With 8 lanes per node
+// the loads of the next two trips are issued together after it; further trips follow one by one.
 // Entry e of the region (row width RW) is grid node (ox + e % RW, oy + e / RW) of the level (m
 // nodes per axis, field stride N); x comes from the LDS tile xs (row width XW, field stride XP) at
 // index (e % RW + 1) + XW (e / RW + 1).
@@ -654,8 +655,19 @@ __device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& 
   const bool first = g < cnt;
   if (first) issue(g, c, bl, e);
   between();
+  // the next trips' loads go out together, before the first trip is finished (8-lane groups, whose
+  // trips hold the fewest registers)
+  constexpr int NX = LPN == 8 ? 2 : 0;
+  T cx[NX > 0 ? NX : 1][NC], blx[NX > 0 ? NX : 1][NF];
+  int ex[NX > 0 ? NX : 1];
+#pragma unroll
+  for (int k = 0; k < NX; ++k)
+    if (g + (k + 1) * NG < cnt) issue(g + (k + 1) * NG, cx[k], blx[k], ex[k]);
   if (first) finish(c, bl, e);
-  for (int t = g + NG; t < cnt; t += NG) {
+#pragma unroll
+  for (int k = 0; k < NX; ++k)
+    if (g + (k + 1) * NG < cnt) finish(cx[k], blx[k], ex[k]);
+  for (int t = g + (NX + 1) * NG; t < cnt; t += NG) {
     issue(t, c, bl, e);
     finish(c, bl, e);
   }

@@ -865,16 +865,17 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
-  // Workgroups 0 .. ntx*nty-1 are part 0 of every tile (XCD-aware order); further workgroups are
-  // extra parts of tiles with more than CAP individual patches (code tile * 4 + part, set-up).
+  // Workgroups 0 .. n_extra-1 are the extra parts of tiles with more than CAP individual patches
+  // (code tile * 4 + part, set-up): the longest-running workgroups, dispatched first. The rest are
+  // part 0 of every tile, in XCD-aware order.
   int tile_lin, part = 0;
-  if (bid < ntx * nty) {
+  if (bid >= J.n_extra) {
     const int nt[3] = {ntx, nty, 1};
     int t[3];
-    tile_coords<2>(bid, nt, t);
+    tile_coords<2>(bid - J.n_extra, nt, t);
     tile_lin = t[0] + ntx * t[1];
   } else {
-    const int code = extra[bid - ntx * nty];
+    const int code = extra[bid];
     tile_lin = code >> 2;
     part = code & 3;
   }
@@ -1102,9 +1103,10 @@ template <int TX, int TY, int NT, int WPE, class T>
 hipError_t launch_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out,
                          int mode, const T* xc, hipStream_t s) {
   const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
-  const Fused2Job<T> J{L.consts, L.node_op,   LV<T>::nsten(L), L.fused_extra, L.node_class, LV<T>::Zcls(L),
-                       LV<T>::Zirr(L), x_in,   b,               x_out,         xc,           (T)c.prm.omega,
-                       ntx,            nty,    mode,            0};
+  const Fused2Job<T> J{L.consts, L.node_op,    LV<T>::nsten(L), L.fused_extra, (int)L.n_fused_extra,
+                       L.node_class,   LV<T>::Zcls(L), LV<T>::Zirr(L), x_in,          b,
+                       x_out,          xc,             (T)c.prm.omega,  ntx,           nty,
+                       mode,           0};
   sweep_fused2_kernel<TX, TY, NT, WPE, T><<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(J);
   return hipGetLastError();
 }
@@ -1262,7 +1264,7 @@ Fused2Job<double> batch_fused2_job(const Ctx& c, const Level& L, const double* x
   const int m = L.n + 1;
   // at most TX*TY individual patches per tile = 4 * NT / 16 per part: no extra parts at this shape
   static_assert(kBatchTX * kBatchTY <= 4 * (kBatchNT / 16), "batched tiles must not need extra parts");
-  return Fused2Job<double>{L.consts, L.node_op, L.nsten, nullptr, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc,
+  return Fused2Job<double>{L.consts, L.node_op, L.nsten, nullptr, 0, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc,
                            c.prm.omega, (m + kBatchTX - 1) / kBatchTX, (m + kBatchTY - 1) / kBatchTY, mode, 0};
 }
 
