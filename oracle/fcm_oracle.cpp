@@ -49,6 +49,7 @@ struct Level {
 
 struct Prob {
   int d = 2, n = 8, nlev = 1, q = 3, force = 0;
+  int immersed = 0;  // 1: the obstacle surfaces are Dirichlet boundaries (no-slip), 2D
   double eta = 1, alpha_f = 1e-8, beta = 20, ubar = 0.3;
   int bc[6] = {0, 0, 0, 0, 0, 0};
   std::vector<Ball> balls;
@@ -153,6 +154,70 @@ void tree_points(const Prob& P, const double* lo, double s, int depth, std::vect
     if (cut_leaf_vol) *cut_leaf_vol += std::pow(s, P.d);
   }
   gauss_box(P, lo, s, out);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Immersed Dirichlet boundary: the obstacle surfaces belong to Gamma_D of Eq. (5) (no-slip, w = 0),
+// 2D. Quadrature on the arcs of the circles inside a cell. Reading (the paper fixes no rule): the
+// circle is split at its crossings with the four lines of the cell box; a piece whose middle point
+// lies in the closed box is cut into ceil(width / (pi/8)) equal angular parts, each integrated with
+// the 6-point Gauss-Legendre rule in the angle, ds = r dtheta. n is the unit normal out of the
+// physical domain, i.e. into the obstacle.
+// ---------------------------------------------------------------------------------------------
+struct APt {
+  double x[3];
+  double w;
+  double n[3];
+};
+
+const double kGL6x[3] = {0.2386191860831969086305017, 0.6612093864662645136613996, 0.9324695142031520278123016};
+const double kGL6w[3] = {0.4679139345726910473898703, 0.3607615730481386075698335, 0.1713244923791703450402961};
+
+void arc_points(const Prob& P, const double* lo, double h, std::vector<APt>& out) {
+  const double two_pi = 2.0 * M_PI;
+  for (const Ball& b : P.balls) {
+    std::vector<double> th = {0.0, two_pi};
+    for (int k = 0; k < 2; ++k)
+      for (int s = 0; s < 2; ++s) {
+        const double dist = lo[k] + s * h - b.c[k];
+        if (std::fabs(dist) >= b.r) continue;
+        const double other = std::sqrt(b.r * b.r - dist * dist);
+        for (int sg = -1; sg <= 1; sg += 2) {
+          double t = k == 0 ? std::atan2(sg * other, dist) : std::atan2(dist, sg * other);
+          if (t < 0) t += two_pi;
+          th.push_back(t);
+        }
+      }
+    std::sort(th.begin(), th.end());
+    for (size_t i = 0; i + 1 < th.size(); ++i) {
+      const double t0 = th[i], t1 = th[i + 1];
+      if (!(t1 > t0)) continue;
+      const double tm = 0.5 * (t0 + t1);
+      const double pm[2] = {b.c[0] + b.r * std::cos(tm), b.c[1] + b.r * std::sin(tm)};
+      bool inside = true;
+      for (int k = 0; k < 2; ++k) inside = inside && pm[k] >= lo[k] && pm[k] <= lo[k] + h;
+      if (!inside) continue;
+      const int parts = (int)std::ceil((t1 - t0) / (M_PI / 8));
+      for (int j = 0; j < parts; ++j) {
+        const double a = t0 + (t1 - t0) * j / parts, e = t0 + (t1 - t0) * (j + 1) / parts;
+        const double mid = 0.5 * (a + e), half = 0.5 * (e - a);
+        for (int g = 0; g < 6; ++g) {
+          const double xi = g < 3 ? -kGL6x[2 - g] : kGL6x[g - 3];
+          const double wg = g < 3 ? kGL6w[2 - g] : kGL6w[g - 3];
+          const double t = mid + half * xi;
+          APt q;
+          q.x[0] = b.c[0] + b.r * std::cos(t);
+          q.x[1] = b.c[1] + b.r * std::sin(t);
+          q.x[2] = 0;
+          q.n[0] = -std::cos(t);
+          q.n[1] = -std::sin(t);
+          q.n[2] = 0;
+          q.w = wg * half * b.r;
+          out.push_back(q);
+        }
+      }
+    }
+  }
 }
 
 // Q1 basis of the cell with lower corner lo and size h, local node a has bit k of a as its
@@ -318,6 +383,29 @@ void element_matrix(const Prob& P, const Level& L, long cell, std::vector<double
           }
       }
     }
+  // Nitsche terms on the immersed obstacle surfaces (2D, cut cells): the same forms as on the walls.
+  if (P.immersed && d == 2 && box_kind(P, lo, h) == 2) {
+    std::vector<APt> ap;
+    arc_points(P, lo, h, ap);
+    for (const APt& q : ap) {
+      q1_basis(d, lo, h, q.x, phi, grad);
+      for (int a = 0; a < nn; ++a)
+        for (int b = 0; b < nn; ++b) {
+          double dna = 0, dnb = 0;
+          for (int k = 0; k < d; ++k) {
+            dna += q.n[k] * grad[a][k];
+            dnb += q.n[k] * grad[b][k];
+          }
+          double kv = q.w * (-P.eta * phi[a] * dnb - P.eta * dna * phi[b] + lam * phi[a] * phi[b]);
+          for (int c = 0; c < d; ++c) Le[(size_t)I(a, c) * ne + I(b, c)] += kv;
+          for (int c = 0; c < d; ++c) {
+            double bv = q.w * phi[a] * q.n[c] * phi[b];
+            Le[(size_t)I(a, c) * ne + I(b, d)] += bv;
+            Le[(size_t)I(b, d) * ne + I(a, c)] += bv;
+          }
+        }
+    }
+  }
   if (pts_out) *pts_out = pts;
 }
 
@@ -879,10 +967,12 @@ int orc_max_threads(void) {
 }
 
 void* orc_create(int d, int n, int nlev, int q, double eta, double alpha_f, double beta, int nballs,
-                 const double* balls, const int* bc, double ubar, int force) {
+                 const double* balls, const int* bc, double ubar, int force, int immersed) {
   if (d < 2 || d > 3 || n < 1 || nlev < 1 || (n >> (nlev - 1)) < 1 || ((n >> (nlev - 1)) << (nlev - 1)) != n)
     return nullptr;
+  if (immersed != 0 && (immersed != 1 || d != 2)) return nullptr;
   Prob* P = new Prob;
+  P->immersed = immersed;
   P->d = d;
   P->n = n;
   P->nlev = nlev;
@@ -932,6 +1022,26 @@ void orc_element_matrix(void* h, int l, long cell, double* out) {
   std::vector<double> Le;
   element_matrix(*P, P->lev[l], cell, Le, nullptr);
   std::copy(Le.begin(), Le.end(), out);
+}
+
+// Immersed-boundary quadrature of one cell (2D): up to max points as [x, y, w, n_x, n_y]; returns
+// the number of points (which may exceed max; then only max are written).
+long orc_arc_points(void* h, int l, long cell, double* out, long max) {
+  Prob* P = static_cast<Prob*>(h);
+  const Level& L = P->lev[l];
+  double lo[3];
+  int ci[3];
+  cell_lo(*P, L, cell, lo, ci);
+  std::vector<APt> ap;
+  if (P->d == 2) arc_points(*P, lo, L.h, ap);
+  for (long i = 0; i < (long)ap.size() && i < max; ++i) {
+    out[5 * i + 0] = ap[i].x[0];
+    out[5 * i + 1] = ap[i].x[1];
+    out[5 * i + 2] = ap[i].w;
+    out[5 * i + 3] = ap[i].n[0];
+    out[5 * i + 4] = ap[i].n[1];
+  }
+  return (long)ap.size();
 }
 
 // Quadrature statistics of one cell: [sum w*alpha, sum w*[alpha==1], number of points,

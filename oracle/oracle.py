@@ -38,7 +38,7 @@ def lib():
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, c_double_p,
-                                 ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int]
+                                 ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_nnodes.restype = ctypes.c_long
         L.orc_nnodes.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -51,6 +51,8 @@ def lib():
         L.orc_inverse_rows.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, c_double_p]
         L.orc_element_matrix.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, c_double_p]
         L.orc_cell_quadrature.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, c_double_p]
+        L.orc_arc_points.restype = ctypes.c_long
+        L.orc_arc_points.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, c_double_p, ctypes.c_long]
         L.orc_cell_kinds.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_byte)]
         L.orc_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p]
         L.orc_matvec.argtypes = [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p]
@@ -100,7 +102,7 @@ class Oracle:
         bc = (ctypes.c_int * 6)(*[int(v) for v in prob.bcs])
         h = L.orc_create(prob.dim, prob.n_cells, prob.n_levels, prob.quad_depth, prob.eta, prob.alpha_fict,
                          prob.nitsche_beta, balls.shape[0], _dp(balls) if balls.size else None, bc,
-                         prob.ubar, prob.force)
+                         prob.ubar, prob.force, int(getattr(prob, "immersed_nitsche", 0)))
         if not h:
             raise ValueError("oracle: invalid problem")
         self.h = ctypes.c_void_p(h)
@@ -154,6 +156,13 @@ class Oracle:
         out = np.zeros(5)
         lib().orc_cell_quadrature(self.h, level, cell, _dp(out))
         return out
+
+    def arc_points(self, level: int, cell: int) -> np.ndarray:
+        """Immersed-boundary quadrature points of one cell (2D): rows [x, y, w, n_x, n_y]."""
+        cnt = lib().orc_arc_points(self.h, level, cell, None, 0)
+        out = np.zeros(max(cnt, 1) * 5)
+        lib().orc_arc_points(self.h, level, cell, _dp(out), cnt)
+        return out[: cnt * 5].reshape(cnt, 5)
 
     def cell_kinds(self, level: int) -> np.ndarray:
         n = self.prob.level_cells(level)

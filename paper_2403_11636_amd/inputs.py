@@ -39,6 +39,7 @@ class Problem:
     nu_post: int = 2
     omega: float = 0.8
     name: str = ""
+    immersed_nitsche: int = 0    # 1: obstacle surfaces are no-slip Dirichlet boundaries (Nitsche, 2D)
 
     @property
     def n_nodes(self) -> int:

@@ -456,3 +456,67 @@ def test_singular_patch_detected():
     x = np.zeros(o.ndofs(0))
     with pytest.raises(np.linalg.LinAlgError):
         o.smooth(0, x, x + 1.0, 1, 0.8, MODE_LU)
+
+
+def test_immersed_arc_quadrature_closed_forms():
+    # Arc quadrature of the obstacle surfaces (2D): over all cells, total length 2 pi sum r, the
+    # normals (into the obstacles) integrate to zero and x_c n_c integrates to -pi sum r^2
+    # (divergence theorem); every point lies on a circle and inside its cell.
+    import dataclasses
+    p = dataclasses.replace(inputs.config2(3, n_cells=64, n_levels=1), immersed_nitsche=1)
+    o = Oracle(p)
+    n = p.n_cells
+    h = 1.0 / n
+    length, sn, sxn = 0.0, np.zeros(2), np.zeros(2)
+    for cell in range(n * n):
+        a = o.arc_points(0, cell)
+        if not len(a):
+            continue
+        lo = np.array([cell % n, cell // n]) * h
+        assert np.all(a[:, 0:2] >= lo - 1e-15) and np.all(a[:, 0:2] <= lo + h + 1e-15)
+        dist = np.min(np.abs(np.linalg.norm(a[:, None, 0:2] - p.balls[None, :, 0:2], axis=2) - p.balls[None, :, 3]),
+                      axis=1)
+        assert np.all(dist < 1e-14)
+        length += a[:, 2].sum()
+        sn += (a[:, 2:3] * a[:, 3:5]).sum(0)
+        sxn += (a[:, 2:3] * a[:, 0:2] * a[:, 3:5]).sum(0)
+    r = p.balls[:, 3]
+    assert abs(length - 2 * np.pi * r.sum()) <= 1e-13 * length
+    assert np.all(np.abs(sn) <= 1e-14)
+    assert np.allclose(sxn, -np.pi * (r ** 2).sum(), rtol=1e-12, atol=0)
+
+
+def test_immersed_nitsche_closed_forms_full_circle():
+    # A circle of radius r inside one cell: the immersed terms (element matrix with them minus
+    # without) applied to nodal values of 1 and x give, with n pointing into the obstacle and
+    # lambda = beta eta / h:  1'K1 = lambda 2 pi r,  1'KX = lambda 2 pi r c_x,
+    # X'KX = -2 eta int x n_x + lambda int x^2 = 2 eta pi r^2 + lambda (2 pi r c_x^2 + pi r^3),
+    # X'B_x 1 = int x n_x = -pi r^2, 1'B_c 1 = int n_c = 0; the block is symmetric and equal for
+    # both velocity components.
+    import dataclasses
+    n, eta, beta = 8, 1.3, 20.0
+    h = 1.0 / n
+    cx, cy, r = 0.31, 0.32, 0.03
+    p0 = inputs.Problem(dim=2, n_cells=n, n_levels=1, balls=np.array([[cx, cy, 0.0, r]]), bcs=(2,) * 6, eta=eta,
+                        nitsche_beta=beta)
+    p1 = dataclasses.replace(p0, immersed_nitsche=1)
+    cell = 2 + n * 2
+    D = Oracle(p1).element_matrix(0, cell) - Oracle(p0).element_matrix(0, cell)
+    lam = beta * eta / h
+    a = np.arange(4)
+    X = 2 * h + h * (a & 1)
+    Y = 2 * h + h * ((a >> 1) & 1)
+    one = np.ones(4)
+    K = D[0:4, 0:4]
+    assert np.allclose(D, D.T, atol=1e-12)
+    assert np.allclose(D[4:8, 4:8], K, atol=1e-13)
+    assert np.allclose(D[0:4, 4:8], 0, atol=1e-14)
+    scale = lam * 2 * np.pi * r
+    assert abs(one @ K @ one - lam * 2 * np.pi * r) <= 1e-12 * scale
+    assert abs(one @ K @ X - lam * 2 * np.pi * r * cx) <= 1e-12 * scale
+    assert abs(X @ K @ X - (2 * eta * np.pi * r ** 2 + lam * (2 * np.pi * r * cx ** 2 + np.pi * r ** 3))) <= 1e-12 * scale
+    B1, B2 = D[0:4, 8:12], D[4:8, 8:12]
+    assert abs(X @ B1 @ one + np.pi * r ** 2) <= 1e-14
+    assert abs(Y @ B2 @ one + np.pi * r ** 2) <= 1e-14
+    assert abs(one @ B1 @ one) <= 1e-15 and abs(one @ B2 @ one) <= 1e-15
+    assert np.allclose(D[8:12, 8:12], 0, atol=1e-15)
