@@ -251,14 +251,24 @@ void node_operator_codes(const Level& L, const std::vector<signed char>& kinds, 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Patch classification: a patch whose 6^d cell window lies inside the grid (at least 3 nodes from
-// every wall) and holds no cut cell and only one kind of uncut cell has the same block L_i as every
-// other such patch of that kind; these patches share one class (at most two classes per level:
-// physical and fictitious). All other patches (cut band, walls) keep individual blocks.
+// Patch classification. The block L_i of a patch is fixed by the cells of its 6^d window (cells
+// c-3 .. c+2 per axis, clipped to the grid) and by the walls among them.
+// * A patch whose window lies inside the grid (at least 3 nodes from every wall) and holds no cut
+//   cell and only one kind of uncut cell has the same block as every other such patch of that
+//   kind: these share one class (at most two per level, physical and fictitious), applied with
+//   scalar loads of its rows.
+// * Every other patch is streamed: individual rows, listed in irr_nodes. With share_walls, a
+//   streamed patch whose window holds no cut cell and one kind (a wall patch) shares its rows with
+//   the patches of the same kind at the same position relative to the walls (per axis: distance
+//   0, 1 or 2 from the low wall, interior, or distance 2, 1, 0 from the high wall), computed once
+//   from the first of them.
+// zrow_nodes lists the nodes whose inverse rows are computed (row k from zrow_nodes[k]); irr_zrow
+// gives the row of every streamed patch; node_class is the class (>= 0) or -(row) - 1.
 // ---------------------------------------------------------------------------------------------
 template <int D>
-void classify_patches(const Level& L, const std::vector<signed char>& kinds, std::vector<int>& node_class,
-                      std::vector<int>& class_rep, std::vector<int>& irr_nodes) {
+void classify_patches(const Level& L, const std::vector<signed char>& kinds, bool share_walls,
+                      std::vector<int>& node_class, std::vector<int>& class_rep, std::vector<int>& irr_nodes,
+                      std::vector<int>& irr_zrow, std::vector<int>& zrow_nodes) {
   const int n = L.n;
   const int64_t m = n + 1;  // summed-area tables over cells, size (n+1)^D
   std::vector<int> sat_cut(D == 2 ? m * m : m * m * m, 0), sat_fic(sat_cut.size(), 0);
@@ -291,25 +301,45 @@ void classify_patches(const Level& L, const std::vector<signed char>& kinds, std
            S[sidx(hi[0] + 1, lo[1], hi[2] + 1)] - S[sidx(hi[0] + 1, hi[1] + 1, lo[2])] + S[sidx(lo[0], lo[1], hi[2] + 1)] +
            S[sidx(lo[0], hi[1] + 1, lo[2])] + S[sidx(hi[0] + 1, lo[1], lo[2])] - S[sidx(lo[0], lo[1], lo[2])];
   };
-  std::map<int, int> key2cls;
+  std::map<int, int> key2cls, wall2row;
   node_class.assign(L.N, 0);
   class_rep.clear();
   irr_nodes.clear();
+  irr_zrow.clear();
+  zrow_nodes.clear();
   for (int64_t node = 0; node < L.N; ++node) {
     int c[3] = {(int)(node % m), (int)((node / m) % m), D == 3 ? (int)(node / (m * m)) : 0};
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     int64_t tot = 1;
-    int key = 0;
+    int key = 0, wkey = 0;
     bool interior = true;
     for (int k = 0; k < D; ++k) {
       lo[k] = std::max(c[k] - 3, 0);
       hi[k] = std::min(c[k] + 2, n - 1);
       tot *= (hi[k] - lo[k] + 1);
       interior = interior && c[k] >= 3 && n - c[k] >= 3;
+      // wall case per axis: 0..2 low wall, 3 interior, 4..6 distance 2..0 from the high wall
+      // (injective in c on a level, also where the ranges meet on small grids)
+      wkey = wkey * 7 + (c[k] <= 2 ? c[k] : (c[k] >= n - 2 ? 4 + c[k] - (n - 2) : 3));
     }
     const int64_t ncut = box_sum(sat_cut, lo, hi);
     const int64_t nfic = box_sum(sat_fic, lo, hi);
-    if (interior && ncut == 0 && (nfic == 0 || nfic == tot)) {
+    const bool uniform = ncut == 0 && (nfic == 0 || nfic == tot);
+    if (!interior && uniform && share_walls) {
+      wkey = wkey * 2 + (nfic ? 1 : 0);
+      auto it = wall2row.find(wkey);
+      int row;
+      if (it == wall2row.end()) {
+        row = (int)zrow_nodes.size();
+        wall2row[wkey] = row;
+        zrow_nodes.push_back((int)node);
+      } else {
+        row = it->second;
+      }
+      node_class[node] = -row - 1;
+      irr_nodes.push_back((int)node);
+      irr_zrow.push_back(row);
+    } else if (interior && uniform) {
       key = key * 2 + (nfic ? 1 : 0);
       auto it = key2cls.find(key);
       int cls;
@@ -322,8 +352,11 @@ void classify_patches(const Level& L, const std::vector<signed char>& kinds, std
       }
       node_class[node] = cls;
     } else {
-      node_class[node] = -(int)irr_nodes.size() - 1;
+      const int row = (int)zrow_nodes.size();
+      node_class[node] = -row - 1;
       irr_nodes.push_back((int)node);
+      irr_zrow.push_back(row);
+      zrow_nodes.push_back((int)node);
     }
   }
 }
@@ -452,12 +485,13 @@ int setup_impl(Ctx& c, hipStream_t s) {
     }
     FCG_HIP(hipStreamSynchronize(s));  // op and sten_nodes must outlive the copies
     // patches
-    std::vector<int> ncls, reps, irr, extra;
-    classify_patches<D>(L, kinds, ncls, reps, irr);
+    std::vector<int> ncls, reps, irr, zrow, znodes, extra;
+    classify_patches<D>(L, kinds, P.cache_policy == FCGMG_CACHE_INVERSE, ncls, reps, irr, zrow, znodes);
     L.n_classes = (int64_t)reps.size();
     L.n_irr = (int64_t)irr.size();
+    L.n_zrows = (int64_t)znodes.size();
     L.irr_cols = 0;
-    for (int node : irr) {
+    for (int node : znodes) {
       int cc[3] = {(int)(node % (L.n + 1)), (int)((node / (L.n + 1)) % (L.n + 1)), D == 3 ? (int)(node / ((int64_t)(L.n + 1) * (L.n + 1))) : 0};
       int64_t nv = 1, np = 1;
       for (int k = 0; k < D; ++k) {
@@ -475,6 +509,12 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if (L.n_irr) {
       if ((rc = alloc_n(c, &L.irr_nodes, L.n_irr))) return rc;
       FCG_HIP(hipMemcpyAsync(L.irr_nodes, irr.data(), L.n_irr * sizeof(int), hipMemcpyHostToDevice, s));
+      if ((rc = alloc_n(c, &L.irr_zrow, L.n_irr))) return rc;
+      FCG_HIP(hipMemcpyAsync(L.irr_zrow, zrow.data(), L.n_irr * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    if (L.n_zrows) {
+      if ((rc = alloc_n(c, &L.zrow_nodes, L.n_zrows))) return rc;
+      FCG_HIP(hipMemcpyAsync(L.zrow_nodes, znodes.data(), L.n_zrows * sizeof(int), hipMemcpyHostToDevice, s));
     }
     if (D == 2 && P.cache_policy == FCGMG_CACHE_INVERSE) {
       plan_fused2(L, ncls, extra);
@@ -490,15 +530,15 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if (P.cache_policy == FCGMG_CACHE_INVERSE) {
       const size_t row = (size_t)(D + 1) * PT<D>::ZSP;
       if ((rc = alloc_n(c, &L.Zcls, L.n_classes * row))) return rc;
-      if ((rc = alloc_n(c, &L.Zirr, L.n_irr * row))) return rc;
-      L.cached_bytes = (L.n_classes + L.n_irr) * row * sizeof(double);
+      if ((rc = alloc_n(c, &L.Zirr, L.n_zrows * row))) return rc;
+      L.cached_bytes = (L.n_classes + L.n_zrows) * row * sizeof(double);
       FCG_HIP(k_patch_inverse_rows<D>(c, L, L.class_rep, L.n_classes, L.Zcls, s));
-      FCG_HIP(k_patch_inverse_rows<D>(c, L, L.irr_nodes, L.n_irr, L.Zirr, s));
+      FCG_HIP(k_patch_inverse_rows<D>(c, L, L.zrow_nodes, L.n_zrows, L.Zirr, s));
       if (P.precision == FCGMG_PREC_MIXED) {
         // FP32 copies, rounded from the FP64 factorisations
         const int64_t nd32 = (D + 1) * L.N;
         if ((rc = alloc_n(c, &L.Zcls32, L.n_classes * row))) return rc;
-        if ((rc = alloc_n(c, &L.Zirr32, L.n_irr * row))) return rc;
+        if ((rc = alloc_n(c, &L.Zirr32, L.n_zrows * row))) return rc;
         if ((rc = alloc_n(c, &L.nsten32, (size_t)L.n_nsten * PT<D>::NSTEN))) return rc;
         if ((rc = alloc_n(c, &L.r32, nd32))) return rc;
         if ((rc = alloc_n(c, &L.x32, nd32))) return rc;
@@ -506,7 +546,7 @@ int setup_impl(Ctx& c, hipStream_t s) {
         if (D == 2)
           if ((rc = alloc_n(c, &L.xalt32, nd32))) return rc;
         FCG_HIP(k_round_to_float(L.Zcls, L.Zcls32, (int64_t)(L.n_classes * row), s));
-        FCG_HIP(k_round_to_float(L.Zirr, L.Zirr32, (int64_t)(L.n_irr * row), s));
+        FCG_HIP(k_round_to_float(L.Zirr, L.Zirr32, (int64_t)(L.n_zrows * row), s));
         FCG_HIP(k_round_to_float(L.nsten, L.nsten32, L.n_nsten * PT<D>::NSTEN, s));
       }
     } else if (P.cache_policy == FCGMG_CACHE_MATRIX) {
@@ -753,12 +793,12 @@ size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
       if (kinds[cell] == 2) ++n_cut;
     }
     bytes += L.ncells * sizeof(int) + (size_t)n_cut * PT<D>::NEL * sizeof(double) + sizeof(OpConsts);
-    std::vector<int> op(L.N), sten, ncls, reps, irr, extra;
+    std::vector<int> op(L.N), sten, ncls, reps, irr, zrow, znodes, extra;
     node_operator_codes<D>(L, kinds, op, sten);
     bytes += L.N * sizeof(int) + sten.size() * PT<D>::NSTEN * sizeof(double);
-    classify_patches<D>(L, kinds, ncls, reps, irr);
-    bytes += (L.N + reps.size() + irr.size()) * sizeof(int);
-    const size_t npatch = reps.size() + irr.size();
+    classify_patches<D>(L, kinds, inverse, ncls, reps, irr, zrow, znodes);
+    bytes += (L.N + reps.size() + 2 * irr.size() + znodes.size()) * sizeof(int);
+    const size_t npatch = reps.size() + znodes.size();  // blocks with stored data
     if (D == 2 && inverse) {
       plan_fused2(L, ncls, extra);
       bytes += extra.size() * sizeof(int);

@@ -105,10 +105,13 @@ struct Level {
   int* fused_extra = nullptr;  // 2D cache_inverse: extra workgroups of heavy tiles (plan_fused2)
   int n_fused_extra = 0;
   int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
-  int* irr_nodes = nullptr;   // centre node of each irregular patch
+  int64_t n_zrows = 0;        // streamed row blocks (n_irr, fewer where wall patches share rows)
+  int* irr_nodes = nullptr;   // centre node of each streamed (irregular) patch
+  int* irr_zrow = nullptr;    // its row block in Zirr / Mirr
+  int* zrow_nodes = nullptr;  // node whose block gives row block k
   int* class_rep = nullptr;   // representative node of each class
   double* Zcls = nullptr;     // cache_inverse: n_classes x (d+1) x ZSP
-  double* Zirr = nullptr;     // cache_inverse: n_irr x (d+1) x ZSP
+  double* Zirr = nullptr;     // cache_inverse: n_zrows x (d+1) x ZSP
   double* Mcls = nullptr;     // cache_matrix: n_classes x n_pattern
   double* Mirr = nullptr;     // cache_matrix: n_irr x n_pattern
   OpConsts* consts = nullptr; // device copy

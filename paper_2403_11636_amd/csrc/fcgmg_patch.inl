@@ -787,6 +787,7 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
 
 template <int D, class T>
 __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nirr, const int* __restrict__ irr_nodes,
+                                                              const int* __restrict__ irr_zrow,
                                                               const T* __restrict__ Zirr,
                                                               const T* __restrict__ r, T* __restrict__ x,
                                                               T omega) {
@@ -809,7 +810,8 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
                 : T(0);
     };
     T acca[D + 1], accb[D + 1];
-    irregular_pair<D, T>(Zirr + pa * (int64_t)(D + 1) * ZSP, Zirr + (has_b ? pb : pa) * (int64_t)(D + 1) * ZSP, has_b,
+    const int64_t za = irr_zrow[pa], zb = has_b ? irr_zrow[pb] : za;
+    irregular_pair<D, T>(Zirr + za * (D + 1) * ZSP, Zirr + zb * (D + 1) * ZSP, has_b,
                       j16, [&](int f, const int* o) { return gather(ca, f, o); },
                       [&](int f, const int* o) { return gather(cb, f, o); }, acca, accb);
     if (j16 <= D) {
@@ -1094,7 +1096,8 @@ hipError_t k_apply_irregular(const Ctx& c, const Level& L, const T* r, T* x, hip
   if (L.n_irr == 0) return hipSuccess;
   int64_t nb = (L.n_irr + 31) / 32;
   if (nb > 65536) nb = 65536;
-  apply_irregular_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.n_irr, L.irr_nodes, LV<T>::Zirr(L),
+  apply_irregular_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.n, L.n_irr, L.irr_nodes, L.irr_zrow,
+                                                                        LV<T>::Zirr(L),
                                                                         r, x, (T)c.prm.omega);
   return hipGetLastError();
 }
