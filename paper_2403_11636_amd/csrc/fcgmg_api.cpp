@@ -216,7 +216,10 @@ void build_consts(const Ctx& c, Level& L) {
 // ---------------------------------------------------------------------------------------------
 // Operator code of every node (Level::node_op): a node at least 2 nodes from every wall whose 2^d
 // cells are uncut and of one kind uses that kind's reference stencil (-1 physical, -2 fictitious);
-// every other node gets a stored stencil, listed in `sten_nodes`.
+// every other node gets a stored stencil. The row of a node is fixed by its cells and the walls
+// that reach it, so nodes nearer a wall whose cells are uncut and of one kind share the row of
+// their kind and wall position (per axis: node 0 or 1 from the low wall, interior, 1 or 0 from the
+// high wall), computed from the first of them. sten_nodes lists the node of each stored row.
 // ---------------------------------------------------------------------------------------------
 template <int D>
 void node_operator_codes(const Level& L, const std::vector<signed char>& kinds, std::vector<int>& op,
@@ -224,25 +227,46 @@ void node_operator_codes(const Level& L, const std::vector<signed char>& kinds, 
   const int n = L.n;
   const int64_t m = n + 1;
   sten_nodes.clear();
+  std::map<int, int> wall2row;
   for (int64_t node = 0; node < L.N; ++node) {
     const int c[3] = {(int)(node % m), (int)((node / m) % m), D == 3 ? (int)(node / (m * m)) : 0};
-    bool uni = true;
-    for (int k = 0; k < D; ++k) uni = uni && c[k] >= 2 && c[k] <= n - 2;
-    int kind0 = -1;
-    if (uni) {
-      for (int sc = 0; sc < (1 << D) && uni; ++sc) {
-        int64_t cell = 0, mul = 1;
-        for (int k = 0; k < D; ++k) {
-          cell += (c[k] - 1 + ((sc >> k) & 1)) * mul;
-          mul *= n;
-        }
-        const int kd = kinds[cell];
-        if (sc == 0) kind0 = kd;
-        uni = kd != 2 && kd == kind0;
-      }
+    bool interior = true;
+    int wkey = 0;
+    for (int k = 0; k < D; ++k) {
+      interior = interior && c[k] >= 2 && c[k] <= n - 2;
+      // wall case per axis: 0, 1 low wall, 2 interior, 3, 4 distance 1, 0 from the high wall
+      // (injective in c on a level, also where the ranges meet on small grids)
+      wkey = wkey * 5 + (c[k] <= 1 ? c[k] : (c[k] >= n - 1 ? 3 + c[k] - (n - 1) : 2));
     }
-    if (uni) {
+    // the cells of the node that exist: uncut and of one kind?
+    bool uni = true;
+    int kind0 = -1;
+    for (int sc = 0; sc < (1 << D) && uni; ++sc) {
+      int64_t cell = 0, mul = 1;
+      bool in = true;
+      for (int k = 0; k < D; ++k) {
+        const int cc = c[k] - 1 + ((sc >> k) & 1);
+        in = in && cc >= 0 && cc < n;
+        cell += cc * mul;
+        mul *= n;
+      }
+      if (!in) continue;
+      const int kd = kinds[cell];
+      if (kind0 < 0) kind0 = kd;
+      uni = kd != 2 && kd == kind0;
+    }
+    if (uni && interior) {
       op[node] = -1 - kind0;
+    } else if (uni) {
+      const int key = wkey * 2 + kind0;
+      auto it = wall2row.find(key);
+      if (it == wall2row.end()) {
+        op[node] = (int)sten_nodes.size();
+        wall2row[key] = op[node];
+        sten_nodes.push_back((int)node);
+      } else {
+        op[node] = it->second;
+      }
     } else {
       op[node] = (int)sten_nodes.size();
       sten_nodes.push_back((int)node);
