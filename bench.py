@@ -53,12 +53,13 @@ def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
                        per node (operator code)
     residual_restrict: read x, b; write the coarse b; stored operator rows; one int per node
     apply_regular:     read r; one int per node; read+write x of the regular nodes; class rows
-    apply_irregular:   the stored rows (d+1)|S_i| of every irregular patch; read+write x and read r
-                       of those nodes; one int per patch
+    apply_irregular:   the distinct stored row blocks (d+1)|S_i| of the streamed patches (wall
+                       patches share theirs); read+write x and read r of those nodes; one int per
+                       patch
     patch_solve:       read r; read+write x (local blocks are built on chip or, for cache_matrix,
                        read from the stored pattern values: added separately by the caller)
-    sweep_fused:       read x, b; write the new x; stored rows of the irregular patches; stored
-                       operator rows; two ints per node (patch class, operator code)
+    sweep_fused:       read x, b; write the new x; distinct row blocks of the streamed patches;
+                       distinct stored operator rows; two ints per node (patch class, operator code)
     """
     N = st["n_nodes"]
     nf = d + 1
@@ -85,8 +86,8 @@ def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
 
 
 def sweep_minimum_bytes(d: int, st: dict) -> float:
-    """Fused minimum of one cache_inverse sweep: read x, b, write x, stored rows of the irregular
-    patches, stored operator rows of the non-uniform nodes (FP64)."""
+    """Fused minimum of one cache_inverse sweep: read x, b, write x, the distinct row blocks of the
+    streamed patches and the distinct stored operator rows, each once (FP64)."""
     nf = d + 1
     nsten = (2 * d + 2) * 3 ** d
     return 8.0 * (3 * nf * st["n_nodes"] + nf * st["irregular_cols"] + nsten * st["n_stencils"])
