@@ -122,7 +122,7 @@ def time_sweeps(torch, h, x, b, count):
     return [a.elapsed_time(z) / 2 for a, z in lat]
 
 
-def time_solves(torch, h, b, count, rtol=1e-8):
+def time_solves(torch, h, b, count, rtol=1e-8, max_iter=200):
     ms, its, rels = [], [], []
     for _ in range(count):
         x = h.zeros()
@@ -130,7 +130,7 @@ def time_solves(torch, h, b, count, rtol=1e-8):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        _, it, rel, _, rc = h.solve(b, x=x, rtol=rtol, max_iter=200)
+        _, it, rel, _, rc = h.solve(b, x=x, rtol=rtol, max_iter=max_iter)
         e1.record()
         torch.cuda.synchronize()
         ms.append(e0.elapsed_time(e1))
@@ -249,6 +249,45 @@ def policy_extras(torch, fcgmg, prob, sweeps=4):
             "setup_s": round(setup, 3)}
         h.close()
         log(f"  {fcgmg.POLICY_NAMES[pol]}: sweep {ms:.3f} ms")
+    return out
+
+
+def immersed_extra(torch, fcgmg, prob, solves=5):
+    """The same 2D workload with the obstacle surfaces as no-slip Dirichlet boundaries (immersed
+    Nitsche, cache_inverse): set-up, the V-cycle, and the time to 1e-8 of the standalone GMG and of
+    FGMRES(30) preconditioned by one V-cycle."""
+    import dataclasses
+    p = dataclasses.replace(prob, immersed_nitsche=1)
+    out = {"workload": prob.name + "_immersed_nitsche"}
+    for solver, tag in ((fcgmg.SOLVER_GMG, "gmg"), (fcgmg.SOLVER_FGMRES, "fgmres")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = fcgmg.Hierarchy(p, fcgmg.CACHE_INVERSE, solver=solver)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        b = h.rhs()
+        rec = {"setup_s": round(setup_s, 3)}
+        if solver == fcgmg.SOLVER_GMG:
+            xx = h.zeros()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            h.vcycle(xx, b)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(10):
+                h.vcycle(xx, b)
+            e1.record()
+            torch.cuda.synchronize()
+            rec["cycle_us"] = round(e0.elapsed_time(e1) / 10 * 1e3, 1)
+        try:
+            h.solve(b, rtol=1e-8, max_iter=300)
+            ms, its, rels = time_solves(torch, h, b, solves, max_iter=300)
+            rec.update({"converged": True, "solve_ms_p50": round(pct(ms, 50), 3), "cycles": int(np.median(its)),
+                        "rel_res": float(np.max(rels))})
+        except fcgmg.FcgmgError as e:
+            rec.update({"converged": False, "error": str(e)[:160]})
+        out[tag] = rec
+        h.close()
     return out
 
 
@@ -554,6 +593,8 @@ def main():
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
         log("precision: FP64 vs mixed ...")
         out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]
+        log("immersed Nitsche ...")
+        out["immersed"] = immersed_extra(torch, fcgmg, inputs.config2(0))
         log("batching ...")
         out["batching"] = batch_extra(torch, fcgmg, inputs)
         log("serving ...")

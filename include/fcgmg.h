@@ -78,6 +78,10 @@ typedef struct {
   int precision;     /* FCGMG_PREC_*: arithmetic of fcgmg_solve's V-cycles                       */
   int solver;        /* FCGMG_SOLVER_*: outer iteration of fcgmg_solve                            */
   int krylov_restart; /* FGMRES restart length m, 1..63 (ignored by FCGMG_SOLVER_GMG)              */
+  int immersed_nitsche; /* 1: the obstacle surfaces are no-slip Dirichlet boundaries (Eq. 5, Gamma_D),
+                           imposed by the Nitsche forms of the walls on arcs through the cut cells;
+                           2D and FCGMG_CACHE_INVERSE only, whose patch rows then come from a dense
+                           LU with partial pivoting. 0: obstacles are fictitious regions only.      */
 } fcgmg_params;
 
 /* Outer iteration of fcgmg_solve. GMG: the standalone multigrid of Sec. 4, x <- V(x, b) until the

@@ -349,6 +349,77 @@ __host__ __device__ inline void tree_quadrature(const Geom& g, const double* lo0
   }
 }
 
+// Immersed boundary (2D): Gauss points on the arcs of the obstacle circles inside the cell box
+// [lo, lo + h]^2, the obstacle surfaces taken as part of Gamma_D in Eq. 5. Each circle is split at
+// its crossings with the four lines of the box; a piece whose middle lies in the closed box is cut
+// into ceil(width / (pi/8)) equal angular parts, each with the 6-point Gauss-Legendre rule in the
+// angle. visit(x, w, nrm): point, weight (ds = r dtheta), unit normal pointing into the obstacle.
+template <class F>
+__host__ __device__ inline void arc_quadrature2(const Geom& g, const double* lo, double h, F&& visit) {
+  const double gx[3] = {0.2386191860831969086305017, 0.6612093864662645136613996, 0.9324695142031520278123016};
+  const double gw[3] = {0.4679139345726910473898703, 0.3607615730481386075698335, 0.1713244923791703450402961};
+  const double two_pi = 6.283185307179586476925287;
+  for (int i = 0; i < g.nballs; ++i) {
+    const double* b = g.balls + 4 * i;
+    const double r = b[3];
+    double th[10];
+    int nt = 0;
+    th[nt++] = 0.0;
+    th[nt++] = two_pi;
+    for (int k = 0; k < 2; ++k)
+      for (int s = 0; s < 2; ++s) {
+        const double dist = lo[k] + s * h - b[k];
+        if (fabs(dist) >= r) continue;
+        const double other = sqrt(r * r - dist * dist);
+        for (int sg = -1; sg <= 1; sg += 2) {
+          double t = k == 0 ? atan2(sg * other, dist) : atan2(dist, sg * other);
+          if (t < 0) t += two_pi;
+          th[nt++] = t;
+        }
+      }
+    for (int a = 1; a < nt; ++a)  // insertion sort of the break angles
+      for (int c = a; c > 0 && th[c - 1] > th[c]; --c) {
+        const double tmp = th[c];
+        th[c] = th[c - 1];
+        th[c - 1] = tmp;
+      }
+    for (int j = 0; j + 1 < nt; ++j) {
+      const double t0 = th[j], t1 = th[j + 1];
+      if (!(t1 > t0)) continue;
+      const double tm = 0.5 * (t0 + t1);
+      const double pm0 = b[0] + r * cos(tm), pm1 = b[1] + r * sin(tm);
+      if (!(pm0 >= lo[0] && pm0 <= lo[0] + h && pm1 >= lo[1] && pm1 <= lo[1] + h)) continue;
+      const int parts = (int)ceil((t1 - t0) / (0.125 * 3.141592653589793238462643));
+      for (int p = 0; p < parts; ++p) {
+        const double ta = t0 + (t1 - t0) * p / parts, te = t0 + (t1 - t0) * (p + 1) / parts;
+        const double mid = 0.5 * (ta + te), half = 0.5 * (te - ta);
+        for (int q = 0; q < 6; ++q) {
+          const double xi = q < 3 ? -gx[2 - q] : gx[q - 3];
+          const double wq = q < 3 ? gw[2 - q] : gw[q - 3];
+          const double t = mid + half * xi;
+          const double ct = cos(t), st = sin(t);
+          const double x[3] = {b[0] + r * ct, b[1] + r * st, 0.0};
+          const double nrm[2] = {-ct, -st};
+          visit(x, wq * half * r, nrm);
+        }
+      }
+    }
+  }
+}
+
+// Entry e of a cell's element data from the Nitsche forms at one boundary point (weight w, normal
+// nrm), the wall forms of Eq. 5 with w = 0: K[a][b] += -eta phi_a (n.grad phi_b) - eta (n.grad phi_a)
+// phi_b + lambda phi_a phi_b; B_c[a][b] += phi_a n_c phi_b.
+__host__ __device__ inline double nitsche_entry2(int e, double eta, double lam, double w, const double* nrm,
+                                                 const double* phi, double (*gr)[3]) {
+  const int blk = e / 16, ab = e % 16, a = ab / 4, b = ab % 4;
+  if (blk == 0) {
+    const double dna = nrm[0] * gr[a][0] + nrm[1] * gr[a][1], dnb = nrm[0] * gr[b][0] + nrm[1] * gr[b][1];
+    return w * (-eta * phi[a] * dnb - eta * dna * phi[b] + lam * phi[a] * phi[b]);
+  }
+  return w * phi[a] * nrm[blk - 1] * phi[b];
+}
+
 // Entry e of a cell's alpha-weighted element data: e < NN*NN: K[a][b] = eta int alpha grad.grad;
 // else B_c[a][b] = -int alpha d_c phi_a phi_b with c = e / (NN*NN) - 1.
 template <int D>

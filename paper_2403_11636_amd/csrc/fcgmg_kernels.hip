@@ -116,8 +116,9 @@ __device__ void integrate_cell_entries(const Geom& g, const double* lo, double h
 }
 
 template <int D>
-__global__ void __launch_bounds__(64) cut_matrices_kernel(Geom g, int n, double h, double eta, const int* cut_cells,
-                                                          int64_t ncut, double* out) {
+__global__ void __launch_bounds__(64) cut_matrices_kernel(Geom g, int n, double h, double eta, int immersed,
+                                                          double lam, const int* cut_cells, int64_t ncut,
+                                                          double* out) {
   __shared__ double lball[4 * kMaxLocalBalls];
   __shared__ int cnt;
   constexpr int NEL = PT<D>::NEL;
@@ -137,6 +138,17 @@ __global__ void __launch_bounds__(64) cut_matrices_kernel(Geom g, int n, double 
     double acc[NPER];
     for (int k = 0; k < NPER; ++k) acc[k] = 0;
     integrate_cell_entries<D>(gl, lo, h, eta, acc, NPER);
+    if constexpr (D == 2) {
+      if (immersed)
+        arc_quadrature2(gl, lo, h, [&](const double* x, double w, const double* nrm) {
+          double phi[4], gr[4][3];
+          q1<2>(lo, h, x, phi, gr);
+          for (int k = 0; k < NPER; ++k) {
+            const int e = (int)threadIdx.x + 64 * k;
+            if (e < NEL) acc[k] += nitsche_entry2(e, eta, lam, w, nrm, phi, gr);
+          }
+        });
+    }
     for (int k = 0; k < NPER; ++k) {
       const int e = (int)threadIdx.x + 64 * k;
       if (e < NEL) out[ic * NEL + e] = acc[k];
@@ -149,8 +161,9 @@ template <int D>
 hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStream_t s) {
   if (L.n_cut == 0) return hipSuccess;
   const int64_t nb = L.n_cut < 65536 ? L.n_cut : 65536;
-  cut_matrices_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(c.geom(), L.n, L.h, c.prm.eta, cut_cells, L.n_cut,
-                                                                 L.cut_mats);
+  cut_matrices_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(
+      c.geom(), L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, c.prm.nitsche_beta * c.prm.eta / L.h, cut_cells,
+      L.n_cut, L.cut_mats);
   return hipGetLastError();
 }
 

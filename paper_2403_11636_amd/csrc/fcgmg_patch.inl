@@ -495,10 +495,136 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_inverse_rows_kernel(
   }
 }
 
+// cache_inverse set-up with the immersed boundary terms (2D). Symmetric Nitsche is not coercive on
+// cells with a small physical part, so the velocity block of a cut-band patch may be indefinite and
+// the block Cholesky above does not apply. The whole block L_i (59 x 59: u_x, u_y, p over the
+// window, decoupled positions outside the grid) is factorised by LU with partial pivoting (largest
+// magnitude, lowest row on ties; Sec. 3.1.2 names LU), and the centre rows of L_i^{-1} come from the
+// transposed solves U^T w = e_f, L^T v = w, z = P^T v. One wavefront per patch.
+__global__ void __launch_bounds__(64) patch_inverse_rows_lu2_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, const int* __restrict__ nodes, int64_t count, double* __restrict__ Z, int* err) {
+  constexpr int D = 2, NV = PT<2>::NV, NP = PT<2>::NP, NB = PT<2>::NB, NPX = NP + 2, ZS = PT<2>::ZS,
+                ZSP = PT<2>::ZSP;
+  static_assert(PT<2>::THREADS == 64, "one wavefront per patch");
+  __shared__ PatchLDS<2> sh;
+  __shared__ double A[ZS * ZS];  // row-major
+  __shared__ double rhs[D + 1][ZS];
+  __shared__ int piv[ZS];
+  const int tid = threadIdx.x;
+  const int n = oc->n;
+  const int centre[D + 1] = {vel_center<2>(), NV + vel_center<2>(), D * NV + pres_center<2>()};
+  for (int64_t pi = blockIdx.x; pi < count; pi += gridDim.x) {
+    const int64_t node = nodes[pi];
+    int c[3];
+    node_coords<D>(node, n, c);
+    patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 0);
+    patch_pad<D>(sh, c, n);
+    // the dense block: I_2 (x) K_i (from the lower band), B_c and B_c^T, C_i
+    for (int e = tid; e < ZS * ZS; e += 64) {
+      const int i = e / ZS, j = e % ZS;
+      double v = 0;
+      if (i < D * NV && j < D * NV) {
+        const int vi = i % NV, vj = j % NV;
+        if (i / NV == j / NV) {
+          const int hi = vi > vj ? vi : vj, lo = vi > vj ? vj : vi;
+          if (hi - lo < NB) v = sh.Kb[hi * NB + (hi - lo)];
+        }
+      } else if (i < D * NV) {
+        v = sh.X[((i / NV) * NV + i % NV) * NPX + (j - D * NV)];
+      } else if (j < D * NV) {
+        v = sh.X[((j / NV) * NV + j % NV) * NPX + (i - D * NV)];
+      } else {
+        v = sh.S[(i - D * NV) * NP + (j - D * NV)];
+      }
+      A[e] = v;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int k = 0; k < ZS; ++k) {
+      // pivot row: largest |A[i][k]|, i >= k, lowest index on ties (one wavefront: a butterfly)
+      const int i0 = k + tid;
+      double pv = i0 < ZS ? fabs(A[i0 * ZS + k]) : -1.0;
+      int pr = i0 < ZS ? i0 : ZS;
+      for (int m = 32; m >= 1; m >>= 1) {
+        const double ov = __shfl_xor(pv, m, 64);
+        const int orow = __shfl_xor(pr, m, 64);
+        if (ov > pv || (ov == pv && orow < pr)) {
+          pv = ov;
+          pr = orow;
+        }
+      }
+      if (tid == 0) piv[k] = pr;
+      if (!(pv > 0)) bad = true;
+      if (pr != k)
+        for (int j = tid; j < ZS; j += 64) {
+          const double t = A[k * ZS + j];
+          A[k * ZS + j] = A[pr * ZS + j];
+          A[pr * ZS + j] = t;
+        }
+      __syncthreads();
+      if (!bad) {
+        const double inv = 1.0 / A[k * ZS + k];
+        for (int i = k + 1 + tid; i < ZS; i += 64) A[i * ZS + k] *= inv;
+        __syncthreads();
+        const int w = ZS - k - 1;
+        for (int e = tid; e < w * w; e += 64) {
+          const int i = k + 1 + e / w, j = k + 1 + e % w;
+          A[i * ZS + j] -= A[i * ZS + k] * A[k * ZS + j];
+        }
+      }
+      __syncthreads();
+    }
+    // centre rows: A^T z_f = e_f with P A = L U  =>  U^T w = e_f, L^T v = w, z = P^T v
+    if (tid <= D && !bad) {
+      double* z = rhs[tid];
+      for (int i = 0; i < ZS; ++i) {
+        double sum = i == centre[tid] ? 1.0 : 0.0;
+        for (int j = 0; j < i; ++j) sum -= A[j * ZS + i] * z[j];
+        z[i] = sum / A[i * ZS + i];
+      }
+      for (int i = ZS - 1; i >= 0; --i) {
+        double sum = z[i];
+        for (int j = i + 1; j < ZS; ++j) sum -= A[j * ZS + i] * z[j];
+        z[i] = sum;
+      }
+      for (int k = ZS - 1; k >= 0; --k) {
+        const int p = piv[k];
+        if (p != k) {
+          const double t = z[k];
+          z[k] = z[p];
+          z[p] = t;
+        }
+      }
+    }
+    __syncthreads();
+    double* Zp = Z + pi * (int64_t)(D + 1) * ZSP;
+    for (int e = tid; e < (D + 1) * ZSP; e += 64) {
+      const int f = e / ZSP, col = e % ZSP;
+      double val = 0;
+      if (!bad && col < ZS) {
+        const bool in = col < D * NV ? vel_in_grid<D>(c, n, col % NV) : pres_in_grid<D>(c, n, col - D * NV);
+        if (in) val = rhs[f][col];
+      }
+      Zp[e] = val;
+    }
+    if (tid == 0 && bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
 template <int D>
 hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count, double* Z,
                                 hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if constexpr (D == 2) {
+    if (c.prm.immersed_nitsche) {
+      const int64_t nb = count < 262144 ? count : 262144;
+      patch_inverse_rows_lu2_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(
+          L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, Z, c.err);
+      return hipGetLastError();
+    }
+  }
   const int64_t nb = count < 262144 ? count : 262144;
   patch_inverse_rows_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
       L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, Z, c.err);

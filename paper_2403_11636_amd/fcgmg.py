@@ -49,7 +49,7 @@ class Params(ctypes.Structure):
         ("nu_post", ctypes.c_int), ("force", ctypes.c_int), ("bc", ctypes.c_int * 6),
         ("eta", ctypes.c_double), ("alpha_fict", ctypes.c_double), ("nitsche_beta", ctypes.c_double),
         ("omega", ctypes.c_double), ("ubar", ctypes.c_double), ("precision", ctypes.c_int),
-        ("solver", ctypes.c_int), ("krylov_restart", ctypes.c_int),
+        ("solver", ctypes.c_int), ("krylov_restart", ctypes.c_int), ("immersed_nitsche", ctypes.c_int),
     ]
 
 
@@ -182,6 +182,7 @@ def make_params(prob, policy: int = CACHE_INVERSE, precision: int = PREC_FP64, s
     p.precision = precision
     p.solver = solver
     p.krylov_restart = krylov_restart
+    p.immersed_nitsche = int(getattr(prob, "immersed_nitsche", 0))
     return p
 
 
