@@ -102,6 +102,21 @@ def test_immersed_vcycle_and_solve(name):
     hk.close()
 
 
+def test_immersed_mixed_precision_fgmres():
+    # FP32 V-cycles (rounded from the FP64 LU rows) inside FP64 FGMRES: the oracle's FP64 residual of
+    # the iterate meets the stopping test.
+    from paper_2403_11636_amd import fcgmg
+    p, o, _ = setup_case("2d_32_l3_s2")
+    h = fcgmg.Hierarchy(p, fcgmg.CACHE_INVERSE, precision=fcgmg.PREC_MIXED, solver=fcgmg.SOLVER_FGMRES,
+                        krylov_restart=30)
+    b = o.rhs()
+    x, it, relk, _, rc = h.solve(dev(b), rtol=1e-8, max_iter=200)
+    assert rc == 0 and relk <= 1e-8
+    r = o.residual(o.fine, host(x), b)
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
+    h.close()
+
+
 def test_immersed_needs_2d_cache_inverse():
     from paper_2403_11636_amd import fcgmg
     p = dataclasses.replace(inputs.config1(32, 3), immersed_nitsche=1)

@@ -44,6 +44,7 @@ SMALL = {
     "2d_16_l3_s0": lambda: inputs.small_problem(2, 16, 3, seed=0),
     "2d_24_l2_s1": lambda: inputs.small_problem(2, 24, 2, seed=1, n_balls=3, rmin=0.05, rmax=0.1),
     "2d_40_l3_noslip": lambda: inputs.small_problem(2, 40, 3, seed=2, bcs=(0,) * 6, n_balls=2),
+    "2d_20_l2_noballs": lambda: inputs.small_problem(2, 20, 2, seed=0, n_balls=0),
     "c1_32_l3": lambda: inputs.config1(32, 3),
     "3d_8_l2_s0": lambda: inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2),
     "3d_12_l2_s3": lambda: inputs.small_problem(3, 12, 2, seed=3, n_balls=2, rmin=0.08, rmax=0.14),
