@@ -842,7 +842,7 @@ __device__ __forceinline__ void irregular_pair(const T* __restrict__ ZA, const T
   for (int f = 0; f <= D; ++f) acca[f] = accb[f] = 0;
   const T* ZBs = has_b ? ZB : ZA;
   // 2D: the four column steps are unrolled so that all row loads are in flight at once
-#pragma unroll(D == 2 ? 4 : 2)
+#pragma unroll(D == 2 ? 4 : 4)
   for (int col = j16; col < ZS; col += 16) {
     int field, o[3];
     patch_column<D>(col, &field, o);
