@@ -483,6 +483,42 @@ def workload_extra(torch, fcgmg, prob, steps=5):
     return res
 
 
+def stacked_extra(torch, fcgmg, prob, nrhs=8, reps=5):
+    """Stacked right-hand sides on one geometry: two sweeps of nrhs vectors through fcgmg_smooth_multi
+    (each streamed patch's rows read once per sweep for all vectors) against nrhs separate two-sweep
+    smooth calls, per sweep of all vectors."""
+    h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
+    n = h.ndofs()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    X = torch.randn(nrhs * n, dtype=torch.float64, device="cuda", generator=g)
+    B = torch.randn(nrhs * n, dtype=torch.float64, device="cuda", generator=g)
+    R = torch.zeros_like(X)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    h.smooth_multi(X, B, R, nrhs, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        h.smooth_multi(X, B, R, nrhs, 2)
+    e1.record()
+    torch.cuda.synchronize()
+    stacked = e0.elapsed_time(e1) / (2 * reps)
+    xs = [X[k * n:(k + 1) * n] for k in range(nrhs)]
+    bs = [B[k * n:(k + 1) * n] for k in range(nrhs)]
+    e0.record()
+    for _ in range(reps):
+        for k in range(nrhs):
+            h.smooth(xs[k], bs[k], 2)
+    e1.record()
+    torch.cuda.synchronize()
+    separate = e0.elapsed_time(e1) / (2 * reps)
+    h.close()
+    return {"workload": prob.name, "nrhs": nrhs, "stacked_ms_per_sweep": round(stacked, 4),
+            "separate_ms_per_sweep": round(separate, 4), "speedup": round(separate / stacked, 2),
+            "stacked_dof_per_s": round(nrhs * n / (stacked * 1e-3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -593,6 +629,8 @@ def main():
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
         log("precision: FP64 vs mixed ...")
         out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]
+        log("stacked right-hand sides ...")
+        out["stacked_rhs"] = [stacked_extra(torch, fcgmg, inputs.config3(0)), stacked_extra(torch, fcgmg, inputs.config2(0))]
         log("immersed Nitsche ...")
         out["immersed"] = immersed_extra(torch, fcgmg, inputs.config2(0))
         log("batching ...")

@@ -140,6 +140,16 @@ int fcgmg_residual(fcgmg_h h, int level, const double* x, const double* b, doubl
  * prolongation R~_i). x is updated in place; b is read. */
 int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream);
 
+/* Stacked right-hand sides (several problems on one geometry): `sweeps` sweeps of Eq. (14)-(15) on
+ * level `level` for nrhs (1..8) vectors at once. x and b hold nrhs vectors of (d+1) N_l doubles,
+ * one after another (vector k at offset k (d+1) N_l); r is caller-owned scratch of the same size (3D:
+ * it holds the residuals of the last sweep on return). In 3D the inverse rows of every streamed patch
+ * are read once per sweep for all right-hand sides; in 2D each vector takes the fused sweep, which is
+ * faster there. Each x_k ends bitwise equal to fcgmg_smooth on x_k, b_k. cache_inverse only.
+ * Asynchronous on `stream`; E_ARG for a bad level, pointer, nrhs or policy. */
+int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double* r, int nrhs, int sweeps,
+                       void* stream);
+
 /* b_coarse = R r_fine with R = P^T (Eq. 13, T = identity): level `fine_level` to fine_level-1. */
 int fcgmg_restrict(fcgmg_h h, int fine_level, const double* r_fine, double* b_coarse, void* stream);
 

@@ -1103,6 +1103,43 @@ int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, v
   return h->prm.dim == 2 ? smooth_impl<2>(*h, level, x, b, sweeps, s) : smooth_impl<3>(*h, level, x, b, sweeps, s);
 }
 
+int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double* r, int nrhs, int sweeps,
+                       void* stream) {
+  if (!valid_level(h, level) || !x || !b || !r || sweeps < 0) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  if (nrhs < 1 || nrhs > fcg::kMaxRhs) return fail(FCGMG_E_ARG, "nrhs must be in [1,8]");
+  if (h->prm.cache_policy != FCGMG_CACHE_INVERSE) return fail(FCGMG_E_ARG, "smooth_multi needs the cache_inverse policy");
+  hipStream_t s = (hipStream_t)stream;
+  auto run = [&](auto dim) -> int {
+    constexpr int D = decltype(dim)::value;
+    const fcg::Ctx& c = *h;
+    const fcg::Level& L = c.lev[level];
+    const int64_t nd = (D + 1) * L.N;
+    int rc;
+    if constexpr (D == 2) {
+      // 2D: the fused sweep of each vector (x and r in LDS per tile) is faster than the stacked
+      // unfused sweep; the results are the same bits either way
+      for (int k = 0; k < nrhs; ++k)
+        if ((rc = smooth_impl<2>(c, level, x + k * nd, b + k * nd, sweeps, s))) return rc;
+      return FCGMG_OK;
+    }
+    for (int it = 0; it < sweeps; ++it) {
+      for (int k = 0; k < nrhs; ++k)
+        if ((rc = residual_impl<D>(c, level, x + k * nd, b + k * nd, r + k * nd, s))) return rc;
+      if (L.n_classes)
+        for (int k = 0; k < nrhs; ++k)
+          if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, level, s,
+                                [&] { return fcg::k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, s); })))
+            return rc;
+      if (L.n_irr)
+        if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, level, s,
+                              [&] { return fcg::k_apply_irregular_multi<D, double>(c, L, r, x, nd, nrhs, s); })))
+          return rc;
+    }
+    return FCGMG_OK;
+  };
+  return h->prm.dim == 2 ? run(std::integral_constant<int, 2>{}) : run(std::integral_constant<int, 3>{});
+}
+
 int fcgmg_restrict(fcgmg_h h, int fine_level, const double* rf, double* bc, void* stream) {
   if (!valid_level(h, fine_level) || fine_level < 1 || !rf || !bc) return fail(FCGMG_E_ARG, "bad level or pointer");
   hipStream_t s = (hipStream_t)stream;

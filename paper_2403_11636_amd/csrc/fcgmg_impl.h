@@ -486,6 +486,10 @@ template <int D, class T>
 hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
 template <int D, class T>
 hipError_t k_apply_irregular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
+constexpr int kMaxRhs = 8;  // right-hand sides of one stacked sweep (fcgmg_smooth_multi)
+template <int D, class T>
+hipError_t k_apply_irregular_multi(const Ctx& c, const Level& L, const T* r, T* x, int64_t nd, int nrhs,
+                                   hipStream_t s);
 template <class T>
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
                           hipStream_t s);

@@ -1315,6 +1315,8 @@ namespace fcg {
   template hipError_t k_apply_irregular<D, double>(const Ctx&, const Level&, const double*, double*,          \
                                                    hipStream_t);                                              \
   template hipError_t k_apply_irregular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t); \
+  template hipError_t k_apply_irregular_multi<D, double>(const Ctx&, const Level&, const double*, double*,    \
+                                                         int64_t, int, hipStream_t);                          \
   template hipError_t k_patch_solve<D>(const Ctx&, const Level&, int, const double*, double*, hipStream_t);  \
   template hipError_t k_store_matrices<D>(const Ctx&, const Level&, const int*, int64_t, double*,             \
                                           hipStream_t);                                                       \

@@ -954,6 +954,79 @@ __global__ void __launch_bounds__(256) apply_irregular_kernel(int n, int64_t nir
   }
 }
 
+// Streamed patches for nrhs right-hand sides at once (vectors nd apart, at most kMaxRhs): each
+// 16-lane group takes one patch per trip, loads its rows once and applies them to the gathers of
+// every right-hand side. Per right-hand side the arithmetic is that of irregular_pair, so each
+// result equals the single-vector apply.
+template <int D, class T>
+__global__ void __launch_bounds__(256) apply_irregular_multi_kernel(int n, int64_t nirr, const int* __restrict__ irr_nodes,
+                                                                    const int* __restrict__ irr_zrow,
+                                                                    const T* __restrict__ Zirr,
+                                                                    const T* __restrict__ r, T* __restrict__ x,
+                                                                    int64_t nd, int nrhs, T omega) {
+  constexpr int ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
+  const int j16 = threadIdx.x & 15;
+  const int m = n + 1;
+  const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
+  const int64_t stride = (int64_t)gridDim.x * 16;
+  for (int64_t pa = blockIdx.x * 16 + (threadIdx.x >> 4); pa < nirr; pa += stride) {
+    const int na = irr_nodes[pa];
+    const T* Z = Zirr + (int64_t)irr_zrow[pa] * (D + 1) * ZSP;
+    const int ca[3] = {na % m, (na / m) % m, D == 3 ? na / (m * m) : 0};
+    T acc[kMaxRhs][D + 1];
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k)
+#pragma unroll
+      for (int f = 0; f <= D; ++f) acc[k][f] = 0;
+#pragma unroll 2
+    for (int col = j16; col < ZS; col += 16) {
+      int field, o[3];
+      patch_column<D>(col, &field, o);
+      T z[D + 1];
+#pragma unroll
+      for (int f = 0; f <= D; ++f) z[f] = Z[f * ZSP + col];
+      const int cc[3] = {ca[0] + o[0], ca[1] + o[1], ca[2] + o[2]};
+      bool in = true;
+      for (int k = 0; k < D; ++k) in = in && cc[k] >= 0 && cc[k] < m;
+      const int64_t gi = field * N + (D == 2 ? cc[0] + (int64_t)m * cc[1] : cc[0] + (int64_t)m * (cc[1] + (int64_t)m * cc[2]));
+#pragma unroll
+      for (int k = 0; k < kMaxRhs; ++k)
+        if (k < nrhs) {
+          const T g = in ? r[k * nd + gi] : T(0);
+#pragma unroll
+          for (int f = 0; f <= D; ++f) acc[k][f] += z[f] * g;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k)
+#pragma unroll
+      for (int f = 0; f <= D; ++f)
+#pragma unroll
+        for (int msk = 8; msk >= 1; msk >>= 1) acc[k][f] += __shfl_xor(acc[k][f], msk, 16);
+    if (j16 <= D)
+#pragma unroll
+      for (int k = 0; k < kMaxRhs; ++k)
+        if (k < nrhs) {
+          T v = acc[k][0];
+#pragma unroll
+          for (int f = 1; f <= D; ++f)
+            if (j16 == f) v = acc[k][f];
+          x[k * nd + j16 * N + na] += omega * v;
+        }
+  }
+}
+
+template <int D, class T>
+hipError_t k_apply_irregular_multi(const Ctx& c, const Level& L, const T* r, T* x, int64_t nd, int nrhs,
+                                   hipStream_t s) {
+  if (L.n_irr == 0) return hipSuccess;
+  int64_t nb = (L.n_irr + 15) / 16;
+  if (nb > 65536) nb = 65536;
+  apply_irregular_multi_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(
+      L.n, L.n_irr, L.irr_nodes, L.irr_zrow, LV<T>::Zirr(L), r, x, nd, nrhs, (T)c.prm.omega);
+  return hipGetLastError();
+}
+
 // Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes by NT >= TX TY
 // threads; thread t < TX TY owns node t of the tile. Large grids use 32 x 8 tiles with one thread per
 // node (less halo work); small grids, whose sweep time is the latency of one workgroup, use small

@@ -1,0 +1,85 @@
+"""Stacked right-hand sides (fcgmg_smooth_multi): nrhs vectors of one geometry smoothed together, the
+inverse rows of every streamed patch read once per sweep. Each result must equal fcgmg_smooth on that
+vector bit for bit (the per-vector arithmetic is the same); one case is also checked against the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2403_11636_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "2d_16_l3_s0": lambda: inputs.small_problem(2, 16, 3, seed=0),
+    "c1_32_l3": lambda: inputs.config1(32, 3),
+    "3d_8_l2_s0": lambda: inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2),
+    "3d_12_l2_s3": lambda: inputs.small_problem(3, 12, 2, seed=3, n_balls=2, rmin=0.08, rmax=0.14),
+}
+
+
+def fcg():
+    from paper_2403_11636_amd import fcgmg
+    return fcgmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+@pytest.mark.parametrize("name", list(CASES))
+def test_stacked_equals_single_sweeps(name, nrhs):
+    f = fcg()
+    h = f.Hierarchy(CASES[name](), f.CACHE_INVERSE)
+    for lev in (h.fine, max(h.fine - 1, 1)):
+        n = h.ndofs(lev)
+        X = np.concatenate([inputs.random_vector(n, 100 + k) for k in range(nrhs)])
+        B = np.concatenate([inputs.random_vector(n, 200 + k) for k in range(nrhs)])
+        for sweeps in (1, 2):
+            xm = dev(X)
+            r = torch.zeros_like(xm)
+            h.smooth_multi(xm, dev(B), r, nrhs, sweeps, level=lev)
+            for k in range(nrhs):
+                xs = dev(X[k * n:(k + 1) * n])
+                h.smooth(xs, dev(B[k * n:(k + 1) * n]), sweeps, level=lev)
+                assert torch.equal(xm[k * n:(k + 1) * n], xs), (lev, sweeps, k)
+    h.close()
+
+
+def test_stacked_against_oracle():
+    f = fcg()
+    p = CASES["3d_12_l2_s3"]()
+    h = f.Hierarchy(p, f.CACHE_INVERSE)
+    o = Oracle(p)
+    n = h.ndofs()
+    X = np.concatenate([inputs.random_vector(n, 300 + k) for k in range(4)])
+    B = np.concatenate([inputs.random_vector(n, 400 + k) for k in range(4)])
+    xm = dev(X)
+    h.smooth_multi(xm, dev(B), torch.zeros_like(xm), 4, 1)
+    torch.cuda.synchronize()
+    got = xm.cpu().numpy()
+    for k in range(4):
+        ref = o.smooth(o.fine, X[k * n:(k + 1) * n], B[k * n:(k + 1) * n], 1, p.omega)
+        err = np.linalg.norm(got[k * n:(k + 1) * n] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, (k, err)
+    h.close()
+
+
+def test_stacked_rejects_bad_arguments():
+    f = fcg()
+    h = f.Hierarchy(CASES["c1_32_l3"](), f.CACHE_INVERSE)
+    n = h.ndofs()
+    x = torch.zeros(9 * n, dtype=torch.float64, device="cuda")
+    rc = f.load().fcgmg_smooth_multi(h.h, h.fine, x.data_ptr(), x.data_ptr(), x.data_ptr(), 0, 1, None)
+    assert rc == f.E_ARG
+    with pytest.raises(f.FcgmgError):
+        h.smooth_multi(x, x.clone(), x.clone(), 9, 1)
+    h.close()
+    hm = f.Hierarchy(CASES["c1_32_l3"](), f.CACHE_MATRIX)
+    x = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    with pytest.raises(f.FcgmgError):
+        hm.smooth_multi(x, x.clone(), x.clone(), 2, 1)
+    hm.close()
