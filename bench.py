@@ -288,6 +288,18 @@ def immersed_extra(torch, fcgmg, prob, solves=5):
             rec.update({"converged": False, "error": str(e)[:160]})
         out[tag] = rec
         h.close()
+    # the three policies of Sec. 3.1.2 with these terms (dense LU of the local blocks at every
+    # application for cache_matrix and cache_none)
+    pol = {}
+    for policy, name in ((fcgmg.CACHE_INVERSE, "cache_inverse"), (fcgmg.CACHE_MATRIX, "cache_matrix"),
+                         (fcgmg.CACHE_NONE, "cache_none")):
+        h = fcgmg.Hierarchy(p, policy)
+        b = h.rhs()
+        x = h.zeros()
+        lat = time_sweeps(torch, h, x, b, 3)
+        pol[name] = {"sweep_ms_p50": round(float(np.median(lat)), 4), "device_bytes": h.device_bytes()}
+        h.close()
+    out["policies"] = pol
     return out
 
 

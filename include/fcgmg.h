@@ -80,8 +80,9 @@ typedef struct {
   int krylov_restart; /* FGMRES restart length m, 1..63 (ignored by FCGMG_SOLVER_GMG)              */
   int immersed_nitsche; /* 1: the obstacle surfaces are no-slip Dirichlet boundaries (Eq. 5, Gamma_D),
                            imposed by the Nitsche forms of the walls on arcs through the cut cells;
-                           2D and FCGMG_CACHE_INVERSE only, whose patch rows then come from a dense
-                           LU with partial pivoting. 0: obstacles are fictitious regions only.      */
+                           2D only. The local blocks may then be indefinite and are factorised by a
+                           dense LU with partial pivoting under every cache policy. 0: obstacles are
+                           fictitious regions only.                                                  */
 } fcgmg_params;
 
 /* Outer iteration of fcgmg_solve. GMG: the standalone multigrid of Sec. 4, x <- V(x, b) until the

@@ -106,6 +106,7 @@ void build_consts(const Ctx& c, Level& L) {
   OpConsts& oc = L.consts_h;
   std::memset(&oc, 0, sizeof(oc));
   oc.n = L.n;
+  oc.immersed = c.prm.immersed_nitsche;
   oc.h = L.h;
   const double eta = c.prm.eta;
   oc.lam = c.prm.nitsche_beta * eta / L.h;
@@ -991,8 +992,7 @@ static int validate_params(const fcgmg_params& prm, const double* balls, int n_b
   if (P.solver == FCGMG_SOLVER_FGMRES && (P.krylov_restart < 1 || P.krylov_restart > 63))
     return fail(FCGMG_E_ARG, "krylov_restart must be in [1,63]");
   if (P.immersed_nitsche != 0 && P.immersed_nitsche != 1) return fail(FCGMG_E_ARG, "immersed_nitsche must be 0 or 1");
-  if (P.immersed_nitsche && (P.dim != 2 || P.cache_policy != FCGMG_CACHE_INVERSE))
-    return fail(FCGMG_E_ARG, "immersed_nitsche needs dim 2 and the cache_inverse policy");
+  if (P.immersed_nitsche && P.dim != 2) return fail(FCGMG_E_ARG, "immersed_nitsche needs dim 2");
   if (!(P.eta > 0) || !(P.alpha_fict >= 0) || !(P.nitsche_beta > 0) || !std::isfinite(P.omega))
     return fail(FCGMG_E_ARG, "eta, nitsche_beta must be > 0, alpha_fict >= 0, omega finite");
   if (P.nu_pre < 0 || P.nu_post < 0) return fail(FCGMG_E_ARG, "negative smoothing steps");

@@ -68,6 +68,7 @@ struct OpConsts {
   double FB[6][64];     // int_F phi_a n_k phi_b on face f (velocity component k = axis of f)
   int dirichlet[6];
   int n;                // cells per axis
+  int immersed;         // 1: Nitsche terms on the obstacle arcs of cut cells (2D)
   double h, lam;
   // Assembled node stencils of a node whose 2^d cells are uncut, of one kind and away from the
   // walls, per kind, over the 3^d neighbour offsets: velocity-velocity (same component), velocity

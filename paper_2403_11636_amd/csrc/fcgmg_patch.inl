@@ -104,6 +104,17 @@ __device__ void patch_assemble(PatchLDS<D>& sh, const OpConsts* __restrict__ oc,
         double acc[NPER];
         for (int k = 0; k < NPER; ++k) acc[k] = 0;
         integrate_cell_entries<D>(gl, lo, oc->h, eta, acc, NPER);
+        if constexpr (D == 2) {
+          if (oc->immersed)
+            arc_quadrature2(gl, lo, oc->h, [&](const double* xq, double w, const double* nrm) {
+              double phi[4], gr[4][3];
+              q1<2>(lo, oc->h, xq, phi, gr);
+              for (int k = 0; k < NPER; ++k) {
+                const int e = tid + k * nt;
+                if (e < NEL) acc[k] += nitsche_entry2(e, eta, oc->lam, w, nrm, phi, gr);
+              }
+            });
+        }
         for (int k = 0; k < NPER; ++k) {
           const int e = tid + k * nt;
           if (e < NEL) sh.cellbuf[e] = acc[k];
@@ -495,20 +506,135 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_inverse_rows_kernel(
   }
 }
 
-// cache_inverse set-up with the immersed boundary terms (2D). Symmetric Nitsche is not coercive on
-// cells with a small physical part, so the velocity block of a cut-band patch may be indefinite and
-// the block Cholesky above does not apply. The whole block L_i (59 x 59: u_x, u_y, p over the
-// window, decoupled positions outside the grid) is factorised by LU with partial pivoting (largest
-// magnitude, lowest row on ties; Sec. 3.1.2 names LU), and the centre rows of L_i^{-1} come from the
-// transposed solves U^T w = e_f, L^T v = w, z = P^T v. One wavefront per patch.
+// Dense LU of a 2D patch block (immersed boundary terms). Symmetric Nitsche is not coercive on cells
+// with a small physical part, so the velocity block of a cut-band patch may be indefinite and the
+// block Cholesky above does not apply. The whole block L_i (59 x 59: u_x, u_y, p over the window,
+// decoupled positions outside the grid) is factorised by LU with partial pivoting (largest
+// magnitude, lowest row on ties; Sec. 3.1.2 names LU). One wavefront per patch, the block in LDS.
+constexpr int kLU2 = PT<2>::ZS;
+
+// A (row-major) = I_2 (x) K_i (from the lower band), B_c and B_c^T, C_i of the assembled patch.
+__device__ void patch_dense2(const PatchLDS<2>& sh, double* A) {
+  constexpr int NV = PT<2>::NV, NP = PT<2>::NP, NB = PT<2>::NB, NPX = NP + 2, ZS = kLU2;
+  for (int e = threadIdx.x; e < ZS * ZS; e += 64) {
+    const int i = e / ZS, j = e % ZS;
+    double v = 0;
+    if (i < 2 * NV && j < 2 * NV) {
+      const int vi = i % NV, vj = j % NV;
+      if (i / NV == j / NV) {
+        const int hi = vi > vj ? vi : vj, lo = vi > vj ? vj : vi;
+        if (hi - lo < NB) v = sh.Kb[hi * NB + (hi - lo)];
+      }
+    } else if (i < 2 * NV) {
+      v = sh.X[((i / NV) * NV + i % NV) * NPX + (j - 2 * NV)];
+    } else if (j < 2 * NV) {
+      v = sh.X[((j / NV) * NV + j % NV) * NPX + (i - 2 * NV)];
+    } else {
+      v = sh.S[(i - 2 * NV) * NP + (j - 2 * NV)];
+    }
+    A[e] = v;
+  }
+  __syncthreads();
+}
+
+// P A = L U in place (unit L below the diagonal, U on and above), row swaps in piv; returns true
+// when a pivot column is zero (singular block). Wavefront-uniform.
+__device__ bool lu_factor2(double* A, int* piv) {
+  constexpr int ZS = kLU2;
+  const int tid = threadIdx.x;
+  bool bad = false;
+  for (int k = 0; k < ZS; ++k) {
+    // pivot row: largest |A[i][k]|, i >= k, lowest index on ties (a butterfly over the wavefront)
+    const int i0 = k + tid;
+    double pv = i0 < ZS ? fabs(A[i0 * ZS + k]) : -1.0;
+    int pr = i0 < ZS ? i0 : ZS;
+    for (int m = 32; m >= 1; m >>= 1) {
+      const double ov = __shfl_xor(pv, m, 64);
+      const int orow = __shfl_xor(pr, m, 64);
+      if (ov > pv || (ov == pv && orow < pr)) {
+        pv = ov;
+        pr = orow;
+      }
+    }
+    if (tid == 0) piv[k] = pr;
+    if (!(pv > 0)) bad = true;
+    if (pr != k)
+      for (int j = tid; j < ZS; j += 64) {
+        const double t = A[k * ZS + j];
+        A[k * ZS + j] = A[pr * ZS + j];
+        A[pr * ZS + j] = t;
+      }
+    __syncthreads();
+    if (!bad) {
+      const double inv = 1.0 / A[k * ZS + k];
+      for (int i = k + 1 + tid; i < ZS; i += 64) A[i * ZS + k] *= inv;
+      __syncthreads();
+      const int w = ZS - k - 1;
+      for (int e = tid; e < w * w; e += 64) {
+        const int i = k + 1 + e / w, j = k + 1 + e % w;
+        A[i * ZS + j] -= A[i * ZS + k] * A[k * ZS + j];
+      }
+    }
+    __syncthreads();
+  }
+  return bad;
+}
+
+// z = row `row` of A^{-1}: A^T z = e_row, i.e. U^T w = e_row, L^T v = w, z = P^T v (one thread).
+__device__ void lu_inverse_row2(const double* A, const int* piv, int row, double* z) {
+  constexpr int ZS = kLU2;
+  for (int i = 0; i < ZS; ++i) {
+    double sum = i == row ? 1.0 : 0.0;
+    for (int j = 0; j < i; ++j) sum -= A[j * ZS + i] * z[j];
+    z[i] = sum / A[i * ZS + i];
+  }
+  for (int i = ZS - 1; i >= 0; --i) {
+    double sum = z[i];
+    for (int j = i + 1; j < ZS; ++j) sum -= A[j * ZS + i] * z[j];
+    z[i] = sum;
+  }
+  for (int k = ZS - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = z[k];
+      z[k] = z[p];
+      z[p] = t;
+    }
+  }
+}
+
+// y = A^{-1} g in place: g <- P g, L u = g, U y = u (one thread).
+__device__ void lu_solve2(const double* A, const int* piv, double* g) {
+  constexpr int ZS = kLU2;
+  for (int k = 0; k < ZS; ++k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = g[k];
+      g[k] = g[p];
+      g[p] = t;
+    }
+  }
+  for (int i = 0; i < ZS; ++i) {
+    double sum = g[i];
+    for (int j = 0; j < i; ++j) sum -= A[i * ZS + j] * g[j];
+    g[i] = sum;
+  }
+  for (int i = ZS - 1; i >= 0; --i) {
+    double sum = g[i];
+    for (int j = i + 1; j < ZS; ++j) sum -= A[i * ZS + j] * g[j];
+    g[i] = sum / A[i * ZS + i];
+  }
+}
+
+// cache_inverse set-up with the immersed boundary terms (2D): the centre rows of L_i^{-1} from the
+// dense LU by transposed solves.
 __global__ void __launch_bounds__(64) patch_inverse_rows_lu2_kernel(
     const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
     double eta, const int* __restrict__ nodes, int64_t count, double* __restrict__ Z, int* err) {
-  constexpr int D = 2, NV = PT<2>::NV, NP = PT<2>::NP, NB = PT<2>::NB, NPX = NP + 2, ZS = PT<2>::ZS,
-                ZSP = PT<2>::ZSP;
+  constexpr int D = 2, NV = PT<2>::NV, ZS = kLU2, ZSP = PT<2>::ZSP;
   static_assert(PT<2>::THREADS == 64, "one wavefront per patch");
   __shared__ PatchLDS<2> sh;
-  __shared__ double A[ZS * ZS];  // row-major
+  __shared__ double A[ZS * ZS];
   __shared__ double rhs[D + 1][ZS];
   __shared__ int piv[ZS];
   const int tid = threadIdx.x;
@@ -520,83 +646,9 @@ __global__ void __launch_bounds__(64) patch_inverse_rows_lu2_kernel(
     node_coords<D>(node, n, c);
     patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 0);
     patch_pad<D>(sh, c, n);
-    // the dense block: I_2 (x) K_i (from the lower band), B_c and B_c^T, C_i
-    for (int e = tid; e < ZS * ZS; e += 64) {
-      const int i = e / ZS, j = e % ZS;
-      double v = 0;
-      if (i < D * NV && j < D * NV) {
-        const int vi = i % NV, vj = j % NV;
-        if (i / NV == j / NV) {
-          const int hi = vi > vj ? vi : vj, lo = vi > vj ? vj : vi;
-          if (hi - lo < NB) v = sh.Kb[hi * NB + (hi - lo)];
-        }
-      } else if (i < D * NV) {
-        v = sh.X[((i / NV) * NV + i % NV) * NPX + (j - D * NV)];
-      } else if (j < D * NV) {
-        v = sh.X[((j / NV) * NV + j % NV) * NPX + (i - D * NV)];
-      } else {
-        v = sh.S[(i - D * NV) * NP + (j - D * NV)];
-      }
-      A[e] = v;
-    }
-    __syncthreads();
-    bool bad = false;
-    for (int k = 0; k < ZS; ++k) {
-      // pivot row: largest |A[i][k]|, i >= k, lowest index on ties (one wavefront: a butterfly)
-      const int i0 = k + tid;
-      double pv = i0 < ZS ? fabs(A[i0 * ZS + k]) : -1.0;
-      int pr = i0 < ZS ? i0 : ZS;
-      for (int m = 32; m >= 1; m >>= 1) {
-        const double ov = __shfl_xor(pv, m, 64);
-        const int orow = __shfl_xor(pr, m, 64);
-        if (ov > pv || (ov == pv && orow < pr)) {
-          pv = ov;
-          pr = orow;
-        }
-      }
-      if (tid == 0) piv[k] = pr;
-      if (!(pv > 0)) bad = true;
-      if (pr != k)
-        for (int j = tid; j < ZS; j += 64) {
-          const double t = A[k * ZS + j];
-          A[k * ZS + j] = A[pr * ZS + j];
-          A[pr * ZS + j] = t;
-        }
-      __syncthreads();
-      if (!bad) {
-        const double inv = 1.0 / A[k * ZS + k];
-        for (int i = k + 1 + tid; i < ZS; i += 64) A[i * ZS + k] *= inv;
-        __syncthreads();
-        const int w = ZS - k - 1;
-        for (int e = tid; e < w * w; e += 64) {
-          const int i = k + 1 + e / w, j = k + 1 + e % w;
-          A[i * ZS + j] -= A[i * ZS + k] * A[k * ZS + j];
-        }
-      }
-      __syncthreads();
-    }
-    // centre rows: A^T z_f = e_f with P A = L U  =>  U^T w = e_f, L^T v = w, z = P^T v
-    if (tid <= D && !bad) {
-      double* z = rhs[tid];
-      for (int i = 0; i < ZS; ++i) {
-        double sum = i == centre[tid] ? 1.0 : 0.0;
-        for (int j = 0; j < i; ++j) sum -= A[j * ZS + i] * z[j];
-        z[i] = sum / A[i * ZS + i];
-      }
-      for (int i = ZS - 1; i >= 0; --i) {
-        double sum = z[i];
-        for (int j = i + 1; j < ZS; ++j) sum -= A[j * ZS + i] * z[j];
-        z[i] = sum;
-      }
-      for (int k = ZS - 1; k >= 0; --k) {
-        const int p = piv[k];
-        if (p != k) {
-          const double t = z[k];
-          z[k] = z[p];
-          z[p] = t;
-        }
-      }
-    }
+    patch_dense2(sh, A);
+    const bool bad = lu_factor2(A, piv);
+    if (tid <= D && !bad) lu_inverse_row2(A, piv, centre[tid], rhs[tid]);
     __syncthreads();
     double* Zp = Z + pi * (int64_t)(D + 1) * ZSP;
     for (int e = tid; e < (D + 1) * ZSP; e += 64) {
@@ -742,9 +794,72 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_solve_kernel(
   }
 }
 
+// cache_matrix / cache_none sweep with the immersed boundary terms (2D): every patch block, loaded
+// from its stored pattern values or assembled on the fly, is factorised by the dense LU at each
+// application and solved for its gathered residual; the centre DoFs take omega times the solution.
+__global__ void __launch_bounds__(64) patch_solve_lu2_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
+    const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
+    const double* __restrict__ r, double* __restrict__ x, double omega, int* err) {
+  constexpr int D = 2, NV = PT<2>::NV, ZS = kLU2;
+  __shared__ PatchLDS<2> sh;
+  __shared__ double A[ZS * ZS];
+  __shared__ double gv[ZS];
+  __shared__ int piv[ZS];
+  const int tid = threadIdx.x;
+  const int n = oc->n;
+  const int centre[D + 1] = {vel_center<2>(), NV + vel_center<2>(), D * NV + pres_center<2>()};
+  for (int64_t node = blockIdx.x; node < N; node += gridDim.x) {
+    int c[3];
+    node_coords<D>(node, n, c);
+    if (policy == FCGMG_CACHE_MATRIX) {
+      const int cls = node_class[node];
+      const double* vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
+      patch_load_pattern<D>(sh, pattern, npat, vals);
+    } else {
+      patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 1);
+    }
+    patch_pad<D>(sh, c, n);
+    // g = R_i r, zero outside the grid
+    for (int e = tid; e < ZS; e += 64) {
+      double val = 0;
+      if (e < D * NV) {
+        const int cmp = e / NV, v = e % NV;
+        if (r && vel_in_grid<D>(c, n, v)) {
+          int cc[3] = {c[0] + v % 5 - 2, c[1] + v / 5 - 2, 0};
+          val = r[cmp * N + node_index<D>(cc, n)];
+        }
+      } else {
+        const int q = e - D * NV;
+        if (r && pres_in_grid<D>(c, n, q)) {
+          int cc[3] = {c[0] + q % 3 - 1, c[1] + q / 3 - 1, 0};
+          val = r[D * N + node_index<D>(cc, n)];
+        }
+      }
+      gv[e] = val;
+    }
+    patch_dense2(sh, A);
+    const bool bad = lu_factor2(A, piv);
+    if (tid == 0 && !bad) lu_solve2(A, piv, gv);
+    __syncthreads();
+    if (x != nullptr && tid <= D && !bad) x[tid * N + node] += omega * gv[centre[tid]];
+    if (tid == 0 && bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
 template <int D>
 hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x, hipStream_t s) {
   const int64_t nb = L.N < 131072 ? L.N : 131072;
+  if constexpr (D == 2) {
+    if (c.prm.immersed_nitsche) {
+      patch_solve_lu2_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(
+          L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr,
+          c.pattern, c.n_pattern, L.N, r, x, c.prm.omega, c.err);
+      return hipGetLastError();
+    }
+  }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
       L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
       c.n_pattern, L.N, r, x, c.prm.omega, c.err);

@@ -63,7 +63,6 @@ def test_kernel_kinds_match_header():
     (lambda p: (setattr(p, "solver", 1), setattr(p, "krylov_restart", 64)), "krylov_restart"),
     (lambda p: (setattr(p, "precision", 1), setattr(p, "cache_policy", 1)), "mixed precision"),
     (lambda p: setattr(p, "immersed_nitsche", 2), "immersed_nitsche"),
-    (lambda p: (setattr(p, "immersed_nitsche", 1), setattr(p, "cache_policy", 1)), "immersed_nitsche"),
     (lambda p: (setattr(p, "immersed_nitsche", 1), setattr(p, "dim", 3), setattr(p, "n_cells", 8),
                 setattr(p, "n_levels", 2)), "immersed_nitsche"),
 ])

@@ -117,8 +117,30 @@ def test_immersed_mixed_precision_fgmres():
     h.close()
 
 
-def test_immersed_needs_2d_cache_inverse():
+@pytest.mark.parametrize("policy", [1, 2])
+@pytest.mark.parametrize("name", ["2d_16_l3_s0", "c1_32_l3"])
+def test_immersed_matrix_and_none_policies(name, policy):
+    # cache_matrix (stored blocks) and cache_none (blocks assembled on the fly, arcs included) with the
+    # dense LU at every application: one and two sweeps against the oracle and the cache_inverse sweep.
     from paper_2403_11636_amd import fcgmg
-    p = dataclasses.replace(inputs.config1(32, 3), immersed_nitsche=1)
+    p, o, hi = setup_case(name)
+    h = fcgmg.Hierarchy(p, policy)
+    n = o.ndofs(o.fine)
+    x = inputs.random_vector(n, 70)
+    b = inputs.random_vector(n, 71)
+    for sweeps in (1, 2):
+        xg, xi = dev(x), dev(x)
+        h.smooth(xg, dev(b), sweeps)
+        hi.smooth(xi, dev(b), sweeps)
+        x_orc = o.smooth(o.fine, x, b, sweeps, p.omega)
+        err, err_inv = rel(host(xg), x_orc), rel(host(xg), host(xi))
+        print(f"{name} policy {policy} sweeps {sweeps}: vs oracle {err:.2e}, vs cache_inverse {err_inv:.2e}")
+        assert err <= 1e-12 and err_inv <= 1e-12, (err, err_inv)
+    h.close()
+
+
+def test_immersed_needs_2d():
+    from paper_2403_11636_amd import fcgmg
+    p = dataclasses.replace(inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2), immersed_nitsche=1)
     with pytest.raises(fcgmg.FcgmgError):
-        fcgmg.Hierarchy(p, fcgmg.CACHE_MATRIX)
+        fcgmg.Hierarchy(p, fcgmg.CACHE_INVERSE)
