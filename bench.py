@@ -544,7 +544,7 @@ def main():
                     help="run only a plain device-to-device copy of MIB MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the multi-GPU (sharded) path is not part of this build; "
+        print("bench.py measures one GPU: the sharded multi-GPU path is not implemented; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
