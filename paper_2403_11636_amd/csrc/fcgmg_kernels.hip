@@ -260,15 +260,26 @@ struct TileShape<3> {
 };
 
 // Tile of block `bid` in an nt[0] x nt[1] x nt[2] tile grid. Consecutive workgroups are dealt
-// round-robin to the 8 XCDs (each with its own L2); the remap gives every XCD a contiguous range of
-// tiles so that halo re-reads of neighbouring tiles hit the same L2. It is a bijection of the first
-// 8*floor(nb/8) blocks onto themselves; the last nb % 8 blocks keep their own tile.
-template <int D>
+// round-robin to the 8 XCDs (each with its own L2), and the remap chooses which tiles share one:
+// * R = 0: every XCD takes a contiguous range of tiles (a band of the grid), so halo re-reads of
+//   neighbouring tiles hit the same L2;
+// * R > 0: every XCD takes runs of R consecutive tiles along x, and each window of 8 R tiles spreads
+//   over all 8 XCDs. The obstacles' cut tiles, which take longest, are then shared out evenly over
+//   the XCDs instead of piling up in the bands that cross them.
+// Either way it is a bijection of the first blocks onto themselves (8*floor(nb/8) for bands,
+// 8R*floor(nb/(8R)) for runs); the remaining blocks keep their own tile.
+template <int D, int R = 0>
 __device__ __forceinline__ void tile_coords(int bid, const int* nt, int* t) {
   const int nb = nt[0] * nt[1] * nt[2];
-  const int nb8 = nb - nb % 8;
   int lin = bid;
-  if (bid < nb8) lin = (bid % 8) * (nb8 / 8) + bid / 8;
+  if constexpr (R == 0) {
+    const int nb8 = nb - nb % 8;
+    if (bid < nb8) lin = (bid % 8) * (nb8 / 8) + bid / 8;
+  } else {
+    constexpr int W = 8 * R;
+    const int nbw = nb - nb % W;
+    if (bid < nbw) lin = ((bid / 8) / R) * W + (bid % 8) * R + (bid / 8) % R;
+  }
   t[0] = lin % nt[0];
   t[1] = (lin / nt[0]) % nt[1];
   t[2] = lin / (nt[0] * nt[1]);
@@ -754,7 +765,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
   const int nt[3] = {ntx, nty, ntz};
   int t[3];
-  tile_coords<D>(blockIdx.x, nt, t);
+  tile_coords<D, D == 3 ? 4 : 0>(blockIdx.x, nt, t);
   const int o0 = t[0] * TX - 1, o1 = t[1] * TY - 1, o2 = D == 3 ? t[2] * TZ - 1 : 0;
   const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = D == 3 ? threadIdx.x / (TX * TY) : 0;
   const int c[3] = {t[0] * TX + tx, t[1] * TY + ty, D == 3 ? t[2] * TZ + tz : 0};

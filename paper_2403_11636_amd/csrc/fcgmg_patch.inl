@@ -998,7 +998,7 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
   const int64_t N = D == 2 ? (int64_t)m * m : (int64_t)m * m * m;
   const int nt[3] = {ntx, nty, ntz};
   int t[3];
-  tile_coords<D>(blockIdx.x, nt, t);
+  tile_coords<D, D == 3 ? 4 : 0>(blockIdx.x, nt, t);
   const int ox = t[0] * TX - 2, oy = t[1] * TY - 2, oz = D == 3 ? t[2] * TZ - 2 : 0;
   for (int e = threadIdx.x; e < (D + 1) * PLANE; e += 256) {
     const int f = e / PLANE, p = e % PLANE;
@@ -1183,12 +1183,12 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   const int64_t N = (int64_t)m * m;
   // Workgroups 0 .. n_extra-1 are the extra parts of tiles with more than CAP individual patches
   // (code tile * 4 + part, set-up): the longest-running workgroups, dispatched first. The rest are
-  // part 0 of every tile, in XCD-aware order.
+  // part 0 of every tile, in runs of 4 tiles per XCD.
   int tile_lin, part = 0;
   if (bid >= J.n_extra) {
     const int nt[3] = {ntx, nty, 1};
     int t[3];
-    tile_coords<2>(bid - J.n_extra, nt, t);
+    tile_coords<2, 4>(bid - J.n_extra, nt, t);
     tile_lin = t[0] + ntx * t[1];
   } else {
     const int code = extra[bid];
