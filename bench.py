@@ -471,13 +471,14 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
     }
 
 
-def workload_extra(torch, fcgmg, prob, steps=5):
+def workload_extra(torch, fcgmg, prob, steps=20, warmup=3):
     t0 = time.perf_counter()
     h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
     setup = time.perf_counter() - t0
     b = h.rhs()
     x = h.zeros()
-    h.vcycle(x, b)
+    for _ in range(warmup):
+        h.vcycle(x, b)
     ms, _ = time_vcycles(torch, h, x, b, steps)
     lat = time_sweeps(torch, h, x, b, 10)
     sw = float(np.median(lat))
