@@ -1142,6 +1142,28 @@ hipError_t k_apply_irregular_multi(const Ctx& c, const Level& L, const T* r, T* 
   return hipGetLastError();
 }
 
+// Tile shapes of the fused 2D sweep by level size (nodes): 32 x 8 tiles by 256 threads from
+// kFusedBigTileNodes on, 8 x 4 by 128 from kFusedMidTileNodes on, 4 x 4 by 128 below.
+constexpr int64_t kFusedBigTileNodes = 200000;
+constexpr int64_t kFusedMidTileNodes = 30000;
+struct Fused2Shape {
+  int tx, ty, nt;
+};
+constexpr Fused2Shape kFusedBig{32, 8, 256}, kFusedMid{8, 4, 128}, kFusedSmall{4, 4, 128};
+Fused2Shape fused2_shape(int64_t N) {
+  return N >= kFusedBigTileNodes ? kFusedBig : (N >= kFusedMidTileNodes ? kFusedMid : kFusedSmall);
+}
+
+// Individual patches per workgroup part of a tile: two trips of all 16-lane groups on 32 x 8 tiles,
+// one on the smaller shapes (where a whole tile takes at most two trips and splitting the heavy ones
+// shortens the launch's tail).
+constexpr int fused2_part_cap(const Fused2Shape& sh) { return (sh.tx * sh.ty >= 256 ? 4 : 2) * (sh.nt / 16); }
+// the part code (tile * 4 + part) allows four parts per tile
+static_assert(kFusedBig.tx * kFusedBig.ty <= 4 * fused2_part_cap(kFusedBig) &&
+                  kFusedMid.tx * kFusedMid.ty <= 4 * fused2_part_cap(kFusedMid) &&
+                  kFusedSmall.tx * kFusedSmall.ty <= 4 * fused2_part_cap(kFusedSmall),
+              "at most four parts per tile");
+
 // Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes by NT >= TX TY
 // threads; thread t < TX TY owns node t of the tile. Large grids use 32 x 8 tiles with one thread per
 // node (less halo work); small grids, whose sweep time is the latency of one workgroup, use small
@@ -1150,7 +1172,7 @@ hipError_t k_apply_irregular_multi(const Ctx& c, const Level& L, const T* r, T* 
 // mode 0: x_in as given; mode 1: x_in is zero (not read; the first sweep on a coarse level);
 // mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
 // V-cycle applied as the x tile is loaded, as prolong_add would apply it).
-template <int TX, int TY, int NT, class T>
+template <int TX, int TY, int NT, int CAP, class T>
 __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
   const OpConsts* __restrict__ oc = J.oc;
@@ -1175,7 +1197,6 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   __shared__ StoredList2<NT, NRES> sl;                    // residual nodes with a stored stencil
   constexpr int NWO = (TX * TY + 63) / 64;               // wavefronts that own tile nodes
   constexpr int NG = NT / 16;                             // 16-lane groups of the workgroup
-  constexpr int CAP = 4 * NG;                             // individual patches per part (two trips)
   __shared__ int irr_tid[NWO * 64], irr_pidx[NWO * 64];
   __shared__ int irr_wcnt[NWO];
   const int n = oc->n;
@@ -1299,8 +1320,8 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
     for (int f = 0; f < 3; ++f) x_out[f * N + node] = xs[f * XP + xb] + omega * y[f];
   }
   // Individual patches of the tile, listed in LDS in node order (one segment per wavefront, so
-  // every part of a tile sees the same list); part p takes entries [p CAP, (p + 1) CAP), which 16
-  // lane groups process two patches at a time.
+  // every part of a tile sees the same list); part p takes entries [p CAP, (p + 1) CAP), which
+  // 16-lane groups process two patches at a time.
   if (threadIdx.x < NWO * 64) {
     const bool irr = inside && cls < 0;
     const unsigned long long mask = __ballot(irr);
@@ -1350,38 +1371,29 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
 template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 sweep_fused2_kernel(Fused2Job<T> J) {
-  fused2_body<TX, TY, NT, T>(J, (int)blockIdx.x);
+  fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(J, (int)blockIdx.x);
 }
 
 // Batched form: the workgroups of several jobs (levels of independent problems) in one launch;
-// block_job maps a workgroup to its job, whose workgroups start at job.block0.
+// block_job maps a workgroup to its job, whose workgroups start at job.block0. There are no extra
+// parts: one part holds the whole tile.
 template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 sweep_fused2_batch_kernel(const Fused2Job<T>* __restrict__ jobs, const int* __restrict__ block_job) {
   const Fused2Job<T> J = jobs[block_job[blockIdx.x]];
-  fused2_body<TX, TY, NT, T>(J, (int)blockIdx.x - J.block0);
+  fused2_body<TX, TY, NT, TX * TY, T>(J, (int)blockIdx.x - J.block0);
 }
 
-// Tile shapes of the fused 2D sweep by level size (nodes): 32 x 8 tiles by 256 threads from
-// kFusedBigTileNodes on, 8 x 4 by 128 from kFusedMidTileNodes on, 4 x 4 by 128 below.
-constexpr int64_t kFusedBigTileNodes = 200000;
-constexpr int64_t kFusedMidTileNodes = 30000;
-struct Fused2Shape {
-  int tx, ty, nt;
-};
-constexpr Fused2Shape kFusedBig{32, 8, 256}, kFusedMid{8, 4, 128}, kFusedSmall{4, 4, 128};
-Fused2Shape fused2_shape(int64_t N) {
-  return N >= kFusedBigTileNodes ? kFusedBig : (N >= kFusedMidTileNodes ? kFusedMid : kFusedSmall);
-}
 
-// Extra workgroups of the fused 2D sweep: tiles whose individual patches exceed one part (two
-// trips of all 16-lane groups) get parts 1, 2, ... (code tile * 4 + part), appended after the
-// part-0 workgroups of all tiles.
+
+// Extra workgroups of the fused 2D sweep: tiles whose individual patches exceed one part
+// (fused2_part_cap) get parts 1, 2, 3 (code tile * 4 + part), dispatched before the part-0 workgroups
+// of all tiles.
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra) {
   const Fused2Shape sh = fused2_shape(L.N);
   const int m = L.n + 1;
   const int ntx = (m + sh.tx - 1) / sh.tx, nty = (m + sh.ty - 1) / sh.ty;
-  const int cap = 4 * (sh.nt / 16);
+  const int cap = fused2_part_cap(sh);
   extra.clear();
   for (int ty = 0; ty < nty; ++ty)
     for (int tx = 0; tx < ntx; ++tx) {
@@ -1579,8 +1591,7 @@ int batch_fused2_blocks(const Level& L) {
 Fused2Job<double> batch_fused2_job(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                                    int mode, const double* xc) {
   const int m = L.n + 1;
-  // at most TX*TY individual patches per tile = 4 * NT / 16 per part: no extra parts at this shape
-  static_assert(kBatchTX * kBatchTY <= 4 * (kBatchNT / 16), "batched tiles must not need extra parts");
+  // no extra parts in a batched launch: one part holds the whole tile
   return Fused2Job<double>{L.consts, L.node_op, L.nsten, nullptr, 0, L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc,
                            c.prm.omega, (m + kBatchTX - 1) / kBatchTX, (m + kBatchTY - 1) / kBatchTY, mode, 0};
 }

@@ -323,19 +323,21 @@ def test_vcycle_bitwise_equals_composed_steps(name):
     assert np.array_equal(host(xv), host(xs))
 
 
-def test_config2_fused_bitwise_equals_unfused():
-    # 512^2 level: 32 x 8 tiles, the cut-band tiles split into several workgroups (parts); the
-    # fused pair must still equal two unfused sweeps bit for bit.
+@pytest.mark.parametrize("below_fine", [0, 1])
+def test_config2_fused_bitwise_equals_unfused(below_fine):
+    # 512^2 level: 32 x 8 tiles; 256^2 level: 8 x 4 tiles. On both, the cut-band tiles split into
+    # several workgroups (parts); the fused pair must still equal two unfused sweeps bit for bit.
     p = inputs.config2(0)
     h = fcg().Hierarchy(p, 0)
-    n = h.ndofs()
+    lev = h.fine - below_fine
+    n = h.ndofs(lev)
     x = inputs.random_vector(n, 61)
     b = inputs.random_vector(n, 62)
     xf = dev(x)
-    h.smooth(xf, dev(b), 2)
+    h.smooth(xf, dev(b), 2, level=lev)
     xu = dev(x)
-    h.smooth(xu, dev(b), 1)
-    h.smooth(xu, dev(b), 1)
+    h.smooth(xu, dev(b), 1, level=lev)
+    h.smooth(xu, dev(b), 1, level=lev)
     assert np.array_equal(host(xf), host(xu))
     h.close()
 
