@@ -540,7 +540,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the policy / 3D / 4096^2 side measurements")
     ap.add_argument("--cycles-only", action="store_true",
-                    help="run warmup + steps V-cycles of the default workload and nothing else (for counter runs)")
+                    help="run warmup + steps V-cycles of one workload and nothing else (for trace and counter runs)")
+    ap.add_argument("--workload", choices=["2d_512", "3d_64", "2d_4096"], default="2d_512",
+                    help="workload of --cycles-only: the bench workload (default), 3D 64^3 with 40 spheres, or "
+                         "2D 4096^2 with 20 discs and 10 levels")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of MIB MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -564,6 +567,10 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "repeats": 5}), flush=True)
         return
     prob = inputs.config2(0)
+    if args.cycles_only and args.workload == "3d_64":
+        prob = inputs.config3(0)
+    elif args.cycles_only and args.workload == "2d_4096":
+        prob = inputs.config2(0, n_cells=4096, n_levels=10)
     d = prob.dim
     log(f"setup {prob.name} (cache_inverse) ...")
     t0 = time.perf_counter()
