@@ -17,8 +17,9 @@ HBM roofline, and the FP64 CPU oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 Prints one JSON line on stdout; progress goes to stderr. Two helper modes for hardware counter runs
-print a short JSON line instead: --cycles-only (the V-cycles alone) and --copy-calibration MIB (a plain
-device copy of known size, the reference for scaling FETCH_SIZE / WRITE_SIZE to bytes).
+print a short JSON line instead: --cycles-only (the V-cycles alone, of the default workload or, with
+--workload 3d_64 / 2d_4096, of a side workload) and --copy-calibration MIB (a plain device copy of known
+size, the reference for scaling FETCH_SIZE / WRITE_SIZE to bytes).
 """
 from __future__ import annotations
 
