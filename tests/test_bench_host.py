@@ -1,0 +1,71 @@
+"""Host logic of bench.py (no GPU): argument handling, the byte model and the traffic figure's tie to
+the kernel sources."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def run_bench(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    p = run_bench("--gpus", "2")
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout == ""
+
+
+def test_unknown_workload_is_refused():
+    p = run_bench("--cycles-only", "--workload", "4d_8")
+    assert p.returncode == 2
+    assert "--workload" in p.stderr
+
+
+STATS = {"n_nodes": 263169, "n_irregular": 22000, "irregular_cols": 1250000, "n_stencils": 15000,
+         "n_classes": 2, "n_cells_axis": 512}
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_fused_sweep_bytes_are_the_minimum_plus_the_class_codes(d):
+    # the fused sweep moves the unfused minimum and one more int per node for each of two tables
+    # (patch class, operator code): 8 bytes per node
+    assert bench.algorithmic_bytes("sweep_fused", d, STATS) - bench.sweep_minimum_bytes(d, STATS) == 8.0 * STATS["n_nodes"]
+
+
+def test_sweep_minimum_grows_with_each_term():
+    base = bench.sweep_minimum_bytes(2, STATS)
+    for key in ("n_nodes", "irregular_cols", "n_stencils"):
+        st = dict(STATS)
+        st[key] += 1
+        assert bench.sweep_minimum_bytes(2, st) > base
+    # x read, b read, x written: 3 (d+1) doubles per node
+    st = dict(STATS, irregular_cols=0, n_stencils=0)
+    assert bench.sweep_minimum_bytes(2, st) == 8.0 * 3 * 3 * STATS["n_nodes"]
+
+
+def test_unknown_kernel_kind_has_no_byte_model():
+    assert bench.algorithmic_bytes("no_such_kernel", 2, STATS) == 0.0
+
+
+def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as f:
+        rec = json.load(f)["sweep_fused@L6"]
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: rec["source_sha256"])
+    assert bench.measured_traffic("sweep_fused@L6") == int(rec["traffic_bytes"])
+    assert bench.measured_traffic("no_such_kernel@L0") is None
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+    assert bench.measured_traffic("sweep_fused@L6") is None
+
+
+def test_committed_counters_match_the_committed_sources():
+    # the traffic figure of the bench line is filled only while the counters belong to these sources
+    assert bench.measured_traffic("sweep_fused@L6") is not None
