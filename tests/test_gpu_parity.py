@@ -342,6 +342,26 @@ def test_config2_fused_bitwise_equals_unfused(below_fine):
     h.close()
 
 
+def test_4096_fused_bitwise_equals_unfused():
+    # 4096^2 level (50.4 M DoFs, 66,177 tiles in about 53 rounds of resident workgroups, the last
+    # tiles outside the runs of the XCD order, 1,385 extra parts): the fused pair equals two unfused
+    # sweeps bit for bit; the unfused kernels are checked against the oracle on the smaller cases
+    import torch
+    p = inputs.config2(0, n_cells=4096, n_levels=10)
+    h = fcg().Hierarchy(p, 0)
+    n = h.ndofs()
+    x = torch.rand(n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(71))
+    b = torch.rand(n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(72))
+    xf = x.clone()
+    h.smooth(xf, b, 2)
+    xu = x.clone()
+    h.smooth(xu, b, 1)
+    h.smooth(xu, b, 1)
+    assert torch.equal(xf, xu)
+    assert torch.isfinite(xf).all()
+    h.close()
+
+
 @pytest.mark.parametrize("policy", [0, 1, 2])
 @pytest.mark.parametrize("name", ["2d_16_l3_s0", "c1_32_l3", "3d_12_l2_s3"])
 def test_footprint_equals_device_bytes(name, policy):
