@@ -230,6 +230,7 @@ struct Ctx {
   bool bordered = false;
   double* red = nullptr;         // reduction scratch
   double* red_host = nullptr;    // pinned host word
+  double* red_host_dev = nullptr; // its device address (the reduction's finishing kernel writes it)
   int* err = nullptr;            // device error flag: first failing patch node, or INT_MAX
   int* pattern = nullptr;        // cache_matrix sparse pattern (encoded entries)
   int n_pattern = 0;
