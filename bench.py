@@ -37,6 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector units, vendor figure
 
 
 def log(*a):
@@ -84,6 +85,42 @@ def algorithmic_bytes(kind: str, d: int, st: dict) -> float:
     if kind in ("restrict", "prolong"):
         return 8.0 * nf * N * 1.25 if d == 2 else 8.0 * nf * N * 1.125
     return 0.0
+
+
+def band_cholesky_flops(n: int, bw: int) -> int:
+    """Floating-point operations of a right-looking Cholesky of an n x n matrix of half bandwidth bw,
+    counting every add, multiply, divide and square root once: per column, the square root, the
+    divisions of the m = min(bw, n - 1 - k) entries below the diagonal and the multiply-subtract
+    updates of the m (m + 1) / 2 entries of the trailing lower triangle."""
+    total = 0
+    for k in range(n):
+        m = min(bw, n - 1 - k)
+        total += 1 + m + m * (m + 1)
+    return total
+
+
+def patch_solve_flops(d: int) -> int:
+    """Operations of one local solve y = L_i^-1 g_i of the cache_matrix and cache_none policies
+    (Eq. 15), as the patch kernel runs it: L_i = [[I_d (x) K, B], [B^T, C]] with K the 5^d velocity
+    block of half bandwidth 5^(d-1) + ... + 1 in lexicographic order, B the 3^d pressure columns of each
+    velocity component.
+    * banded Cholesky K = L L^T;
+    * forward substitution L V = [B_c | g_c | e_centre] for every component c (3^d + 2 columns);
+    * Schur complement S = C - sum_c V_c^T V_c and the reduced right-hand side;
+    * dense Cholesky of -S and the two triangular solves for the pressures;
+    * the d velocity rows of the centre node.
+    Assembling L_i (cache_none) comes on top and is not counted."""
+    nv, npr = 5 ** d, 3 ** d
+    bw = sum(5 ** k for k in range(d))
+    mc = (nv - 1) // 2
+    ncol = npr + 2
+    chol_k = band_cholesky_flops(nv, bw)
+    fwd_col = sum(2 * (i - max(0, i - bw)) + 1 for i in range(nv))
+    schur = npr * npr * (2 * d * nv + 1) + d * npr * 2 * (nv - mc) + npr * (2 * d * nv + 1) + d * 2 * (nv - mc)
+    chol_s = npr * npr + band_cholesky_flops(npr, npr - 1)
+    tri = sum(2 * i + 2 for i in range(npr)) + sum(2 * (npr - 1 - i) + 2 for i in range(npr))
+    centre = d * 2 * npr
+    return chol_k + d * ncol * fwd_col + schur + chol_s + tri + centre
 
 
 def sweep_minimum_bytes(d: int, st: dict) -> float:
@@ -244,10 +281,14 @@ def policy_extras(torch, fcgmg, prob, sweeps=4):
         lat = time_sweeps(torch, h, x, b, sweeps)
         ms = float(np.median(lat))
         st = h.stats()
+        # one local solve per node and sweep, FP64 vector arithmetic: the fraction of the FP64 peak
+        flops = patch_solve_flops(prob.dim) * st["n_nodes"]
+        tflops = flops / (ms * 1e-3) / 1e12
         out[fcgmg.POLICY_NAMES[pol]] = {
             "sweep_ms_p50": round(ms, 4), "smoother_dof_per_s": round(h.ndofs() / (ms * 1e-3), 1),
             "cached_bytes_finest": st["cached_bytes"], "device_bytes": h.device_bytes(),
-            "setup_s": round(setup, 3)}
+            "setup_s": round(setup, 3), "solve_gflop_per_sweep": round(flops / 1e9, 3),
+            "achieved_tflops": round(tflops, 4), "fp64_vector_peak_frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 5)}
         h.close()
         log(f"  {fcgmg.POLICY_NAMES[pol]}: sweep {ms:.3f} ms")
     return out

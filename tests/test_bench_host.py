@@ -69,3 +69,18 @@ def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
 def test_committed_counters_match_the_committed_sources():
     # the traffic figure of the bench line is filled only while the counters belong to these sources
     assert bench.measured_traffic("sweep_fused@L6") is not None
+
+
+@pytest.mark.parametrize("n", [1, 2, 9, 25])
+def test_band_cholesky_count_reduces_to_dense_and_diagonal(n):
+    # full band: sum over the columns of 1 + 2m + m^2, m = n-1-k (the dense Cholesky count)
+    assert bench.band_cholesky_flops(n, n - 1) == n + n * (n - 1) + (n - 1) * n * (2 * n - 1) // 6
+    # no band: one square root per diagonal entry
+    assert bench.band_cholesky_flops(n, 0) == n
+
+
+def test_patch_solve_count_is_below_dense_lu_and_grows_with_dimension():
+    for d in (2, 3):
+        size = d * 5 ** d + 3 ** d  # 59 / 402 DoFs of a patch
+        assert 0 < bench.patch_solve_flops(d) < 2 * size ** 3 // 3
+    assert bench.patch_solve_flops(3) > 50 * bench.patch_solve_flops(2)
