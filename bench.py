@@ -243,11 +243,12 @@ def measured_traffic(kernel_key: str):
     return int(rec["traffic_bytes"])
 
 
-def cpu_baseline(prob, budget_s=10.0):
+def cpu_baseline(prob, budget_s=10.0, budget_1core_s=5.0):
     """The FP64 oracle (as it stands) on the host cores: cache_inverse-form V(2,2) cycles on the same
-    problem, repeated until about `budget_s` seconds of cycles have run. The oracle's inverse-row
-    set-up runs first, untimed."""
-    from oracle.oracle import MODE_INVERSE, Oracle, max_threads
+    problem, repeated until about `budget_s` seconds of cycles have run, on all cores and then on one
+    core (about `budget_1core_s` seconds, at least two cycles). The oracle's inverse-row set-up runs
+    first, untimed."""
+    from oracle.oracle import MODE_INVERSE, Oracle, max_threads, set_threads
     t0 = time.perf_counter()
     o = Oracle(prob)
     b = o.rhs()
@@ -259,13 +260,25 @@ def cpu_baseline(prob, budget_s=10.0):
         x = o.vcycle(x, b, mode=MODE_INVERSE)
         steps += 1
     dt = (time.perf_counter() - t0) / steps
+    cores = max_threads()
+    set_threads(1)
+    try:
+        steps1 = 0
+        t0 = time.perf_counter()
+        while steps1 < 2 or time.perf_counter() - t0 < budget_1core_s:
+            x = o.vcycle(x, b, mode=MODE_INVERSE)
+            steps1 += 1
+        dt1 = (time.perf_counter() - t0) / steps1
+    finally:
+        set_threads(cores)
     nd = o.ndofs(o.fine)
+    work = nd * (prob.nu_pre + prob.nu_post)
     return {
-        "value": round(nd * (prob.nu_pre + prob.nu_post) / dt, 1), "unit": "DOF/s", "cores": max_threads(),
-        "kind": "oracle",
+        "value": round(work / dt, 1), "unit": "DOF/s", "cores": cores, "kind": "oracle",
+        "value_1core": round(work / dt1, 1),
         "sample": f"{prob.name}: {steps} V({prob.nu_pre},{prob.nu_post}) cycles of the FP64 oracle in "
-                  f"cache_inverse form after its untimed {setup_s:.1f} s inverse-row set-up; "
-                  f"{dt * 1e3:.1f} ms per cycle",
+                  f"cache_inverse form on {cores} threads after its untimed {setup_s:.1f} s inverse-row set-up, "
+                  f"{dt * 1e3:.1f} ms per cycle; then {steps1} cycles on one thread, {dt1 * 1e3:.1f} ms per cycle",
     }
 
 
