@@ -322,6 +322,53 @@ def test_sweep_equals_dense_smoother(d, n):
     assert np.linalg.norm(got_inv - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("d,n,seed,rmax", [(2, 24, 1, 0.14), (3, 12, 2, 0.08)])
+def test_uniform_patches_of_one_wall_case_share_their_block(d, n, seed, rmax):
+    # Patches whose 6^d cell window (cells c-3 .. c+2 per axis, clipped at the walls) holds no cut cell
+    # and one kind of cell see the same local system wherever they sit, given their distance to
+    # each wall (0, 1, 2 nodes, or farther, per side and axis): interior ones form the shared
+    # classes of cache_inverse / cache_matrix, wall ones share their row blocks. The oracle assembles
+    # every patch on its own, with quadrature at absolute coordinates: equal keys must give the same
+    # blocks and inverse rows up to rounding (observed: 2.4e-15 relative at most).
+    rng = np.random.default_rng(seed)
+    balls = inputs.place_balls(rng, d, 2, rmax - 0.04, rmax, lo=0.3, hi=0.7)
+    p = inputs.Problem(dim=d, n_cells=n, n_levels=1, balls=balls, bcs=(1, 2, 0, 0, 0, 0)[: 2 * d] + (0,) * (6 - 2 * d))
+    o = Oracle(p)
+    kinds = o.cell_kinds(0).reshape((n,) * d)  # cell kinds, x fastest: index [z][y][x] / [y][x]
+    m = n + 1
+    groups = {}
+    for node in range(m ** d):
+        c = [(node // m ** k) % m for k in range(d)]
+        win = tuple(slice(max(c[k] - 3, 0), min(c[k] + 2, n - 1) + 1) for k in reversed(range(d)))
+        w = kinds[win]
+        if (w == 2).any() or ((w == 1).any() and not (w == 1).all()):
+            continue
+        case = tuple(c[k] if c[k] <= 2 else (4 + c[k] - (n - 2) if c[k] >= n - 2 else 3) for k in range(d))
+        groups.setdefault((case, bool((w == 1).all())), []).append(node)
+    interior = [g for (case, _), g in groups.items() if all(v == 3 for v in case)]
+    assert interior and max(len(g) for g in interior) >= 4
+    assert any(len(g) >= 2 for (case, _), g in groups.items() if any(v != 3 for v in case))
+    for nodes in groups.values():
+        L0, Z0 = o.patch_matrix(0, nodes[0]), o.inverse_rows(0, nodes[0])
+        for node in nodes[1:]:
+            L, Z = o.patch_matrix(0, node), o.inverse_rows(0, node)
+            assert L.shape == L0.shape
+            assert np.abs(L - L0).max() <= 1e-13 * np.abs(L0).max()
+            assert np.abs(Z - Z0).max() <= 1e-13 * np.abs(Z0).max()
+    # a cut window changes the block: the sharing rule must not merge such a patch
+    cut_nodes = [node for node in range(m ** d)
+                 if (kinds[tuple(slice(max((node // m ** k) % m - 3, 0), min((node // m ** k) % m + 2, n - 1) + 1)
+                                 for k in reversed(range(d)))] == 2).any()]
+    some_cut = cut_nodes[len(cut_nodes) // 2]
+    c = [(some_cut // m ** k) % m for k in range(d)]
+    case = tuple(c[k] if c[k] <= 2 else (4 + c[k] - (n - 2) if c[k] >= n - 2 else 3) for k in range(d))
+    same_case = [g for (cs, _), g in groups.items() if cs == case]
+    if same_case:
+        L0 = o.patch_matrix(0, same_case[0][0])
+        Lc = o.patch_matrix(0, some_cut)
+        assert Lc.shape != L0.shape or np.abs(Lc - L0).max() > 1e-6 * np.abs(L0).max()
+
+
 def test_centre_patch_is_exact_solve():
     # 2 x 2 cells: the centre node's subdomain is the whole system, so with omega = 1 one sweep gives
     # the exact solution at the centre node.
