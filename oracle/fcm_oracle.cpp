@@ -38,6 +38,7 @@ struct Ball {
 struct Level {
   int n = 0;        // cells per axis
   double h = 0;     // cell size
+  int qd = 0;       // space-tree depth of its cut cells (the finest level's leaf size on every level)
   long N = 0;       // nodes (n+1)^d
   std::vector<double> st;       // node stencil, size N*(d+1)*3^d*(d+1)
   std::vector<signed char> kind;  // per cell: 0 physical, 1 fictitious, 2 cut
@@ -112,8 +113,14 @@ int box_kind(const Prob& P, const double* lo, double s) {
 // ---------------------------------------------------------------------------------------------
 // Quadrature. The paper only asks for a "sufficiently accurate integration" of cut cells (Sec. 1).
 // Reading: a space tree (quadtree/octree) splits a cell into 2^d children while the child is cut
-// and its depth is below q; every leaf gets the 2^d-point tensor Gauss rule with alpha evaluated at
-// each Gauss point. Uncut cells are leaves at depth 0.
+// and its depth is below the level's depth; every leaf gets the 2^d-point tensor Gauss rule with
+// alpha evaluated at each Gauss point. Uncut cells are leaves at depth 0. The depth is q on the
+// finest level and one more per coarser level, so every level of the hierarchy of discretisations
+// (Sec. 3) integrates its cut cells on leaves of the same size h_finest / 2^q: the coarse cell's
+// tree descends through its fine cells and ends on their leaves. The alpha-weighted forms of a
+// coarse level are then the Galerkin restrictions of the fine ones, and a physical sliver that the
+// fine level resolves is not lost on a coarser one (with alpha_f = 1e-10 such a loss makes the
+// coarse operator up to 1/alpha_f-fold softer there and the V-cycle diverge).
 // ---------------------------------------------------------------------------------------------
 struct QPt {
   double x[3];
@@ -137,15 +144,15 @@ void gauss_box(const Prob& P, const double* lo, double s, std::vector<QPt>& out)
   }
 }
 
-void tree_points(const Prob& P, const double* lo, double s, int depth, std::vector<QPt>& out,
+void tree_points(const Prob& P, const double* lo, double s, int depth, int maxdepth, std::vector<QPt>& out,
                  long* cut_leaves, double* cut_leaf_vol) {
   int kind = box_kind(P, lo, s);
-  if (kind == 2 && depth < P.q) {
+  if (kind == 2 && depth < maxdepth) {
     int nc = 1 << P.d;
     for (int c = 0; c < nc; ++c) {
       double clo[3] = {0, 0, 0};
       for (int k = 0; k < P.d; ++k) clo[k] = lo[k] + (((c >> k) & 1) ? 0.5 * s : 0.0);
-      tree_points(P, clo, 0.5 * s, depth + 1, out, cut_leaves, cut_leaf_vol);
+      tree_points(P, clo, 0.5 * s, depth + 1, maxdepth, out, cut_leaves, cut_leaf_vol);
     }
     return;
   }
@@ -316,7 +323,7 @@ void element_matrix(const Prob& P, const Level& L, long cell, std::vector<double
   auto I = [&](int a, int f) { return f * nn + a; };
 
   std::vector<QPt> pts;
-  tree_points(P, lo, h, 0, pts, nullptr, nullptr);
+  tree_points(P, lo, h, 0, L.qd, pts, nullptr, nullptr);
   double phi[8], grad[8][3];
   for (const QPt& q : pts) {
     q1_basis(d, lo, h, q.x, phi, grad);
@@ -996,6 +1003,7 @@ void* orc_create(int d, int n, int nlev, int q, double eta, double alpha_f, doub
     Level& L = P->lev[l];
     L.n = n >> (nlev - 1 - l);
     L.h = 1.0 / L.n;
+    L.qd = q + (nlev - 1 - l);
     L.N = 1;
     for (int k = 0; k < d; ++k) L.N *= (L.n + 1);
     assemble_level(*P, l);
@@ -1055,7 +1063,7 @@ void orc_cell_quadrature(void* h, int l, long cell, double* out) {
   std::vector<QPt> pts;
   long cl = 0;
   double cv = 0;
-  tree_points(*P, lo, L.h, 0, pts, &cl, &cv);
+  tree_points(*P, lo, L.h, 0, L.qd, pts, &cl, &cv);
   double sa = 0, sp = 0;
   for (const QPt& q : pts) {
     sa += q.w * q.alpha;
@@ -1082,7 +1090,7 @@ void orc_rhs(void* h, int l, double* b) {
     int ci[3];
     cell_lo(*P, L, c, lo, ci);
     std::vector<QPt> pts;
-    tree_points(*P, lo, L.h, 0, pts, nullptr, nullptr);
+    tree_points(*P, lo, L.h, 0, L.qd, pts, nullptr, nullptr);
     element_rhs(*P, L, c, pts, &Fall[(size_t)c * nn * nf]);
   }
   for (long k = 0; k < (long)nf * L.N; ++k) b[k] = 0;

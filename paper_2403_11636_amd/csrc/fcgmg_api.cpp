@@ -421,6 +421,22 @@ bool dense_inverse(int n, std::vector<double>& A, std::vector<double>& Inv) {
 constexpr int kCoarseMaxDofs = 6000;
 constexpr int kRedBlocks = 512;
 
+// True when a cut or fictitious cell has a face on a Dirichlet wall of the box. The Nitsche wall terms
+// carry no alpha, so inside an obstacle they can outweigh the alpha_f-weighted volume terms and leave
+// the velocity block of a patch indefinite.
+template <int D>
+bool obstacle_on_dirichlet_face(const fcgmg_params& P, const Level& L, const std::vector<signed char>& kinds) {
+  for (int64_t cell = 0; cell < L.ncells; ++cell) {
+    if (kinds[cell] == 0) continue;
+    const int64_t ci[3] = {cell % L.n, (cell / L.n) % L.n, D == 3 ? cell / ((int64_t)L.n * L.n) : 0};
+    for (int k = 0; k < D; ++k) {
+      if (ci[k] == 0 && P.bc[2 * k] != FCGMG_BC_NEUMANN) return true;
+      if (ci[k] == L.n - 1 && P.bc[2 * k + 1] != FCGMG_BC_NEUMANN) return true;
+    }
+  }
+  return false;
+}
+
 template <int D>
 int setup_impl(Ctx& c, hipStream_t s) {
   const fcgmg_params& P = c.prm;
@@ -449,6 +465,7 @@ int setup_impl(Ctx& c, hipStream_t s) {
   for (int l = 0; l < nlev; ++l) {
     Level& L = c.lev[l];
     L.n = P.n_cells >> (nlev - 1 - l);
+    L.qd = P.quad_depth + (nlev - 1 - l);
     L.h = 1.0 / L.n;
     L.N = 1;
     L.ncells = 1;
@@ -482,6 +499,7 @@ int setup_impl(Ctx& c, hipStream_t s) {
       }
     }
     L.n_cut = (int64_t)cut_list.size();
+    L.dense_lu = D == 2 && (P.immersed_nitsche || obstacle_on_dirichlet_face<D>(P, L, kinds));
     if ((rc = alloc_n(c, &L.cell_info, L.ncells))) return rc;
     FCG_HIP(hipMemcpyAsync(L.cell_info, info.data(), L.ncells * sizeof(int), hipMemcpyHostToDevice, s));
     int* cut_d = nullptr;
@@ -984,6 +1002,8 @@ static int validate_params(const fcgmg_params& prm, const double* balls, int n_b
   if ((int64_t)P.n_cells + 1 > (P.dim == 2 ? 46340 : 1290))
     return fail(FCGMG_E_ARG, "grid too large for 32-bit node indices");
   if (P.quad_depth < 0 || P.quad_depth > 7) return fail(FCGMG_E_ARG, "quad_depth must be in [0,7]");
+  if (P.quad_depth + P.n_levels - 1 > fcg::kMaxTreeDepth)
+    return fail(FCGMG_E_ARG, "quad_depth + n_levels - 1 exceeds the deepest space tree (20)");
   if (P.cache_policy < 0 || P.cache_policy > 2) return fail(FCGMG_E_ARG, "unknown cache policy");
   if (P.precision != FCGMG_PREC_FP64 && P.precision != FCGMG_PREC_MIXED)
     return fail(FCGMG_E_ARG, "unknown precision");

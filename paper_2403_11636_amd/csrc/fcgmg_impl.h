@@ -80,20 +80,28 @@ struct OpConsts {
   double pack[RefLayout<3>::TOT];  // the entries above in RefLayout<d> order
 };
 
+// Deepest space tree: quad_depth + n_levels - 1 may not exceed it.
+constexpr int kMaxTreeDepth = 20;
+
 struct Geom {
   const double* balls;  // nballs x 4 (centre, radius)
   int nballs;
-  int q;                // space-tree depth
+  int q;                // space-tree depth of the level's cut cells
   double alpha_f;
 };
 
 struct Level {
   int n = 0;
   double h = 0;
+  int qd = 0;                 // space-tree depth: quad_depth on the finest level, one more per coarser level
   int64_t N = 0, ncells = 0;
   int* cell_info = nullptr;   // -1 physical, -2 fictitious, >=0 index into cut_mats
   double* cut_mats = nullptr; // n_cut x NEL: K (NN x NN) then B_c (NN x NN) for c < d
   int64_t n_cut = 0, n_fict = 0;
+  // 2D: the patch blocks are factorised by dense LU with partial pivoting instead of the block
+  // Cholesky, because their velocity blocks may be indefinite (immersed Nitsche terms, or the
+  // alpha-free Nitsche terms of a Dirichlet face that crosses an obstacle)
+  bool dense_lu = false;
   int* node_class = nullptr;  // >=0 regular class id, <0: -(irregular index)-1
   // Operator row of each node: -1 / -2 when its 2^d cells are uncut, all physical / all fictitious
   // and it is at least 2 nodes from every wall (the level's reference stencil applies), otherwise
@@ -246,7 +254,7 @@ struct Ctx {
   mutable std::vector<hipEvent_t> prof_pool;
   mutable std::vector<double> prof_ms;      // [kind * nlev + level]
   mutable std::vector<int64_t> prof_count;
-  Geom geom() const { return Geom{balls, (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
+  Geom geom(const Level& L) const { return Geom{balls, (int)balls_h.size() / 4, L.qd, prm.alpha_fict}; }
   Geom geom_host() const { return Geom{balls_h.data(), (int)balls_h.size() / 4, prm.quad_depth, prm.alpha_fict}; }
 };
 
@@ -321,15 +329,15 @@ __host__ __device__ inline void q1(const double* lo, double h, const double* x, 
 // Gauss rule with alpha evaluated at each point. Iterative depth-first traversal (no recursion).
 template <int D, class F>
 __host__ __device__ inline void tree_quadrature(const Geom& g, const double* lo0, double h, F&& visit) {
-  int child[8];
-  double lo[8][3];
+  int child[kMaxTreeDepth + 1];
+  double lo[kMaxTreeDepth + 1][3];
   for (int k = 0; k < 3; ++k) lo[0][k] = k < D ? lo0[k] : 0.0;
   int t = 0;
   child[0] = 0;
   for (;;) {
     const double s = h / (double)(1 << t);
     bool descend = false;
-    if (t < g.q && t < 7) descend = box_kind<D>(g, lo[t], s) == 2;
+    if (t < g.q && t < kMaxTreeDepth) descend = box_kind<D>(g, lo[t], s) == 2;
     if (descend) {
       ++t;
       child[t] = 0;

@@ -91,7 +91,7 @@ template <int D>
 hipError_t k_classify_cells(const Ctx& c, Level& L, signed char* kinds, hipStream_t s) {
   const int bs = 256;
   const int64_t nb = (L.ncells + bs - 1) / bs;
-  classify_cells_kernel<D><<<dim3((unsigned)nb), dim3(bs), 0, s>>>(c.geom(), L.n, L.h, L.ncells, kinds);
+  classify_cells_kernel<D><<<dim3((unsigned)nb), dim3(bs), 0, s>>>(c.geom(L), L.n, L.h, L.ncells, kinds);
   return hipGetLastError();
 }
 
@@ -162,7 +162,7 @@ hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStrea
   if (L.n_cut == 0) return hipSuccess;
   const int64_t nb = L.n_cut < 65536 ? L.n_cut : 65536;
   cut_matrices_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(
-      c.geom(), L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, c.prm.nitsche_beta * c.prm.eta / L.h, cut_cells,
+      c.geom(L), L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, c.prm.nitsche_beta * c.prm.eta / L.h, cut_cells,
       L.n_cut, L.cut_mats);
   return hipGetLastError();
 }
@@ -237,7 +237,7 @@ hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s) {
   const int bs = 128;
   const int64_t nb = (L.N + bs - 1) / bs;
   const int* bc = c.prm.bc;
-  rhs_kernel<D><<<dim3((unsigned)nb), dim3(bs), 0, s>>>(c.geom(), L.consts, c.prm.force, c.prm.eta, c.prm.ubar, bc[0],
+  rhs_kernel<D><<<dim3((unsigned)nb), dim3(bs), 0, s>>>(c.geom(L), L.consts, c.prm.force, c.prm.eta, c.prm.ubar, bc[0],
                                                         bc[1], bc[2], bc[3], bc[4], bc[5], L.N, b);
   return hipGetLastError();
 }

@@ -670,16 +670,16 @@ hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, 
                                 hipStream_t s) {
   if (count == 0) return hipSuccess;
   if constexpr (D == 2) {
-    if (c.prm.immersed_nitsche) {
+    if (L.dense_lu) {
       const int64_t nb = count < 262144 ? count : 262144;
       patch_inverse_rows_lu2_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(
-          L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, Z, c.err);
+          L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, nodes, count, Z, c.err);
       return hipGetLastError();
     }
   }
   const int64_t nb = count < 262144 ? count : 262144;
   patch_inverse_rows_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
-      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, Z, c.err);
+      L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, nodes, count, Z, c.err);
   return hipGetLastError();
 }
 
@@ -719,7 +719,7 @@ hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int6
   if (count == 0) return hipSuccess;
   const int64_t nb = count < 262144 ? count : 262144;
   store_matrices_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
-      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, nodes, count, c.pattern, c.n_pattern, M);
+      L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, nodes, count, c.pattern, c.n_pattern, M);
   return hipGetLastError();
 }
 
@@ -853,15 +853,15 @@ template <int D>
 hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x, hipStream_t s) {
   const int64_t nb = L.N < 131072 ? L.N : 131072;
   if constexpr (D == 2) {
-    if (c.prm.immersed_nitsche) {
+    if (L.dense_lu) {
       patch_solve_lu2_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(
-          L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr,
+          L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr,
           c.pattern, c.n_pattern, L.N, r, x, c.prm.omega, c.err);
       return hipGetLastError();
     }
   }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
-      L.consts, L.cell_info, L.cut_mats, c.geom(), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
+      L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
       c.n_pattern, L.N, r, x, c.prm.omega, c.err);
   return hipGetLastError();
 }

@@ -131,6 +131,32 @@ def small_problem(dim: int, n_cells: int, n_levels: int, seed: int, n_balls: int
                    name=f"{dim}d_small_{n_cells}_seed{seed}")
 
 
+EDGE_CASES = ("inflow_wall", "corner", "two_in_cell")
+
+
+def edge_problem(dim: int, n_cells: int, n_levels: int, case: str, alpha_fict: float = 1e-8) -> Problem:
+    """Obstacles where the seeded generators never put them (their centres keep a margin from the
+    walls and from each other):
+      * "inflow_wall": a ball crossing the x- (inflow) face, inflow / do-nothing / no-slip walls;
+      * "corner": a ball covering the corner x = y (= z) = 0 of an all no-slip box;
+      * "two_in_cell": two balls whose gap of 0.02 lies inside one cell of a 16-cell-per-axis grid,
+        so that cell (and the coarser cells around it) is cut by both."""
+    z = 0.5 if dim == 3 else 0.0
+    if case == "inflow_wall":
+        balls = [[0.03, 0.47, z, 0.11]]
+        bcs = (INFLOW, NEUMANN, NOSLIP, NOSLIP, NOSLIP, NOSLIP)
+    elif case == "corner":
+        balls = [[0.03, 0.04, 0.03 if dim == 3 else 0.0, 0.13]]
+        bcs = (NOSLIP,) * 6
+    elif case == "two_in_cell":
+        balls = [[0.40, 0.53, z, 0.10], [0.62, 0.53, z, 0.10]]
+        bcs = (INFLOW, NEUMANN, NOSLIP, NOSLIP, NOSLIP, NOSLIP)
+    else:
+        raise ValueError(f"unknown edge case {case!r}")
+    return Problem(dim=dim, n_cells=n_cells, n_levels=n_levels, balls=np.asarray(balls, dtype=np.float64),
+                   bcs=bcs, alpha_fict=alpha_fict, force=1, name=f"{dim}d_edge_{case}_{n_cells}")
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded standard-normal FP64 vector."""
     return np.random.default_rng(seed).standard_normal(n)

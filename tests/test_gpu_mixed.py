@@ -126,21 +126,23 @@ def test_fgmres_solve(name, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fgmres_converges_where_the_standalone_cycle_diverges(precision):
-    # 1024^2, 20 discs, seed 1: the standalone V(2,2) cycle diverges (an error mode grows by about
-    # 1.9 per cycle); as a preconditioner it still drives FGMRES to the tolerance.
+def test_fgmres_converges_where_the_standalone_cycle_is_slow(precision):
+    # 1024^2, 20 discs, seed 1, 8 levels: the standalone V(2,2) cycle contracts by only about 0.92 per
+    # cycle (the oracle's own cycle on the CPU: 80 cycles to 9.3e-4), through a near-null pressure
+    # mode inside the obstacles that the rediscretised stabilisation of the coarse levels corrects
+    # only in part. As a preconditioner the same cycle drives FGMRES to the tolerance.
     f = fcg()
     p = inputs.config2(1, n_cells=1024, n_levels=8)
     hg = f.Hierarchy(p, f.CACHE_INVERSE, precision=precision)
     b = hg.rhs()
-    with pytest.raises(f.FcgmgError):
-        hg.solve(b, rtol=1e-8, max_iter=200)
+    x, it, relg, _, rc = hg.solve(b, rtol=1e-8, max_iter=60, raise_on_noconv=False)
+    assert rc == f.E_NOCONV and it == 60 and 1e-4 < relg < 1e-1, (rc, it, relg)
     hg.close()
     hk = f.Hierarchy(p, f.CACHE_INVERSE, precision=precision, solver=f.SOLVER_FGMRES, krylov_restart=30)
-    x, it, relk, _, rc = hk.solve(hk.rhs(), rtol=1e-8, max_iter=200)
-    assert rc == 0 and relk <= 1e-8
+    x, it, relk, _, rc = hk.solve(hk.rhs(), rtol=1e-8, max_iter=60)
+    assert rc == 0 and relk <= 1e-8 and it < 60
     # the library's own FP64 residual of the iterate
     r = hk.residual(x, hk.rhs())
     assert torch.linalg.vector_norm(r).item() <= 1e-8 * torch.linalg.vector_norm(hk.rhs()).item() * 1.0001
-    print(f"1024^2 seed 1 prec={precision}: FGMRES {it} cycles")
+    print(f"1024^2 seed 1 prec={precision}: FGMRES {it} cycles, standalone GMG {relg:.2e} after 60")
     hk.close()

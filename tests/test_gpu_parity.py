@@ -8,7 +8,8 @@ Tolerances (FP64 on both sides):
     LU (banded Cholesky + pressure Schur complement), the oracle by LU with partial pivoting;
   * coarse solve / V-cycle: the coarsest solve uses the explicit inverse (GPU) vs LU (oracle), whose
     difference is bounded by cond(L_0) * eps; tolerances are set from the measured condition number;
-  * solve: same final relative residual below the 1e-8 target, iteration counts within +-1.
+  * solve: residual histories equal cycle by cycle to 1e-10 of the initial residual, the same final
+    relative residual within 1e-10 and iteration counts within +-1 (the stated target).
 Full-size configurations are checked on sampled nodes that the oracle computes one by one.
 """
 import numpy as np
@@ -48,7 +49,21 @@ SMALL = {
     "c1_32_l3": lambda: inputs.config1(32, 3),
     "3d_8_l2_s0": lambda: inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2),
     "3d_12_l2_s3": lambda: inputs.small_problem(3, 12, 2, seed=3, n_balls=2, rmin=0.08, rmax=0.14),
+    # obstacles across a Dirichlet wall, over a no-slip corner, and two of them cutting one cell
+    "2d_16_edge_inflow": lambda: inputs.edge_problem(2, 16, 3, "inflow_wall"),
+    "2d_16_edge_corner": lambda: inputs.edge_problem(2, 16, 3, "corner"),
+    "2d_32_edge_corner": lambda: inputs.edge_problem(2, 32, 3, "corner"),
+    "2d_16_edge_two": lambda: inputs.edge_problem(2, 16, 3, "two_in_cell"),
+    "3d_8_edge_inflow": lambda: inputs.edge_problem(3, 8, 2, "inflow_wall"),
+    "3d_8_edge_corner": lambda: inputs.edge_problem(3, 8, 2, "corner"),
+    "3d_8_edge_two": lambda: inputs.edge_problem(3, 8, 2, "two_in_cell"),
 }
+
+# The standalone V(2,2) cycle diverges on these in the oracle as well: an obstacle over a Dirichlet
+# corner on a grid this coarse (the alpha-free Nitsche terms inside the obstacle leave some velocity
+# blocks indefinite). Their sweeps and cycles are still compared; their solves are not.
+DIVERGING = {"2d_16_edge_corner", "3d_8_edge_corner"}
+SOLVE_CASES = [k for k in SMALL if k not in DIVERGING]
 
 _cache = {}
 
@@ -131,9 +146,10 @@ def coarse_cond(o):
     return np.linalg.cond(A)
 
 
+@pytest.mark.parametrize("policy", [0, 1, 2])
 @pytest.mark.parametrize("name", list(SMALL))
-def test_coarse_solve_and_vcycle_parity(name):
-    p, o, h = setup_case(name)
+def test_coarse_solve_and_vcycle_parity(name, policy):
+    p, o, h = setup_case(name, policy)
     kappa = coarse_cond(o)
     tol = max(1e-12, 50 * kappa * 2.2e-16)
     b0 = inputs.random_vector(o.ndofs(0), 8)
@@ -147,20 +163,32 @@ def test_coarse_solve_and_vcycle_parity(name):
     assert rel(host(xg), x_orc) <= max(1e-10, tol), (rel(host(xg), x_orc), kappa)
 
 
-@pytest.mark.parametrize("name", list(SMALL))
-def test_solve_parity(name):
-    p, o, h = setup_case(name)
+@pytest.mark.parametrize("policy", [0, 1, 2])
+@pytest.mark.parametrize("name", SOLVE_CASES)
+def test_solve_parity(name, policy):
+    # Standalone GMG to 1e-8: the same final relative residual within 1e-10 and the same iteration
+    # count (a difference of one is allowed where the two residual norms straddle the tolerance),
+    # with the residual histories equal cycle by cycle to 1e-10 of the initial residual.
+    p, o, h = setup_case(name, policy)
     b = o.rhs()
     x_orc, it_orc, rel_orc, hist_orc, rc = o.solve(b, rtol=1e-8, mode=MODE_INVERSE)
     assert rc == 0
     xg, it_gpu, rel_gpu, hist_gpu, rc_gpu = h.solve(dev(b), rtol=1e-8, max_iter=100)
     assert rc_gpu == 0 and rel_gpu <= 1e-8
     assert abs(it_gpu - it_orc) <= 1, (it_gpu, it_orc)
+    k = min(it_gpu, it_orc) + 1
+    dh = np.max(np.abs(hist_gpu[:k] - hist_orc[:k])) / hist_orc[0]
+    assert dh <= 1e-10, dh
+    if it_gpu == it_orc:
+        assert abs(rel_gpu - rel_orc) <= 1e-10, (rel_gpu, rel_orc)
     # the final residual measured by the oracle on the GPU iterate
     r = o.residual(o.fine, host(xg), b)
     assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
-    assert abs(rel_gpu - rel_orc) <= 1e-10 + 0.5 * rel_orc
-    assert rel(host(xg), x_orc) <= 1e-6
+    dx = rel(host(xg), x_orc)
+    print(f"{name} policy {policy}: {it_gpu} / {it_orc} cycles, history {dh:.1e}, "
+          f"final residual {abs(rel_gpu - rel_orc):.1e}, iterate {dx:.1e}")
+    if it_gpu == it_orc:
+        assert dx <= 1e-9, dx
 
 
 def test_policies_agree():
@@ -210,7 +238,7 @@ def test_tiny_single_level_grid(d):
         h.close()
 
 
-def _sampled_sweep(p, policy, samples_per_kind, seed=0):
+def _sampled_sweep(p, policy, samples_per_kind, seed=0, res_tol=1e-13):
     """One fine-level sweep at full size, checked on sampled nodes (irregular, regular, walls)."""
     o = Oracle(p)
     h = fcg().Hierarchy(p, policy)
@@ -222,7 +250,7 @@ def _sampled_sweep(p, policy, samples_per_kind, seed=0):
     # residual: full vector, componentwise bound
     r_gpu = host(h.residual(dev(x), dev(b)))
     r_orc = o.residual(lev, x, b)
-    bound = 1e-13 * (np.abs(b) + o.abs_matvec(lev, np.abs(x))) + 1e-300
+    bound = res_tol * (np.abs(b) + o.abs_matvec(lev, np.abs(x))) + 1e-300
     assert np.all(np.abs(r_gpu - r_orc) <= bound), np.max(np.abs(r_gpu - r_orc) / bound)
     xg = dev(x)
     h.smooth(xg, dev(b), 1)
@@ -252,6 +280,25 @@ def _sampled_sweep(p, policy, samples_per_kind, seed=0):
 def test_config2_full_size_sampled():
     st = _sampled_sweep(inputs.config2(0), 0, 600)
     assert st["n_cut_cells"] > 1000 and st["n_irregular"] > 5000
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+def test_config2_full_size_sampled_factorising_policies(policy):
+    # 263,169 patches: more than the 131,072 workgroups of one launch, so the grid-stride pass of the
+    # per-sweep factorisation kernel runs
+    st = _sampled_sweep(inputs.config2(0), policy, 300)
+    assert st["n_cut_cells"] > 1000
+
+
+def test_config2_immersed_full_size_sampled_cache_matrix():
+    import dataclasses
+    p = dataclasses.replace(inputs.config2(0), immersed_nitsche=1)
+    # An operator entry of a cut cell here is an arc-quadrature sum whose terms (up to lambda w with
+    # lambda = beta eta / h = 10,240) cancel, so its rounding is relative to the sum of their
+    # magnitudes, not to the entry: the residual is held to 1e-12 (|b| + |L| |x|) componentwise
+    # (measured: 4.3e-13).
+    st = _sampled_sweep(p, 1, 200, res_tol=1e-12)
+    assert st["n_cut_cells"] > 1000
 
 
 def test_config3_full_size_sampled():

@@ -4,6 +4,7 @@ rejected. Results are compared bit for bit with a solve of the same problem on i
 import numpy as np
 import pytest
 
+from oracle.oracle import Oracle
 from paper_2403_11636_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -53,6 +54,11 @@ def test_results_same_alone_and_in_mix():
         xa, it = solve_alone(p, res["policy"], prec)
         assert res["iters"] == it
         assert np.array_equal(x.cpu().numpy(), xa)
+        # the oracle's FP64 residual of the served iterate meets the tolerance (its right-hand side
+        # equals the library's to 1e-13)
+        o = Oracle(p)
+        b = o.rhs()
+        assert np.linalg.norm(o.residual(o.fine, x.cpu().numpy(), b)) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-4)
     assert hits >= 1
     srv.close()
 
