@@ -141,6 +141,20 @@ int fcgmg_residual(fcgmg_h h, int level, const double* x, const double* b, doubl
  * prolongation R~_i). x is updated in place; b is read. */
 int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): fcgmg_smooth with the same kernels and arithmetic (x ends bitwise
+ * equal), whose scratch (the residual and, 2D cache_inverse, the second iterate of the fused sweep
+ * pairs) lives in a static device array of 96 MiB per GPU, held until the process ends, instead of
+ * the level's own buffers. The call allocates nothing. The array's device address is looked up once
+ * per device on the first call there (hipGetSymbolAddress, with that device current). Every call on
+ * one GPU shares that array and leaves the last call's contents in it; nothing in it needs to start
+ * at zero (each sweep writes its scratch before reading it). Calls that overlap on one GPU (other
+ * streams, other threads) race on it. The level's scratch, (d+1) N_l doubles padded to a multiple of
+ * 32 plus another (d+1) N_l for the 2D cache_inverse second iterate, must fit the 12,582,912 doubles
+ * of the array: up to 1,447 cells per axis for 2D cache_inverse, 2,047 for the other 2D policies,
+ * 145 in 3D. E_ARG for a larger level, or a bad level or pointer. */
+int fcgmg_smooth_noalloc(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream);
+
 /* Stacked right-hand sides (several problems on one geometry): `sweeps` sweeps of Eq. (14)-(15) on
  * level `level` for nrhs (1..8) vectors at once. x and b hold nrhs vectors of (d+1) N_l doubles,
  * one after another (vector k at offset k (d+1) N_l); r is caller-owned scratch of the same size (3D:

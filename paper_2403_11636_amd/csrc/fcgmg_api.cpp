@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -681,9 +682,9 @@ int prolong_impl(const Ctx& c, int l, const T* xc, T* xf, hipStream_t s) {
 }
 
 template <int D, class T = double>
-int sweep_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s) {
+int sweep_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s, T* rbuf = nullptr) {
   const Level& L = c.lev[l];
-  T* r = LV<T>::r(L);
+  T* r = rbuf ? rbuf : LV<T>::r(L);
   int rc;
   if ((rc = residual_impl<D, T>(c, l, x, b, r, s))) return rc;
   if (c.prm.cache_policy == FCGMG_CACHE_INVERSE) {
@@ -705,11 +706,12 @@ int sweep_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s) {
 // `mode` describes x on entry: 0 as given; 1 zero (contents undefined, not read); 2 still to be
 // corrected by the prolongation of the coarse vector xc. The fused pair applies modes 1 and 2 while
 // loading; otherwise x is zeroed or corrected first.
+// `rbuf` / `abuf` replace the level's residual and second-iterate buffers when given.
 template <int D, class T = double>
 int smooth_impl(const Ctx& c, int l, T* x, const T* b, int sweeps, hipStream_t s, int mode = 0,
-                const T* xc = nullptr) {
+                const T* xc = nullptr, T* rbuf = nullptr, T* abuf = nullptr) {
   const Level& L = c.lev[l];
-  T* xalt = LV<T>::xalt(L);
+  T* xalt = (abuf && LV<T>::xalt(L)) ? abuf : LV<T>::xalt(L);
   int rc;
   const bool fused = D == 2 && c.prm.cache_policy == FCGMG_CACHE_INVERSE && xalt;
   if (mode != 0 && (!fused || sweeps % 2 == 1 || sweeps == 0)) {
@@ -723,7 +725,7 @@ int smooth_impl(const Ctx& c, int l, T* x, const T* b, int sweeps, hipStream_t s
   if (fused) {
     int k = 0;
     if (sweeps % 2 == 1) {
-      if ((rc = sweep_impl<D, T>(c, l, x, b, s))) return rc;
+      if ((rc = sweep_impl<D, T>(c, l, x, b, s, rbuf))) return rc;
       k = 1;
     }
     for (; k < sweeps; k += 2) {
@@ -738,7 +740,35 @@ int smooth_impl(const Ctx& c, int l, T* x, const T* b, int sweeps, hipStream_t s
     return FCGMG_OK;
   }
   for (int i = 0; i < sweeps; ++i)
-    if ((rc = sweep_impl<D, T>(c, l, x, b, s))) return rc;
+    if ((rc = sweep_impl<D, T>(c, l, x, b, s, rbuf))) return rc;
+  return FCGMG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Scratch of fcgmg_smooth_noalloc: one file-scope device array per GPU, held until the process
+// ends. Host code never passes the array's name to a kernel (on the host it only stands in for the
+// symbol): the device address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchDoubles = (size_t)12 << 20;  // 96 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(double** out) {
+  int dev = -1;
+  FCG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FCGMG_E_ARG, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    FCG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(FCGMG_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
   return FCGMG_OK;
 }
 
@@ -1122,6 +1152,25 @@ int fcgmg_smooth(fcgmg_h h, int level, double* x, const double* b, int sweeps, v
   if (!valid_level(h, level) || !x || !b || sweeps < 0) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
   hipStream_t s = (hipStream_t)stream;
   return h->prm.dim == 2 ? smooth_impl<2>(*h, level, x, b, sweeps, s) : smooth_impl<3>(*h, level, x, b, sweeps, s);
+}
+
+int fcgmg_smooth_noalloc(fcgmg_h h, int level, double* x, const double* b, int sweeps, void* stream) {
+  if (!valid_level(h, level) || !x || !b || sweeps < 0) return fail(FCGMG_E_ARG, "bad handle, level or pointer");
+  const Level& L = h->lev[level];
+  const size_t nd = (size_t)(h->prm.dim + 1) * (size_t)L.N;
+  const size_t nd_pad = (nd + 31) / 32 * 32;  // second buffer on a 256-byte boundary
+  const size_t need = nd_pad + (L.xalt ? nd : 0);
+  if (need > kNoAllocScratchDoubles)
+    return fail(FCGMG_E_ARG, "level needs " + std::to_string(need) + " doubles of scratch; the static scratch holds " +
+                                 std::to_string(kNoAllocScratchDoubles));
+  double* base = nullptr;
+  int rc;
+  if ((rc = scratch_for_current_device(&base))) return rc;
+  double* rbuf = base;
+  double* abuf = L.xalt ? base + nd_pad : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  return h->prm.dim == 2 ? smooth_impl<2, double>(*h, level, x, b, sweeps, s, 0, nullptr, rbuf, abuf)
+                         : smooth_impl<3, double>(*h, level, x, b, sweeps, s, 0, nullptr, rbuf, abuf);
 }
 
 int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double* r, int nrhs, int sweeps,

@@ -24,7 +24,7 @@ OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, 
 
 EXPORTS = [
     "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
-    "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
+    "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_noalloc", "fcgmg_smooth_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
@@ -93,6 +93,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_rhs.argtypes = [vp, ctypes.c_int, vp, vp]
     L.fcgmg_residual.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.fcgmg_smooth.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    L.fcgmg_smooth_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.fcgmg_smooth_multi.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     L.fcgmg_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fcgmg_prolongate_add.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -296,6 +297,14 @@ class Hierarchy:
         level = self.fine if level is None else level
         n = self.ndofs(level)
         _check(load().fcgmg_smooth(self.h, level, _dptr(x, "x", n), _dptr(b, "b", n), sweeps, _stream_ptr(stream)))
+        return x
+
+    def smooth_noalloc(self, x, b, sweeps: int = 1, level: Optional[int] = None, stream=None):
+        """fcgmg_smooth_noalloc: the same sweeps with the library's static scratch (no allocation)."""
+        level = self.fine if level is None else level
+        n = self.ndofs(level)
+        _check(load().fcgmg_smooth_noalloc(self.h, level, _dptr(x, "x", n), _dptr(b, "b", n), sweeps,
+                                           _stream_ptr(stream)))
         return x
 
     def smooth_multi(self, x, b, r, nrhs: int, sweeps: int = 1, level: Optional[int] = None, stream=None):
