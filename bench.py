@@ -123,6 +123,20 @@ def patch_solve_flops(d: int) -> int:
     return chol_k + d * ncol * fwd_col + schur + chol_s + tri + centre
 
 
+# Cut-cell element data of the byte model: K (symmetric, 10 / 36 distinct doubles) and the d blocks
+# B_c (32 / 192 doubles) per cut cell, 2D / 3D.
+CUT_CELL_DOUBLES = {2: 42, 3: 228}
+
+
+def sweep_bytes(d: int, st: dict) -> float:
+    """Algorithmic bytes of one fused cache_inverse sweep on a level (FP64): read x and b and write the
+    new x, 3 n_DoF values; the (d+1) |S_i| inverse-row values of every distinct streamed row block;
+    the element data of every cut cell (CUT_CELL_DOUBLES). Shared class rows and reference data are
+    level constants and count nothing."""
+    nf = d + 1
+    return 8.0 * (3 * nf * st["n_nodes"] + nf * st["irregular_cols"] + CUT_CELL_DOUBLES[d] * st["n_cut_cells"])
+
+
 def sweep_minimum_bytes(d: int, st: dict) -> float:
     """Fused minimum of one cache_inverse sweep: read x, b, write x, the distinct row blocks of the
     streamed patches and the distinct stored operator rows, each once (FP64)."""
@@ -206,7 +220,8 @@ def dominant_kernel(torch, h, x, b, steps, d):
         avg_ms = e0.elapsed_time(e1) / 100
         timing = "100 back-to-back launches between two events"
     st = h.stats(lev)
-    nbytes = algorithmic_bytes(kind, d, st)
+    model = algorithmic_bytes(kind, d, st)
+    nbytes = sweep_bytes(d, st) if kind == "sweep_fused" else model
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     table = {f"{k}@L{l}": {"avg_us": round(v[0] / v[1] * 1e3, 3), "launches": v[1],
                            "share": round(v[0] / total_all, 4)} for (k, l), v in sorted(prof.items())}
@@ -214,7 +229,10 @@ def dominant_kernel(torch, h, x, b, steps, d):
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"{kind}@L{lev}"),
         "kernel": f"{kind}@L{lev}", "avg_launch_us": round(avg_ms * 1e3, 3), "avg_launch_timing": timing,
-        "algorithmic_bytes_per_launch": int(nbytes), "time_share": round(tot / total_all, 4),
+        "algorithmic_bytes_per_launch": int(nbytes),
+        "bytes_model": "8 [3 n_DoF + (d+1) sum_irr |S_i| + e_d n_cut], e_d = 42 (2D) / 228 (3D)"
+                       if kind == "sweep_fused" else "per-kernel minimum (algorithmic_bytes)",
+        "builder_model_bytes_per_launch": int(model), "time_share": round(tot / total_all, 4),
     }, table
 
 
@@ -565,6 +583,17 @@ def workload_extra(torch, fcgmg, prob, steps=20, warmup=3):
     sw = float(np.median(lat))
     st = h.stats()
     nd = h.ndofs()
+    fine = prob.n_levels - 1
+    sbytes = sweep_bytes(prob.dim, st)
+    if prob.dim == 2:
+        keys = [f"sweep_fused@L{fine}"]
+    else:
+        keys = [f"residual@L{fine}", f"apply_regular@L{fine}", f"apply_irregular@L{fine}"]
+    parts = [measured_traffic(k) for k in keys]
+    roof = {"bound": "hbm", "kernels": keys, "algorithmic_bytes_per_sweep": int(sbytes),
+            "sweep_us_p50": round(sw * 1e3, 2), "achieved": round(sbytes / (sw * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(sbytes / (sw * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": sum(parts) if all(p is not None for p in parts) else None}
     res = {
         "workload": prob.name, "n_dof": nd, "setup_s": round(setup, 3), "vcycle_ms": round(ms, 4),
         "value_dof_per_s": round(nd * (prob.nu_pre + prob.nu_post) / (ms * 1e-3), 1),
@@ -572,6 +601,7 @@ def workload_extra(torch, fcgmg, prob, steps=20, warmup=3):
         "sweep_min_bytes": int(sweep_minimum_bytes(prob.dim, st)),
         "sweep_gbs_vs_min_bytes": round(sweep_minimum_bytes(prob.dim, st) / (sw * 1e-3) / 1e9, 1),
         "n_irregular": st["n_irregular"], "n_cut_cells": st["n_cut_cells"], "device_bytes": h.device_bytes(),
+        "roofline": roof,
     }
     h.close()
     return res
@@ -728,6 +758,7 @@ def main():
                                            "cached_bytes_finest": st["cached_bytes"]}
         log("3D 64^3 ...")
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
+        out["roofline_3d"] = out["extra_3d"]["roofline"]
         log("precision: FP64 vs mixed ...")
         out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]
         log("stacked right-hand sides ...")
@@ -742,6 +773,7 @@ def main():
         big = inputs.config2(0, n_cells=4096, n_levels=10)
         big.name = "2d_20discs_4096_seed0"
         out["extra_2d_4096"] = workload_extra(torch, fcgmg, big)
+        out["roofline_4096"] = out["extra_2d_4096"]["roofline"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob)

@@ -31,7 +31,20 @@ def test_unknown_workload_is_refused():
 
 
 STATS = {"n_nodes": 263169, "n_irregular": 22000, "irregular_cols": 1250000, "n_stencils": 15000,
-         "n_classes": 2, "n_cells_axis": 512}
+         "n_classes": 2, "n_cells_axis": 512, "n_cut_cells": 3295}
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_sweep_bytes_follow_the_byte_model(d):
+    # 8 [3 n_DoF + (d+1) sum_irr |S_i| + e_d n_cut], e_d = 42 (2D) / 228 (3D)
+    nf = d + 1
+    e_d = 42 if d == 2 else 228
+    expect = 8.0 * (3 * nf * STATS["n_nodes"] + nf * STATS["irregular_cols"] + e_d * STATS["n_cut_cells"])
+    assert bench.sweep_bytes(d, STATS) == expect
+    for key in ("n_nodes", "irregular_cols", "n_cut_cells"):
+        st = dict(STATS)
+        st[key] += 1
+        assert bench.sweep_bytes(d, st) > bench.sweep_bytes(d, STATS)
 
 
 @pytest.mark.parametrize("d", [2, 3])
