@@ -655,6 +655,11 @@ def main():
     ap.add_argument("--workload", choices=["2d_512", "3d_64", "2d_4096"], default="2d_512",
                     help="workload of --cycles-only: the bench workload (default), 3D 64^3 with 40 spheres, or "
                          "2D 4096^2 with 20 discs and 10 levels")
+    ap.add_argument("--sweeps-only", action="store_true",
+                    help="run warmup + steps single fine-level sweeps of --workload under --policy and nothing else "
+                         "(for trace and counter runs of the factorising policies)")
+    ap.add_argument("--policy", choices=["inverse", "matrix", "none"], default="inverse",
+                    help="cache policy of --sweeps-only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of MIB MiB, 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -678,10 +683,21 @@ def main():
         print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "repeats": 5}), flush=True)
         return
     prob = inputs.config2(0)
-    if args.cycles_only and args.workload == "3d_64":
+    if (args.cycles_only or args.sweeps_only) and args.workload == "3d_64":
         prob = inputs.config3(0)
-    elif args.cycles_only and args.workload == "2d_4096":
+    elif (args.cycles_only or args.sweeps_only) and args.workload == "2d_4096":
         prob = inputs.config2(0, n_cells=4096, n_levels=10)
+    if args.sweeps_only:
+        pol = {"inverse": fcgmg.CACHE_INVERSE, "matrix": fcgmg.CACHE_MATRIX, "none": fcgmg.CACHE_NONE}[args.policy]
+        h = fcgmg.Hierarchy(prob, pol)
+        x, b = h.zeros(), h.rhs()
+        for _ in range(args.warmup + args.steps):
+            h.smooth(x, b, 1)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": prob.name, "policy": args.policy, "sweeps": args.warmup + args.steps,
+                          "n_dof": h.ndofs()}), flush=True)
+        h.close()
+        return
     d = prob.dim
     log(f"setup {prob.name} (cache_inverse) ...")
     t0 = time.perf_counter()

@@ -849,6 +849,417 @@ __global__ void __launch_bounds__(64) patch_solve_lu2_kernel(
   }
 }
 
+// ================================================================================================
+// cache_matrix / cache_none application in 2D: two patches per wavefront, 32 lanes each, and no
+// workgroup barrier. L_i = [[I_2 (x) K, B], [B^T, C]] (K: 25 x 25 of half bandwidth 6, B_c: 25 x 9,
+// C: 9 x 9) is solved by the same block elimination as patch_solve_kernel, arranged so that every
+// lane carries one right-hand-side column of the velocity solves: lanes 0-8 the columns of B_x,
+// lane 9 g_x, lanes 10-18 B_y, lane 19 g_y, lane 20 the unit vector of the centre velocity node
+// (lanes 21-31 shadow column 0). Row i of the Cholesky factor of K is formed in every lane (the same
+// values; no exchange) from the previous rows kept in registers; each lane advances its column by
+// one row of the forward substitution, the 21 new values are exchanged through LDS, and the
+// products that build the pressure Schur complement S = C - sum_c V_c^T V_c, its right-hand side
+// and the centre-row terms are accumulated as the rows complete, so V is never stored. The 9 x 9
+// system in F = -S is factorised in every lane. A lane's accumulation order does not depend on its
+// column, so the computed S is exactly symmetric.
+// ================================================================================================
+constexpr int kS2Cols = 21;
+
+// f(std::integral_constant<int, I>) for I = B .. E-1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Six zero rows precede K and the right-hand-side columns, so the six-row window of every row of the
+// factorisation and of the forward substitution is read without bounds tests.
+constexpr int kS2Pad = 6;
+// Largest stored pattern of a 2D patch block (288 entries), rounded up to whole lane rounds.
+constexpr int kMaxPattern2 = 320;
+
+template <bool NONE>
+struct Solve2LDS {
+  double Kb[(25 + kS2Pad) * 7];        // row v at v + 6: Kb[(v + 6) * 7 + (v - j)] = K[v][j], then L[v][j]
+  double dinv[25 + kS2Pad];            // 1 / L[v][v] at v + 6 (zero in the padding)
+  double X[(25 + kS2Pad) * kS2Cols];   // row v at v + 6, column l: right-hand sides, then V = L^-1 X
+  double C[81];                        // C, then F = -S (column l written by lane l)
+  double aux[32];                      // pressure right-hand side, then t (0-8); w_c (9-26); y^T z_c (27, 28)
+  double cell[NONE ? 48 : 1];                  // one cut cell integrated on the fly
+  double lball[NONE ? 4 * kMaxLocalBalls : 1];  // the balls that touch it
+  int bad;
+};
+
+// Orders the LDS accesses of one wavefront (its LDS instructions execute in order; this only stops
+// the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  asm volatile("" ::: "memory");
+}
+
+// The balls that touch the box [lo, lo + s]^2, collected by the 32 lanes of one half-wavefront (lane
+// l, half h) into `out`; -1 if more than kMaxLocalBalls touch it (the caller keeps the full list).
+__device__ int cull_balls_half(const Geom& g, const double* lo, double s, double* out, int l, int half) {
+  int cnt = 0;
+  for (int base = 0; base < g.nballs; base += 32) {
+    const int i = base + l;
+    bool touch = false;
+    if (i < g.nballs) {
+      const double* b = g.balls + 4 * i;
+      double dmin2 = 0;
+      for (int k = 0; k < 2; ++k) {
+        const double a = lo[k] - b[k], e = lo[k] + s - b[k];
+        const double m = a > 0 ? a : (e < 0 ? -e : 0.0);
+        dmin2 += m * m;
+      }
+      touch = dmin2 <= b[3] * b[3];
+    }
+    const unsigned hm = (unsigned)(__ballot(touch) >> (32 * half));
+    const int pos = cnt + __popc(hm & ((1u << l) - 1u));
+    if (touch && pos < kMaxLocalBalls)
+      for (int k = 0; k < 4; ++k) out[4 * pos + k] = g.balls[4 * i + k];
+    cnt += __popc(hm);
+  }
+  wave_lds_sync();
+  return cnt > kMaxLocalBalls ? -1 : cnt;
+}
+
+template <bool NONE>
+__global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, Geom g, double eta,
+    const int* __restrict__ node_class, const double* __restrict__ Mcls, const double* __restrict__ Mirr,
+    const int* __restrict__ pattern, int npat, int64_t N, const double* __restrict__ r, double* __restrict__ x,
+    double omega, int* err) {
+  constexpr int NV = 25, NP = 9, NB = 7, NC = kS2Cols, MC = 12;
+  __shared__ Solve2LDS<NONE> shp[2];
+  const int half = (int)threadIdx.x >> 5, l = (int)threadIdx.x & 31;
+  const int n = oc->n;
+  const double h = oc->h;
+  const int64_t npair = (N + 1) / 2;
+  for (int64_t pair = blockIdx.x; pair < npair; pair += gridDim.x) {
+    // the half's LDS block through an opaque index, so that the hundreds of addresses derived from
+    // it are formed where they are used instead of being hoisted out of this loop into registers
+    int hsel = half;
+    asm volatile("" : "+v"(hsel));
+    Solve2LDS<NONE>& sh = shp[hsel];
+    const int64_t node_raw = 2 * pair + half;
+    const bool live = node_raw < N;
+    const int64_t node = live ? node_raw : N - 1;  // a spare half repeats the last patch, unwritten
+    int c[3];
+    node_coords<2>(node, n, c);
+    // global loads first, all independent of each other except the stored values (which follow the
+    // patch class): the residual gather g = R_i r and, for cache_matrix, the pattern codes and values
+    double rv[2], rp = 0;
+    for (int k = 0; k < 2; ++k) {
+      const int e = l + 32 * k, cmp = e / NV, v = e % NV;
+      rv[k] = 0;
+      if (r && e < 2 * NV && vel_in_grid<2>(c, n, v)) {
+        const int cc[3] = {c[0] + v % 5 - 2, c[1] + v / 5 - 2, 0};
+        rv[k] = r[cmp * N + node_index<2>(cc, n)];
+      }
+    }
+    if (r && l < NP && pres_in_grid<2>(c, n, l)) {
+      const int cc[3] = {c[0] + l % 3 - 1, c[1] + l / 3 - 1, 0};
+      rp = r[2 * N + node_index<2>(cc, n)];
+    }
+    constexpr int NPL = NONE ? 1 : kMaxPattern2 / 32;  // stored pattern entries per lane
+    int pcode[NPL];
+    double pval[NPL];
+    if constexpr (!NONE) {
+      const int cls = node_class[node];
+      const double* vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        const int e = l + 32 * k;
+        pcode[k] = e < npat ? pattern[e] : -1;
+        pval[k] = e < npat ? vals[e] : 0.0;
+      }
+    }
+    for (int i = l; i < (NV + kS2Pad) * NC; i += 32) sh.X[i] = 0;
+    for (int i = l; i < (NV + kS2Pad) * NB; i += 32) sh.Kb[i] = 0;
+    for (int i = l; i < NV + kS2Pad; i += 32) sh.dinv[i] = 0;
+    for (int i = l; i < NP * NP; i += 32) sh.C[i] = 0;
+    if (l == 0) sh.bad = 0;
+    wave_lds_sync();
+    if constexpr (!NONE) {
+      // the stored pattern values of L_i (one shared block per class, one per individual patch)
+#pragma unroll
+      for (int k = 0; k < NPL; ++k) {
+        const int code = pcode[k];
+        if (code < 0) continue;
+        const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
+        const double v = pval[k];
+        if (type == 0) {
+          sh.Kb[(i + kS2Pad) * NB + (i - j)] = v;
+        } else if (type <= 2) {
+          sh.X[(i + kS2Pad) * NC + (type - 1) * 10 + j] = v;
+        } else {
+          sh.C[i * NP + j] = v;
+          sh.C[j * NP + i] = v;
+        }
+      }
+      wave_lds_sync();
+    } else {
+      // on-the-fly assembly from the 6 x 6 cell window, in window order (Eq. 15: L_i = R_i L R_i^T);
+      // lane l holds the cell codes of window cells l and l + 32 (-3: outside the grid)
+      int info2[2];
+      for (int k = 0; k < 2; ++k) {
+        const int w = l + 32 * k;
+        const int cx = c[0] + w % 6 - 3, cy = c[1] + w / 6 - 3;
+        info2[k] = (w < 36 && cx >= 0 && cx < n && cy >= 0 && cy < n) ? cell_info[cx + (int64_t)n * cy] : -3;
+      }
+      for (int w = 0; w < 36; ++w) {
+        const int info = __shfl(w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
+        if (info == -3) continue;
+        const int wx = w % 6, wy = w / 6;
+        const int cx = c[0] + wx - 3, cy = c[1] + wy - 3;
+        const double* Kp;
+        const double* Bp;
+        int bstride;
+        if (info >= 0) {
+          const double lo[3] = {cx * h, cy * h, 0.0};
+          const int nb = cull_balls_half(g, lo, h, sh.lball, l, half);
+          Geom gl = g;
+          if (nb >= 0) {
+            gl.balls = sh.lball;
+            gl.nballs = nb;
+          }
+          if (gl.q >= 3) {
+            // the cell's tree below depth 3: lane l integrates sub-boxes l and l + 32 of the 8 x 8
+            // (side h / 8) to the level's depth, every entry at once; the 32 partial sums are then
+            // added by a butterfly. (A box above depth 3 that is not cut becomes uncut sub-boxes
+            // here: the 2 x 2 Gauss rule is exact on each, so the integral is the same up to rounding.)
+            double acc[48];
+#pragma unroll
+            for (int e = 0; e < 48; ++e) acc[e] = 0;
+            const double hs = 0.125 * h;
+            Geom gs = gl;
+            gs.q = gl.q - 3;
+            for (int k = 0; k < 2; ++k) {
+              const int bidx = l + 32 * k;
+              const double los[3] = {lo[0] + (bidx & 7) * hs, lo[1] + (bidx >> 3) * hs, 0.0};
+              tree_quadrature<2>(gs, los, hs, [&](const double* xq, double wq, double alpha) {
+                double phi[4], gr[4][3];
+                q1<2>(lo, h, xq, phi, gr);
+                const double wa = wq * alpha;
+#pragma unroll
+                for (int e = 0; e < 48; ++e) acc[e] += point_entry<2>(e, eta, wa, phi, gr);
+              });
+            }
+#pragma unroll
+            for (int e = 0; e < 48; ++e) {
+              double v = acc[e];
+              for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 32);
+              acc[e] = v;
+            }
+            if (l == 0)
+#pragma unroll
+              for (int e = 0; e < 48; ++e) sh.cell[e] = acc[e];
+          } else {
+            // trees of depth 0 to 2: every lane walks the whole tree for entries l and l + 32
+            double a0 = 0, a1 = 0;
+            tree_quadrature<2>(gl, lo, h, [&](const double* xq, double wq, double alpha) {
+              double phi[4], gr[4][3];
+              q1<2>(lo, h, xq, phi, gr);
+              const double wa = wq * alpha;
+              a0 += point_entry<2>(l, eta, wa, phi, gr);
+              if (l < 16) a1 += point_entry<2>(l + 32, eta, wa, phi, gr);
+            });
+            sh.cell[l] = a0;
+            if (l < 16) sh.cell[l + 32] = a1;
+          }
+          wave_lds_sync();
+          Kp = sh.cell;
+          Bp = sh.cell + 16;
+          bstride = 16;
+        } else {
+          const int kind = info == -1 ? 0 : 1;
+          Kp = oc->K[kind];
+          Bp = oc->B[kind][0];
+          bstride = 64;
+        }
+        int fmask = 0;
+        if (cx == 0 && oc->dirichlet[0]) fmask |= 1;
+        if (cx == n - 1 && oc->dirichlet[1]) fmask |= 2;
+        if (cy == 0 && oc->dirichlet[2]) fmask |= 4;
+        if (cy == n - 1 && oc->dirichlet[3]) fmask |= 8;
+        for (int k = 0; k < 2; ++k) {
+          const int it = l + 32 * k;  // (block, a, b): K, B_x, B_y, C, 16 pairs each
+          const int blk = it >> 4, ab = it & 15, a = ab >> 2, b = ab & 3;
+          const int xa = wx + (a & 1) - 1, ya = wy + (a >> 1) - 1, xb = wx + (b & 1) - 1, yb = wy + (b >> 1) - 1;
+          const int pxa = xa - 1, pya = ya - 1, pxb = xb - 1, pyb = yb - 1;
+          const bool va_ok = xa >= 0 && xa <= 4 && ya >= 0 && ya <= 4;
+          const bool vb_ok = xb >= 0 && xb <= 4 && yb >= 0 && yb <= 4;
+          const bool qa_ok = pxa >= 0 && pxa <= 2 && pya >= 0 && pya <= 2;
+          const bool qb_ok = pxb >= 0 && pxb <= 2 && pyb >= 0 && pyb <= 2;
+          const int va = xa + 5 * ya, vb = xb + 5 * yb, qa = pxa + 3 * pya, qb = pxb + 3 * pyb;
+          if (blk == 0) {
+            if (va_ok && vb_ok && va >= vb) {
+              double v = Kp[a * 4 + b];
+              for (int f = 0; f < 4; ++f)
+                if (fmask & (1 << f)) v += oc->FK[f][a * 4 + b];
+              sh.Kb[(va + kS2Pad) * NB + (va - vb)] += v;
+            }
+          } else if (blk <= 2) {
+            const int cmp = blk - 1;
+            if (va_ok && qb_ok) {
+              double v = Bp[cmp * bstride + a * 4 + b];
+              for (int sd = 0; sd < 2; ++sd)
+                if (fmask & (1 << (2 * cmp + sd))) v += oc->FB[2 * cmp + sd][a * 4 + b];
+              sh.X[(va + kS2Pad) * NC + cmp * 10 + qb] += v;
+            }
+          } else if (qa_ok && qb_ok) {
+            sh.C[qa * NP + qb] += oc->C[a * 4 + b];
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    // window positions outside the grid are decoupled; g = R_i r (zero outside the grid) into the
+    // columns 9 and 19, its pressure part into aux; the unit column of the centre velocity node
+    if (l < NV && !vel_in_grid<2>(c, n, l)) sh.Kb[(l + kS2Pad) * NB] = 1.0;
+    if (l < NP && !pres_in_grid<2>(c, n, l)) sh.C[l * NP + l] = -1.0;
+    for (int k = 0; k < 2; ++k) {
+      const int e = l + 32 * k, cmp = e / NV, v = e % NV;
+      if (e < 2 * NV) sh.X[(v + kS2Pad) * NC + cmp * 10 + 9] = rv[k];
+    }
+    if (l < NV) sh.X[(l + kS2Pad) * NC + 20] = l == MC ? 1.0 : 0.0;
+    if (l < NP) sh.aux[l] = rp;
+    wave_lds_sync();
+    // velocity phase: band Cholesky of K row by row (every lane forms the same row and keeps the last
+    // six in registers, shifted by one row per step), forward substitution of this lane's column (its
+    // last six values in registers too), the new row of V exchanged through LDS, and the Schur
+    // products accumulated as each row completes. Rows before the first are zero (dinv = 0), so the
+    // first steps need no bounds tests.
+    const int lc = l < NC ? l : 0;
+    const int cb = lc < 10 ? 0 : 10;  // first column of this lane's component block
+    double Lw[6][5];                  // Lw[s][k - 1] = L[i - 6 + s][i - 6 + s - k], k = 1..5 (rows i-6..i-1)
+    double Dw[6];                     // Dw[s] = 1 / L[i - 6 + s][i - 6 + s]
+    double vw[6];                     // vw[s] = V[i - 6 + s][column]
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      Dw[s] = 0.0;
+      vw[s] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) Lw[s][k] = 0.0;
+    }
+    double sacc[9], wacc = 0;
+    for (int a = 0; a < 9; ++a) sacc[a] = 0;
+    bool bad = false;
+#pragma unroll 1
+    for (int i = 0; i < NV; ++i) {
+      const int ko = (i + kS2Pad) * NB, xo = (i + kS2Pad) * NC;
+      double li[6];  // li[t] = L[i][i - 6 + t]
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        double s = sh.Kb[ko + (6 - t)];
+#pragma unroll
+        for (int u = 0; u < t; ++u) s -= li[u] * Lw[t][t - u - 1];  // L[i-6+t][i-6+u]
+        li[t] = s * Dw[t];
+      }
+      double d = sh.Kb[ko];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) d -= li[t] * li[t];
+      bad |= !(d > 0.0);
+      const double inv = rsqrt(d);
+      double v = sh.X[xo + lc];
+#pragma unroll
+      for (int t = 0; t < 6; ++t) v -= li[t] * vw[t];
+      v *= inv;
+      // shift the windows by one row: row i enters at s = 5 with L[i][i-k] = li[6-k]
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        Dw[s] = Dw[s + 1];
+        vw[s] = vw[s + 1];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Lw[s][k] = Lw[s + 1][k];
+      }
+      Dw[5] = inv;
+      vw[5] = v;
+#pragma unroll
+      for (int k = 1; k <= 5; ++k) Lw[5][k - 1] = li[6 - k];
+      wave_lds_sync();  // every lane has read row i of X
+      if (l < NC) sh.X[xo + l] = v;
+      wave_lds_sync();
+#pragma unroll
+      for (int a = 0; a < 9; ++a) sacc[a] += sh.X[xo + cb + a] * v;
+      if (i >= MC) wacc += sh.X[xo + 20] * v;
+    }
+    // F = -S = sum_c V_c^T V_c - C, column a from lanes a (B_x) and 10 + a (B_y); t = g_p - sum_c V_c^T z_c
+    // from lanes 9 and 19; w_c and y^T z_c from every column lane
+    double* sy = sh.X;  // 10 x 9: the sums of lanes 10-19 (X is no longer read)
+    if (l >= 10 && l < 20)
+      for (int a = 0; a < 9; ++a) sy[(l - 10) * 9 + a] = sacc[a];
+    if (l < 20) sh.aux[l % 10 == 9 ? 27 + l / 10 : 9 + (l / 10) * 9 + l % 10] = wacc;
+    wave_lds_sync();
+    if (l < 9) {
+      for (int a = 0; a < 9; ++a) sh.C[a * NP + l] = sacc[a] + sy[l * 9 + a] - sh.C[a * NP + l];
+    } else if (l == 9) {
+      for (int a = 0; a < 9; ++a) sh.aux[a] = sh.aux[a] - (sacc[a] + sy[9 * 9 + a]);
+    }
+    wave_lds_sync();
+    // F p = -t by Cholesky F = R R^T in every lane (R in registers; the barrier at each row keeps
+    // the compiler from loading all of F at once), then the two triangular solves
+    const double* F = sh.C;
+    double R[45], rinv[9], p[9];
+    static_for<0, NP>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      wave_lds_sync();
+      static_for<0, i>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        double s = F[i * NP + j];
+        static_for<0, j>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          s -= R[i * (i + 1) / 2 + k] * R[j * (j + 1) / 2 + k];
+        });
+        R[i * (i + 1) / 2 + j] = s * rinv[j];
+      });
+      double d = F[i * NP + i];
+      static_for<0, i>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        d -= R[i * (i + 1) / 2 + k] * R[i * (i + 1) / 2 + k];
+      });
+      bad |= !(d > 0.0);
+      rinv[i] = rsqrt(d);
+    });
+    static_for<0, NP>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      double s = -sh.aux[i];
+      static_for<0, i>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        s -= R[i * (i + 1) / 2 + k] * p[k];
+      });
+      p[i] = s * rinv[i];
+    });
+    static_for<0, NP>([&](auto ic) {
+      constexpr int i = NP - 1 - decltype(ic)::value;
+      double s = p[i];
+      static_for<i + 1, NP>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        s -= R[k * (k + 1) / 2 + i] * p[k];
+      });
+      p[i] = s * rinv[i];
+    });
+    if (live && l <= 2 && x != nullptr && !bad) {
+      double y;
+      if (l < 2) {
+        y = sh.aux[27 + l];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) y -= sh.aux[9 + l * 9 + a] * p[a];
+      } else {
+        y = p[4];
+      }
+      x[l * N + node] += omega * y;
+    }
+    if (live && bad && l == 0) atomicMin(err, (int)node);
+    wave_lds_sync();
+  }
+}
+
 template <int D>
 hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double* r, double* x, hipStream_t s) {
   const int64_t nb = L.N < 131072 ? L.N : 131072;
@@ -859,6 +1270,18 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
           c.pattern, c.n_pattern, L.N, r, x, c.prm.omega, c.err);
       return hipGetLastError();
     }
+    if (c.n_pattern > kMaxPattern2) return hipErrorInvalidValue;
+    const int64_t npair = (L.N + 1) / 2;
+    const int64_t nb2 = npair < 65536 ? npair : 65536;
+    if (policy == FCGMG_CACHE_MATRIX)
+      patch_solve_lanes2_kernel<false><<<dim3((unsigned)nb2), dim3(64), 0, s>>>(
+          L.consts, L.cell_info, c.geom(L), c.prm.eta, L.node_class, L.Mcls, L.Mirr, c.pattern, c.n_pattern, L.N,
+          r, x, c.prm.omega, c.err);
+    else
+      patch_solve_lanes2_kernel<true><<<dim3((unsigned)nb2), dim3(64), 0, s>>>(
+          L.consts, L.cell_info, c.geom(L), c.prm.eta, L.node_class, L.Mcls, L.Mirr, c.pattern, c.n_pattern, L.N,
+          r, x, c.prm.omega, c.err);
+    return hipGetLastError();
   }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
       L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
