@@ -874,19 +874,15 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-// Six zero rows precede K and the right-hand-side columns, so the six-row window of every row of the
-// factorisation and of the forward substitution is read without bounds tests.
-constexpr int kS2Pad = 6;
 // Largest stored pattern of a 2D patch block (288 entries), rounded up to whole lane rounds.
 constexpr int kMaxPattern2 = 320;
 
 template <bool NONE>
 struct Solve2LDS {
-  double Kb[(25 + kS2Pad) * 7];        // row v at v + 6: Kb[(v + 6) * 7 + (v - j)] = K[v][j], then L[v][j]
-  double dinv[25 + kS2Pad];            // 1 / L[v][v] at v + 6 (zero in the padding)
-  double X[(25 + kS2Pad) * kS2Cols];   // row v at v + 6, column l: right-hand sides, then V = L^-1 X
-  double C[81];                        // C, then F = -S (column l written by lane l)
-  double aux[32];                      // pressure right-hand side, then t (0-8); w_c (9-26); y^T z_c (27, 28)
+  double Kb[25 * 7];              // lower band of K: Kb[v * 7 + (v - j)] = K[v][j]
+  double X[25 * kS2Cols];         // X[v * 21 + l]: right-hand-side column l at velocity window node v, then V
+  double C[81];                   // C, then F = -S (column l written by lane l)
+  double aux[32];                 // pressure right-hand side, then t (0-8); w_c (9-26); y^T z_c (27, 28)
   double cell[NONE ? 48 : 1];                  // one cut cell integrated on the fly
   double lball[NONE ? 4 * kMaxLocalBalls : 1];  // the balls that touch it
   int bad;
@@ -979,9 +975,8 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
         pval[k] = e < npat ? vals[e] : 0.0;
       }
     }
-    for (int i = l; i < (NV + kS2Pad) * NC; i += 32) sh.X[i] = 0;
-    for (int i = l; i < (NV + kS2Pad) * NB; i += 32) sh.Kb[i] = 0;
-    for (int i = l; i < NV + kS2Pad; i += 32) sh.dinv[i] = 0;
+    for (int i = l; i < NV * NC; i += 32) sh.X[i] = 0;
+    for (int i = l; i < NV * NB; i += 32) sh.Kb[i] = 0;
     for (int i = l; i < NP * NP; i += 32) sh.C[i] = 0;
     if (l == 0) sh.bad = 0;
     wave_lds_sync();
@@ -994,9 +989,9 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
         const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
         const double v = pval[k];
         if (type == 0) {
-          sh.Kb[(i + kS2Pad) * NB + (i - j)] = v;
+          sh.Kb[i * NB + (i - j)] = v;
         } else if (type <= 2) {
-          sh.X[(i + kS2Pad) * NC + (type - 1) * 10 + j] = v;
+          sh.X[i * NC + (type - 1) * 10 + j] = v;
         } else {
           sh.C[i * NP + j] = v;
           sh.C[j * NP + i] = v;
@@ -1004,84 +999,20 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
       }
       wave_lds_sync();
     } else {
-      // on-the-fly assembly from the 6 x 6 cell window, in window order (Eq. 15: L_i = R_i L R_i^T);
-      // lane l holds the cell codes of window cells l and l + 32 (-3: outside the grid)
+      // on-the-fly assembly from the 6 x 6 cell window (Eq. 15: L_i = R_i L R_i^T): first the uncut
+      // cells from the reference matrices, in window order, then the cut cells, integrated on the
+      // fly; in the second pass each half takes its k-th cut cell at step k, so that the two halves
+      // of the wavefront integrate together. Lane l holds the codes of window cells l and l + 32
+      // (-3: outside the grid).
       int info2[2];
       for (int k = 0; k < 2; ++k) {
         const int w = l + 32 * k;
         const int cx = c[0] + w % 6 - 3, cy = c[1] + w / 6 - 3;
         info2[k] = (w < 36 && cx >= 0 && cx < n && cy >= 0 && cy < n) ? cell_info[cx + (int64_t)n * cy] : -3;
       }
-      for (int w = 0; w < 36; ++w) {
-        const int info = __shfl(w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
-        if (info == -3) continue;
+      auto scatter = [&](int w, const double* Kp, const double* Bp, int bstride) {
         const int wx = w % 6, wy = w / 6;
         const int cx = c[0] + wx - 3, cy = c[1] + wy - 3;
-        const double* Kp;
-        const double* Bp;
-        int bstride;
-        if (info >= 0) {
-          const double lo[3] = {cx * h, cy * h, 0.0};
-          const int nb = cull_balls_half(g, lo, h, sh.lball, l, half);
-          Geom gl = g;
-          if (nb >= 0) {
-            gl.balls = sh.lball;
-            gl.nballs = nb;
-          }
-          if (gl.q >= 3) {
-            // the cell's tree below depth 3: lane l integrates sub-boxes l and l + 32 of the 8 x 8
-            // (side h / 8) to the level's depth, every entry at once; the 32 partial sums are then
-            // added by a butterfly. (A box above depth 3 that is not cut becomes uncut sub-boxes
-            // here: the 2 x 2 Gauss rule is exact on each, so the integral is the same up to rounding.)
-            double acc[48];
-#pragma unroll
-            for (int e = 0; e < 48; ++e) acc[e] = 0;
-            const double hs = 0.125 * h;
-            Geom gs = gl;
-            gs.q = gl.q - 3;
-            for (int k = 0; k < 2; ++k) {
-              const int bidx = l + 32 * k;
-              const double los[3] = {lo[0] + (bidx & 7) * hs, lo[1] + (bidx >> 3) * hs, 0.0};
-              tree_quadrature<2>(gs, los, hs, [&](const double* xq, double wq, double alpha) {
-                double phi[4], gr[4][3];
-                q1<2>(lo, h, xq, phi, gr);
-                const double wa = wq * alpha;
-#pragma unroll
-                for (int e = 0; e < 48; ++e) acc[e] += point_entry<2>(e, eta, wa, phi, gr);
-              });
-            }
-#pragma unroll
-            for (int e = 0; e < 48; ++e) {
-              double v = acc[e];
-              for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 32);
-              acc[e] = v;
-            }
-            if (l == 0)
-#pragma unroll
-              for (int e = 0; e < 48; ++e) sh.cell[e] = acc[e];
-          } else {
-            // trees of depth 0 to 2: every lane walks the whole tree for entries l and l + 32
-            double a0 = 0, a1 = 0;
-            tree_quadrature<2>(gl, lo, h, [&](const double* xq, double wq, double alpha) {
-              double phi[4], gr[4][3];
-              q1<2>(lo, h, xq, phi, gr);
-              const double wa = wq * alpha;
-              a0 += point_entry<2>(l, eta, wa, phi, gr);
-              if (l < 16) a1 += point_entry<2>(l + 32, eta, wa, phi, gr);
-            });
-            sh.cell[l] = a0;
-            if (l < 16) sh.cell[l + 32] = a1;
-          }
-          wave_lds_sync();
-          Kp = sh.cell;
-          Bp = sh.cell + 16;
-          bstride = 16;
-        } else {
-          const int kind = info == -1 ? 0 : 1;
-          Kp = oc->K[kind];
-          Bp = oc->B[kind][0];
-          bstride = 64;
-        }
         int fmask = 0;
         if (cx == 0 && oc->dirichlet[0]) fmask |= 1;
         if (cx == n - 1 && oc->dirichlet[1]) fmask |= 2;
@@ -1102,7 +1033,7 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
               double v = Kp[a * 4 + b];
               for (int f = 0; f < 4; ++f)
                 if (fmask & (1 << f)) v += oc->FK[f][a * 4 + b];
-              sh.Kb[(va + kS2Pad) * NB + (va - vb)] += v;
+              sh.Kb[va * NB + (va - vb)] += v;
             }
           } else if (blk <= 2) {
             const int cmp = blk - 1;
@@ -1110,31 +1041,104 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
               double v = Bp[cmp * bstride + a * 4 + b];
               for (int sd = 0; sd < 2; ++sd)
                 if (fmask & (1 << (2 * cmp + sd))) v += oc->FB[2 * cmp + sd][a * 4 + b];
-              sh.X[(va + kS2Pad) * NC + cmp * 10 + qb] += v;
+              sh.X[va * NC + cmp * 10 + qb] += v;
             }
           } else if (qa_ok && qb_ok) {
             sh.C[qa * NP + qb] += oc->C[a * 4 + b];
           }
         }
         wave_lds_sync();
+      };
+      for (int w = 0; w < 36; ++w) {
+        const int info = __shfl(w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
+        if (info == -3 || info >= 0) continue;
+        const int kind = info == -1 ? 0 : 1;
+        scatter(w, oc->K[kind], oc->B[kind][0], 64);
+      }
+      // the cut cells of this half's window as a bit mask over the 36 window positions
+      const unsigned long long m0 = __ballot(info2[0] >= 0), m1 = __ballot(info2[1] >= 0);
+      unsigned long long cutm = ((m0 >> (32 * half)) & 0xffffffffull) | (((m1 >> (32 * half)) & 0xfull) << 32);
+      const int ncut_h = __popcll(cutm);
+      const int ncut_o = __shfl(ncut_h, ((1 - half) << 5), 64);
+      const int nsteps = ncut_h > ncut_o ? ncut_h : ncut_o;
+      for (int k = 0; k < nsteps; ++k) {
+        const int w = cutm ? __builtin_ctzll(cutm) : -1;
+        cutm &= cutm ? cutm - 1 : 0ull;
+        const int info = __shfl(w >= 0 && w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
+        if (w < 0) continue;  // this half has no more cut cells
+        (void)info;
+        const int wx = w % 6, wy = w / 6;
+        const double lo[3] = {(c[0] + wx - 3) * h, (c[1] + wy - 3) * h, 0.0};
+        const int nb = cull_balls_half(g, lo, h, sh.lball, l, half);
+        Geom gl = g;
+        if (nb >= 0) {
+          gl.balls = sh.lball;
+          gl.nballs = nb;
+        }
+        if (gl.q >= 3) {
+          // the cell's tree below depth 3: lane l integrates sub-boxes l and l + 32 of the 8 x 8
+          // (side h / 8) to the level's depth, every entry at once; the 32 partial sums are then
+          // added by a butterfly. (A box above depth 3 that is not cut becomes uncut sub-boxes here:
+          // the 2 x 2 Gauss rule is exact on each, so the integral is the same up to rounding.)
+          double acc[48];
+#pragma unroll
+          for (int e = 0; e < 48; ++e) acc[e] = 0;
+          const double hs = 0.125 * h;
+          Geom gs = gl;
+          gs.q = gl.q - 3;
+          for (int k2 = 0; k2 < 2; ++k2) {
+            const int bidx = l + 32 * k2;
+            const double los[3] = {lo[0] + (bidx & 7) * hs, lo[1] + (bidx >> 3) * hs, 0.0};
+            tree_quadrature<2>(gs, los, hs, [&](const double* xq, double wq, double alpha) {
+              double phi[4], gr[4][3];
+              q1<2>(lo, h, xq, phi, gr);
+              const double wa = wq * alpha;
+#pragma unroll
+              for (int e = 0; e < 48; ++e) acc[e] += point_entry<2>(e, eta, wa, phi, gr);
+            });
+          }
+#pragma unroll
+          for (int e = 0; e < 48; ++e) {
+            double v = acc[e];
+            for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 32);
+            acc[e] = v;
+          }
+          if (l == 0)
+#pragma unroll
+            for (int e = 0; e < 48; ++e) sh.cell[e] = acc[e];
+        } else {
+          // trees of depth 0 to 2: every lane walks the whole tree for entries l and l + 32
+          double a0 = 0, a1 = 0;
+          tree_quadrature<2>(gl, lo, h, [&](const double* xq, double wq, double alpha) {
+            double phi[4], gr[4][3];
+            q1<2>(lo, h, xq, phi, gr);
+            const double wa = wq * alpha;
+            a0 += point_entry<2>(l, eta, wa, phi, gr);
+            if (l < 16) a1 += point_entry<2>(l + 32, eta, wa, phi, gr);
+          });
+          sh.cell[l] = a0;
+          if (l < 16) sh.cell[l + 32] = a1;
+        }
+        wave_lds_sync();
+        scatter(w, sh.cell, sh.cell + 16, 16);
       }
     }
     // window positions outside the grid are decoupled; g = R_i r (zero outside the grid) into the
     // columns 9 and 19, its pressure part into aux; the unit column of the centre velocity node
-    if (l < NV && !vel_in_grid<2>(c, n, l)) sh.Kb[(l + kS2Pad) * NB] = 1.0;
+    if (l < NV && !vel_in_grid<2>(c, n, l)) sh.Kb[l * NB] = 1.0;
     if (l < NP && !pres_in_grid<2>(c, n, l)) sh.C[l * NP + l] = -1.0;
     for (int k = 0; k < 2; ++k) {
       const int e = l + 32 * k, cmp = e / NV, v = e % NV;
-      if (e < 2 * NV) sh.X[(v + kS2Pad) * NC + cmp * 10 + 9] = rv[k];
+      if (e < 2 * NV) sh.X[v * NC + cmp * 10 + 9] = rv[k];
     }
-    if (l < NV) sh.X[(l + kS2Pad) * NC + 20] = l == MC ? 1.0 : 0.0;
+    if (l < NV) sh.X[l * NC + 20] = l == MC ? 1.0 : 0.0;
     if (l < NP) sh.aux[l] = rp;
     wave_lds_sync();
     // velocity phase: band Cholesky of K row by row (every lane forms the same row and keeps the last
     // six in registers, shifted by one row per step), forward substitution of this lane's column (its
     // last six values in registers too), the new row of V exchanged through LDS, and the Schur
-    // products accumulated as each row completes. Rows before the first are zero (dinv = 0), so the
-    // first steps need no bounds tests.
+    // products accumulated as each row completes. The windows start as zero rows (inverse diagonal
+    // 0), so the first steps need no bounds tests.
     const int lc = l < NC ? l : 0;
     const int cb = lc < 10 ? 0 : 10;  // first column of this lane's component block
     double Lw[6][5];                  // Lw[s][k - 1] = L[i - 6 + s][i - 6 + s - k], k = 1..5 (rows i-6..i-1)
@@ -1152,7 +1156,7 @@ __global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
     bool bad = false;
 #pragma unroll 1
     for (int i = 0; i < NV; ++i) {
-      const int ko = (i + kS2Pad) * NB, xo = (i + kS2Pad) * NC;
+      const int ko = i * NB, xo = i * NC;
       double li[6];  // li[t] = L[i][i - 6 + t]
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
