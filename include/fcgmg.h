@@ -253,14 +253,23 @@ int fcgmg_batch_destroy(fcgmg_batch_h bt);
  * (fcgmg_footprint_bytes plus its right-hand side) fits the memory budget, after evicting idle
  * hierarchies least recently used first. With cache_policy = -1 the server picks the fastest policy
  * of Sec. 3.1.2 that fits (cache_inverse, then cache_matrix, then cache_none). A request that can
- * never fit completes with E_NOMEM. Each solve is fcgmg_solve from x = 0 on the problem's own
- * right-hand side (fcgmg_rhs), so its result does not depend on what else runs. */
+ * never fit completes with E_NOMEM. Each solve is standalone GMG (or FGMRES) from x = 0 on the
+ * problem's own right-hand side (fcgmg_rhs).
+ * Continuous batching (continuous_batching = 1): a request that the batched cycle takes (2D,
+ * cache_inverse, FP64, GMG, V(2,2)) is set up by a worker and then joins the running batch: one
+ * engine thread advances every such request by one V-cycle per step, all of them in the launches
+ * of fcgmg_batch_vcycle, with their residual norms from one launch; requests join as their set-up
+ * finishes and leave when they meet their stopping test (or the cycle limit). Each problem's cycle
+ * and norm are computed by workgroups of its own, so a result is bit for bit the same alone and in
+ * any mix; against fcgmg_solve its norms are summed in another order (iterations within one). The
+ * other requests run fcgmg_solve on their worker. */
 typedef struct fcgmg_server* fcgmg_server_h;
 
 typedef struct {
-  int workers;         /* concurrent solves, 1..16                                                */
-  int max_iter;        /* cycle limit of every solve                                              */
-  int64_t hbm_budget;  /* device bytes for resident hierarchies; 0: 80% of the free memory         */
+  int workers;             /* concurrent set-ups and unbatched solves, 1..16                      */
+  int max_iter;            /* cycle limit of every solve                                          */
+  int64_t hbm_budget;      /* device bytes for resident hierarchies; 0: 80% of the free memory     */
+  int continuous_batching; /* 1: batchable requests share the batched cycle (see above); 0: off   */
 } fcgmg_server_params;
 
 typedef struct {
@@ -286,6 +295,9 @@ int fcgmg_server_submit(fcgmg_server_h srv, const fcgmg_params* prm, const doubl
 int fcgmg_server_wait(fcgmg_server_h srv, int64_t request_id, fcgmg_request_result* res);
 /* Device bytes and number of hierarchies currently resident. */
 int fcgmg_server_resident_bytes(fcgmg_server_h srv, int64_t* bytes, int* hierarchies);
+/* Continuous batching so far: batched cycle steps run, and the sum over those steps of the number of
+ * requests each advanced (their ratio is the mean batch size), and the largest batch. */
+int fcgmg_server_stats(fcgmg_server_h srv, int64_t* steps, int64_t* request_cycles, int* max_batch);
 /* Finish queued requests, join the workers, free every resident hierarchy. */
 int fcgmg_server_destroy(fcgmg_server_h srv);
 

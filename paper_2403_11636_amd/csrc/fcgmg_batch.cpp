@@ -46,6 +46,7 @@ struct fcgmg_batch {
   double* norms = nullptr;
   double* norms_host = nullptr;
   int part_cap = 0;
+  int norm_cap = 0;        // problems that norms / norms_host hold
 
   void clear() {
     fj.clear();
@@ -177,7 +178,19 @@ struct fcgmg_batch {
   }
 
   int ensure_norm_space(int nblocks, int njobs) {
-    if (nblocks <= part_cap && njobs <= (int)hs.size()) return FCGMG_OK;
+    if (njobs > norm_cap) {
+      if (norms) (void)hipFree(norms);
+      if (norms_host) (void)hipHostFree(norms_host);
+      norms = nullptr;
+      norms_host = nullptr;
+      norm_cap = 0;
+      const int cap = std::max(njobs, 2 * norm_cap);
+      if (hipMalloc((void**)&norms, cap * sizeof(double)) != hipSuccess ||
+          hipHostMalloc((void**)&norms_host, cap * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return set_error(FCGMG_E_NOMEM, "batch: norm allocation failed");
+      norm_cap = cap;
+    }
+    if (nblocks <= part_cap) return FCGMG_OK;
     if (part) (void)hipFree(part);
     part = nullptr;
     part_cap = 0;
@@ -229,6 +242,7 @@ int fcgmg_batch_create(const fcgmg_h* hs, int count, fcgmg_batch_h* out) {
     fcgmg_batch_destroy(bt);
     return set_error(FCGMG_E_NOMEM, "batch: allocation failed");
   }
+  bt->norm_cap = count;
   *out = bt;
   return FCGMG_OK;
 }
@@ -293,3 +307,33 @@ int fcgmg_batch_destroy(fcgmg_batch_h bt) {
 }
 
 }  // extern "C"
+
+namespace fcg {
+
+bool batch_engine_accepts(const fcgmg_params& p) {
+  return p.dim == 2 && p.cache_policy == FCGMG_CACHE_INVERSE && p.precision == FCGMG_PREC_FP64 &&
+         p.solver == FCGMG_SOLVER_GMG && p.nu_pre == 2 && p.nu_post == 2;
+}
+
+int batch_engine_create(fcgmg_batch** out) {
+  *out = new fcgmg_batch();
+  return FCGMG_OK;
+}
+
+int batch_engine_step(fcgmg_batch* bt, const std::vector<fcgmg_ctx*>& hs, double* const* x, const double* const* b,
+                      bool cycle, hipStream_t s, std::vector<double>& norms) {
+  bt->hs = hs;
+  std::vector<int> act(hs.size());
+  for (size_t i = 0; i < act.size(); ++i) act[i] = (int)i;
+  int rc;
+  if (cycle) {
+    bt->clear();
+    bt->record_vcycle(act, x, b);
+    if ((rc = bt->run(s))) return rc;
+  }
+  return bt->norms_of(act, x, b, s, norms);
+}
+
+void batch_engine_destroy(fcgmg_batch* bt) { fcgmg_batch_destroy(bt); }
+
+}  // namespace fcg

@@ -550,6 +550,16 @@ hipError_t k_scale_copy(const double* w, double a, double* v, int64_t n, hipStre
 template <int D> int pattern_size();
 template <int D> void pattern_entries(std::vector<int>& enc);
 
+// Batched standalone GMG steps for the solve server (fcgmg_batch.cpp): a batch whose set of problems
+// changes from step to step. Every problem must be 2D, cache_inverse, FP64 with nu_pre = nu_post = 2.
+bool batch_engine_accepts(const fcgmg_params& p);
+int batch_engine_create(fcgmg_batch** out);
+// norms[k] = ||b_k - L x_k||_2 of the finest level of hs[k]; with `cycle`, one V-cycle on every
+// problem first. One synchronisation of s.
+int batch_engine_step(fcgmg_batch* bt, const std::vector<fcgmg_ctx*>& hs, double* const* x, const double* const* b,
+                      bool cycle, hipStream_t s, std::vector<double>& norms);
+void batch_engine_destroy(fcgmg_batch* bt);
+
 }  // namespace fcg
 
 // The library handle (fcgmg_h) is the context of one hierarchy.

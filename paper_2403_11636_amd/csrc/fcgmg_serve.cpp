@@ -7,10 +7,15 @@
 // policy the server picks the fastest of the three policies of Sec. 3.1.2 whose footprint fits
 // (cache_inverse, cache_matrix, cache_none). Requests with the same problem reuse one hierarchy,
 // one solve at a time (its level buffers are scratch of the solve).
+//
+// Continuous batching: a request that the batched cycle takes is only set up by its worker; it then
+// joins the running batch of an engine thread, which advances every joined request by one V-cycle
+// per step in shared launches (fcgmg_batch.cpp) and retires each as it meets its stopping test.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -58,6 +63,8 @@ struct Request {
   Clock::time_point t_submit, t_start, t_setup_done, t_done;
   bool done = false;
   fcgmg_request_result res{};
+  Entry* entry = nullptr;  // the hierarchy it runs on (batched requests: while in the batch)
+  double r0 = 0;           // initial residual norm (batched requests)
 };
 
 std::string problem_key(const fcgmg_params& p, const std::vector<double>& balls) {
@@ -81,6 +88,123 @@ struct fcgmg_server {
   uint64_t tick = 0;
   bool stop = false;
   std::vector<std::thread> workers;
+  // continuous batching
+  std::deque<Request*> joining;  // set up, waiting to join the batch
+  std::condition_variable cv_engine;
+  bool engine_stop = false;
+  std::thread engine;
+  int64_t engine_steps = 0, engine_request_cycles = 0;
+  int engine_max_batch = 0;
+
+  // Completion of a request under the lock: results, timings, its hierarchy released.
+  void finish_locked(Request* r, int rc) {
+    r->t_done = Clock::now();
+    r->res.status = rc;
+    r->res.t_queue_ms = ms_since(r->t_submit, r->t_start);
+    r->res.t_setup_ms = ms_since(r->t_start, r->t_setup_done);
+    r->res.t_solve_ms = ms_since(r->t_setup_done, r->t_done);
+    r->res.t_total_ms = ms_since(r->t_submit, r->t_done);
+    if (Entry* e = r->entry) {
+      e->busy = false;
+      e->last_use = ++tick;
+    }
+    r->done = true;
+  }
+
+  void engine_loop() {
+    (void)hipSetDevice(device);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    fcgmg_batch* bt = nullptr;
+    (void)batch_engine_create(&bt);
+    std::vector<Request*> active;
+    for (;;) {
+      std::vector<Request*> join;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_engine.wait(lk, [&] { return !joining.empty() || !active.empty() || engine_stop; });
+        if (joining.empty() && active.empty() && engine_stop) break;
+        join.assign(joining.begin(), joining.end());
+        joining.clear();
+      }
+      std::vector<Request*> retire;
+      std::vector<int> codes;
+      auto vecs = [](const std::vector<Request*>& rs, std::vector<fcgmg_ctx*>& hs, std::vector<double*>& xs,
+                     std::vector<const double*>& bs) {
+        hs.clear();
+        xs.clear();
+        bs.clear();
+        for (Request* r : rs) {
+          hs.push_back(r->entry->h);
+          xs.push_back(r->x);
+          bs.push_back(r->entry->b);
+        }
+      };
+      std::vector<fcgmg_ctx*> hs;
+      std::vector<double*> xs;
+      std::vector<const double*> bs;
+      std::vector<double> nrm;
+      if (!join.empty()) {  // initial residual norms of the joining requests
+        vecs(join, hs, xs, bs);
+        const int rc = batch_engine_step(bt, hs, xs.data(), bs.data(), false, s, nrm);
+        for (size_t k = 0; k < join.size(); ++k) {
+          Request* r = join[k];
+          if (rc != FCGMG_OK || !std::isfinite(nrm[k])) {
+            retire.push_back(r);
+            codes.push_back(rc != FCGMG_OK ? rc : set_error(FCGMG_E_NAN, "server: non-finite initial residual"));
+          } else if (nrm[k] == 0.0) {
+            retire.push_back(r);
+            codes.push_back(FCGMG_OK);
+          } else {
+            r->r0 = nrm[k];
+            active.push_back(r);
+          }
+        }
+      }
+      if (!active.empty()) {  // one V-cycle of every request in the batch
+        vecs(active, hs, xs, bs);
+        const int rc = batch_engine_step(bt, hs, xs.data(), bs.data(), true, s, nrm);
+        std::vector<Request*> keep;
+        for (size_t k = 0; k < active.size(); ++k) {
+          Request* r = active[k];
+          r->res.iters += 1;
+          if (rc != FCGMG_OK) {
+            retire.push_back(r);
+            codes.push_back(rc);
+            continue;
+          }
+          r->res.rel_res = nrm[k] / r->r0;
+          if (!std::isfinite(nrm[k])) {
+            retire.push_back(r);
+            codes.push_back(set_error(FCGMG_E_NAN, "server: non-finite residual"));
+          } else if (nrm[k] <= r->rtol * r->r0) {
+            retire.push_back(r);
+            codes.push_back(FCGMG_OK);
+          } else if (r->res.iters >= sp.max_iter) {
+            retire.push_back(r);
+            codes.push_back(set_error(FCGMG_E_NOCONV, "server: cycle limit reached"));
+          } else {
+            keep.push_back(r);
+          }
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ++engine_steps;
+        engine_request_cycles += (int64_t)active.size();
+        engine_max_batch = std::max(engine_max_batch, (int)active.size());
+        active.swap(keep);
+      }
+      if (!retire.empty()) {
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (size_t k = 0; k < retire.size(); ++k) finish_locked(retire[k], codes[k]);
+        }
+        cv_done.notify_all();
+        cv_work.notify_all();
+      }
+    }
+    batch_engine_destroy(bt);
+    if (s) (void)hipStreamDestroy(s);
+  }
 
   // Pick the entry for `r` under the lock: a resident idle hierarchy of the same problem, or a new
   // one admitted within the budget (evicting idle ones). Returns nullptr when `r` has to wait; sets
@@ -192,9 +316,27 @@ struct fcgmg_server {
           if (rc == FCGMG_OK) rc = fcgmg_rhs(e->h, r->prm.n_levels - 1, e->b, s);
           if (rc == FCGMG_OK) e->ready = true;
         }
-        r->t_setup_done = Clock::now();
         if (rc == FCGMG_OK && hipMemsetAsync(r->x, 0, e->ndof * sizeof(double), s) != hipSuccess)
           rc = set_error(FCGMG_E_HIP, "server: clearing x failed");
+        fcgmg_params pr = r->prm;
+        pr.cache_policy = e->policy;
+        if (rc == FCGMG_OK && sp.continuous_batching && batch_engine_accepts(pr)) {
+          // set-up, right-hand side and x = 0 complete before the engine's stream reads them
+          if (hipStreamSynchronize(s) != hipSuccess) {
+            rc = set_error(FCGMG_E_HIP, "server: stream synchronisation failed");
+          } else {
+            r->t_setup_done = Clock::now();
+            r->res.footprint = e->bytes;
+            r->entry = e;
+            {
+              std::lock_guard<std::mutex> lk(mu);
+              joining.push_back(r);
+            }
+            cv_engine.notify_one();
+            continue;  // the engine completes it
+          }
+        }
+        r->t_setup_done = Clock::now();
         if (rc == FCGMG_OK)
           rc = fcgmg_solve(e->h, r->x, e->b, r->rtol, sp.max_iter, &r->res.iters, &r->res.rel_res, nullptr, s);
         if (hipStreamSynchronize(s) != hipSuccess && rc == FCGMG_OK)
@@ -203,17 +345,11 @@ struct fcgmg_server {
       } else {
         r->t_setup_done = r->t_start;
       }
-      r->t_done = Clock::now();
       {
         std::lock_guard<std::mutex> lk(mu);
-        r->res.status = rc;
-        r->res.t_queue_ms = ms_since(r->t_submit, r->t_start);
-        r->res.t_setup_ms = ms_since(r->t_start, r->t_setup_done);
-        r->res.t_solve_ms = ms_since(r->t_setup_done, r->t_done);
-        r->res.t_total_ms = ms_since(r->t_submit, r->t_done);
+        r->entry = e;
+        finish_locked(r, rc);
         if (e) {
-          e->busy = false;
-          e->last_use = ++tick;
           if (!e->ready) {  // failed set-up: give its reservation back
             in_use -= e->bytes;
             if (e->h) fcgmg_destroy(e->h);
@@ -222,7 +358,6 @@ struct fcgmg_server {
                                        [&](const std::unique_ptr<Entry>& u) { return u.get() == e; }));
           }
         }
-        r->done = true;
       }
       cv_done.notify_all();
       cv_work.notify_all();
@@ -252,7 +387,12 @@ int fcgmg_server_create(const fcgmg_server_params* sp, fcgmg_server_h* out) {
     }
     srv->sp.hbm_budget = (int64_t)(0.8 * (double)free_b);
   }
+  if (sp->continuous_batching != 0 && sp->continuous_batching != 1) {
+    delete srv;
+    return set_error(FCGMG_E_ARG, "continuous_batching must be 0 or 1");
+  }
   for (int i = 0; i < sp->workers; ++i) srv->workers.emplace_back([srv] { srv->worker_loop(); });
+  if (sp->continuous_batching) srv->engine = std::thread([srv] { srv->engine_loop(); });
   *out = srv;
   return FCGMG_OK;
 }
@@ -311,6 +451,15 @@ int fcgmg_server_resident_bytes(fcgmg_server_h srv, int64_t* bytes, int* hierarc
   return FCGMG_OK;
 }
 
+int fcgmg_server_stats(fcgmg_server_h srv, int64_t* steps, int64_t* request_cycles, int* max_batch) {
+  if (!srv || !steps || !request_cycles || !max_batch) return set_error(FCGMG_E_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  *steps = srv->engine_steps;
+  *request_cycles = srv->engine_request_cycles;
+  *max_batch = srv->engine_max_batch;
+  return FCGMG_OK;
+}
+
 int fcgmg_server_destroy(fcgmg_server_h srv) {
   if (!srv) return FCGMG_OK;
   {
@@ -319,6 +468,14 @@ int fcgmg_server_destroy(fcgmg_server_h srv) {
   }
   srv->cv_work.notify_all();
   for (auto& t : srv->workers) t.join();
+  if (srv->engine.joinable()) {  // the workers have handed over every batched request
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->engine_stop = true;
+    }
+    srv->cv_engine.notify_all();
+    srv->engine.join();
+  }
   for (auto& e : srv->entries) {
     if (e->b) (void)hipFree(e->b);
     if (e->h) fcgmg_destroy(e->h);

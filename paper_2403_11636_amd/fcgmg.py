@@ -28,6 +28,7 @@ EXPORTS = [
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
+    "fcgmg_server_stats",
     "fcgmg_server_destroy", "fcgmg_batch_create", "fcgmg_batch_vcycle", "fcgmg_batch_solve",
     "fcgmg_batch_destroy",
 ]
@@ -54,7 +55,8 @@ class Params(ctypes.Structure):
 
 
 class ServerParams(ctypes.Structure):
-    _fields_ = [("workers", ctypes.c_int), ("max_iter", ctypes.c_int), ("hbm_budget", ctypes.c_int64)]
+    _fields_ = [("workers", ctypes.c_int), ("max_iter", ctypes.c_int), ("hbm_budget", ctypes.c_int64),
+                ("continuous_batching", ctypes.c_int)]
 
 
 class RequestResult(ctypes.Structure):
@@ -107,6 +109,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_server_submit.argtypes = [vp, ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.c_double, vp, i64p]
     L.fcgmg_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(RequestResult)]
     L.fcgmg_server_resident_bytes.argtypes = [vp, i64p, ctypes.POINTER(ctypes.c_int)]
+    L.fcgmg_server_stats.argtypes = [vp, i64p, i64p, ctypes.POINTER(ctypes.c_int)]
     L.fcgmg_server_destroy.argtypes = [vp]
     L.fcgmg_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
     L.fcgmg_batch_vcycle.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
@@ -374,13 +377,13 @@ class Server:
     device-memory footprint. submit() queues a problem and returns an id; wait(id) returns the
     solution tensor and the request's result fields."""
 
-    def __init__(self, workers: int = 4, hbm_budget: int = 0, max_iter: int = 200):
+    def __init__(self, workers: int = 4, hbm_budget: int = 0, max_iter: int = 200, continuous_batching: int = 1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("fcgmg needs a GPU; none is visible")
         _init_device()
         L = load()
-        sp = ServerParams(workers, max_iter, hbm_budget)
+        sp = ServerParams(workers, max_iter, hbm_budget, continuous_batching)
         h = ctypes.c_void_p()
         _check(L.fcgmg_server_create(ctypes.byref(sp), ctypes.byref(h)))
         self.h = h
@@ -411,6 +414,14 @@ class Server:
         n = ctypes.c_int()
         _check(load().fcgmg_server_resident_bytes(self.h, ctypes.byref(b), ctypes.byref(n)))
         return b.value, n.value
+
+    def stats(self):
+        """Continuous batching so far: (batched cycle steps, request-cycles, largest batch)."""
+        s = ctypes.c_int64()
+        rc = ctypes.c_int64()
+        mb = ctypes.c_int()
+        _check(load().fcgmg_server_stats(self.h, ctypes.byref(s), ctypes.byref(rc), ctypes.byref(mb)))
+        return s.value, rc.value, mb.value
 
     def close(self):
         if getattr(self, "h", None):

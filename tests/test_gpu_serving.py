@@ -1,6 +1,9 @@
 """The solve server (fcgmg_server_*): each result is the same alone and in a concurrent mix, admission
 by device-memory footprint picks a policy that fits or waits, and a request that can never fit is
-rejected. Results are compared bit for bit with a solve of the same problem on its own hierarchy."""
+rejected. With continuous batching, the 2D cache_inverse FP64 V(2,2) requests share the batched
+cycle: their results equal, bit for bit, those of the same request served alone; the others run
+fcgmg_solve and equal a solve of the problem on its own hierarchy. Every served iterate meets the
+tolerance in the oracle's FP64 residual."""
 import numpy as np
 import pytest
 
@@ -31,6 +34,24 @@ def mix():
     return probs + [probs[1], probs[3], probs[0], probs[2]]
 
 
+def serve_alone(prob, policy, precision, continuous_batching=1):
+    f = fcg()
+    srv = f.Server(workers=1, continuous_batching=continuous_batching)
+    x, res = srv.wait(srv.submit(prob, policy=policy, precision=precision))
+    srv.close()
+    return x.cpu().numpy(), res
+
+
+def batched(prob, policy, precision):
+    return prob.dim == 2 and policy == fcg().CACHE_INVERSE and precision == fcg().PREC_FP64
+
+
+def check_oracle_residual(prob, x):
+    o = Oracle(prob)
+    b = o.rhs()
+    assert np.linalg.norm(o.residual(o.fine, x, b)) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-4)
+
+
 def solve_alone(prob, policy, precision):
     f = fcg()
     h = f.Hierarchy(prob, policy, precision=precision)
@@ -51,16 +72,50 @@ def test_results_same_alone_and_in_mix():
         assert res["status"] == f.OK and res["rel_res"] <= 1e-8
         assert res["policy"] == f.CACHE_INVERSE  # everything fits the default budget
         hits += res["cache_hit"]
-        xa, it = solve_alone(p, res["policy"], prec)
-        assert res["iters"] == it
-        assert np.array_equal(x.cpu().numpy(), xa)
-        # the oracle's FP64 residual of the served iterate meets the tolerance (its right-hand side
-        # equals the library's to 1e-13)
-        o = Oracle(p)
-        b = o.rhs()
-        assert np.linalg.norm(o.residual(o.fine, x.cpu().numpy(), b)) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-4)
+        xs = x.cpu().numpy()
+        # the same request alone in a server: the same bits
+        xa, ra = serve_alone(p, res["policy"], prec)
+        assert ra["iters"] == res["iters"]
+        assert np.array_equal(xs, xa)
+        # against the problem's own fcgmg_solve
+        xo, it = solve_alone(p, res["policy"], prec)
+        if batched(p, res["policy"], prec):
+            assert abs(res["iters"] - it) <= 1
+            if res["iters"] == it:
+                assert np.array_equal(xs, xo)
+        else:
+            assert res["iters"] == it and np.array_equal(xs, xo)
+        check_oracle_residual(p, xs)
     assert hits >= 1
+    steps, cycles, _ = srv.stats()
+    assert steps >= 1 and cycles >= steps
     srv.close()
+
+
+def test_continuous_batching_shares_launches():
+    # eight 2D problems submitted at once: their cycles run in shared launches (the largest batch
+    # holds several requests), and each result equals the one the request gets alone
+    f = fcg()
+    probs = [inputs.small_problem(2, 64, 4, seed=20 + k, n_balls=3, rmin=0.03, rmax=0.08) for k in range(8)]
+    srv = f.Server(workers=8)
+    ids = [srv.submit(p) for p in probs]
+    outs = [srv.wait(i) for i in ids]
+    steps, cycles, max_batch = srv.stats()
+    srv.close()
+    assert max_batch >= 2 and cycles > steps, (steps, cycles, max_batch)
+    for p, (x, res) in zip(probs, outs):
+        assert res["status"] == f.OK and res["rel_res"] <= 1e-8
+        xa, ra = serve_alone(p, f.CACHE_INVERSE, f.PREC_FP64)
+        assert ra["iters"] == res["iters"] and np.array_equal(x.cpu().numpy(), xa)
+        check_oracle_residual(p, x.cpu().numpy())
+
+
+def test_without_batching_results_equal_fcgmg_solve():
+    f = fcg()
+    p = inputs.small_problem(2, 32, 3, seed=1, n_balls=3, rmin=0.05, rmax=0.1)
+    xs, res = serve_alone(p, f.CACHE_INVERSE, f.PREC_FP64, continuous_batching=0)
+    xo, it = solve_alone(p, f.CACHE_INVERSE, f.PREC_FP64)
+    assert res["iters"] == it and np.array_equal(xs, xo)
 
 
 def test_policy_chosen_under_memory_pressure():
@@ -91,8 +146,9 @@ def test_one_resident_at_a_time_and_rejection():
     for rid, p in zip(ids, probs):
         x, res = srv.wait(rid)
         assert res["status"] == f.OK and res["rel_res"] <= 1e-8
-        xa, _ = solve_alone(p, f.CACHE_INVERSE, f.PREC_FP64)
+        xa, _ = serve_alone(p, f.CACHE_INVERSE, f.PREC_FP64)
         assert np.array_equal(x.cpu().numpy(), xa)
+        check_oracle_residual(p, x.cpu().numpy())
     _, res = srv.wait(bad)
     assert res["status"] == f.E_NOMEM
     b, n = srv.resident()
