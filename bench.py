@@ -492,6 +492,49 @@ def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0, n_war
     }
 
 
+def serving_batched_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=8, n_pool=32, seed=1):
+    """Continuous batching: standalone GMG solves (V(2,2), FP64, cache_inverse, tolerance 1e-8) drawn
+    from `n_pool` problems of the batching workload (2D, 64^2..256^2, 1..12 discs, alpha_f in
+    {1e-6, 1e-8, 1e-10}), served with continuous batching on and off on the same request sequence,
+    each from a cold start: a Poisson stream of `rate` requests per second, and the same requests
+    submitted at once (a burst, which saturates the server). Latency is submit to completion."""
+    out = {"requests": n_req, "workers": workers, "pool": n_pool,
+           "poisson": serving_batched_run(fcgmg, inputs, n_req, rate, workers, n_pool, seed),
+           "burst": serving_batched_run(fcgmg, inputs, n_req, None, workers, n_pool, seed)}
+    out["poisson"]["arrival_rate_per_s"] = rate
+    return out
+
+
+def serving_batched_run(fcgmg, inputs, n_req, rate, workers, n_pool, seed):
+    rng = np.random.default_rng(seed)
+    pool = [inputs.batch_problem(k) for k in range(n_pool)]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req)) if rate else np.zeros(n_req)
+    picks = rng.integers(0, n_pool, n_req)
+    out = {}
+    for mode in (1, 0):
+        srv = fcgmg.Server(workers=workers, continuous_batching=mode)
+        t0 = time.perf_counter()
+        ids = []
+        for k in range(n_req):
+            delay = t0 + arrivals[k] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(pool[picks[k]], policy=fcgmg.CACHE_INVERSE))
+        res = [srv.wait(i)[1] for i in ids]
+        wall = time.perf_counter() - t0
+        steps, cycles, max_batch = srv.stats()
+        srv.close()
+        ok = [r for r in res if r["status"] == fcgmg.OK]
+        lat = [r["t_total_ms"] for r in ok]
+        out["batching_on" if mode else "batching_off"] = {
+            "completed": len(ok), "throughput_req_per_s": round(len(ok) / wall, 2),
+            "latency_ms_p50": round(pct(lat, 50), 2), "latency_ms_p99": round(pct(lat, 99), 2),
+            "cache_hits": int(sum(r["cache_hit"] for r in ok)), "max_rel_res": float(max(r["rel_res"] for r in ok)),
+            "wall_s": round(wall, 2), "batched_steps": steps, "request_cycles": cycles,
+            "mean_batch": round(cycles / steps, 2) if steps else None, "max_batch": max_batch}
+    return out
+
+
 def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
     """Batching workload: 256 independent 2D problems of uneven sizes (64^2..256^2, 1..12 discs,
     alpha_f in {1e-6, 1e-8, 1e-10}). Hierarchies are set up first (untimed). Measured: FGMRES(30)
@@ -785,6 +828,8 @@ def main():
         out["batching"] = batch_extra(torch, fcgmg, inputs)
         log("serving ...")
         out["serving"] = serving_extra(fcgmg, inputs)
+        log("serving with continuous batching ...")
+        out["serving_batched"] = serving_batched_extra(fcgmg, inputs)
         log("2D 4096^2 ...")
         big = inputs.config2(0, n_cells=4096, n_levels=10)
         big.name = "2d_20discs_4096_seed0"

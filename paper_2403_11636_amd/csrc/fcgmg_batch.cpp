@@ -73,12 +73,15 @@ struct fcgmg_batch {
     launches.push_back(L);
   }
 
-  // Copy the tables into the device buffer (one transfer) and run the recorded launches.
-  int run(hipStream_t s) {
+  // Copy the tables into the device buffer (one transfer) and run the recorded launches. The host
+  // staging buffer is reused, so the previous transfer must be complete: `synced` says the caller
+  // has synchronised the stream since the last run; otherwise run waits for it first.
+  int run(hipStream_t s, bool synced = false) {
     const size_t o_f = 0, o_r = o_f + fj.size() * sizeof(fj[0]), o_d = o_r + rj.size() * sizeof(rj[0]),
                  o_n = o_d + dj.size() * sizeof(dj[0]), o_b = o_n + nj.size() * sizeof(nj[0]),
                  total = o_b + bj.size() * sizeof(int);
-    if (hipStreamSynchronize(s) != hipSuccess) return set_error(FCGMG_E_HIP, "batch: stream synchronisation failed");
+    if (!synced && hipStreamSynchronize(s) != hipSuccess)
+      return set_error(FCGMG_E_HIP, "batch: stream synchronisation failed");
     if (total > buf_cap) {
       if (host_buf) (void)hipHostFree(host_buf);
       if (dev_buf) (void)hipFree(dev_buf);
@@ -322,16 +325,23 @@ int batch_engine_create(fcgmg_batch** out) {
 
 int batch_engine_step(fcgmg_batch* bt, const std::vector<fcgmg_ctx*>& hs, double* const* x, const double* const* b,
                       bool cycle, hipStream_t s, std::vector<double>& norms) {
+  // the cycle and the norms in one table, one transfer and one synchronisation (the engine
+  // synchronises at the end of every step, so the staging buffer is free when the next one starts)
   bt->hs = hs;
   std::vector<int> act(hs.size());
   for (size_t i = 0; i < act.size(); ++i) act[i] = (int)i;
+  bt->clear();
+  if (cycle) bt->record_vcycle(act, x, b);
+  bt->record_norms(act, x, b);
   int rc;
-  if (cycle) {
-    bt->clear();
-    bt->record_vcycle(act, x, b);
-    if ((rc = bt->run(s))) return rc;
-  }
-  return bt->norms_of(act, x, b, s, norms);
+  if ((rc = bt->ensure_norm_space((int)bt->bj.size(), (int)act.size()))) return rc;
+  if ((rc = bt->run(s, true))) return rc;
+  if (hipMemcpyAsync(bt->norms_host, bt->norms, act.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(FCGMG_E_HIP, "batch: norm read-back failed");
+  norms.assign(bt->norms_host, bt->norms_host + act.size());
+  for (double& v : norms) v = std::sqrt(v);
+  return FCGMG_OK;
 }
 
 void batch_engine_destroy(fcgmg_batch* bt) { fcgmg_batch_destroy(bt); }
