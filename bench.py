@@ -650,6 +650,34 @@ def workload_extra(torch, fcgmg, prob, steps=20, warmup=3):
     return res
 
 
+def autotune_extra(torch, fcgmg, prob, reps=20, steps=20):
+    """Fused-sweep tile shapes: the V-cycle with the default shapes by level size, then the library's
+    autotuner (every shape timed per level, the fastest kept) and the V-cycle again."""
+    h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
+    b = h.rhs()
+    x = h.zeros()
+    for _ in range(3):
+        h.vcycle(x, b)
+    ms_default, _ = time_vcycles(torch, h, x, b, steps)
+    t0 = time.perf_counter()
+    res = h.autotune(reps=reps)
+    tune_s = time.perf_counter() - t0
+    for _ in range(3):
+        h.vcycle(x, b)
+    ms_tuned, _ = time_vcycles(torch, h, x, b, steps)
+    shapes = [fcgmg.fused_shape(k) for k in range(fcgmg.N_FUSED_SHAPES)]
+    levels = []
+    for lev in range(1, h.n_levels):
+        us = res["us"][lev]
+        k = res["shape"][lev]
+        levels.append({"level": lev, "n_cells": prob.level_cells(lev), "tuned": list(shapes[k]),
+                       "us_per_shape": [round(u, 2) for u in us]})
+    h.close()
+    return {"workload": prob.name, "shapes_tile_x_tile_y_threads_waves_per_simd": [list(s) for s in shapes],
+            "reps": reps, "tune_s": round(tune_s, 3), "vcycle_ms_default": round(ms_default, 4),
+            "vcycle_ms_tuned": round(ms_tuned, 4), "levels": levels}
+
+
 def stacked_extra(torch, fcgmg, prob, nrhs=8, reps=5):
     """Stacked right-hand sides on one geometry: two sweeps of nrhs vectors through fcgmg_smooth_multi
     (each streamed patch's rows read once per sweep for all vectors) against nrhs separate two-sweep
@@ -835,6 +863,8 @@ def main():
         big.name = "2d_20discs_4096_seed0"
         out["extra_2d_4096"] = workload_extra(torch, fcgmg, big)
         out["roofline_4096"] = out["extra_2d_4096"]["roofline"]
+        log("fused-sweep shape autotuning ...")
+        out["autotune"] = [autotune_extra(torch, fcgmg, prob), autotune_extra(torch, fcgmg, big, reps=10)]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(prob)

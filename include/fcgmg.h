@@ -218,6 +218,28 @@ int fcgmg_profile_enable(fcgmg_h h, int on);
 int fcgmg_profile_reset(fcgmg_h h);
 int fcgmg_profile_read(fcgmg_h h, int kind, int level, double* total_ms, int64_t* launches);
 
+/* Tile-shape autotuner of the fused 2D sweep (FCGMG_K_SWEEP_FUSED; 2D cache_inverse only). The
+ * sweep covers the level's nodes in tiles of tile_x x tile_y nodes, one workgroup of `threads` per
+ * tile plus extra workgroups for tiles with many individually stored patches, compiled for at least
+ * `waves_per_simd` resident wavefronts per SIMD (which bounds its registers per lane);
+ * fcgmg_fused_shape(k, ...) gives these four numbers of shape k, for k in [0, 8). Set-up picks a
+ * shape by level size.
+ * fcgmg_autotune times `reps` (1..1000) pairs of fused sweeps with every shape on every level above
+ * the coarsest (on scratch vectors it allocates and frees; the level's own vectors are untouched),
+ * keeps the fastest shape per level and rebuilds that level's extra-workgroup plan. Every shape
+ * computes the same numbers in the same order: results are bitwise those of the default shapes.
+ * shape_out: host array of n_levels ints, the shape index per level afterwards (-1 = default by
+ * size; levels without the fused sweep keep -1). us_out: NULL or a host array of n_levels * 8
+ * doubles, microseconds per sweep of level l with shape k at [l * 8 + k] (-1 where not timed).
+ * Synchronises `stream`; must not overlap other work on the handle. The plan buffer may grow, so
+ * fcgmg_device_bytes can exceed fcgmg_footprint_bytes afterwards by a few KiB.
+ * Errors: E_ARG (bad handle, pointer or reps), E_NOMEM, E_HIP. */
+int fcgmg_autotune(fcgmg_h h, int reps, int* shape_out, double* us_out, void* stream);
+int fcgmg_fused_shape(int k, int* tile_x, int* tile_y, int* threads, int* waves_per_simd);
+/* Apply a stored choice: shape k (-1 = default by size) on one level, plan rebuilt. Synchronises
+ * `stream`. Errors: E_ARG (bad level or k, or a level without the fused sweep), E_NOMEM, E_HIP. */
+int fcgmg_set_fused_shape(fcgmg_h h, int level, int k, void* stream);
+
 /* Device bytes held by the handle (all levels, all policy data). */
 int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
 

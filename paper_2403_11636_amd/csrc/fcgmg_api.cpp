@@ -564,6 +564,7 @@ int setup_impl(Ctx& c, hipStream_t s) {
     if (D == 2 && P.cache_policy == FCGMG_CACHE_INVERSE) {
       plan_fused2(L, ncls, extra);
       L.n_fused_extra = (int)extra.size();
+      L.fused_extra_cap = L.n_fused_extra;
       if (L.n_fused_extra) {
         if ((rc = alloc_n(c, &L.fused_extra, extra.size()))) return rc;
         FCG_HIP(hipMemcpyAsync(L.fused_extra, extra.data(), extra.size() * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1015,6 +1016,136 @@ int norm_impl(const Ctx& c, const double* v, int64_t n, double* out, hipStream_t
   return FCGMG_OK;
 }
 
+// Device buffers of the autotuner, freed on every exit path.
+struct TuneBuffers {
+  std::vector<void*> p;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~TuneBuffers() {
+    for (void* q : p) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+// Time `reps` pairs of fused sweeps on level l with the level's current shape and plan; returns
+// microseconds per sweep.
+int time_fused_pairs(const Ctx& c, const Level& L, double* x, const double* b, double* y, int reps, TuneBuffers& tb,
+                     hipStream_t s, double* us) {
+  for (int w = 0; w < 2; ++w) {
+    FCG_HIP(k_sweep_fused2<double>(c, L, x, b, y, 0, nullptr, s));
+    FCG_HIP(k_sweep_fused2<double>(c, L, y, b, x, 0, nullptr, s));
+  }
+  FCG_HIP(hipEventRecord(tb.e0, s));
+  for (int r = 0; r < reps; ++r) {
+    FCG_HIP(k_sweep_fused2<double>(c, L, x, b, y, 0, nullptr, s));
+    FCG_HIP(k_sweep_fused2<double>(c, L, y, b, x, 0, nullptr, s));
+  }
+  FCG_HIP(hipEventRecord(tb.e1, s));
+  FCG_HIP(hipEventSynchronize(tb.e1));
+  float ms = 0.f;
+  FCG_HIP(hipEventElapsedTime(&ms, tb.e0, tb.e1));
+  *us = 1e3 * ms / (2.0 * reps);
+  return FCGMG_OK;
+}
+
+// Upload the extra-workgroup plan of shape k for level L into its (grown if needed) plan buffer.
+int install_fused_plan(Ctx& c, Level& L, int k, const std::vector<int>& extra, hipStream_t s) {
+  if ((int)extra.size() > L.fused_extra_cap) {
+    int* grown = nullptr;
+    int rc;
+    if ((rc = alloc_n(c, &grown, extra.size()))) return rc;
+    if (L.fused_extra) {
+      auto it = std::find(c.allocs.begin(), c.allocs.end(), (void*)L.fused_extra);
+      if (it != c.allocs.end()) c.allocs.erase(it);
+      FCG_HIP(hipStreamSynchronize(s));
+      FCG_HIP(hipFree(L.fused_extra));
+      c.bytes -= (size_t)L.fused_extra_cap * sizeof(int);
+    }
+    L.fused_extra = grown;
+    L.fused_extra_cap = (int)extra.size();
+  }
+  L.fshape = k;
+  L.n_fused_extra = (int)extra.size();
+  if (!extra.empty()) {
+    FCG_HIP(hipMemcpyAsync(L.fused_extra, extra.data(), extra.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    FCG_HIP(hipStreamSynchronize(s));  // `extra` is the caller's host vector
+  }
+  return FCGMG_OK;
+}
+
+// Per 2D cache_inverse level below the coarsest: time the fused sweep with every tile shape on a
+// vector of the level's size (the sweep's cost depends on the patch layout, not on the values) and
+// keep the fastest. All shapes compute the same numbers, so only the time changes.
+int autotune_impl(Ctx& c, int reps, int* shape_out, double* us_out, hipStream_t s) {
+  const int ns = fused2_num_shapes(), nlev = (int)c.lev.size();
+  for (int l = 0; l < nlev; ++l) {
+    shape_out[l] = c.lev[l].fshape;
+    if (us_out)
+      for (int k = 0; k < ns; ++k) us_out[(size_t)l * ns + k] = -1.0;
+  }
+  if (c.prm.dim != 2 || c.prm.cache_policy != FCGMG_CACHE_INVERSE) return FCGMG_OK;
+  TuneBuffers tb;
+  FCG_HIP(hipEventCreate(&tb.e0));
+  FCG_HIP(hipEventCreate(&tb.e1));
+  int rc;
+  for (int l = 1; l < nlev; ++l) {
+    Level& L = c.lev[l];
+    if (!L.xalt) continue;
+    const size_t nd = (size_t)3 * (size_t)L.N;
+    double* v[3] = {nullptr, nullptr, nullptr};
+    for (double*& q : v) {
+      hipError_t e = hipMalloc((void**)&q, nd * sizeof(double));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FCGMG_E_NOMEM, "autotune: hipMalloc of " + std::to_string(nd * sizeof(double)) + " bytes failed");
+      }
+      tb.p.push_back(q);
+    }
+    FCG_HIP(hipMemsetAsync(v[0], 0, nd * sizeof(double), s));
+    FCG_HIP(hipMemsetAsync(v[1], 0x3f, nd * sizeof(double), s));  // every double 0x3f3f...: finite, positive
+    std::vector<int> ncls((size_t)L.N);
+    FCG_HIP(hipMemcpyAsync(ncls.data(), L.node_class, ncls.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    FCG_HIP(hipStreamSynchronize(s));
+    int best = -1;
+    double best_us = 0.0;
+    std::vector<int> extra;
+    for (int k = 0; k < ns; ++k) {
+      L.fshape = k;
+      plan_fused2(L, ncls, extra);
+      if ((rc = install_fused_plan(c, L, k, extra, s))) return rc;
+      double us = 0.0;
+      if ((rc = time_fused_pairs(c, L, v[0], v[1], v[2], reps, tb, s, &us))) return rc;
+      if (us_out) us_out[(size_t)l * ns + k] = us;
+      if (best < 0 || us < best_us) {
+        best = k;
+        best_us = us;
+      }
+    }
+    L.fshape = best;
+    plan_fused2(L, ncls, extra);
+    if ((rc = install_fused_plan(c, L, best, extra, s))) return rc;
+    shape_out[l] = best;
+    for (double* q : v) {
+      tb.p.erase(std::find(tb.p.begin(), tb.p.end(), (void*)q));
+      FCG_HIP(hipFree(q));
+    }
+  }
+  return FCGMG_OK;
+}
+
+// Give level l fused-sweep shape k (-1: default by size) and rebuild its plan.
+int set_fused_shape_impl(Ctx& c, int l, int k, hipStream_t s) {
+  Level& L = c.lev[l];
+  if (c.prm.dim != 2 || c.prm.cache_policy != FCGMG_CACHE_INVERSE || !L.xalt)
+    return fail(FCGMG_E_ARG, "the fused sweep runs on 2D cache_inverse levels only");
+  std::vector<int> ncls((size_t)L.N), extra;
+  FCG_HIP(hipMemcpyAsync(ncls.data(), L.node_class, ncls.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  FCG_HIP(hipStreamSynchronize(s));
+  L.fshape = k;
+  plan_fused2(L, ncls, extra);
+  return install_fused_plan(c, L, k, extra, s);
+}
+
 bool valid_level(const Ctx* c, int l) { return c && l >= 0 && l < (int)c->lev.size(); }
 
 }  // namespace
@@ -1288,6 +1419,24 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
   }
   return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
                                   std::to_string(*rel_res) + ")");
+}
+
+int fcgmg_autotune(fcgmg_h h, int reps, int* shape_out, double* us_out, void* stream) {
+  if (!h || !shape_out || reps < 1 || reps > 1000) return fail(FCGMG_E_ARG, "bad handle, pointer or reps (1..1000)");
+  return autotune_impl(*h, reps, shape_out, us_out, (hipStream_t)stream);
+}
+
+int fcgmg_set_fused_shape(fcgmg_h h, int level, int k, void* stream) {
+  if (!valid_level(h, level) || k < -1 || k >= fused2_num_shapes())
+    return fail(FCGMG_E_ARG, "bad handle, level or shape index");
+  return set_fused_shape_impl(*h, level, k, (hipStream_t)stream);
+}
+
+int fcgmg_fused_shape(int k, int* tile_x, int* tile_y, int* threads, int* waves_per_simd) {
+  if (k < 0 || k >= fused2_num_shapes() || !tile_x || !tile_y || !threads || !waves_per_simd)
+    return fail(FCGMG_E_ARG, "shape index out of range or null pointer");
+  fused2_shape_dims(k, tile_x, tile_y, threads, waves_per_simd);
+  return FCGMG_OK;
 }
 
 int fcgmg_profile_enable(fcgmg_h h, int on) {

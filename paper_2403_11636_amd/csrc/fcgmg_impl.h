@@ -113,6 +113,8 @@ struct Level {
   int64_t n_nsten = 0;
   int* fused_extra = nullptr;  // 2D cache_inverse: extra workgroups of heavy tiles (plan_fused2)
   int n_fused_extra = 0;
+  int fused_extra_cap = 0;     // ints allocated for fused_extra
+  int fshape = -1;             // fused-sweep tile shape chosen by fcgmg_autotune, -1: default by size
   int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
   int64_t n_zrows = 0;        // streamed row blocks (n_irr, fewer where wall patches share rows)
   int* irr_nodes = nullptr;   // centre node of each streamed (irregular) patch
@@ -504,6 +506,8 @@ template <class T>
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
                           hipStream_t s);
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra);
+int fused2_num_shapes();
+void fused2_shape_dims(int k, int* tx, int* ty, int* nt, int* wpe);
 // Batched launches over independent 2D problems (one tile shape for all jobs)
 int batch_fused2_blocks(const Level& L);
 Fused2Job<double> batch_fused2_job(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,

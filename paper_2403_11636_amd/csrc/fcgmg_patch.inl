@@ -1577,10 +1577,28 @@ constexpr int64_t kFusedBigTileNodes = 200000;
 constexpr int64_t kFusedMidTileNodes = 30000;
 struct Fused2Shape {
   int tx, ty, nt;
+  int wpe;  // minimum waves per SIMD the compiler must allow (bounds the registers per lane)
 };
-constexpr Fused2Shape kFusedBig{32, 8, 256}, kFusedMid{8, 4, 128}, kFusedSmall{4, 4, 128};
+constexpr Fused2Shape kFusedBig{32, 8, 256, 5}, kFusedMid{8, 4, 128, 5}, kFusedSmall{4, 4, 128, 4};
 Fused2Shape fused2_shape(int64_t N) {
   return N >= kFusedBigTileNodes ? kFusedBig : (N >= kFusedMidTileNodes ? kFusedMid : kFusedSmall);
+}
+
+// The shapes fcgmg_autotune chooses from (tile x, tile y, threads, waves per SIMD); every shape does the same
+// arithmetic per node, so the choice changes the time, not the result.
+constexpr Fused2Shape kFusedShapes[] = {{32, 8, 256, 5}, {32, 8, 256, 4}, {32, 8, 256, 6}, {16, 16, 256, 5},
+                                        {16, 8, 256, 5},  {8, 8, 128, 5},  {8, 4, 128, 5},  {4, 4, 128, 4}};
+constexpr int kNumFusedShapes = 8;
+
+// The level's shape: its autotuned one, else the default by size.
+Fused2Shape level_fused2_shape(const Level& L) { return L.fshape >= 0 ? kFusedShapes[L.fshape] : fused2_shape(L.N); }
+
+int fused2_num_shapes() { return kNumFusedShapes; }
+void fused2_shape_dims(int k, int* tx, int* ty, int* nt, int* wpe) {
+  *tx = kFusedShapes[k].tx;
+  *ty = kFusedShapes[k].ty;
+  *nt = kFusedShapes[k].nt;
+  *wpe = kFusedShapes[k].wpe;
 }
 
 // Individual patches per workgroup part of a tile: two trips of all 16-lane groups on 32 x 8 tiles,
@@ -1588,10 +1606,17 @@ Fused2Shape fused2_shape(int64_t N) {
 // shortens the launch's tail).
 constexpr int fused2_part_cap(const Fused2Shape& sh) { return (sh.tx * sh.ty >= 256 ? 4 : 2) * (sh.nt / 16); }
 // the part code (tile * 4 + part) allows four parts per tile
+constexpr bool fused2_shapes_fit() {
+  for (int k = 0; k < kNumFusedShapes; ++k)
+    if (kFusedShapes[k].tx * kFusedShapes[k].ty > 4 * fused2_part_cap(kFusedShapes[k]) ||
+        kFusedShapes[k].nt < kFusedShapes[k].tx * kFusedShapes[k].ty || kFusedShapes[k].nt % 64)
+      return false;
+  return true;
+}
 static_assert(kFusedBig.tx * kFusedBig.ty <= 4 * fused2_part_cap(kFusedBig) &&
                   kFusedMid.tx * kFusedMid.ty <= 4 * fused2_part_cap(kFusedMid) &&
-                  kFusedSmall.tx * kFusedSmall.ty <= 4 * fused2_part_cap(kFusedSmall),
-              "at most four parts per tile");
+                  kFusedSmall.tx * kFusedSmall.ty <= 4 * fused2_part_cap(kFusedSmall) && fused2_shapes_fit(),
+              "at most four parts per tile, and one thread per tile node at least");
 
 // Fused sweep (2D): x_out = x_in + omega S (b - L x_in) for one TX x TY tile of nodes by NT >= TX TY
 // threads; thread t < TX TY owns node t of the tile. Large grids use 32 x 8 tiles with one thread per
@@ -1819,7 +1844,7 @@ sweep_fused2_batch_kernel(const Fused2Job<T>* __restrict__ jobs, const int* __re
 // (fused2_part_cap) get parts 1, 2, 3 (code tile * 4 + part), dispatched before the part-0 workgroups
 // of all tiles.
 void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector<int>& extra) {
-  const Fused2Shape sh = fused2_shape(L.N);
+  const Fused2Shape sh = level_fused2_shape(L);
   const int m = L.n + 1;
   const int ntx = (m + sh.tx - 1) / sh.tx, nty = (m + sh.ty - 1) / sh.ty;
   const int cap = fused2_part_cap(sh);
@@ -1884,9 +1909,27 @@ template <class T>
 hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* b, T* x_out, int mode, const T* xc,
                           hipStream_t s) {
   constexpr Fused2Shape B = kFusedBig, M = kFusedMid, S = kFusedSmall;
-  if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, 5, T>(c, L, x_in, b, x_out, mode, xc, s);
-  if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, 5, T>(c, L, x_in, b, x_out, mode, xc, s);
-  return launch_fused2<S.tx, S.ty, S.nt, 4, T>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.fshape >= 0) {
+#define FCG_FUSED_CASE(k)                                                                                  \
+  case k:                                                                                                  \
+    return launch_fused2<kFusedShapes[k].tx, kFusedShapes[k].ty, kFusedShapes[k].nt, kFusedShapes[k].wpe, T>( \
+        c, L, x_in, b, x_out, mode, xc, s);
+    static_assert(kNumFusedShapes == 8, "one case per shape");
+    switch (L.fshape) {
+      FCG_FUSED_CASE(0)
+      FCG_FUSED_CASE(1)
+      FCG_FUSED_CASE(2)
+      FCG_FUSED_CASE(3)
+      FCG_FUSED_CASE(4)
+      FCG_FUSED_CASE(5)
+      FCG_FUSED_CASE(6)
+      default: FCG_FUSED_CASE(7)
+    }
+#undef FCG_FUSED_CASE
+  }
+  if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, B.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
+  if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, M.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
+  return launch_fused2<S.tx, S.ty, S.nt, S.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
 }
 
 // Residual and restriction in one pass (2D, V-cycle): b_c = P^T (b - L x) for a TXC x TYC tile of

@@ -27,11 +27,22 @@ EXPORTS = [
     "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_noalloc", "fcgmg_smooth_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
+    "fcgmg_autotune", "fcgmg_fused_shape", "fcgmg_set_fused_shape",
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
     "fcgmg_server_stats",
     "fcgmg_server_destroy", "fcgmg_batch_create", "fcgmg_batch_vcycle", "fcgmg_batch_solve",
     "fcgmg_batch_destroy",
 ]
+
+N_FUSED_SHAPES = 8  # tile shapes of the fused 2D sweep (fcgmg_fused_shape)
+
+
+def fused_shape(k: int) -> tuple:
+    """(tile_x, tile_y, threads, waves_per_simd) of fused-sweep shape k."""
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().fcgmg_fused_shape(int(k), *[ctypes.byref(q) for q in v]))
+    return tuple(q.value for q in v)
+
 
 KERNEL_KINDS = ["residual", "apply_regular", "apply_irregular", "patch_solve", "restrict", "prolong", "coarse",
                 "zero", "sweep_fused", "residual_restrict"]
@@ -121,6 +132,10 @@ def load(path: str = LIB_PATH):
     L.fcgmg_profile_enable.argtypes = [vp, ctypes.c_int]
     L.fcgmg_profile_reset.argtypes = [vp]
     L.fcgmg_profile_read.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, i64p]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.fcgmg_autotune.argtypes = [vp, ctypes.c_int, ip, dp, vp]
+    L.fcgmg_fused_shape.argtypes = [ctypes.c_int, ip, ip, ip, ip]
+    L.fcgmg_set_fused_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int
     L.fcgmg_destroy.restype = None
@@ -272,6 +287,20 @@ class Hierarchy:
                 if cnt.value:
                     out[(name, lev)] = (ms.value, cnt.value)
         return out
+
+    def autotune(self, reps: int = 20, stream=None) -> dict:
+        """Time every fused-sweep tile shape per level and keep the fastest (2D cache_inverse).
+
+        Returns {"shape": [index per level, -1 = default], "us": [[us per sweep per shape] per level]}."""
+        nl, ns = self.n_levels, N_FUSED_SHAPES
+        shapes = (ctypes.c_int * nl)()
+        us = (ctypes.c_double * (nl * ns))()
+        _check(load().fcgmg_autotune(self.h, int(reps), shapes, us, _stream_ptr(stream)))
+        return {"shape": list(shapes), "us": [[us[l * ns + k] for k in range(ns)] for l in range(nl)]}
+
+    def set_fused_shape(self, level: int, k: int, stream=None):
+        """Use fused-sweep shape k (-1 = default by size) on `level`, e.g. a stored autotune choice."""
+        _check(load().fcgmg_set_fused_shape(self.h, int(level), int(k), _stream_ptr(stream)))
 
     def device_bytes(self) -> int:
         v = ctypes.c_size_t()

@@ -1,0 +1,121 @@
+"""Fused-sweep tile shapes: every shape gives the sweep bitwise, and the autotuner keeps one of them.
+
+The fused 2D sweep (cache_inverse) computes each node's residual and patch correction with the same
+arithmetic in the same order whatever tile covers the node; the shape only decides how nodes are
+grouped into workgroups and which tiles get extra workgroups. So two fused sweeps with any shape must
+equal those with the default shape bit for bit, and the default is pinned to the oracle (one sweep
+here again, on the small case, and in the parity tests).
+"""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+from paper_2403_11636_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    # 41 x 41 nodes: a ragged last tile row and column for every shape
+    "2d_40_l3_ragged": lambda: inputs.small_problem(2, 40, 3, seed=2),
+    # the 20-disc channel at 256^2: levels on all three default shapes, tiles with extra workgroups
+    "2d_256_l6_20discs": lambda: inputs.config2(0, 256, 6),
+}
+
+
+def fcg():
+    from paper_2403_11636_amd import fcgmg
+    return fcgmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def test_shape_table():
+    f = fcg()
+    seen = set()
+    for k in range(f.N_FUSED_SHAPES):
+        tx, ty, nt, wpe = f.fused_shape(k)
+        assert tx > 0 and ty > 0 and nt % 64 == 0 and nt >= tx * ty and 1 <= wpe <= 8
+        seen.add((tx, ty, nt, wpe))
+    assert len(seen) == f.N_FUSED_SHAPES
+    with pytest.raises(RuntimeError):
+        f.fused_shape(f.N_FUSED_SHAPES)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_every_shape_bitwise_equals_default(name):
+    p = CASES[name]()
+    f = fcg()
+    h = f.Hierarchy(p, f.CACHE_INVERSE)
+    for lev in range(1, h.n_levels):
+        b = dev(inputs.random_vector(h.ndofs(lev), 11 + lev))
+        x0 = dev(inputs.random_vector(h.ndofs(lev), 29 + lev))
+        ref = host(h.smooth(x0.clone(), b, 2, level=lev))
+        for k in range(f.N_FUSED_SHAPES):
+            h.set_fused_shape(lev, k)
+            got = host(h.smooth(x0.clone(), b, 2, level=lev))
+            assert np.array_equal(got, ref), f"level {lev}, shape {k} ({f.fused_shape(k)})"
+        h.set_fused_shape(lev, -1)
+        again = host(h.smooth(x0.clone(), b, 2, level=lev))
+        assert np.array_equal(again, ref)
+
+
+def test_small_case_shapes_match_oracle():
+    p = CASES["2d_40_l3_ragged"]()
+    f = fcg()
+    h = f.Hierarchy(p, f.CACHE_INVERSE)
+    o = Oracle(p)
+    lev = h.n_levels - 1
+    b = o.rhs(lev)
+    x0 = inputs.random_vector(h.ndofs(lev), 5)
+    want = o.smooth(lev, x0, b, sweeps=2, omega=p.omega)
+    for k in range(f.N_FUSED_SHAPES):
+        h.set_fused_shape(lev, k)
+        got = host(h.smooth(dev(x0), dev(b), 2, level=lev))
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        print(f"shape {k}: rel err {err:.2e}")
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_autotune_keeps_a_shape_and_results(name):
+    p = CASES[name]()
+    f = fcg()
+    hd = f.Hierarchy(p, f.CACHE_INVERSE)
+    ht = f.Hierarchy(p, f.CACHE_INVERSE)
+    res = ht.autotune(reps=3)
+    assert res["shape"][0] == -1  # the coarsest level is solved directly
+    for lev in range(1, ht.n_levels):
+        k = res["shape"][lev]
+        assert 0 <= k < f.N_FUSED_SHAPES
+        us = res["us"][lev]
+        assert all(u > 0 for u in us)
+        assert us[k] == min(us)
+        print(f"level {lev}: shape {f.fused_shape(k)}, us {['%.1f' % u for u in us]}")
+    b = hd.rhs()
+    xd, xt = hd.zeros(), ht.zeros()
+    for _ in range(2):
+        hd.vcycle(xd, b)
+        ht.vcycle(xt, b)
+    assert np.array_equal(host(xd), host(xt))
+    # the autotuned plan buffer may only have grown
+    assert ht.device_bytes() >= hd.device_bytes()
+
+
+def test_autotune_leaves_other_policies_alone():
+    p = inputs.small_problem(2, 16, 3, seed=0)
+    f = fcg()
+    h = f.Hierarchy(p, f.CACHE_MATRIX)
+    res = h.autotune(reps=1)
+    assert res["shape"] == [-1] * h.n_levels
+    assert all(u == -1.0 for row in res["us"] for u in row)
+    with pytest.raises(RuntimeError):
+        h.set_fused_shape(h.n_levels - 1, 0)
