@@ -241,6 +241,8 @@ def kernel_sources_sha256() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_11636_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith((".hip", ".cpp", ".h", ".inl")):
+            continue
         with open(os.path.join(csrc, fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
