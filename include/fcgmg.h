@@ -40,7 +40,10 @@ typedef struct fcgmg_ctx* fcgmg_h;
 enum {
   FCGMG_CACHE_INVERSE = 0, /* store the d+1 kept rows of L_i^{-1} (shared per regular patch class) */
   FCGMG_CACHE_MATRIX = 1,  /* store L_i (sparse pattern values), factorise at every application    */
-  FCGMG_CACHE_NONE = 2     /* assemble L_i on the fly (incl. cut-cell integration), factorise, solve */
+  FCGMG_CACHE_NONE = 2     /* retrieve L_i from the operator rows at every application, factorise,
+                              solve; nothing is stored beyond the operator itself (2D: the rows the
+                              residual applies; 3D and the immersed-boundary case: the element
+                              matrices of the window cells, cut cells integrated on the fly)      */
 };
 
 /* Face codes, faces ordered x-, x+, y-, y+, z-, z+. */

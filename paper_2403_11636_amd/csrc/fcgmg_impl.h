@@ -3,7 +3,7 @@
 //
 // The element routines are __host__ __device__: the host planner evaluates the uncut reference
 // cells and the Nitsche face matrices once per level; the kernels integrate cut cells (setup, and
-// on the fly for the cache_none policy of Sec. 3.1.2) and the right-hand side.
+// on the fly in the immersed-boundary cache_none blocks) and the right-hand side.
 #pragma once
 
 #include <hip/hip_runtime.h>
