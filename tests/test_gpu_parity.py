@@ -290,19 +290,28 @@ def test_config2_full_size_sampled_factorising_policies(policy):
     assert st["n_cut_cells"] > 1000
 
 
-def test_config2_immersed_full_size_sampled_cache_matrix():
+@pytest.mark.parametrize("policy", [1, 2])
+def test_config2_immersed_full_size_sampled_factorising_policies(policy):
     import dataclasses
     p = dataclasses.replace(inputs.config2(0), immersed_nitsche=1)
     # An operator entry of a cut cell here is an arc-quadrature sum whose terms (up to lambda w with
     # lambda = beta eta / h = 10,240) cancel, so its rounding is relative to the sum of their
     # magnitudes, not to the entry: the residual is held to 1e-12 (|b| + |L| |x|) componentwise
     # (measured: 4.3e-13).
-    st = _sampled_sweep(p, 1, 200, res_tol=1e-12)
+    st = _sampled_sweep(p, policy, 200, res_tol=1e-12)
     assert st["n_cut_cells"] > 1000
 
 
 def test_config3_full_size_sampled():
     st = _sampled_sweep(inputs.config3(0), 0, 40)
+    assert st["n_cut_cells"] > 1000
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+def test_config3_full_size_sampled_factorising_policies(policy):
+    # 274,625 patches: more than the 131,072 workgroups of one launch, so the grid-stride pass of the
+    # 3D factorisation kernel runs; cache_none reads every block from the operator rows
+    st = _sampled_sweep(inputs.config3(0), policy, 20)
     assert st["n_cut_cells"] > 1000
 
 
