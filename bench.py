@@ -847,6 +847,8 @@ def main():
                                            "cached_bytes_finest": st["cached_bytes"]}
         log("3D 64^3 ...")
         out["extra_3d"] = workload_extra(torch, fcgmg, inputs.config3(0))
+        log("3D 64^3 policies ...")
+        out["policies_3d"] = policy_extras(torch, fcgmg, inputs.config3(0), sweeps=3)
         out["roofline_3d"] = out["extra_3d"]["roofline"]
         log("precision: FP64 vs mixed ...")
         out["precision"] = [precision_extra(torch, fcgmg, inputs.config2(0)), precision_extra(torch, fcgmg, inputs.config3(0))]

@@ -724,11 +724,11 @@ hipError_t k_store_matrices(const Ctx& c, const Level& L, const int* nodes, int6
 }
 
 // L_i = R_i L R_i^T (Eq. 15) of the 3D patch centred at node c, retrieved from the rows of L that the
-// residual applies (cache_none): thread v < 125 takes velocity node v of the 5^3 window, reads its
-// operator code and row (the level's reference stencil of its kind, or its stored stencil) and
-// writes the entries whose column lies in the patch: its row of the lower band of K, of B_x, B_y,
-// B_z (columns of the 3^3 pressure window) and, for the 27 inner nodes, its pressure row of C.
-// Every entry is written once, by the thread of its row.
+// residual applies (cache_none): the block's threads take the velocity nodes of the 5^3 window in
+// turn; each reads its node's operator code and row (the level's reference stencil of its kind, or
+// its stored stencil) and writes the entries whose column lies in the patch: its row of the lower
+// band of K, of B_x, B_y, B_z (columns of the 3^3 pressure window) and, for the 27 inner nodes, its
+// pressure row of C. Every entry is written once, by the thread of its row.
 __device__ void patch_retrieve3(PatchLDS<3>& sh, const OpConsts* __restrict__ oc, const int* __restrict__ node_op,
                                 const double* __restrict__ nsten, const int* c) {
   constexpr int NV = PT<3>::NV, NP = PT<3>::NP, NB = PT<3>::NB, NPX = NP + 2, NS = PT<3>::NST;
@@ -739,8 +739,8 @@ __device__ void patch_retrieve3(PatchLDS<3>& sh, const OpConsts* __restrict__ oc
   for (int i = tid; i < 3 * NV * NPX; i += nt) sh.X[i] = 0;
   for (int i = tid; i < NP * NP; i += nt) sh.S[i] = 0;
   __syncthreads();
-  if (tid < NV) {
-    const int v[3] = {tid % 5, (tid / 5) % 5, tid / 25};
+  for (int row = tid; row < NV; row += nt) {
+    const int v[3] = {row % 5, (row / 5) % 5, row / 25};
     const int g0[3] = {c[0] + v[0] - 2, c[1] + v[1] - 2, c[2] + v[2] - 2};
     bool in = true;
     for (int k = 0; k < 3; ++k) in = in && g0[k] >= 0 && g0[k] <= n;
@@ -772,11 +772,11 @@ __device__ void patch_retrieve3(PatchLDS<3>& sh, const OpConsts* __restrict__ oc
         if (!ok) continue;
         if (inwin) {
           const int vb = xb[0] + 5 * xb[1] + 25 * xb[2];
-          if (vb <= tid) sh.Kb[tid * NB + (tid - vb)] = coef(0, o);
+          if (vb <= row) sh.Kb[row * NB + (row - vb)] = coef(0, o);
         }
         if (inpres) {
           const int qb = (xb[0] - 1) + 3 * (xb[1] - 1) + 9 * (xb[2] - 1);
-          for (int cmp = 0; cmp < 3; ++cmp) sh.X[(cmp * NV + tid) * NPX + qb] = coef(1 + cmp, o);
+          for (int cmp = 0; cmp < 3; ++cmp) sh.X[(cmp * NV + row) * NPX + qb] = coef(1 + cmp, o);
           if (inner) sh.S[qa * NP + qb] = coef(7, o);
         }
       }
