@@ -89,3 +89,28 @@ def test_footprint_orders_policies_on_host():
         mixed = fcgmg.footprint_bytes(prob, fcgmg.CACHE_INVERSE, fcgmg.PREC_MIXED)
         assert none < inv < mat
         assert inv < mixed < 2 * inv
+
+
+def test_fused_shape_table_on_host():
+    # the shape table is host data: every shape tiles with at least one thread per node, and the
+    # first index past the table is an argument error
+    seen = set()
+    for k in range(fcgmg.N_FUSED_SHAPES):
+        tx, ty, nt, wpe = fcgmg.fused_shape(k)
+        assert tx * ty <= nt and nt % 64 == 0 and 1 <= wpe <= 8
+        seen.add((tx, ty, nt, wpe))
+    assert len(seen) == fcgmg.N_FUSED_SHAPES
+    lib = fcgmg.load()
+    v = [ctypes.c_int() for _ in range(4)]
+    for k in (-1, fcgmg.N_FUSED_SHAPES):
+        assert lib.fcgmg_fused_shape(k, *[ctypes.byref(q) for q in v]) == fcgmg.E_ARG
+    assert lib.fcgmg_fused_shape(0, None, None, None, None) == fcgmg.E_ARG
+
+
+def test_tuning_calls_reject_a_null_handle_on_host():
+    lib = fcgmg.load()
+    shapes = (ctypes.c_int * 8)()
+    us = (ctypes.c_double * 80)()
+    assert lib.fcgmg_autotune(None, 3, shapes, us, None) == fcgmg.E_ARG
+    assert lib.fcgmg_set_fused_shape(None, 0, 0, None) == fcgmg.E_ARG
+    assert lib.fcgmg_smooth_noalloc(None, 0, None, None, 1, None) == fcgmg.E_ARG
