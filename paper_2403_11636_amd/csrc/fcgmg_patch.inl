@@ -962,7 +962,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <bool NONE>
-__global__ void __launch_bounds__(64) patch_solve_lanes2_kernel(
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) patch_solve_lanes2_kernel(
     const OpConsts* __restrict__ oc, const int* __restrict__ node_op, const double* __restrict__ nsten,
     const int* __restrict__ node_class, const double* __restrict__ Mcls, const double* __restrict__ Mirr,
     const int* __restrict__ pattern, int npat, int64_t N, const double* __restrict__ r, double* __restrict__ x,
