@@ -243,6 +243,14 @@ int fcgmg_fused_shape(int k, int* tile_x, int* tile_y, int* threads, int* waves_
  * `stream`. Errors: E_ARG (bad level or k, or a level without the fused sweep), E_NOMEM, E_HIP. */
 int fcgmg_set_fused_shape(fcgmg_h h, int level, int k, void* stream);
 
+/* How cache_none obtains each patch block L_i at every application (Sec. 3.1.2). integrate = 0
+ * (default): read from the operator rows that the residual applies, as the policy retrieves the
+ * block from the global operator; 1: assembled from the element integrals of the patch's cell
+ * window, every cut cell of the window integrated on the fly by its space tree (no operator data
+ * read; several times slower). Both give L_i = R_i L R_i^T to rounding. The immersed-boundary blocks
+ * are always assembled. Errors: E_ARG (bad handle or mode, or a hierarchy of another policy). */
+int fcgmg_set_cache_none_assembly(fcgmg_h h, int integrate);
+
 /* Device bytes held by the handle (all levels, all policy data). */
 int fcgmg_device_bytes(fcgmg_h h, size_t* bytes);
 

@@ -1432,6 +1432,13 @@ int fcgmg_set_fused_shape(fcgmg_h h, int level, int k, void* stream) {
   return set_fused_shape_impl(*h, level, k, (hipStream_t)stream);
 }
 
+int fcgmg_set_cache_none_assembly(fcgmg_h h, int integrate) {
+  if (!h || (integrate != 0 && integrate != 1)) return fail(FCGMG_E_ARG, "bad handle or mode");
+  if (h->prm.cache_policy != FCGMG_CACHE_NONE) return fail(FCGMG_E_ARG, "the hierarchy does not use cache_none");
+  h->none_integrate = integrate != 0;
+  return FCGMG_OK;
+}
+
 int fcgmg_fused_shape(int k, int* tile_x, int* tile_y, int* threads, int* waves_per_simd) {
   if (k < 0 || k >= fused2_num_shapes() || !tile_x || !tile_y || !threads || !waves_per_simd)
     return fail(FCGMG_E_ARG, "shape index out of range or null pointer");

@@ -244,6 +244,7 @@ struct Ctx {
   int* err = nullptr;            // device error flag: first failing patch node, or INT_MAX
   int* pattern = nullptr;        // cache_matrix sparse pattern (encoded entries)
   int n_pattern = 0;
+  bool none_integrate = false;  // cache_none: assemble from element integrals, cut cells integrated per sweep
   size_t bytes = 0;
   std::vector<void*> allocs;
   // event profiler

@@ -797,7 +797,7 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_solve_kernel(
     double eta, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
     const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
     const double* __restrict__ r, double* __restrict__ x, double omega, int* err, const int* __restrict__ node_op,
-    const double* __restrict__ nsten) {
+    const double* __restrict__ nsten, bool integrate) {
   constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NPX = NP + 2;
   __shared__ PatchLDS<D> sh;
   const int tid = threadIdx.x;
@@ -811,8 +811,8 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_solve_kernel(
       const int cls = node_class[node];
       const double* vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
       patch_load_pattern<D>(sh, pattern, npat, vals);
-    } else if constexpr (D == 3) {
-      patch_retrieve3(sh, oc, node_op, nsten, c);
+    } else if (D == 3 && !integrate) {
+      if constexpr (D == 3) patch_retrieve3(sh, oc, node_op, nsten, c);
     } else {
       patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 1);
     }
@@ -943,12 +943,19 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Largest stored pattern of a 2D patch block (288 entries), rounded up to whole lane rounds.
 constexpr int kMaxPattern2 = 320;
 
-template <bool NONE>
+// Modes of the 2D factorising kernel: the stored pattern values (cache_matrix), the operator rows
+// (cache_none), or the element integrals of the window with its cut cells integrated on the fly
+// (cache_none, fcgmg_set_cache_none_assembly).
+enum { kSolveMatrix = 0, kSolveRows = 1, kSolveIntegrate = 2 };
+
+template <int MODE>
 struct Solve2LDS {
   double Kb[25 * 7];              // lower band of K: Kb[v * 7 + (v - j)] = K[v][j]
   double X[25 * kS2Cols];         // X[v * 21 + l]: right-hand-side column l at velocity window node v, then V
   double C[81];                   // C, then F = -S (column l written by lane l)
   double aux[32];                 // pressure right-hand side, then t (0-8); w_c (9-26); y^T z_c (27, 28)
+  double cell[MODE == kSolveIntegrate ? 48 : 1];                  // one cut cell integrated on the fly
+  double lball[MODE == kSolveIntegrate ? 4 * kMaxLocalBalls : 1];  // the balls that touch it
   int bad;
 };
 
@@ -961,14 +968,43 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("" ::: "memory");
 }
 
-template <bool NONE>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) patch_solve_lanes2_kernel(
+// The balls that touch the box [lo, lo + s]^2, collected by the 32 lanes of one half-wavefront (lane
+// l, half h) into `out`; -1 if more than kMaxLocalBalls touch it (the caller keeps the full list).
+__device__ int cull_balls_half(const Geom& g, const double* lo, double s, double* out, int l, int half) {
+  int cnt = 0;
+  for (int base = 0; base < g.nballs; base += 32) {
+    const int i = base + l;
+    bool touch = false;
+    if (i < g.nballs) {
+      const double* b = g.balls + 4 * i;
+      double dmin2 = 0;
+      for (int k = 0; k < 2; ++k) {
+        const double a = lo[k] - b[k], e = lo[k] + s - b[k];
+        const double m = a > 0 ? a : (e < 0 ? -e : 0.0);
+        dmin2 += m * m;
+      }
+      touch = dmin2 <= b[3] * b[3];
+    }
+    const unsigned hm = (unsigned)(__ballot(touch) >> (32 * half));
+    const int pos = cnt + __popc(hm & ((1u << l) - 1u));
+    if (touch && pos < kMaxLocalBalls)
+      for (int k = 0; k < 4; ++k) out[4 * pos + k] = g.balls[4 * i + k];
+    cnt += __popc(hm);
+  }
+  wave_lds_sync();
+  return cnt > kMaxLocalBalls ? -1 : cnt;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kSolveIntegrate ? 1 : 3, 8)))
+patch_solve_lanes2_kernel(
     const OpConsts* __restrict__ oc, const int* __restrict__ node_op, const double* __restrict__ nsten,
     const int* __restrict__ node_class, const double* __restrict__ Mcls, const double* __restrict__ Mirr,
     const int* __restrict__ pattern, int npat, int64_t N, const double* __restrict__ r, double* __restrict__ x,
-    double omega, int* err) {
+    double omega, int* err, const int* __restrict__ cell_info, Geom g, double eta) {
   constexpr int NV = 25, NP = 9, NB = 7, NC = kS2Cols, MC = 12;
-  __shared__ Solve2LDS<NONE> shp[2];
+  constexpr bool NONE = MODE != kSolveMatrix;
+  __shared__ Solve2LDS<MODE> shp[2];
   const int half = (int)threadIdx.x >> 5, l = (int)threadIdx.x & 31;
   const int n = oc->n;
   const int64_t npair = (N + 1) / 2;
@@ -977,7 +1013,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
     // it are formed where they are used instead of being hoisted out of this loop into registers
     int hsel = half;
     asm volatile("" : "+v"(hsel));
-    Solve2LDS<NONE>& sh = shp[hsel];
+    Solve2LDS<MODE>& sh = shp[hsel];
     const int64_t node_raw = 2 * pair + half;
     const bool live = node_raw < N;
     const int64_t node = live ? node_raw : N - 1;  // a spare half repeats the last patch, unwritten
@@ -1034,8 +1070,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
         }
       }
       wave_lds_sync();
-    } else {
-
+    } else if constexpr (MODE == kSolveRows) {
       // L_i = R_i L R_i^T (Eq. 15) retrieved from the rows of L that the residual applies: lane
       // v < 25 takes velocity node v of the 5 x 5 window, reads its operator code and row (the
       // level's reference stencil of its kind, or its stored stencil) and writes the entries whose
@@ -1078,6 +1113,131 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8)))
         }
       }
       wave_lds_sync();
+    } else {
+      const double h = oc->h;
+      // on-the-fly assembly from the 6 x 6 cell window (Eq. 15: L_i = R_i L R_i^T): first the uncut
+      // cells from the reference matrices, in window order, then the cut cells, integrated on the
+      // fly; in the second pass each half takes its k-th cut cell at step k, so that the two halves
+      // of the wavefront integrate together. Lane l holds the codes of window cells l and l + 32
+      // (-3: outside the grid).
+      int info2[2];
+      for (int k = 0; k < 2; ++k) {
+        const int w = l + 32 * k;
+        const int cx = c[0] + w % 6 - 3, cy = c[1] + w / 6 - 3;
+        info2[k] = (w < 36 && cx >= 0 && cx < n && cy >= 0 && cy < n) ? cell_info[cx + (int64_t)n * cy] : -3;
+      }
+      auto scatter = [&](int w, const double* Kp, const double* Bp, int bstride) {
+        const int wx = w % 6, wy = w / 6;
+        const int cx = c[0] + wx - 3, cy = c[1] + wy - 3;
+        int fmask = 0;
+        if (cx == 0 && oc->dirichlet[0]) fmask |= 1;
+        if (cx == n - 1 && oc->dirichlet[1]) fmask |= 2;
+        if (cy == 0 && oc->dirichlet[2]) fmask |= 4;
+        if (cy == n - 1 && oc->dirichlet[3]) fmask |= 8;
+        for (int k = 0; k < 2; ++k) {
+          const int it = l + 32 * k;  // (block, a, b): K, B_x, B_y, C, 16 pairs each
+          const int blk = it >> 4, ab = it & 15, a = ab >> 2, b = ab & 3;
+          const int xa = wx + (a & 1) - 1, ya = wy + (a >> 1) - 1, xb = wx + (b & 1) - 1, yb = wy + (b >> 1) - 1;
+          const int pxa = xa - 1, pya = ya - 1, pxb = xb - 1, pyb = yb - 1;
+          const bool va_ok = xa >= 0 && xa <= 4 && ya >= 0 && ya <= 4;
+          const bool vb_ok = xb >= 0 && xb <= 4 && yb >= 0 && yb <= 4;
+          const bool qa_ok = pxa >= 0 && pxa <= 2 && pya >= 0 && pya <= 2;
+          const bool qb_ok = pxb >= 0 && pxb <= 2 && pyb >= 0 && pyb <= 2;
+          const int va = xa + 5 * ya, vb = xb + 5 * yb, qa = pxa + 3 * pya, qb = pxb + 3 * pyb;
+          if (blk == 0) {
+            if (va_ok && vb_ok && va >= vb) {
+              double v = Kp[a * 4 + b];
+              for (int f = 0; f < 4; ++f)
+                if (fmask & (1 << f)) v += oc->FK[f][a * 4 + b];
+              sh.Kb[va * NB + (va - vb)] += v;
+            }
+          } else if (blk <= 2) {
+            const int cmp = blk - 1;
+            if (va_ok && qb_ok) {
+              double v = Bp[cmp * bstride + a * 4 + b];
+              for (int sd = 0; sd < 2; ++sd)
+                if (fmask & (1 << (2 * cmp + sd))) v += oc->FB[2 * cmp + sd][a * 4 + b];
+              sh.X[va * NC + cmp * 10 + qb] += v;
+            }
+          } else if (qa_ok && qb_ok) {
+            sh.C[qa * NP + qb] += oc->C[a * 4 + b];
+          }
+        }
+        wave_lds_sync();
+      };
+      for (int w = 0; w < 36; ++w) {
+        const int info = __shfl(w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
+        if (info == -3 || info >= 0) continue;
+        const int kind = info == -1 ? 0 : 1;
+        scatter(w, oc->K[kind], oc->B[kind][0], 64);
+      }
+      // the cut cells of this half's window as a bit mask over the 36 window positions
+      const unsigned long long m0 = __ballot(info2[0] >= 0), m1 = __ballot(info2[1] >= 0);
+      unsigned long long cutm = ((m0 >> (32 * half)) & 0xffffffffull) | (((m1 >> (32 * half)) & 0xfull) << 32);
+      const int ncut_h = __popcll(cutm);
+      const int ncut_o = __shfl(ncut_h, ((1 - half) << 5), 64);
+      const int nsteps = ncut_h > ncut_o ? ncut_h : ncut_o;
+      for (int k = 0; k < nsteps; ++k) {
+        const int w = cutm ? __builtin_ctzll(cutm) : -1;
+        cutm &= cutm ? cutm - 1 : 0ull;
+        const int info = __shfl(w >= 0 && w < 32 ? info2[0] : info2[1], (half << 5) + (w & 31), 64);
+        if (w < 0) continue;  // this half has no more cut cells
+        (void)info;
+        const int wx = w % 6, wy = w / 6;
+        const double lo[3] = {(c[0] + wx - 3) * h, (c[1] + wy - 3) * h, 0.0};
+        const int nb = cull_balls_half(g, lo, h, sh.lball, l, half);
+        Geom gl = g;
+        if (nb >= 0) {
+          gl.balls = sh.lball;
+          gl.nballs = nb;
+        }
+        if (gl.q >= 3) {
+          // the cell's tree below depth 3: lane l integrates sub-boxes l and l + 32 of the 8 x 8
+          // (side h / 8) to the level's depth, every entry at once; the 32 partial sums are then
+          // added by a butterfly. (A box above depth 3 that is not cut becomes uncut sub-boxes here:
+          // the 2 x 2 Gauss rule is exact on each, so the integral is the same up to rounding.)
+          double acc[48];
+#pragma unroll
+          for (int e = 0; e < 48; ++e) acc[e] = 0;
+          const double hs = 0.125 * h;
+          Geom gs = gl;
+          gs.q = gl.q - 3;
+          for (int k2 = 0; k2 < 2; ++k2) {
+            const int bidx = l + 32 * k2;
+            const double los[3] = {lo[0] + (bidx & 7) * hs, lo[1] + (bidx >> 3) * hs, 0.0};
+            tree_quadrature<2>(gs, los, hs, [&](const double* xq, double wq, double alpha) {
+              double phi[4], gr[4][3];
+              q1<2>(lo, h, xq, phi, gr);
+              const double wa = wq * alpha;
+#pragma unroll
+              for (int e = 0; e < 48; ++e) acc[e] += point_entry<2>(e, eta, wa, phi, gr);
+            });
+          }
+#pragma unroll
+          for (int e = 0; e < 48; ++e) {
+            double v = acc[e];
+            for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 32);
+            acc[e] = v;
+          }
+          if (l == 0)
+#pragma unroll
+            for (int e = 0; e < 48; ++e) sh.cell[e] = acc[e];
+        } else {
+          // trees of depth 0 to 2: every lane walks the whole tree for entries l and l + 32
+          double a0 = 0, a1 = 0;
+          tree_quadrature<2>(gl, lo, h, [&](const double* xq, double wq, double alpha) {
+            double phi[4], gr[4][3];
+            q1<2>(lo, h, xq, phi, gr);
+            const double wa = wq * alpha;
+            a0 += point_entry<2>(l, eta, wa, phi, gr);
+            if (l < 16) a1 += point_entry<2>(l + 32, eta, wa, phi, gr);
+          });
+          sh.cell[l] = a0;
+          if (l < 16) sh.cell[l + 32] = a1;
+        }
+        wave_lds_sync();
+        scatter(w, sh.cell, sh.cell + 16, 16);
+      }
     }
     // window positions outside the grid are decoupled; g = R_i r (zero outside the grid) into the
     // columns 9 and 19, its pressure part into aux; the unit column of the centre velocity node
@@ -1233,19 +1393,22 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
     if (c.n_pattern > kMaxPattern2) return hipErrorInvalidValue;
     const int64_t npair = (L.N + 1) / 2;
     const int64_t nb2 = npair < 65536 ? npair : 65536;
+#define FCG_LANES2(MODE)                                                                                     \
+  patch_solve_lanes2_kernel<MODE><<<dim3((unsigned)nb2), dim3(64), 0, s>>>(                                  \
+      L.consts, L.node_op, L.nsten, L.node_class, L.Mcls, L.Mirr, c.pattern, c.n_pattern, L.N, r, x,           \
+      c.prm.omega, c.err, L.cell_info, c.geom(L), c.prm.eta)
     if (policy == FCGMG_CACHE_MATRIX)
-      patch_solve_lanes2_kernel<false><<<dim3((unsigned)nb2), dim3(64), 0, s>>>(
-          L.consts, L.node_op, L.nsten, L.node_class, L.Mcls, L.Mirr, c.pattern, c.n_pattern, L.N, r, x,
-          c.prm.omega, c.err);
+      FCG_LANES2(kSolveMatrix);
+    else if (c.none_integrate)
+      FCG_LANES2(kSolveIntegrate);
     else
-      patch_solve_lanes2_kernel<true><<<dim3((unsigned)nb2), dim3(64), 0, s>>>(
-          L.consts, L.node_op, L.nsten, L.node_class, L.Mcls, L.Mirr, c.pattern, c.n_pattern, L.N, r, x,
-          c.prm.omega, c.err);
+      FCG_LANES2(kSolveRows);
+#undef FCG_LANES2
     return hipGetLastError();
   }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
       L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr, c.pattern,
-      c.n_pattern, L.N, r, x, c.prm.omega, c.err, L.node_op, L.nsten);
+      c.n_pattern, L.N, r, x, c.prm.omega, c.err, L.node_op, L.nsten, c.none_integrate);
   return hipGetLastError();
 }
 

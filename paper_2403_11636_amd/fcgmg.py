@@ -27,7 +27,7 @@ EXPORTS = [
     "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_noalloc", "fcgmg_smooth_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
-    "fcgmg_autotune", "fcgmg_fused_shape", "fcgmg_set_fused_shape",
+    "fcgmg_autotune", "fcgmg_fused_shape", "fcgmg_set_fused_shape", "fcgmg_set_cache_none_assembly",
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
     "fcgmg_server_stats",
     "fcgmg_server_destroy", "fcgmg_batch_create", "fcgmg_batch_vcycle", "fcgmg_batch_solve",
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_autotune.argtypes = [vp, ctypes.c_int, ip, dp, vp]
     L.fcgmg_fused_shape.argtypes = [ctypes.c_int, ip, ip, ip, ip]
     L.fcgmg_set_fused_shape.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    L.fcgmg_set_cache_none_assembly.argtypes = [vp, ctypes.c_int]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int
     L.fcgmg_destroy.restype = None
@@ -301,6 +302,11 @@ class Hierarchy:
     def set_fused_shape(self, level: int, k: int, stream=None):
         """Use fused-sweep shape k (-1 = default by size) on `level`, e.g. a stored autotune choice."""
         _check(load().fcgmg_set_fused_shape(self.h, int(level), int(k), _stream_ptr(stream)))
+
+    def set_cache_none_assembly(self, integrate: bool):
+        """cache_none: read each block from the operator rows (False, default) or assemble it from the
+        window's element integrals with its cut cells integrated on the fly (True)."""
+        _check(load().fcgmg_set_cache_none_assembly(self.h, 1 if integrate else 0))
 
     def device_bytes(self) -> int:
         v = ctypes.c_size_t()

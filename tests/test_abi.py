@@ -114,3 +114,4 @@ def test_tuning_calls_reject_a_null_handle_on_host():
     assert lib.fcgmg_autotune(None, 3, shapes, us, None) == fcgmg.E_ARG
     assert lib.fcgmg_set_fused_shape(None, 0, 0, None) == fcgmg.E_ARG
     assert lib.fcgmg_smooth_noalloc(None, 0, None, None, 1, None) == fcgmg.E_ARG
+    assert lib.fcgmg_set_cache_none_assembly(None, 1) == fcgmg.E_ARG

@@ -125,6 +125,32 @@ def test_sweep_parity(name, policy):
     assert rel(host(xg2), o.smooth(lev2, x2, b2, 2, p.omega)) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["2d_16_l3_s0", "c1_32_l3", "2d_16_edge_two", "2d_16_edge_inflow", "3d_8_l2_s0",
+                                  "3d_8_edge_two"])
+def test_cache_none_integrated_assembly(name):
+    # cache_none with every block assembled from the window's element integrals, its cut cells
+    # integrated during the sweep: the oracle's sweep to 1e-12, and the default retrieval from the
+    # operator rows to 1e-12 (both form L_i = R_i L R_i^T; only the rounding of the sums differs)
+    p, o, _ = setup_case(name, 0)
+    f = fcg()
+    h = f.Hierarchy(p, f.CACHE_NONE)
+    lev = h.fine
+    n = o.ndofs(lev)
+    x = inputs.random_vector(n, 11)
+    b = inputs.random_vector(n, 12)
+    xr = dev(x)
+    h.smooth(xr, dev(b), 1, lev)
+    h.set_cache_none_assembly(True)
+    xi = dev(x)
+    h.smooth(xi, dev(b), 1, lev)
+    x_orc = o.smooth(lev, x, b, 1, p.omega)
+    assert rel(host(xi), x_orc) <= 1e-12, rel(host(xi), x_orc)
+    assert rel(host(xi) - x, host(xr) - x) <= 1e-10
+    h.close()
+    with pytest.raises(RuntimeError):
+        f.Hierarchy(p, f.CACHE_MATRIX).set_cache_none_assembly(True)
+
+
 @pytest.mark.parametrize("name", list(SMALL))
 def test_transfer_parity(name):
     p, o, h = setup_case(name)
@@ -238,10 +264,12 @@ def test_tiny_single_level_grid(d):
         h.close()
 
 
-def _sampled_sweep(p, policy, samples_per_kind, seed=0, res_tol=1e-13):
+def _sampled_sweep(p, policy, samples_per_kind, seed=0, res_tol=1e-13, integrate=False):
     """One fine-level sweep at full size, checked on sampled nodes (irregular, regular, walls)."""
     o = Oracle(p)
     h = fcg().Hierarchy(p, policy)
+    if integrate:
+        h.set_cache_none_assembly(True)
     lev = h.fine
     n = o.ndofs(lev)
     N = o.nnodes(lev)
@@ -282,11 +310,11 @@ def test_config2_full_size_sampled():
     assert st["n_cut_cells"] > 1000 and st["n_irregular"] > 5000
 
 
-@pytest.mark.parametrize("policy", [1, 2])
+@pytest.mark.parametrize("policy", [1, 2, "2i"])
 def test_config2_full_size_sampled_factorising_policies(policy):
-    # 263,169 patches: more than the 131,072 workgroups of one launch, so the grid-stride pass of the
-    # per-sweep factorisation kernel runs
-    st = _sampled_sweep(inputs.config2(0), policy, 300)
+    # 263,169 patches: more than the 65,536 workgroups of one launch, so the grid-stride pass of the
+    # per-sweep factorisation kernel runs; "2i": cache_none with the cut cells integrated per sweep
+    st = _sampled_sweep(inputs.config2(0), 2 if policy == "2i" else policy, 300, integrate=policy == "2i")
     assert st["n_cut_cells"] > 1000
 
 
