@@ -737,7 +737,7 @@ def main():
     ap.add_argument("--sweeps-only", action="store_true",
                     help="run warmup + steps single fine-level sweeps of --workload under --policy and nothing else "
                          "(for trace and counter runs of the factorising policies)")
-    ap.add_argument("--policy", choices=["inverse", "matrix", "none"], default="inverse",
+    ap.add_argument("--policy", choices=["inverse", "matrix", "none", "none_integrated"], default="inverse",
                     help="cache policy of --sweeps-only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run only a plain device-to-device copy of MIB MiB, 5 times (HBM counter calibration)")
@@ -767,8 +767,11 @@ def main():
     elif (args.cycles_only or args.sweeps_only) and args.workload == "2d_4096":
         prob = inputs.config2(0, n_cells=4096, n_levels=10)
     if args.sweeps_only:
-        pol = {"inverse": fcgmg.CACHE_INVERSE, "matrix": fcgmg.CACHE_MATRIX, "none": fcgmg.CACHE_NONE}[args.policy]
+        pol = {"inverse": fcgmg.CACHE_INVERSE, "matrix": fcgmg.CACHE_MATRIX, "none": fcgmg.CACHE_NONE,
+               "none_integrated": fcgmg.CACHE_NONE}[args.policy]
         h = fcgmg.Hierarchy(prob, pol)
+        if args.policy == "none_integrated":
+            h.set_cache_none_assembly(True)
         x, b = h.zeros(), h.rhs()
         for _ in range(args.warmup + args.steps):
             h.smooth(x, b, 1)
