@@ -180,8 +180,8 @@ __device__ void patch_assemble(PatchLDS<D>& sh, const OpConsts* __restrict__ oc,
 }
 
 // Decouple window positions that lie outside the grid (truncated patches at the walls).
-template <int D>
-__device__ void patch_pad(PatchLDS<D>& sh, const int* c, int n) {
+template <int D, class LDS>
+__device__ void patch_pad(LDS& sh, const int* c, int n) {
   constexpr int NV = PT<D>::NV, NP = PT<D>::NP, NB = PT<D>::NB;
   for (int v = threadIdx.x; v < NV; v += blockDim.x)
     if (!vel_in_grid<D>(c, n, v)) sh.Kb[v * NB] = 1.0;
@@ -191,8 +191,8 @@ __device__ void patch_pad(PatchLDS<D>& sh, const int* c, int n) {
 }
 
 // Banded Cholesky K = L L^T in place (right-looking, one barrier pair per column).
-template <int D>
-__device__ void band_cholesky(PatchLDS<D>& sh) {
+template <int D, class LDS>
+__device__ void band_cholesky(LDS& sh) {
   constexpr int NV = PT<D>::NV, NB = PT<D>::NB, BW = PT<D>::BW;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < NV; ++k) {
@@ -291,8 +291,8 @@ __device__ void schur_update(PatchLDS<D>& sh, bool with_rhs) {
 }
 
 // Dense Cholesky of F = -S (lower factor in sh.S).
-template <int D>
-__device__ void schur_cholesky(PatchLDS<D>& sh) {
+template <int D, class LDS>
+__device__ void schur_cholesky(LDS& sh) {
   constexpr int NP = PT<D>::NP;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < NP * NP; e += nt) sh.S[e] = -sh.S[e];
@@ -316,8 +316,8 @@ __device__ void schur_cholesky(PatchLDS<D>& sh) {
 
 // p = S^{-1} t = -F^{-1} t by forward/back substitution with the factor of F (first wavefront;
 // each row's dot product is a wavefront reduction). Result overwrites sh.t.
-template <int D>
-__device__ void schur_solve(PatchLDS<D>& sh) {
+template <int D, class LDS>
+__device__ void schur_solve(LDS& sh) {
   constexpr int NP = PT<D>::NP;
   const int lane = threadIdx.x;
   if (lane < 64) {
@@ -854,6 +854,282 @@ __global__ void __launch_bounds__(PT<D>::THREADS) patch_solve_kernel(
         y = sh.t[ip];
       }
       x[tid * N + node] += omega * y;
+    }
+    if (tid == 0 && sh.bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
+// ---- 3D factorising policies, one velocity component's columns at a time -----------------------
+// The velocity block of L_i is I_3 (x) K, so the forward substitutions of the three components'
+// coupling columns share the factor of K and are independent: each component's 27 columns B_c and
+// its right-hand side g_c are loaded, substituted and folded into the Schur complement in turn. The
+// block then needs LDS for K's band, one component's columns and S (about 68 KB instead of 134 KB),
+// so two patches run on a CU at once.
+struct Patch3LDS {
+  static constexpr int NV = 125, NP = 27, NB = PT<3>::NB, NX = NP + 2;  // columns: B_c, g_c, e_m
+  double Kb[NV * NB];  // lower band of K, then its Cholesky factor
+  double X[NV * NX];   // [B_c | g_c | e_m] of one component, then L^{-1} of it
+  double y[NV];        // L^{-1} e_m (row m of K^{-1} after the back substitution implied by y^T V)
+  double S[NP * NP];   // C - sum_c V_c^T V_c, then the Cholesky factor of -S
+  double t[NP];        // pressure right-hand side, then the pressures
+  double w[3][NP];     // y^T V_c
+  double qg[3];        // y^T z_c
+  int bad;
+};
+
+// Entries of L_i for one pass: pass < 0 takes K (lower band) and C; pass c the columns B_c. From the
+// stored pattern values (cache_matrix) or from the operator rows of the window's velocity nodes
+// (cache_none). The buffers of the pass were zeroed before.
+__device__ void patch3_load(Patch3LDS& sh, int pass, bool rows, const OpConsts* __restrict__ oc,
+                            const int* __restrict__ node_op, const double* __restrict__ nsten,
+                            const int* __restrict__ pattern, int npat, const double* __restrict__ vals,
+                            const int* c) {
+  constexpr int NV = Patch3LDS::NV, NP = Patch3LDS::NP, NB = Patch3LDS::NB, NX = Patch3LDS::NX, NS = PT<3>::NST;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (!rows) {
+    for (int e = tid; e < npat; e += nt) {
+      const int code = pattern[e];
+      const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
+      if (pass < 0) {
+        if (type == 0) {
+          sh.Kb[i * NB + (i - j)] = vals[e];
+        } else if (type > 3) {
+          sh.S[i * NP + j] = vals[e];
+          sh.S[j * NP + i] = vals[e];
+        }
+      } else if (type == pass + 1) {
+        sh.X[i * NX + j] = vals[e];
+      }
+    }
+    return;
+  }
+  using RL = RefLayout<3>;
+  const int n = oc->n;
+  const double* __restrict__ pk = oc->pack;
+  for (int row = tid; row < NV; row += nt) {
+    const int v[3] = {row % 5, (row / 5) % 5, row / 25};
+    const int g0[3] = {c[0] + v[0] - 2, c[1] + v[1] - 2, c[2] + v[2] - 2};
+    bool in = true;
+    for (int k = 0; k < 3; ++k) in = in && g0[k] >= 0 && g0[k] <= n;
+    if (!in) continue;
+    const int op = node_op[node_index<3>(g0, n)];
+    const bool inner = v[0] >= 1 && v[0] <= 3 && v[1] >= 1 && v[1] <= 3 && v[2] >= 1 && v[2] <= 3;
+    const int qa = (v[0] - 1) + 3 * (v[1] - 1) + 9 * (v[2] - 1);
+    const double* __restrict__ st = op >= 0 ? nsten + (int64_t)op * PT<3>::NSTEN : nullptr;
+    const int ku = op >= 0 ? 0 : -op - 1;
+    // coefficient j of offset o: 0 K, 1..3 B_x, B_y, B_z, 7 C (the layout of the stored stencils)
+    auto coef = [&](int j, int o) -> double {
+      if (st) return st[j * NS + o];
+      if (j == 0) return pk[RL::oSK + ku * NS + o];
+      if (j <= 3) return pk[RL::oSB + (ku * 3 + j - 1) * NS + o];
+      return pk[RL::oSC + o];
+    };
+    for (int o = 0; o < NS; ++o) {
+      const int oo[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+      bool ok = true, inwin = true, inpres = true;
+      int xb[3];
+      for (int k = 0; k < 3; ++k) {
+        const int gk = g0[k] + oo[k];
+        ok = ok && gk >= 0 && gk <= n;
+        xb[k] = v[k] + oo[k];
+        inwin = inwin && xb[k] >= 0 && xb[k] <= 4;
+        inpres = inpres && xb[k] >= 1 && xb[k] <= 3;
+      }
+      if (!ok) continue;
+      if (pass < 0) {
+        if (inwin) {
+          const int vb = xb[0] + 5 * xb[1] + 25 * xb[2];
+          if (vb <= row) sh.Kb[row * NB + (row - vb)] = coef(0, o);
+        }
+        if (inpres && inner) sh.S[qa * NP + (xb[0] - 1) + 3 * (xb[1] - 1) + 9 * (xb[2] - 1)] = coef(7, o);
+      } else if (inpres) {
+        sh.X[row * NX + (xb[0] - 1) + 3 * (xb[1] - 1) + 9 * (xb[2] - 1)] = coef(1 + pass, o);
+      }
+    }
+  }
+}
+
+// Orders one wavefront's LDS accesses (they execute in order; this only keeps the compiler from
+// moving them across).
+__device__ __forceinline__ void patch3_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward substitution L V = X for the first ncol columns of the component buffer: a group of 8
+// lanes of one wavefront per column. For row i, lane j of the group takes the band terms k = i - 1 -
+// j - 8 t (t < 4), whose loads are all in flight together, and a butterfly over the group adds the
+// partial sums; the group's first lane writes the row's value, which the next row reads.
+__device__ void patch3_forward(Patch3LDS& sh, int ncol) {
+  constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, NX = Patch3LDS::NX, BW = PT<3>::BW, G = 8;
+  static_assert(G * 4 >= BW, "four terms per lane cover the band");
+  const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
+  const bool act = grp < ncol;
+  double* Xc = sh.X + (act ? grp : 0);
+  for (int i = 0; i < NV; ++i) {
+    double part = 0;
+    if (act) {
+      double a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = i - 1 - j - G * t;
+        const bool ok = k >= 0 && k >= i - BW;
+        a[t] = ok ? sh.Kb[i * NB + (i - k)] : 0.0;
+        b[t] = ok ? Xc[k * NX] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) part += a[t] * b[t];
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) part += __shfl_xor(part, m, G);
+    if (act && j == 0) Xc[i * NX] = (Xc[i * NX] - part) / sh.Kb[i * NB];
+    patch3_wave_sync();
+  }
+  __syncthreads();
+}
+
+// Banded Cholesky K = L L^T in place with one barrier per column: at step k every thread updates its
+// entries (ii, jj), k < jj <= ii <= k + BW, of the trailing band by K_ii,k K_jj,k / K_kk from the still
+// unscaled column k, and scales column k - 1, which no thread reads any more; the last column is
+// scaled after the loop. Thread (a, b) of the 8 x 32 layout takes rows k + 1 + a + 8 s and column
+// k + 1 + b.
+__device__ void patch3_cholesky(Patch3LDS& sh) {
+  constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, BW = PT<3>::BW;
+  const int a = (int)threadIdx.x / 32, b = (int)threadIdx.x % 32;
+  for (int k = 0; k < NV; ++k) {
+    if (k > 0) {
+      // scale column k - 1 by its square root (entries below the diagonal, then the diagonal)
+      const int kp = k - 1;
+      const double lp = sqrt(sh.Kb[kp * NB]);
+      const int lastp = kp + BW < NV - 1 ? kp + BW : NV - 1;
+      for (int i = kp + 1 + (int)threadIdx.x; i <= lastp; i += (int)blockDim.x) sh.Kb[i * NB + (i - kp)] /= lp;
+    }
+    const double dkk = sh.Kb[k * NB];
+    if (threadIdx.x == 0 && !(dkk > 0.0)) sh.bad = 1;
+    const int last = k + BW < NV - 1 ? k + BW : NV - 1;
+    const int jj = k + 1 + b;
+    if (jj <= last) {
+      const double cj = sh.Kb[jj * NB + (jj - k)];
+      for (int ii = k + 1 + a; ii <= last; ii += 8)
+        if (ii >= jj) sh.Kb[ii * NB + (ii - jj)] -= sh.Kb[ii * NB + (ii - k)] * cj / dkk;
+    }
+    __syncthreads();
+    if (k > 0 && threadIdx.x == 0) sh.Kb[(k - 1) * NB] = sqrt(sh.Kb[(k - 1) * NB]);
+  }
+  if (threadIdx.x == 0) sh.Kb[(NV - 1) * NB] = sqrt(sh.Kb[(NV - 1) * NB]);
+  __syncthreads();
+}
+
+// Component cmp's part of the Schur complement and of the reduced right-hand side:
+// S -= V^T V, t -= V^T z, w_cmp = y^T V, qg_cmp = y^T z.
+__device__ void patch3_schur(Patch3LDS& sh, int cmp) {
+  constexpr int NV = Patch3LDS::NV, NP = Patch3LDS::NP, NX = Patch3LDS::NX;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int mc = vel_center<3>();
+  for (int e = tid; e < NP * NP + 2 * NP + 1; e += nt) {
+    if (e < NP * NP) {
+      const int i = e / NP, j = e % NP;
+      double s = 0;
+#pragma unroll 5
+      for (int k = 0; k < NV; ++k) s += sh.X[k * NX + i] * sh.X[k * NX + j];
+      sh.S[e] -= s;
+    } else if (e < NP * NP + NP) {
+      const int i = e - NP * NP;
+      double s = 0;
+#pragma unroll 5
+      for (int k = 0; k < NV; ++k) s += sh.X[k * NX + i] * sh.X[k * NX + NP];
+      sh.t[i] -= s;
+    } else if (e < NP * NP + 2 * NP) {
+      const int i = e - NP * NP - NP;
+      double s = 0;
+      for (int k = mc; k < NV; ++k) s += sh.y[k] * sh.X[k * NX + i];
+      sh.w[cmp][i] = s;
+    } else {
+      double s = 0;
+      for (int k = mc; k < NV; ++k) s += sh.y[k] * sh.X[k * NX + NP];
+      sh.qg[cmp] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// cache_matrix / cache_none application in 3D (Eq. 14-15), one workgroup per patch: L_i from its
+// stored values or from the operator rows, banded Cholesky of K, then per velocity component the
+// forward substitution of [B_c | g_c (| e_m)] and its Schur contribution, the Cholesky of -S and the
+// pressure solve; x[i] += omega times the centre entries. x == nullptr: factorise only and report
+// singular blocks (set-up validation).
+__global__ void __launch_bounds__(256) patch_solve3c_kernel(
+    const OpConsts* __restrict__ oc, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
+    const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
+    const double* __restrict__ r, double* __restrict__ x, double omega, int* err, const int* __restrict__ node_op,
+    const double* __restrict__ nsten) {
+  constexpr int NV = Patch3LDS::NV, NP = Patch3LDS::NP, NB = Patch3LDS::NB, NX = Patch3LDS::NX;
+  __shared__ Patch3LDS sh;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n = oc->n;
+  const int mc = vel_center<3>(), ip = pres_center<3>();
+  const bool rows = policy != FCGMG_CACHE_MATRIX;
+  for (int64_t node = blockIdx.x; node < N; node += gridDim.x) {
+    int c[3];
+    node_coords<3>(node, n, c);
+    const double* vals = nullptr;
+    if (!rows) {
+      const int cls = node_class[node];
+      vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
+    }
+    for (int i = tid; i < NV * NB; i += nt) sh.Kb[i] = 0;
+    for (int i = tid; i < NP * NP; i += nt) sh.S[i] = 0;
+    if (tid == 0) sh.bad = 0;
+    // the pressure right-hand side
+    for (int q = tid; q < NP; q += nt) {
+      double val = 0;
+      if (r && pres_in_grid<3>(c, n, q)) {
+        const int cc[3] = {c[0] + q % 3 - 1, c[1] + (q / 3) % 3 - 1, c[2] + q / 9 - 1};
+        val = r[3 * N + node_index<3>(cc, n)];
+      }
+      sh.t[q] = val;
+    }
+    __syncthreads();
+    patch3_load(sh, -1, rows, oc, node_op, nsten, pattern, npat, vals, c);
+    __syncthreads();
+    patch_pad<3>(sh, c, n);
+    patch3_cholesky(sh);
+    for (int cmp = 0; cmp < 3; ++cmp) {
+      for (int i = tid; i < NV * NX; i += nt) sh.X[i] = 0;
+      __syncthreads();
+      patch3_load(sh, cmp, rows, oc, node_op, nsten, pattern, npat, vals, c);
+      // g_c = R_i r (zero outside the grid), and for the first component the unit column e_m
+      for (int v = tid; v < NV; v += nt) {
+        double val = 0;
+        if (r && vel_in_grid<3>(c, n, v)) {
+          const int cc[3] = {c[0] + v % 5 - 2, c[1] + (v / 5) % 5 - 2, c[2] + v / 25 - 2};
+          val = r[cmp * N + node_index<3>(cc, n)];
+        }
+        sh.X[v * NX + NP] = val;
+        if (cmp == 0) sh.X[v * NX + NP + 1] = v == mc ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      patch3_forward(sh, cmp == 0 ? NX : NX - 1);
+      if (cmp == 0) {
+        for (int v = tid; v < NV; v += nt) sh.y[v] = sh.X[v * NX + NP + 1];
+        __syncthreads();
+      }
+      patch3_schur(sh, cmp);
+    }
+    schur_cholesky<3>(sh);
+    schur_solve<3>(sh);
+    if (x != nullptr && tid <= 3) {
+      double yv;
+      if (tid < 3) {
+        double s = sh.qg[tid];
+        for (int j = 0; j < NP; ++j) s -= sh.w[tid][j] * sh.t[j];
+        yv = s;
+      } else {
+        yv = sh.t[ip];
+      }
+      x[tid * N + node] += omega * yv;
     }
     if (tid == 0 && sh.bad) atomicMin(err, (int)node);
     __syncthreads();
@@ -1404,6 +1680,12 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
     else
       FCG_LANES2(kSolveRows);
 #undef FCG_LANES2
+    return hipGetLastError();
+  }
+  if (D == 3 && !(policy == FCGMG_CACHE_NONE && c.none_integrate)) {
+    patch_solve3c_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, policy, L.node_class, L.Mcls, L.Mirr,
+                                                                   c.pattern, c.n_pattern, L.N, r, x, c.prm.omega,
+                                                                   c.err, L.node_op, L.nsten);
     return hipGetLastError();
   }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
