@@ -408,6 +408,15 @@ void pattern_entries(std::vector<int>& enc) {
     }
 }
 
+// Entries of one type (0: K, 1..3: B_c, 4: C) in the 3D pattern.
+int pattern_count3(int type) {
+  std::vector<int> e;
+  pattern_entries<3>(e);
+  int n = 0;
+  for (int code : e) n += (code >> 24) == type ? 1 : 0;
+  return n;
+}
+
 template <int D>
 int pattern_size() {
   std::vector<int> e;
@@ -883,22 +892,25 @@ struct Patch3LDS {
 // (cache_none). The buffers of the pass were zeroed before.
 __device__ void patch3_load(Patch3LDS& sh, int pass, bool rows, const OpConsts* __restrict__ oc,
                             const int* __restrict__ node_op, const double* __restrict__ nsten,
-                            const int* __restrict__ pattern, int npat, const double* __restrict__ vals,
-                            const int* c) {
+                            const int* __restrict__ pattern, int npat, int nk, int nbc,
+                            const double* __restrict__ vals, const int* c) {
   constexpr int NV = Patch3LDS::NV, NP = Patch3LDS::NP, NB = Patch3LDS::NB, NX = Patch3LDS::NX, NS = PT<3>::NST;
   const int tid = threadIdx.x, nt = blockDim.x;
   if (!rows) {
-    for (int e = tid; e < npat; e += nt) {
+    // the pattern lists K (nk entries), then B_x, B_y, B_z (nbc each), then C: a pass reads its parts
+    const int lo0 = pass < 0 ? 0 : nk + pass * nbc, hi0 = pass < 0 ? nk : lo0 + nbc;
+    const int lo1 = pass < 0 ? nk + 3 * nbc : 0, hi1 = pass < 0 ? npat : 0;
+    const int cnt0 = hi0 - lo0;
+    for (int t = tid; t < cnt0 + (hi1 - lo1); t += nt) {
+      const int e = t < cnt0 ? lo0 + t : lo1 + (t - cnt0);
       const int code = pattern[e];
       const int type = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;
-      if (pass < 0) {
-        if (type == 0) {
-          sh.Kb[i * NB + (i - j)] = vals[e];
-        } else if (type > 3) {
-          sh.S[i * NP + j] = vals[e];
-          sh.S[j * NP + i] = vals[e];
-        }
-      } else if (type == pass + 1) {
+      if (type == 0) {
+        sh.Kb[i * NB + (i - j)] = vals[e];
+      } else if (type > 3) {
+        sh.S[i * NP + j] = vals[e];
+        sh.S[j * NP + i] = vals[e];
+      } else {
         sh.X[i * NX + j] = vals[e];
       }
     }
@@ -1064,7 +1076,7 @@ __global__ void __launch_bounds__(256) patch_solve3c_kernel(
     const OpConsts* __restrict__ oc, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
     const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
     const double* __restrict__ r, double* __restrict__ x, double omega, int* err, const int* __restrict__ node_op,
-    const double* __restrict__ nsten) {
+    const double* __restrict__ nsten, int nk, int nbc) {
   constexpr int NV = Patch3LDS::NV, NP = Patch3LDS::NP, NB = Patch3LDS::NB, NX = Patch3LDS::NX;
   __shared__ Patch3LDS sh;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -1092,14 +1104,14 @@ __global__ void __launch_bounds__(256) patch_solve3c_kernel(
       sh.t[q] = val;
     }
     __syncthreads();
-    patch3_load(sh, -1, rows, oc, node_op, nsten, pattern, npat, vals, c);
+    patch3_load(sh, -1, rows, oc, node_op, nsten, pattern, npat, nk, nbc, vals, c);
     __syncthreads();
     patch_pad<3>(sh, c, n);
     patch3_cholesky(sh);
     for (int cmp = 0; cmp < 3; ++cmp) {
       for (int i = tid; i < NV * NX; i += nt) sh.X[i] = 0;
       __syncthreads();
-      patch3_load(sh, cmp, rows, oc, node_op, nsten, pattern, npat, vals, c);
+      patch3_load(sh, cmp, rows, oc, node_op, nsten, pattern, npat, nk, nbc, vals, c);
       // g_c = R_i r (zero outside the grid), and for the first component the unit column e_m
       for (int v = tid; v < NV; v += nt) {
         double val = 0;
@@ -1683,9 +1695,11 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
     return hipGetLastError();
   }
   if (D == 3 && !(policy == FCGMG_CACHE_NONE && c.none_integrate)) {
+    // sizes of the K and B_c parts of the stored pattern (pattern_entries lists K, B_x, B_y, B_z, C)
+    static const int nk = pattern_count3(0), nbc = pattern_count3(1);
     patch_solve3c_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, policy, L.node_class, L.Mcls, L.Mirr,
                                                                    c.pattern, c.n_pattern, L.N, r, x, c.prm.omega,
-                                                                   c.err, L.node_op, L.nsten);
+                                                                   c.err, L.node_op, L.nsten, nk, nbc);
     return hipGetLastError();
   }
   patch_solve_kernel<D><<<dim3((unsigned)nb), dim3(PT<D>::THREADS), 0, s>>>(
