@@ -971,32 +971,65 @@ __device__ __forceinline__ void patch3_wave_sync() {
 }
 
 // Forward substitution L V = X for the first ncol columns of the component buffer: a group of 8
-// lanes of one wavefront per column. For row i, lane j of the group takes the band terms k = i - 1 -
-// j - 8 t (t < 4), whose loads are all in flight together, and a butterfly over the group adds the
-// partial sums; the group's first lane writes the row's value, which the next row reads.
+// lanes of one wavefront per column, rows in blocks of 4. For a block starting at row i0, lane j of
+// the group takes the band terms k = i0 - 1 - j - 8 t (t < 4) of all four rows, whose loads are in
+// flight together, and a butterfly over the group adds each row's partial sums; the group's first
+// lane then solves the block's own 4 x 4 triangle in registers and writes the four values, which the
+// next block reads.
 __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
-  constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, NX = Patch3LDS::NX, BW = PT<3>::BW, G = 8;
+  constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, NX = Patch3LDS::NX, BW = PT<3>::BW, G = 8, RB = 4;
   static_assert(G * 4 >= BW, "four terms per lane cover the band");
   const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
   const bool act = grp < ncol;
   double* Xc = sh.X + (act ? grp : 0);
-  for (int i = 0; i < NV; ++i) {
-    double part = 0;
+  for (int i0 = 0; i0 < NV; i0 += RB) {
+    double part[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) part[r] = 0;
+    double rhs[RB], lblk[RB][RB];
     if (act) {
-      double a[4], b[4];
+      double xv[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int k = i - 1 - j - G * t;
-        const bool ok = k >= 0 && k >= i - BW;
-        a[t] = ok ? sh.Kb[i * NB + (i - k)] : 0.0;
-        b[t] = ok ? Xc[k * NX] : 0.0;
+        const int k = i0 - 1 - j - G * t;
+        xv[t] = k >= 0 ? Xc[k * NX] : 0.0;
       }
+      double a[RB][4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) part += a[t] * b[t];
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = i0 + r, k = i0 - 1 - j - G * t;
+          a[r][t] = (row < NV && k >= 0 && k >= row - BW) ? sh.Kb[row * NB + (row - k)] : 0.0;
+        }
+      if (j == 0)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int row = i0 + r;
+          rhs[r] = row < NV ? Xc[row * NX] : 0.0;
+#pragma unroll
+          for (int q = 0; q <= r; ++q) lblk[r][q] = row < NV ? sh.Kb[row * NB + (r - q)] : 1.0;
+        }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) part[r] += a[r][t] * xv[t];
     }
 #pragma unroll
-    for (int m = 1; m < G; m <<= 1) part += __shfl_xor(part, m, G);
-    if (act && j == 0) Xc[i * NX] = (Xc[i * NX] - part) / sh.Kb[i * NB];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int m = 1; m < G; m <<= 1) part[r] += __shfl_xor(part[r], m, G);
+    if (act && j == 0) {
+      double v[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        double s = rhs[r] - part[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) s -= lblk[r][q] * v[q];
+        v[r] = s / lblk[r][r];
+        if (i0 + r < NV) Xc[(i0 + r) * NX] = v[r];
+      }
+    }
     patch3_wave_sync();
   }
   __syncthreads();
@@ -1004,33 +1037,81 @@ __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
 
 // Banded Cholesky K = L L^T in place with one barrier per column: at step k every thread updates its
 // entries (ii, jj), k < jj <= ii <= k + BW, of the trailing band by K_ii,k K_jj,k / K_kk from the still
-// unscaled column k, and scales column k - 1, which no thread reads any more; the last column is
-// scaled after the loop. Thread (a, b) of the 8 x 32 layout takes rows k + 1 + a + 8 s and column
-// k + 1 + b.
+// unscaled column k (its four entries' loads in flight together), and scales column k - 1, which no
+// thread reads any more; the last column is scaled after the loop. Thread (a, b) of the 8 x 32 layout
+// takes rows k + 1 + a + 8 s (s < 4) and column k + 1 + b.
 __device__ void patch3_cholesky(Patch3LDS& sh) {
   constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, BW = PT<3>::BW;
   const int a = (int)threadIdx.x / 32, b = (int)threadIdx.x % 32;
   for (int k = 0; k < NV; ++k) {
     if (k > 0) {
-      // scale column k - 1 by its square root (entries below the diagonal, then the diagonal)
-      const int kp = k - 1;
-      const double lp = sqrt(sh.Kb[kp * NB]);
+      // scale column k - 1 below the diagonal by 1 / sqrt(its diagonal)
+      const int kp = k - 1, i = kp + 1 + (int)threadIdx.x;
       const int lastp = kp + BW < NV - 1 ? kp + BW : NV - 1;
-      for (int i = kp + 1 + (int)threadIdx.x; i <= lastp; i += (int)blockDim.x) sh.Kb[i * NB + (i - kp)] /= lp;
+      if (i <= lastp) sh.Kb[i * NB + (i - kp)] *= 1.0 / sqrt(sh.Kb[kp * NB]);
     }
     const double dkk = sh.Kb[k * NB];
     if (threadIdx.x == 0 && !(dkk > 0.0)) sh.bad = 1;
     const int last = k + BW < NV - 1 ? k + BW : NV - 1;
     const int jj = k + 1 + b;
     if (jj <= last) {
-      const double cj = sh.Kb[jj * NB + (jj - k)];
-      for (int ii = k + 1 + a; ii <= last; ii += 8)
-        if (ii >= jj) sh.Kb[ii * NB + (ii - jj)] -= sh.Kb[ii * NB + (ii - k)] * cj / dkk;
+      const double cj = sh.Kb[jj * NB + (jj - k)] / dkk;
+      double li[4], kv[4];
+      int idx[4];
+      bool ok[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int ii = k + 1 + a + 8 * s;
+        ok[s] = ii <= last && ii >= jj;
+        idx[s] = ok[s] ? ii * NB + (ii - jj) : 0;
+        li[s] = ok[s] ? sh.Kb[ii * NB + (ii - k)] : 0.0;
+        kv[s] = ok[s] ? sh.Kb[idx[s]] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (ok[s]) sh.Kb[idx[s]] = kv[s] - li[s] * cj;
     }
     __syncthreads();
     if (k > 0 && threadIdx.x == 0) sh.Kb[(k - 1) * NB] = sqrt(sh.Kb[(k - 1) * NB]);
   }
   if (threadIdx.x == 0) sh.Kb[(NV - 1) * NB] = sqrt(sh.Kb[(NV - 1) * NB]);
+  __syncthreads();
+}
+
+// Dense Cholesky of F = -S (27 x 27, lower factor in sh.S) with one barrier per column, the same
+// scheme as patch3_cholesky.
+__device__ void patch3_schur_cholesky(Patch3LDS& sh) {
+  constexpr int NP = Patch3LDS::NP;
+  const int a = (int)threadIdx.x / 32, b = (int)threadIdx.x % 32;
+  for (int e = (int)threadIdx.x; e < NP * NP; e += (int)blockDim.x) sh.S[e] = -sh.S[e];
+  __syncthreads();
+  for (int k = 0; k < NP; ++k) {
+    if (k > 0) {
+      const int kp = k - 1, i = kp + 1 + (int)threadIdx.x;
+      if (i < NP) sh.S[i * NP + kp] *= 1.0 / sqrt(sh.S[kp * NP + kp]);
+    }
+    const double dkk = sh.S[k * NP + k];
+    if (threadIdx.x == 0 && !(dkk > 0.0)) sh.bad = 1;
+    const int jj = k + 1 + b;
+    if (jj < NP) {
+      const double cj = sh.S[jj * NP + k] / dkk;
+      double li[4], kv[4];
+      bool ok[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int ii = k + 1 + a + 8 * s;
+        ok[s] = ii < NP && ii >= jj;
+        li[s] = ok[s] ? sh.S[ii * NP + k] : 0.0;
+        kv[s] = ok[s] ? sh.S[ii * NP + jj] : 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (ok[s]) sh.S[(k + 1 + a + 8 * s) * NP + jj] = kv[s] - li[s] * cj;
+    }
+    __syncthreads();
+    if (k > 0 && threadIdx.x == 0) sh.S[(k - 1) * NP + (k - 1)] = sqrt(sh.S[(k - 1) * NP + (k - 1)]);
+  }
+  if (threadIdx.x == 0) sh.S[(NP - 1) * NP + (NP - 1)] = sqrt(sh.S[(NP - 1) * NP + (NP - 1)]);
   __syncthreads();
 }
 
@@ -1130,7 +1211,7 @@ __global__ void __launch_bounds__(256) patch_solve3c_kernel(
       }
       patch3_schur(sh, cmp);
     }
-    schur_cholesky<3>(sh);
+    patch3_schur_cholesky(sh);
     schur_solve<3>(sh);
     if (x != nullptr && tid <= 3) {
       double yv;
