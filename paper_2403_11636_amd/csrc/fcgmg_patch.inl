@@ -880,6 +880,7 @@ struct Patch3LDS {
   double Kb[NV * NB];  // lower band of K, then its Cholesky factor
   double X[NV * NX];   // [B_c | g_c | e_m] of one component, then L^{-1} of it
   double y[NV];        // L^{-1} e_m (row m of K^{-1} after the back substitution implied by y^T V)
+  double rd[NV];       // 1 / L_ii
   double S[NP * NP];   // C - sum_c V_c^T V_c, then the Cholesky factor of -S
   double t[NP];        // pressure right-hand side, then the pressures
   double w[3][NP];     // y^T V_c
@@ -974,11 +975,11 @@ __device__ __forceinline__ void patch3_wave_sync() {
 // lanes of one wavefront per column, rows in blocks of 4. For a block starting at row i0, lane j of
 // the group takes the band terms k = i0 - 1 - j - 8 t (t < 4) of all four rows, whose loads are in
 // flight together, and a butterfly over the group adds each row's partial sums; the group's first
-// lane then solves the block's own 4 x 4 triangle in registers and writes the four values, which the
-// next block reads.
+// lane then solves the block's own 4 x 4 triangle in registers (multiplying by the stored reciprocal
+// diagonal) and writes the four values, which the next block reads.
 __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
   constexpr int NV = Patch3LDS::NV, NB = Patch3LDS::NB, NX = Patch3LDS::NX, BW = PT<3>::BW, G = 8, RB = 4;
-  static_assert(G * 4 >= BW, "four terms per lane cover the band");
+  static_assert(G * 4 >= BW && RB <= G * 4 - BW + 1 + RB, "four terms per lane cover the band");
   const int grp = (int)threadIdx.x / G, j = (int)threadIdx.x % G;
   const bool act = grp < ncol;
   double* Xc = sh.X + (act ? grp : 0);
@@ -986,7 +987,7 @@ __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
     double part[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) part[r] = 0;
-    double rhs[RB], lblk[RB][RB];
+    double rhs[RB], rdg[RB], lblk[RB][RB];
     if (act) {
       double xv[4];
 #pragma unroll
@@ -1007,8 +1008,9 @@ __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
         for (int r = 0; r < RB; ++r) {
           const int row = i0 + r;
           rhs[r] = row < NV ? Xc[row * NX] : 0.0;
+          rdg[r] = row < NV ? sh.rd[row] : 1.0;
 #pragma unroll
-          for (int q = 0; q <= r; ++q) lblk[r][q] = row < NV ? sh.Kb[row * NB + (r - q)] : 1.0;
+          for (int q = 0; q < r; ++q) lblk[r][q] = row < NV ? sh.Kb[row * NB + (r - q)] : 0.0;
         }
 #pragma unroll
       for (int r = 0; r < RB; ++r)
@@ -1026,7 +1028,7 @@ __device__ void patch3_forward(Patch3LDS& sh, int ncol) {
         double s = rhs[r] - part[r];
 #pragma unroll
         for (int q = 0; q < r; ++q) s -= lblk[r][q] * v[q];
-        v[r] = s / lblk[r][r];
+        v[r] = s * rdg[r];
         if (i0 + r < NV) Xc[(i0 + r) * NX] = v[r];
       }
     }
@@ -1075,6 +1077,8 @@ __device__ void patch3_cholesky(Patch3LDS& sh) {
     if (k > 0 && threadIdx.x == 0) sh.Kb[(k - 1) * NB] = sqrt(sh.Kb[(k - 1) * NB]);
   }
   if (threadIdx.x == 0) sh.Kb[(NV - 1) * NB] = sqrt(sh.Kb[(NV - 1) * NB]);
+  __syncthreads();
+  for (int i = (int)threadIdx.x; i < NV; i += (int)blockDim.x) sh.rd[i] = 1.0 / sh.Kb[i * NB];
   __syncthreads();
 }
 
