@@ -680,8 +680,10 @@ def autotune_extra(torch, fcgmg, prob, reps=20, steps=20):
         k = res["shape"][lev]
         levels.append({"level": lev, "n_cells": prob.level_cells(lev), "tuned": list(shapes[k]),
                        "us_per_shape": [round(u, 2) for u in us]})
+    table = h.tuning_table(res)
     h.close()
     return {"workload": prob.name, "shapes_tile_x_tile_y_threads_waves_per_simd": [list(s) for s in shapes],
+            "choice_by_level_cells": {k: list(v) for k, v in table.items()},
             "reps": reps, "tune_s": round(tune_s, 3), "vcycle_ms_default": round(ms_default, 4),
             "vcycle_ms_tuned": round(ms_tuned, 4), "levels": levels}
 

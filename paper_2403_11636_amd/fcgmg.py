@@ -303,6 +303,28 @@ class Hierarchy:
         """Use fused-sweep shape k (-1 = default by size) on `level`, e.g. a stored autotune choice."""
         _check(load().fcgmg_set_fused_shape(self.h, int(level), int(k), _stream_ptr(stream)))
 
+    def tuning_table(self, result: dict) -> dict:
+        """The choices of `autotune` keyed by level size: {"<cells per axis>": (tile_x, tile_y, threads,
+        waves_per_simd)}, for storing (JSON) and applying to other hierarchies with `apply_tuning`."""
+        table = {}
+        for lev, k in enumerate(result["shape"]):
+            if k >= 0:
+                table[str(self.prob.level_cells(lev))] = tuple(fused_shape(k))
+        return table
+
+    def apply_tuning(self, table: dict, stream=None) -> list:
+        """Give every level whose size appears in `table` the stored shape; returns the shape index per
+        level afterwards (-1 where the table has no entry: the default by size)."""
+        by_dims = {tuple(fused_shape(k)): k for k in range(N_FUSED_SHAPES)}
+        out = []
+        for lev in range(self.n_levels):
+            dims = table.get(str(self.prob.level_cells(lev)))
+            k = by_dims.get(tuple(dims), -1) if dims is not None else -1
+            if k >= 0 and lev > 0:
+                self.set_fused_shape(lev, k, stream)
+            out.append(k if lev > 0 else -1)
+        return out
+
     def set_cache_none_assembly(self, integrate: bool):
         """cache_none: read each block from the operator rows (False, default) or assemble it from the
         window's element integrals with its cut cells integrated on the fly (True)."""

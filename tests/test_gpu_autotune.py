@@ -119,3 +119,25 @@ def test_autotune_leaves_other_policies_alone():
     assert all(u == -1.0 for row in res["us"] for u in row)
     with pytest.raises(RuntimeError):
         h.set_fused_shape(h.n_levels - 1, 0)
+
+
+def test_stored_choices_apply_by_level_size():
+    # the autotuner's choices, stored by level size, give another hierarchy with those level sizes
+    # the same shapes and the same bits
+    import json
+    f = fcg()
+    p = inputs.config2(0, 256, 6)
+    ht = f.Hierarchy(p, f.CACHE_INVERSE)
+    table = json.loads(json.dumps(ht.tuning_table(ht.autotune(reps=2))))
+    assert len(table) == ht.n_levels - 1
+    q = inputs.config2(1, 256, 6)   # another geometry, the same level sizes
+    ha, hd = f.Hierarchy(q, f.CACHE_INVERSE), f.Hierarchy(q, f.CACHE_INVERSE)
+    shapes = ha.apply_tuning(table)
+    for lev in range(1, ha.n_levels):
+        assert f.fused_shape(shapes[lev]) == tuple(table[str(q.level_cells(lev))])
+    b = hd.rhs()
+    xa, xd = ha.zeros(), hd.zeros()
+    for _ in range(2):
+        ha.vcycle(xa, b)
+        hd.vcycle(xd, b)
+    assert np.array_equal(host(xa), host(xd))
