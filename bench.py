@@ -691,7 +691,8 @@ def autotune_extra(torch, fcgmg, prob, reps=20, steps=20):
 def stacked_extra(torch, fcgmg, prob, nrhs=8, reps=5):
     """Stacked right-hand sides on one geometry: two sweeps of nrhs vectors through fcgmg_smooth_multi
     (each streamed patch's rows read once per sweep for all vectors) against nrhs separate two-sweep
-    smooth calls, per sweep of all vectors."""
+    smooth calls, per sweep of all vectors; then one V-cycle of every vector through fcgmg_vcycle_multi
+    against nrhs fcgmg_vcycle calls."""
     h = fcgmg.Hierarchy(prob, fcgmg.CACHE_INVERSE)
     n = h.ndofs()
     g = torch.Generator(device="cuda")
@@ -718,10 +719,28 @@ def stacked_extra(torch, fcgmg, prob, nrhs=8, reps=5):
     e1.record()
     torch.cuda.synchronize()
     separate = e0.elapsed_time(e1) / (2 * reps)
+    # one V-cycle of every vector: fcgmg_vcycle_multi against nrhs fcgmg_vcycle calls
+    h.vcycle_multi(X, B, nrhs)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        h.vcycle_multi(X, B, nrhs)
+    e1.record()
+    torch.cuda.synchronize()
+    stacked_cycle = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        for k in range(nrhs):
+            h.vcycle(xs[k], bs[k])
+    e1.record()
+    torch.cuda.synchronize()
+    separate_cycle = e0.elapsed_time(e1) / reps
     h.close()
     return {"workload": prob.name, "nrhs": nrhs, "stacked_ms_per_sweep": round(stacked, 4),
             "separate_ms_per_sweep": round(separate, 4), "speedup": round(separate / stacked, 2),
-            "stacked_dof_per_s": round(nrhs * n / (stacked * 1e-3), 1)}
+            "stacked_dof_per_s": round(nrhs * n / (stacked * 1e-3), 1),
+            "stacked_ms_per_vcycle": round(stacked_cycle, 4), "separate_ms_per_vcycle": round(separate_cycle, 4),
+            "vcycle_speedup": round(separate_cycle / stacked_cycle, 2)}
 
 
 def main():

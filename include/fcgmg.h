@@ -168,6 +168,16 @@ int fcgmg_smooth_noalloc(fcgmg_h h, int level, double* x, const double* b, int s
 int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double* r, int nrhs, int sweeps,
                        void* stream);
 
+/* One V-cycle (as fcgmg_vcycle) for each of nrhs right-hand sides of one geometry: x and b hold nrhs
+ * finest-level vectors one after another (device, FP64, each (d+1) N_fine). cache_inverse only.
+ * Every result is bitwise that of fcgmg_vcycle on its vector. In 3D each sweep of every level
+ * streams the individual patches' inverse rows once for all vectors (as fcgmg_smooth_multi); in 2D
+ * the vectors take the fused single-vector cycle in turn. The first 3D call allocates a workspace of
+ * 8 vectors of r per level and of x and b per coarse level, kept by the handle (counted by
+ * fcgmg_device_bytes, not by fcgmg_footprint_bytes). Errors: E_ARG (nrhs outside 1..8, another policy),
+ * E_NOMEM, E_HIP. */
+int fcgmg_vcycle_multi(fcgmg_h h, double* x, const double* b, int nrhs, void* stream);
+
 /* b_coarse = R r_fine with R = P^T (Eq. 13, T = identity): level `fine_level` to fine_level-1. */
 int fcgmg_restrict(fcgmg_h h, int fine_level, const double* r_fine, double* b_coarse, void* stream);
 

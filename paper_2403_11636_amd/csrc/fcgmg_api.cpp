@@ -812,6 +812,78 @@ int vcycle_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s, bool x_zer
   return smooth_impl<D, T>(c, l, x, b, c.prm.nu_post, s, 2, cx);
 }
 
+// The sweeps of one level for nrhs vectors of one geometry (vectors nd apart): per sweep the
+// residual and the shared-class rows per vector, then one stacked launch that streams each individual
+// patch's rows once for all vectors. Per vector the arithmetic is that of sweep_impl.
+template <int D>
+int sweeps_multi(const Ctx& c, int l, double* x, const double* b, double* r, int nrhs, int sweeps, hipStream_t s) {
+  const Level& L = c.lev[l];
+  const int64_t nd = (D + 1) * L.N;
+  int rc;
+  for (int it = 0; it < sweeps; ++it) {
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = residual_impl<D>(c, l, x + k * nd, b + k * nd, r + k * nd, s))) return rc;
+    if (L.n_classes)
+      for (int k = 0; k < nrhs; ++k)
+        if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s,
+                         [&] { return k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, s); })))
+          return rc;
+    if (L.n_irr)
+      if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s,
+                       [&] { return k_apply_irregular_multi<D, double>(c, L, r, x, nd, nrhs, s); })))
+        return rc;
+  }
+  return FCGMG_OK;
+}
+
+// The V-cycle of vcycle_impl (3D, unfused sweeps) for nrhs vectors of one geometry: every step per
+// vector, except the streamed patch rows, which each sweep reads once for all vectors. The coarse
+// levels use the handle's multi-vector workspace. Per vector the result is that of vcycle_impl.
+template <int D>
+int vcycle_multi_impl(const Ctx& c, int l, double* x, const double* b, int nrhs, hipStream_t s, bool x_zero) {
+  const Level& L = c.lev[l];
+  const int64_t nd = (D + 1) * L.N;
+  int rc;
+  if (l == 0) {
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = coarse_impl<double>(c, b + k * nd, x + k * nd, s))) return rc;
+    return FCGMG_OK;
+  }
+  if (x_zero)
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x + k * nd, nd, s); }))) return rc;
+  if ((rc = sweeps_multi<D>(c, l, x, b, L.rm, nrhs, c.prm.nu_pre, s))) return rc;
+  const Level& C = c.lev[l - 1];
+  const int64_t ndc = (D + 1) * C.N;
+  for (int k = 0; k < nrhs; ++k) {
+    if ((rc = residual_impl<D>(c, l, x + k * nd, b + k * nd, L.rm + k * nd, s))) return rc;
+    if ((rc = restrict_impl<D>(c, l, L.rm + k * nd, C.bm + k * ndc, s))) return rc;
+  }
+  if ((rc = vcycle_multi_impl<D>(c, l - 1, C.xm, C.bm, nrhs, s, true))) return rc;
+  for (int k = 0; k < nrhs; ++k)
+    if ((rc = prolong_impl<D, double>(c, l, C.xm + k * ndc, x + k * nd, s))) return rc;
+  return sweeps_multi<D>(c, l, x, b, L.rm, nrhs, c.prm.nu_post, s);
+}
+
+// Allocate the multi-vector workspace (kMaxRhs vectors of r on every level, of x and b on the coarse
+// levels) on first use; it stays with the handle.
+int multi_workspace(Ctx& c) {
+  if (c.multi_ready) return FCGMG_OK;
+  const int nlev = (int)c.lev.size();
+  int rc;
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = c.lev[l];
+    const size_t nd = (size_t)(c.prm.dim + 1) * (size_t)L.N;
+    if ((rc = alloc_n(c, &L.rm, (size_t)kMaxRhs * nd))) return rc;
+    if (l < nlev - 1) {
+      if ((rc = alloc_n(c, &L.xm, (size_t)kMaxRhs * nd))) return rc;
+      if ((rc = alloc_n(c, &L.bm, (size_t)kMaxRhs * nd))) return rc;
+    }
+  }
+  c.multi_ready = true;
+  return FCGMG_OK;
+}
+
 // x += V32(0, r): the FP32 V-cycle on the residual equation of the finest level from a zero guess
 // (mixed precision). r is rounded into the finest level's FP32 right-hand side, the correction
 // widened and added to the FP64 x.
@@ -1315,30 +1387,35 @@ int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double*
     const fcg::Ctx& c = *h;
     const fcg::Level& L = c.lev[level];
     const int64_t nd = (D + 1) * L.N;
-    int rc;
     if constexpr (D == 2) {
+      int rc;
       // 2D: the fused sweep of each vector (x and r in LDS per tile) is faster than the stacked
       // unfused sweep; the results are the same bits either way
       for (int k = 0; k < nrhs; ++k)
         if ((rc = smooth_impl<2>(c, level, x + k * nd, b + k * nd, sweeps, s))) return rc;
       return FCGMG_OK;
     }
-    for (int it = 0; it < sweeps; ++it) {
-      for (int k = 0; k < nrhs; ++k)
-        if ((rc = residual_impl<D>(c, level, x + k * nd, b + k * nd, r + k * nd, s))) return rc;
-      if (L.n_classes)
-        for (int k = 0; k < nrhs; ++k)
-          if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, level, s,
-                                [&] { return fcg::k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, s); })))
-            return rc;
-      if (L.n_irr)
-        if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, level, s,
-                              [&] { return fcg::k_apply_irregular_multi<D, double>(c, L, r, x, nd, nrhs, s); })))
-          return rc;
-    }
-    return FCGMG_OK;
+    return sweeps_multi<D>(c, level, x, b, r, nrhs, sweeps, s);
   };
   return h->prm.dim == 2 ? run(std::integral_constant<int, 2>{}) : run(std::integral_constant<int, 3>{});
+}
+
+int fcgmg_vcycle_multi(fcgmg_h h, double* x, const double* b, int nrhs, void* stream) {
+  if (!h || !x || !b) return fail(FCGMG_E_ARG, "bad handle or pointer");
+  if (nrhs < 1 || nrhs > fcg::kMaxRhs) return fail(FCGMG_E_ARG, "nrhs must be in [1,8]");
+  if (h->prm.cache_policy != FCGMG_CACHE_INVERSE) return fail(FCGMG_E_ARG, "vcycle_multi needs the cache_inverse policy");
+  hipStream_t s = (hipStream_t)stream;
+  const int top = (int)h->lev.size() - 1;
+  const int64_t nd = (int64_t)(h->prm.dim + 1) * h->lev[top].N;
+  int rc;
+  if (h->prm.dim == 2) {
+    // 2D: the fused per-vector cycle is faster than stacking (see fcgmg_smooth_multi); same bits
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = vcycle_impl<2>(*h, top, x + k * nd, b + k * nd, s))) return rc;
+    return FCGMG_OK;
+  }
+  if ((rc = multi_workspace(*h))) return rc;
+  return vcycle_multi_impl<3>(*h, top, x, b, nrhs, s, false);
 }
 
 int fcgmg_restrict(fcgmg_h h, int fine_level, const double* rf, double* bc, void* stream) {

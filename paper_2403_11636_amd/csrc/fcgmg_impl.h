@@ -114,6 +114,9 @@ struct Level {
   int* fused_extra = nullptr;  // 2D cache_inverse: extra workgroups of heavy tiles (plan_fused2)
   int n_fused_extra = 0;
   int fused_extra_cap = 0;     // ints allocated for fused_extra
+  double* rm = nullptr;        // fcgmg_vcycle_multi workspace: kMaxRhs residuals
+  double* xm = nullptr;        //   kMaxRhs iterates (coarse levels)
+  double* bm = nullptr;        //   kMaxRhs right-hand sides (coarse levels)
   int fshape = -1;             // fused-sweep tile shape chosen by fcgmg_autotune, -1: default by size
   int64_t n_classes = 0, n_irr = 0, irr_cols = 0;
   int64_t n_zrows = 0;        // streamed row blocks (n_irr, fewer where wall patches share rows)
@@ -244,7 +247,8 @@ struct Ctx {
   int* err = nullptr;            // device error flag: first failing patch node, or INT_MAX
   int* pattern = nullptr;        // cache_matrix sparse pattern (encoded entries)
   int n_pattern = 0;
-  bool none_integrate = false;  // cache_none: assemble from element integrals, cut cells integrated per sweep
+  bool none_integrate = false;
+  bool multi_ready = false;     // fcgmg_vcycle_multi workspace allocated  // cache_none: assemble from element integrals, cut cells integrated per sweep
   size_t bytes = 0;
   std::vector<void*> allocs;
   // event profiler

@@ -24,7 +24,7 @@ OK, E_ARG, E_NOMEM, E_HIP, E_SINGULAR, E_NOCONV, E_NAN = 0, -1, -2, -3, -4, -5, 
 
 EXPORTS = [
     "fcgmg_setup_hierarchy", "fcgmg_num_levels", "fcgmg_num_dofs", "fcgmg_level_stats_get", "fcgmg_rhs",
-    "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_noalloc", "fcgmg_smooth_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
+    "fcgmg_residual", "fcgmg_smooth", "fcgmg_smooth_noalloc", "fcgmg_smooth_multi", "fcgmg_vcycle_multi", "fcgmg_restrict", "fcgmg_prolongate_add", "fcgmg_coarse_solve",
     "fcgmg_vcycle", "fcgmg_vcycle_fp32", "fcgmg_solve", "fcgmg_norm", "fcgmg_device_bytes", "fcgmg_footprint_bytes", "fcgmg_destroy", "fcgmg_last_error",
     "fcgmg_profile_enable", "fcgmg_profile_reset", "fcgmg_profile_read",
     "fcgmg_autotune", "fcgmg_fused_shape", "fcgmg_set_fused_shape", "fcgmg_set_cache_none_assembly",
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_smooth.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.fcgmg_smooth_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.fcgmg_smooth_multi.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    L.fcgmg_vcycle_multi.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.fcgmg_restrict.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fcgmg_prolongate_add.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.fcgmg_coarse_solve.argtypes = [vp, vp, vp, vp]
@@ -373,6 +374,12 @@ class Hierarchy:
         n = self.ndofs(level) * nrhs
         _check(load().fcgmg_smooth_multi(self.h, level, _dptr(x, "x", n), _dptr(b, "b", n), _dptr(r, "r", n), nrhs,
                                          sweeps, _stream_ptr(stream)))
+        return x
+
+    def vcycle_multi(self, x, b, nrhs: int, stream=None):
+        """One V-cycle for each of nrhs stacked finest-level vectors (x, b: nrhs vectors one after another)."""
+        n = self.ndofs() * nrhs
+        _check(load().fcgmg_vcycle_multi(self.h, _dptr(x, "x", n), _dptr(b, "b", n), nrhs, _stream_ptr(stream)))
         return x
 
     def restrict(self, r_fine, fine_level: Optional[int] = None, out=None, stream=None):

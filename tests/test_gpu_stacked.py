@@ -1,6 +1,7 @@
-"""Stacked right-hand sides (fcgmg_smooth_multi): nrhs vectors of one geometry smoothed together, the
-inverse rows of every streamed patch read once per sweep. Each result must equal fcgmg_smooth on that
-vector bit for bit (the per-vector arithmetic is the same); one case is also checked against the oracle.
+"""Stacked right-hand sides (fcgmg_smooth_multi, fcgmg_vcycle_multi): nrhs vectors of one geometry
+smoothed (or cycled) together, the inverse rows of every streamed patch read once per sweep. Each result
+must equal fcgmg_smooth (fcgmg_vcycle) on that vector bit for bit (the per-vector arithmetic is the
+same); one case of each is also checked against the oracle.
 """
 import numpy as np
 import pytest
@@ -82,4 +83,64 @@ def test_stacked_rejects_bad_arguments():
     x = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
     with pytest.raises(f.FcgmgError):
         hm.smooth_multi(x, x.clone(), x.clone(), 2, 1)
+    hm.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+@pytest.mark.parametrize("name", list(CASES))
+def test_stacked_vcycle_equals_single_vcycles(name, nrhs):
+    # fcgmg_vcycle_multi: two cycles in a row (the second reuses the workspace and starts from the
+    # first's iterates), every vector bitwise that of fcgmg_vcycle on it
+    f = fcg()
+    h = f.Hierarchy(CASES[name](), f.CACHE_INVERSE)
+    n = h.ndofs()
+    X = np.concatenate([inputs.random_vector(n, 500 + k) for k in range(nrhs)])
+    B = np.concatenate([inputs.random_vector(n, 600 + k) for k in range(nrhs)])
+    xm, bm = dev(X), dev(B)
+    xs = [dev(X[k * n:(k + 1) * n]) for k in range(nrhs)]
+    for cycle in range(2):
+        h.vcycle_multi(xm, bm, nrhs)
+        for k in range(nrhs):
+            h.vcycle(xs[k], bm[k * n:(k + 1) * n])
+            assert torch.equal(xm[k * n:(k + 1) * n], xs[k]), (cycle, k)
+    # a smaller stack after a larger one on the same handle
+    if nrhs > 1:
+        h.vcycle_multi(xm[:n], bm[:n], 1)
+        h.vcycle(xs[0], bm[:n])
+        assert torch.equal(xm[:n], xs[0])
+    h.close()
+
+
+def test_stacked_vcycle_against_oracle():
+    from oracle.oracle import MODE_INVERSE
+    f = fcg()
+    p = CASES["3d_12_l2_s3"]()
+    h = f.Hierarchy(p, f.CACHE_INVERSE)
+    o = Oracle(p)
+    n = h.ndofs()
+    B = np.concatenate([o.rhs() * (1.0 + 0.25 * k) + 1e-3 * inputs.random_vector(n, 700 + k) for k in range(3)])
+    xm = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    h.vcycle_multi(xm, dev(B), 3)
+    torch.cuda.synchronize()
+    got = xm.cpu().numpy()
+    for k in range(3):
+        b = B[k * n:(k + 1) * n]
+        ref = o.vcycle(np.zeros(n), b, mode=MODE_INVERSE)
+        err = np.linalg.norm(got[k * n:(k + 1) * n] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, (k, err)
+    h.close()
+
+
+def test_stacked_vcycle_rejects_bad_arguments():
+    f = fcg()
+    h = f.Hierarchy(CASES["3d_8_l2_s0"](), f.CACHE_INVERSE)
+    n = h.ndofs()
+    x = torch.zeros(9 * n, dtype=torch.float64, device="cuda")
+    for nrhs in (0, 9):
+        assert f.load().fcgmg_vcycle_multi(h.h, x.data_ptr(), x.data_ptr(), nrhs, None) == f.E_ARG
+    h.close()
+    hm = f.Hierarchy(CASES["3d_8_l2_s0"](), f.CACHE_MATRIX)
+    x = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    with pytest.raises(f.FcgmgError):
+        hm.vcycle_multi(x, x.clone(), 2)
     hm.close()
