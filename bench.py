@@ -548,8 +548,9 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
     alpha_f in {1e-6, 1e-8, 1e-10}). Hierarchies are set up first (untimed). Measured: FGMRES(30)
     solves to 1e-8 one after another on one stream and through the solve server's concurrent
     workers; one V-cycle of all 256 problems one after another and as one batched cycle (one launch
-    per cycle step); the batched standalone GMG solve (at most 60 cycles; the problems on which the
-    standalone cycle does not converge are counted, not solved)."""
+    per cycle step, with one workgroup per tile or persistent sweeps); the batched standalone GMG
+    solve (at most 60 cycles; the problems on which the standalone cycle does not converge are
+    counted, not solved)."""
     probs = [inputs.batch_problem(k) for k in range(n_prob)]
     ndof = sum((p.dim + 1) * (p.n_cells + 1) ** p.dim for p in probs)
     # sequential: one stream, resident hierarchies
@@ -586,6 +587,16 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
         bt.vcycle(xs, bs)
     torch.cuda.synchronize()
     t_cyc_bat = (time.perf_counter() - t0) / 5
+    # the same batched cycle with every fused sweep as one persistent launch
+    bt.set_persistent(True)
+    bt.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        bt.vcycle(xs, bs)
+    torch.cuda.synchronize()
+    t_cyc_per = (time.perf_counter() - t0) / 5
+    bt.set_persistent(False)
     xs = [h.zeros() for h in hs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -614,6 +625,7 @@ def batch_extra(torch, fcgmg, inputs, n_prob=256, workers=4):
         "server_completed": ok, "server_cache_hits": int(sum(r["cache_hit"] for r in res)),
         "speedup": round(t_seq / t_srv, 3),
         "vcycle_all_sequential_ms": round(t_cyc_seq * 1e3, 3), "vcycle_all_batched_ms": round(t_cyc_bat * 1e3, 3),
+        "vcycle_all_batched_persistent_ms": round(t_cyc_per * 1e3, 3),
         "batched_vcycle_dof_per_s": round(ndof * 4 / t_cyc_bat, 1),
         "batched_vcycle_speedup": round(t_cyc_seq / t_cyc_bat, 2),
         "batched_gmg_solve_s": round(t_bsolve, 3), "batched_gmg_converged": len(conv),

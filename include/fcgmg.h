@@ -288,6 +288,11 @@ int fcgmg_batch_vcycle(fcgmg_batch_h bt, double* const* x, const double* const* 
  * converge in max_iter cycles (the others are converged and their x final). */
 int fcgmg_batch_solve(fcgmg_batch_h bt, double* const* x, const double* const* b, double rtol, int max_iter,
                       int* iters, double* rel_res, void* stream);
+/* on = 1: every fused sweep of the batched cycle (fcgmg_batch_vcycle, fcgmg_batch_solve) runs as one
+ * persistent launch, as many workgroups as the device holds at once, each taking every G-th tile of
+ * the launch (G workgroups) over all problems; on = 0 (default): one workgroup per tile. The results
+ * are the same bits either way. E_ARG: null handle, on not 0 or 1. */
+int fcgmg_batch_set_persistent(fcgmg_batch_h bt, int on);
 int fcgmg_batch_destroy(fcgmg_batch_h bt);
 
 /* ---- Solve server: concurrent solves with device-resident hierarchies ------------------------

@@ -39,6 +39,7 @@ struct fcgmg_batch {
   std::vector<NormJob> nj;
   std::vector<int> bj;
   std::vector<LaunchRec> launches;
+  bool persistent = false;  // fused sweeps as persistent launches (fcgmg_batch_set_persistent)
   char* host_buf = nullptr;  // pinned staging
   char* dev_buf = nullptr;
   size_t buf_cap = 0;
@@ -108,7 +109,9 @@ struct fcgmg_batch {
     const auto* d_b = reinterpret_cast<const int*>(dev_buf + o_b);
     for (const LaunchRec& L : launches) {
       hipError_t e = hipSuccess;
-      if (L.kind == kFused) e = k_batch_fused2(d_f + L.job0, d_b + L.block0, L.nblocks, s);
+      if (L.kind == kFused)
+        e = persistent ? k_batch_fused2_persistent(d_f + L.job0, d_b + L.block0, L.nblocks, s)
+                       : k_batch_fused2(d_f + L.job0, d_b + L.block0, L.nblocks, s);
       if (L.kind == kRR) e = k_batch_rr2(d_r + L.job0, d_b + L.block0, L.nblocks, s);
       if (L.kind == kDense) e = k_batch_dense(d_d + L.job0, d_b + L.block0, L.nblocks, s);
       if (L.kind == kNorm) e = k_batch_sumsq(d_n + L.job0, L.njobs, d_b + L.block0, L.nblocks, part, norms, s);
@@ -295,6 +298,12 @@ int fcgmg_batch_solve(fcgmg_batch_h bt, double* const* x, const double* const* b
   if (!live.empty())
     return set_error(FCGMG_E_NOCONV, "batch: " + std::to_string(live.size()) + " problems not converged in " +
                                          std::to_string(max_iter) + " cycles");
+  return FCGMG_OK;
+}
+
+int fcgmg_batch_set_persistent(fcgmg_batch_h bt, int on) {
+  if (!bt || (on != 0 && on != 1)) return set_error(FCGMG_E_ARG, "bad argument");
+  bt->persistent = on == 1;
   return FCGMG_OK;
 }
 

@@ -15,6 +15,13 @@ namespace fcg {
 template <class T>
 using cconst = __attribute__((address_space(4))) const T;
 
+// Device (global) memory. Pointers that a kernel reads from a table in memory (the job tables of
+// the batched launches) carry no address space, and loads through them would be issued as flat
+// instructions, which count against both the vector-memory and the LDS wait counters (a wait for an
+// LDS read then also waits for every load in flight). Cast to this space, they give global loads.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+
 namespace {
 
 constexpr int kMaxLocalBalls = 16;
@@ -421,8 +428,8 @@ __device__ __forceinline__ void stencil_apply(CF&& cf, XA&& xat, T* acc) {
 // with u = x at the node + o. The fused multiply-adds are explicit, and contraction is off here
 // and in the sums of the terms below, so that every form of the row sum rounds alike in every
 // kernel.
-template <class T>
-__device__ __forceinline__ void stored_coefs2(const T* __restrict__ p, int o, T* c) {
+template <class T, class P>
+__device__ __forceinline__ void stored_coefs2(P __restrict__ p, int o, T* c) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) c[j] = p[j * 9 + o];
 }
@@ -449,8 +456,8 @@ __device__ __forceinline__ void in_flight_together(T (&v)[K]) {
 //   = (((t0 + t8) + t4) + (t2 + t6)) + ((t1 + t5) + (t3 + t7)),
 // so that the 8-lane form (stored_rows_group2), which starts from R(l, 8), gives the same bits. The
 // coefficients load in three batches of three offsets.
-template <class T, class XA>
-__device__ __forceinline__ void stored_row2(const T* __restrict__ p, XA&& xat, T* row) {
+template <class T, class XA, class P>
+__device__ __forceinline__ void stored_row2(P __restrict__ p, XA&& xat, T* row) {
 #pragma clang fp contract(off)
   auto terms = [&](const T* c, int o, T* t) {
     const int oo[3] = {o % 3 - 1, o / 3 - 1, 0};
@@ -525,10 +532,10 @@ __device__ __forceinline__ void ref_row_apply(const double* __restrict__ pack, i
 // Stored-stencil row (op >= 0), one lane: 2D sums the offset terms in the butterfly order of
 // stored_row2; 3D runs the offsets in sequence, partly rolled so that the loads of the row do not
 // all occupy registers at once.
-template <int D, class T, class XA>
-__device__ __forceinline__ void stored_row_apply(int op, const T* __restrict__ nsten, XA&& xat, T* acc) {
+template <int D, class T, class XA, class PN>
+__device__ __forceinline__ void stored_row_apply(int op, PN __restrict__ nsten, XA&& xat, T* acc) {
 #pragma clang fp contract(off)
-  const T* p = nsten + (int64_t)op * PT<D>::NSTEN;
+  const auto p = nsten + (int64_t)op * PT<D>::NSTEN;
   if constexpr (D == 2) {
     T t[3];
     stored_row2<T>(p, xat, t);
@@ -541,8 +548,8 @@ __device__ __forceinline__ void stored_row_apply(int op, const T* __restrict__ n
 
 // Row of L at a node with operator code op: the level's reference stencil of a uniform
 // neighbourhood (op < 0), or the node's own assembled stencil in nsten (op >= 0).
-template <int D, bool UNR = true, class T, class XA>
-__device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, int op, const T* __restrict__ nsten,
+template <int D, bool UNR = true, class T, class XA, class PN>
+__device__ __forceinline__ void node_row_apply(const double* __restrict__ pack, int op, PN __restrict__ nsten,
                                                XA&& xat, T* acc) {
   ref_row_apply<D, UNR, T>(pack, op, xat, acc);
   if (op >= 0) stored_row_apply<D, T>(op, nsten, xat, acc);
@@ -560,17 +567,17 @@ struct StoredList2 {
 };
 
 template <int NT, int NRES>
-__device__ __forceinline__ void stored_list_add(StoredList2<NT, NRES>& sl, int k, int e, int op) {
+__device__ __forceinline__ void stored_list_add(StoredList2<NT, NRES>& sl, int k, int e, int op, unsigned tid) {
   constexpr int NW = NT / 64;
   const bool st = op >= 0;
   const unsigned long long msk = __ballot(st);
   const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(msk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)msk, 0));
-  const int seg = k * NW + (int)(threadIdx.x >> 6);
+  const int seg = k * NW + (int)(tid >> 6);
   if (st) {
     sl.e[seg * 64 + pos] = (short)e;
     sl.op[seg * 64 + pos] = op;
   }
-  if ((threadIdx.x & 63) == 0) sl.cnt[seg] = __popcll(msk);
+  if ((tid & 63) == 0) sl.cnt[seg] = __popcll(msk);
 }
 
 // Partial sum R(j + OFF, S) of the butterfly order of stored_row2, for S >= LPN (the offsets of one
@@ -609,10 +616,10 @@ __device__ __forceinline__ void lane_tree2(int j, TF&& term, T* out) {
 // Entry e of the region (row width RW) is grid node (ox + e % RW, oy + e / RW) of the level (m
 // nodes per axis, field stride N); x comes from the LDS tile xs (row width XW, field stride XP) at
 // index (e % RW + 1) + XW (e / RW + 1).
-template <int NT, int NRES, int RW, int RP, int XW, int XP, int LPN, class T, class BF>
-__device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& sl, const T* __restrict__ nsten,
-                                                   const T* __restrict__ b, int64_t N, int m, int ox, int oy,
-                                                   const T* xs, T* rs, BF&& between) {
+template <int NT, int NRES, int RW, int RP, int XW, int XP, int LPN, class T, class BF, class PN, class PB>
+__device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& sl, PN __restrict__ nsten,
+                                                   PB __restrict__ b, int64_t N, int m, int ox, int oy,
+                                                   const T* xs, T* rs, BF&& between, unsigned tid) {
 #pragma clang fp contract(off)
   static_assert(LPN == 8 || LPN == 4 || LPN == 2, "lanes per node");
   constexpr int NSEG = StoredList2<NT, NRES>::NSEG, NG = NT / LPN;
@@ -625,7 +632,7 @@ __device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& 
 #pragma unroll
   for (int s = 0; s < NSEG; ++s) pre[s + 1] = pre[s] + sl.cnt[s];
   const int cnt = pre[NSEG];
-  const int j = threadIdx.x & (LPN - 1), g = (int)(threadIdx.x / LPN);
+  const int j = tid & (LPN - 1), g = (int)(tid / LPN);
   auto slot = [&](int t) {
     int s = 0;
 #pragma unroll
@@ -637,7 +644,7 @@ __device__ __forceinline__ void stored_rows_group2(const StoredList2<NT, NRES>& 
   auto issue = [&](int t, T* c, T* bl, int& e) {
     const int sidx = slot(t);
     e = sl.e[sidx];
-    const T* p = nsten + (int64_t)sl.op[sidx] * PT<2>::NSTEN;
+    const auto p = nsten + (int64_t)sl.op[sidx] * PT<2>::NSTEN;
     const int64_t g = (ox + e % RW) + (int64_t)m * (oy + e / RW);
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
@@ -815,8 +822,14 @@ __global__ void __launch_bounds__(256) residual_sumsq2_batch_kernel(const NormJo
   __shared__ double xs[3 * XP];
   __shared__ double sh[4];
   const NormJob J = jobs[block_job[blockIdx.x]];
+  // every pointer of the job addresses device memory (see gmem)
+  const gmem<const OpConsts>* __restrict__ oc = (const gmem<const OpConsts>*)J.oc;
+  const gmem<const double>* __restrict__ jb = (const gmem<const double>*)J.b;
+  const gmem<const double>* __restrict__ jx = (const gmem<const double>*)J.x;
+  const gmem<const int>* __restrict__ jop = (const gmem<const int>*)J.node_op;
+  const gmem<const double>* __restrict__ jst = (const gmem<const double>*)J.nsten;
   const int bid = (int)blockIdx.x - J.block0;
-  const int n = J.oc->n;
+  const int n = oc->n;
   const int m = n + 1;
   const int64_t N = (int64_t)m * m;
   const int nt[3] = {J.ntx, J.nty, 1};
@@ -829,8 +842,8 @@ __global__ void __launch_bounds__(256) residual_sumsq2_batch_kernel(const NormJo
   const int64_t node = c[0] + (int64_t)m * c[1];
   double bv[3];
 #pragma unroll
-  for (int f = 0; f < 3; ++f) bv[f] = inside ? J.b[f * N + node] : 0.0;
-  const int op = inside ? J.node_op[node] : -1;
+  for (int f = 0; f < 3; ++f) bv[f] = inside ? jb[f * N + node] : 0.0;
+  const int op = inside ? jop[node] : -1;
   double xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
@@ -838,7 +851,7 @@ __global__ void __launch_bounds__(256) residual_sumsq2_batch_kernel(const NormJo
     const int f = e / XP, p = e % XP;
     const int gx = o0 + p % XW, gy = o1 + p / XW;
     const bool ok = e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m;
-    xv[k] = ok ? J.x[f * N + gx + (int64_t)m * gy] : 0.0;
+    xv[k] = ok ? jx[f * N + gx + (int64_t)m * gy] : 0.0;
   }
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
@@ -848,7 +861,7 @@ __global__ void __launch_bounds__(256) residual_sumsq2_batch_kernel(const NormJo
   if (inside) {
     const int base = (tx + 1) + XW * (ty + 1);
     double acc[3] = {0, 0, 0};
-    node_row_apply<2, true, double>(J.oc->pack, op, J.nsten,
+    node_row_apply<2, true, double>((const double*)oc->pack, op, jst,
                                     [&](int f, const int* o) { return xs[f * XP + base + o[0] + XW * o[1]]; }, acc);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -1113,9 +1126,9 @@ hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hip
 
 // x = A b with a dense row-major n x n matrix (coarsest-grid solve through the stored inverse):
 // one wavefront per row.
-template <class T>
-__device__ __forceinline__ void dense_row(const T* __restrict__ A, int n, const T* __restrict__ b, T* __restrict__ x,
-                                          int row, int lane) {
+template <class T, class PA, class PB, class PX>
+__device__ __forceinline__ void dense_row(PA __restrict__ A, int n, PB __restrict__ b, PX __restrict__ x, int row,
+                                          int lane) {
   T s = 0;
   for (int j = lane; j < n; j += 64) s += A[(int64_t)row * n + j] * b[j];
   s = wave_sum(s);
@@ -1125,13 +1138,15 @@ __device__ __forceinline__ void dense_row(const T* __restrict__ A, int n, const 
 template <class T>
 __global__ void dense_matvec_kernel(const T* __restrict__ A, int n, const T* __restrict__ b, T* __restrict__ x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row < n) dense_row(A, n, b, x, row, threadIdx.x & 63);
+  if (row < n) dense_row<T>(A, n, b, x, row, threadIdx.x & 63);
 }
 
 __global__ void dense_matvec_batch_kernel(const DenseJob* __restrict__ jobs, const int* __restrict__ block_job) {
   const DenseJob J = jobs[block_job[blockIdx.x]];
   const int row = ((int)blockIdx.x - J.block0) * 4 + (threadIdx.x >> 6);
-  if (row < J.n) dense_row(J.A, J.n, J.b, J.x, row, threadIdx.x & 63);
+  if (row < J.n)
+    dense_row<double>((const gmem<const double>*)J.A, J.n, (const gmem<const double>*)J.b, (gmem<double>*)J.x, row,
+                      threadIdx.x & 63);
 }
 
 hipError_t k_batch_dense(const DenseJob* jobs, const int* block_job, int nblocks, hipStream_t s) {

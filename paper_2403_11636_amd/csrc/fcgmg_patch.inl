@@ -1875,14 +1875,14 @@ __device__ __forceinline__ void patch_column(int col, int* field, int* o) {
 // lane of the group returns the full sums. A wavefront holds 4 groups and each group takes two
 // patches at once (A, B), so the rows of 8 patches stream from HBM per wavefront and loop trip.
 // The arithmetic of each patch does not depend on which patch it is paired with.
-template <int D, class T, class RGA, class RGB>
-__device__ __forceinline__ void irregular_pair(const T* __restrict__ ZA, const T* __restrict__ ZB,
+template <int D, class T, class RGA, class RGB, class PZ>
+__device__ __forceinline__ void irregular_pair(PZ __restrict__ ZA, PZ __restrict__ ZB,
                                                bool has_b, int j16, RGA&& rga, RGB&& rgb, T* acca,
                                                T* accb) {
   constexpr int ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
 #pragma unroll
   for (int f = 0; f <= D; ++f) acca[f] = accb[f] = 0;
-  const T* ZBs = has_b ? ZB : ZA;
+  const PZ ZBs = has_b ? ZB : ZA;
   // 2D: the four column steps are unrolled so that all row loads are in flight at once
 #pragma unroll(D == 2 ? 4 : 4)
   for (int col = j16; col < ZS; col += 16) {
@@ -2127,19 +2127,20 @@ static_assert(kFusedBig.tx * kFusedBig.ty <= 4 * fused2_part_cap(kFusedBig) &&
 // mode 2: x_in plus the Q1 interpolation of the coarse vector xc (the coarse-grid correction of a
 // V-cycle applied as the x tile is loaded, as prolong_add would apply it).
 template <int TX, int TY, int NT, int CAP, class T>
-__device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
+__device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid, unsigned tid) {
   static_assert(NT >= TX * TY && NT % 64 == 0, "one thread per tile node at least");
-  const OpConsts* __restrict__ oc = J.oc;
-  const int* __restrict__ node_op = J.node_op;
-  const T* __restrict__ nsten = J.nsten;
-  const int* __restrict__ extra = J.extra;
-  const int* __restrict__ node_class = J.node_class;
-  const T* __restrict__ Zcls = J.Zcls;
-  const T* __restrict__ Zirr = J.Zirr;
-  const T* __restrict__ x_in = J.x_in;
-  const T* __restrict__ b = J.b;
-  T* __restrict__ x_out = J.x_out;
-  const T* __restrict__ xc = J.xc;
+  // every pointer of the job addresses device memory (see gmem)
+  const gmem<const OpConsts>* __restrict__ oc = (const gmem<const OpConsts>*)J.oc;
+  const gmem<const int>* __restrict__ node_op = (const gmem<const int>*)J.node_op;
+  const gmem<const T>* __restrict__ nsten = (const gmem<const T>*)J.nsten;
+  const gmem<const int>* __restrict__ extra = (const gmem<const int>*)J.extra;
+  const gmem<const int>* __restrict__ node_class = (const gmem<const int>*)J.node_class;
+  const T* __restrict__ Zcls = J.Zcls;  // read through the constant space (regular_apply)
+  const gmem<const T>* __restrict__ Zirr = (const gmem<const T>*)J.Zirr;
+  const gmem<const T>* __restrict__ x_in = (const gmem<const T>*)J.x_in;
+  const gmem<const T>* __restrict__ b = (const gmem<const T>*)J.b;
+  gmem<T>* __restrict__ x_out = (gmem<T>*)J.x_out;
+  const gmem<const T>* __restrict__ xc = (const gmem<const T>*)J.xc;
   const T omega = J.omega;
   const int ntx = J.ntx, nty = J.nty, mode = J.mode;
   constexpr int XW = TX + 6, XH = TY + 6, XP = XW * XH;  // x tile, halo 3
@@ -2173,14 +2174,14 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   const int bx = (tile_lin % ntx) * TX, by = (tile_lin / ntx) * TY;
   // every global load that depends on no other one is issued before the first LDS store: the own
   // patch class, the x tile, and the operator code and b of this thread's residual nodes
-  const int tx0 = threadIdx.x % TX, ty0 = threadIdx.x / TX;
-  const bool inside0 = threadIdx.x < TX * TY && bx + tx0 < m && by + ty0 < m;
+  const int tx0 = tid % TX, ty0 = tid / TX;
+  const bool inside0 = tid < TX * TY && bx + tx0 < m && by + ty0 < m;
   const int cls = inside0 ? node_class[(bx + tx0) + (int64_t)m * (by + ty0)] : -1;
   constexpr int NXL = (3 * XP + NT - 1) / NT;
   T xv[NXL];
 #pragma unroll
   for (int k = 0; k < NXL; ++k) {
-    const int e = threadIdx.x + NT * k;
+    const int e = tid + NT * k;
     const int f = e / XP, p = e % XP;
     const int gx = bx - 3 + p % XW, gy = by - 3 + p / XW;
     const bool ok = e < 3 * XP && gx >= 0 && gx < m && gy >= 0 && gy < m;
@@ -2198,7 +2199,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   if (mode == 2)
 #pragma unroll
     for (int k = 0; k < NCL; ++k) {
-      const int e = threadIdx.x + NT * k;
+      const int e = tid + NT * k;
       const int f = e / CP, p = e % CP;
       const int gx = cx0 + p % CW, gy = cy0 + p / CW;
       cv[k] = (e < 3 * CP && gx >= 0 && gx < mc && gy >= 0 && gy < mc) ? xc[f * Nc + gx + (int64_t)mc * gy] : T(0);
@@ -2207,7 +2208,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   T bvv[NRES][3];
 #pragma unroll
   for (int k = 0; k < NRES; ++k) {
-    const int e = threadIdx.x + NT * k;
+    const int e = tid + NT * k;
     const int cx = bx - 2 + e % RW, cy = by - 2 + e / RW;
     const bool ok = e < RP && cx >= 0 && cx < m && cy >= 0 && cy < m;
     const int64_t g = cx + (int64_t)m * cy;
@@ -2218,11 +2219,11 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   if (mode == 2) {
 #pragma unroll
     for (int k = 0; k < NCL; ++k)
-      if (threadIdx.x + NT * k < 3 * CP) rs[threadIdx.x + NT * k] = cv[k];
+      if (tid + NT * k < 3 * CP) rs[tid + NT * k] = cv[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NXL; ++k) {
-      const int e = threadIdx.x + NT * k;
+      const int e = tid + NT * k;
       const int f = e / XP, p = e % XP;
       const int c[3] = {bx - 3 + p % XW, by - 3 + p / XW, 0};
       if (e < 3 * XP && c[0] >= 0 && c[0] < m && c[1] >= 0 && c[1] < m)
@@ -2231,17 +2232,17 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   }
 #pragma unroll
   for (int k = 0; k < NXL; ++k)
-    if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
+    if (tid + NT * k < 3 * XP) xs[tid + NT * k] = xv[k];
   // nodes with a stored stencil are listed; groups of lanes compute their residuals
 #pragma unroll
-  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, threadIdx.x + NT * k, opv[k]);
+  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, tid + NT * k, opv[k], tid);
   __syncthreads();
   // residuals: nodes with a reference stencil per thread, while the stored rows load
   constexpr int LPN = TX * TY >= 256 ? 8 : (TX * TY >= 32 ? 4 : 2);  // lanes per stored row
   stored_rows_group2<NT, NRES, RW, RP, XW, XP, LPN, T>(sl, nsten, b, N, m, bx - 2, by - 2, xs, rs, [&] {
 #pragma unroll
     for (int k = 0; k < NRES; ++k) {
-      const int e = threadIdx.x + NT * k;
+      const int e = tid + NT * k;
       if (e < RP && opv[k] < 0) {
         const int px = e % RW, py = e / RW;
         const int cx = bx - 2 + px, cy = by - 2 + py;
@@ -2250,7 +2251,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
           const T* bv = bvv[k];
           const int xb = (px + 1) + XW * (py + 1);
           T acc[3] = {0, 0, 0};
-          ref_row_apply<2, true, T>(oc->pack, opv[k],
+          ref_row_apply<2, true, T>((const double*)oc->pack, opv[k],
                                     [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; }, acc);
 #pragma unroll
           for (int f = 0; f < 3; ++f) rv[f] = bv[f] - acc[f];
@@ -2259,7 +2260,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
         for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
       }
     }
-  });
+  }, tid);
   __syncthreads();
   const int tx = tx0, ty = ty0;
   const bool inside = inside0;
@@ -2276,15 +2277,15 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
   // Individual patches of the tile, listed in LDS in node order (one segment per wavefront, so
   // every part of a tile sees the same list); part p takes entries [p CAP, (p + 1) CAP), which
   // 16-lane groups process two patches at a time.
-  if (threadIdx.x < NWO * 64) {
+  if (tid < NWO * 64) {
     const bool irr = inside && cls < 0;
     const unsigned long long mask = __ballot(irr);
     const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
     if (irr) {
-      irr_tid[(threadIdx.x & ~63) + pos] = threadIdx.x;
-      irr_pidx[(threadIdx.x & ~63) + pos] = -cls - 1;
+      irr_tid[(tid & ~63) + pos] = tid;
+      irr_pidx[(tid & ~63) + pos] = -cls - 1;
     }
-    if ((threadIdx.x & 63) == 0) irr_wcnt[threadIdx.x >> 6] = __popcll(mask);
+    if ((tid & 63) == 0) irr_wcnt[tid >> 6] = __popcll(mask);
   }
   __syncthreads();
   int pre[NWO + 1];
@@ -2299,8 +2300,8 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
     return w * 64 + e - pre[w];
   };
   const int lo = part * CAP, hi = min(cnt, lo + CAP);
-  const int j16 = threadIdx.x & 15;
-  for (int ea = lo + (threadIdx.x >> 4); ea < hi; ea += 2 * NG) {
+  const int j16 = tid & 15;
+  for (int ea = lo + (tid >> 4); ea < hi; ea += 2 * NG) {
     const int eb = ea + NG;
     const bool has_b = eb < hi;
     const int sa = slot(ea), sb = has_b ? slot(eb) : sa;
@@ -2325,7 +2326,7 @@ __device__ __forceinline__ void fused2_body(const Fused2Job<T>& J, int bid) {
 template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 sweep_fused2_kernel(Fused2Job<T> J) {
-  fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(J, (int)blockIdx.x);
+  fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(J, (int)blockIdx.x, threadIdx.x);
 }
 
 // Batched form: the workgroups of several jobs (levels of independent problems) in one launch;
@@ -2335,7 +2336,29 @@ template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 sweep_fused2_batch_kernel(const Fused2Job<T>* __restrict__ jobs, const int* __restrict__ block_job) {
   const Fused2Job<T> J = jobs[block_job[blockIdx.x]];
-  fused2_body<TX, TY, NT, TX * TY, T>(J, (int)blockIdx.x - J.block0);
+  fused2_body<TX, TY, NT, TX * TY, T>(J, (int)blockIdx.x - J.block0, threadIdx.x);
+}
+
+// Persistent form of the batched launch: as many workgroups as the chip holds at once, workgroup w
+// taking tiles w, w + G, w + 2G, ... (G workgroups) in turn. Consecutive tiles go to consecutive
+// workgroups, and so to the XCDs in the same round-robin order as the one-tile-per-workgroup launch.
+// Every tile is taken exactly once and its arithmetic is that of that launch. (Handing out tiles by
+// an atomic ticket instead serialises on the one counter: about 11 ns per ticket, three times the
+// batched cycle's time.)
+template <int TX, int TY, int NT, int WPE, class T>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+sweep_fused2_batch_persistent_kernel(const Fused2Job<T>* __restrict__ jobs, const int* __restrict__ block_job,
+                                     int nblocks) {
+  for (int blk = (int)blockIdx.x; blk < nblocks; blk += (int)gridDim.x) {
+    // the thread index, opaque to the compiler: nothing derived from it is hoisted out of the loop,
+    // where it would stay live across every tile and spill
+    unsigned tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+    const Fused2Job<T> J = jobs[block_job[blk]];
+    fused2_body<TX, TY, NT, TX * TY, T>(J, blk - J.block0, tid);
+    // every thread is done with this tile's LDS before the next tile's stores
+    __syncthreads();
+  }
 }
 
 
@@ -2439,12 +2462,13 @@ hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* 
 template <int TXC, int TYC, int NT, class T>
 __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int bid) {
   static_assert(NT >= TXC * TYC && NT % 64 == 0, "one thread per coarse node at least");
-  const OpConsts* __restrict__ oc = J.oc;
-  const int* __restrict__ node_op = J.node_op;
-  const T* __restrict__ nsten = J.nsten;
-  const T* __restrict__ x = J.x;
-  const T* __restrict__ b = J.b;
-  T* __restrict__ bc = J.bc;
+  // every pointer of the job addresses device memory (see gmem)
+  const gmem<const OpConsts>* __restrict__ oc = (const gmem<const OpConsts>*)J.oc;
+  const gmem<const int>* __restrict__ node_op = (const gmem<const int>*)J.node_op;
+  const gmem<const T>* __restrict__ nsten = (const gmem<const T>*)J.nsten;
+  const gmem<const T>* __restrict__ x = (const gmem<const T>*)J.x;
+  const gmem<const T>* __restrict__ b = (const gmem<const T>*)J.b;
+  gmem<T>* __restrict__ bc = (gmem<T>*)J.bc;
   const int ntx = J.ntx, nty = J.nty;
   constexpr int RW = 2 * TXC + 1, RH = 2 * TYC + 1, RP = RW * RH;  // fine residual region
   constexpr int XW = RW + 2, XH = RH + 2, XP = XW * XH;            // x region, halo 1
@@ -2487,7 +2511,7 @@ __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int 
     if (threadIdx.x + NT * k < 3 * XP) xs[threadIdx.x + NT * k] = xv[k];
   // nodes with a stored stencil are listed; groups of lanes compute their residuals
 #pragma unroll
-  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, threadIdx.x + NT * k, opv[k]);
+  for (int k = 0; k < NRES; ++k) stored_list_add<NT, NRES>(sl, k, threadIdx.x + NT * k, opv[k], threadIdx.x);
   __syncthreads();
   // residuals: nodes with a reference stencil per thread, while the stored rows load
   constexpr int LPN = TXC * TYC >= 128 ? 8 : 2;  // lanes per stored row
@@ -2502,7 +2526,7 @@ __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int 
         if (gx >= 0 && gx < m && gy >= 0 && gy < m) {
           const int xb = (px + 1) + XW * (py + 1);
           T acc[3] = {0, 0, 0};
-          ref_row_apply<2, true, T>(oc->pack, opv[k], [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
+          ref_row_apply<2, true, T>((const double*)oc->pack, opv[k], [&](int f, const int* o) { return xs[f * XP + xb + o[0] + XW * o[1]]; },
                                     acc);
 #pragma unroll
           for (int f = 0; f < 3; ++f) rv[f] = bv[k][f] - acc[f];
@@ -2511,7 +2535,7 @@ __device__ __forceinline__ void residual_restrict2_body(const RR2Job<T>& J, int 
         for (int f = 0; f < 3; ++f) rs[f * RP + e] = rv[f];
       }
     }
-  });
+  }, threadIdx.x);
   __syncthreads();
   if (threadIdx.x >= TXC * TYC) return;
   const int cx = cx0 + threadIdx.x % TXC, cy = cy0 + threadIdx.x / TXC;
@@ -2594,6 +2618,33 @@ hipError_t k_batch_fused2(const Fused2Job<double>* jobs, const int* block_job, i
   if (nblocks == 0) return hipSuccess;
   sweep_fused2_batch_kernel<kBatchTX, kBatchTY, kBatchNT, 5, double><<<dim3((unsigned)nblocks), dim3(kBatchNT), 0, s>>>(
       jobs, block_job);
+  return hipGetLastError();
+}
+
+// Workgroups of the persistent batched sweep that the device holds at once (occupancy per CU times
+// CUs), looked up once per device.
+int batch_fused2_resident_blocks() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] > 0) return cache[dev];
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, sweep_fused2_batch_persistent_kernel<kBatchTX, kBatchTY, kBatchNT, 5, double>, kBatchNT, 0) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 || cus < 1)
+    return 0;
+  cache[dev] = per_cu * cus;
+  return cache[dev];
+}
+
+hipError_t k_batch_fused2_persistent(const Fused2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  const int resident = batch_fused2_resident_blocks();
+  if (resident < 1) return hipErrorInvalidValue;
+  const int grid = nblocks < resident ? nblocks : resident;
+  sweep_fused2_batch_persistent_kernel<kBatchTX, kBatchTY, kBatchNT, 5, double>
+      <<<dim3((unsigned)grid), dim3(kBatchNT), 0, s>>>(jobs, block_job, nblocks);
   return hipGetLastError();
 }
 

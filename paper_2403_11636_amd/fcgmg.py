@@ -31,7 +31,7 @@ EXPORTS = [
     "fcgmg_server_create", "fcgmg_server_submit", "fcgmg_server_wait", "fcgmg_server_resident_bytes",
     "fcgmg_server_stats",
     "fcgmg_server_destroy", "fcgmg_batch_create", "fcgmg_batch_vcycle", "fcgmg_batch_solve",
-    "fcgmg_batch_destroy",
+    "fcgmg_batch_destroy", "fcgmg_batch_set_persistent",
 ]
 
 N_FUSED_SHAPES = 8  # tile shapes of the fused 2D sweep (fcgmg_fused_shape)
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     L.fcgmg_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), dp, vp]
     L.fcgmg_batch_destroy.argtypes = [vp]
+    L.fcgmg_batch_set_persistent.argtypes = [vp, ctypes.c_int]
     L.fcgmg_footprint_bytes.argtypes = [ctypes.POINTER(Params), dp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.fcgmg_destroy.argtypes = [vp]
     L.fcgmg_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -514,6 +515,10 @@ class Batch:
     def _ptrs(self, vecs, name):
         assert len(vecs) == len(self.hs)
         return (ctypes.c_void_p * len(vecs))(*[_dptr(v, name, h.ndofs()).value for v, h in zip(vecs, self.hs)])
+
+    def set_persistent(self, on: bool = True):
+        """Fused sweeps as persistent launches (tiles handed out by ticket) or one workgroup per tile."""
+        _check(load().fcgmg_batch_set_persistent(self.h, int(on)))
 
     def vcycle(self, xs, bs, stream=None):
         _check(load().fcgmg_batch_vcycle(self.h, self._ptrs(xs, "x"), self._ptrs(bs, "b"), _stream_ptr(stream)))

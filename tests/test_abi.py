@@ -117,3 +117,4 @@ def test_tuning_calls_reject_a_null_handle_on_host():
     assert lib.fcgmg_set_cache_none_assembly(None, 1) == fcgmg.E_ARG
     assert lib.fcgmg_vcycle_multi(None, None, None, 2, None) == fcgmg.E_ARG
     assert lib.fcgmg_smooth_multi(None, 0, None, None, None, 2, 1, None) == fcgmg.E_ARG
+    assert lib.fcgmg_batch_set_persistent(None, 1) == fcgmg.E_ARG

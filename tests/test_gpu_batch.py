@@ -48,6 +48,43 @@ def test_batched_vcycle_bitwise_equals_single():
         h.close()
 
 
+def test_persistent_batched_vcycle_bitwise_equals_single():
+    # persistent launches (tiles by ticket) give the bits of the one-tile-per-workgroup launches and
+    # of each hierarchy alone; switched back, the default launches again
+    f = fcg()
+    probs = problems() + [inputs.batch_problem(k) for k in range(40, 72)]
+    hs = [f.Hierarchy(p) for p in probs]
+    xs0 = [torch.from_numpy(inputs.random_vector(h.ndofs(), 90 + k)).cuda() for k, h in enumerate(hs)]
+    bs = [h.rhs() for h in hs]
+    bt = f.Batch(hs)
+    bt.set_persistent(True)
+    xp = [x.clone() for x in xs0]
+    for _ in range(3):
+        bt.vcycle(xp, bs)
+    bt.set_persistent(False)
+    xd = [x.clone() for x in xs0]
+    for _ in range(3):
+        bt.vcycle(xd, bs)
+    for k, (h, x0, b) in enumerate(zip(hs, xs0, bs)):
+        assert torch.equal(xp[k], xd[k]), probs[k].name
+        if k < len(problems()):
+            xa = x0.clone()
+            for _ in range(3):
+                h.vcycle(xa, b)
+            assert torch.equal(xa, xp[k]), probs[k].name
+    bt.set_persistent(True)
+    xs, its, rel, rc = bt.solve(bs, rtol=1e-8, max_iter=60)
+    assert rc == f.OK and max(rel) <= 1e-8
+    bt.set_persistent(False)
+    xs2, its2, rel2, rc2 = bt.solve(bs, rtol=1e-8, max_iter=60)
+    assert its == its2 and all(torch.equal(a, b) for a, b in zip(xs, xs2))
+    with pytest.raises(f.FcgmgError):
+        bt.set_persistent(2)
+    bt.close()
+    for h in hs:
+        h.close()
+
+
 def test_batched_solve_matches_single():
     f = fcg()
     probs = problems() + [inputs.batch_problem(k) for k in range(10, 30)]
