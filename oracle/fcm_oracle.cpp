@@ -50,7 +50,7 @@ struct Level {
 
 struct Prob {
   int d = 2, n = 8, nlev = 1, q = 3, force = 0;
-  int immersed = 0;  // 1: the obstacle surfaces are Dirichlet boundaries (no-slip), 2D
+  int immersed = 0;  // 1: the obstacle surfaces are Dirichlet boundaries (no-slip)
   double eta = 1, alpha_f = 1e-8, beta = 20, ubar = 0.3;
   int bc[6] = {0, 0, 0, 0, 0, 0};
   std::vector<Ball> balls;
@@ -227,6 +227,113 @@ void arc_points(const Prob& P, const double* lo, double h, std::vector<APt>& out
   }
 }
 
+// Immersed Dirichlet boundary in 3D: quadrature on the parts of the sphere surfaces inside a cell
+// box. Reading (the paper fixes no rule): a point of a sphere is c + r u with
+// u = (sin theta cos phi, sin theta sin phi, cos theta), area element r^2 sin theta dtheta dphi.
+// The part inside the box is where every u_k lies in [a_k, b_k] (the box bounds relative to the
+// centre, divided by r). The theta-range is cut wherever the circle of radius rho = sin theta in the
+// (u_0, u_1) plane starts or stops meeting one of the lines u_0 = a_0, b_0, u_1 = a_1, b_1 (rho equal
+// to the line's distance) or passes a corner of their rectangle (rho^2 = x^2 + y^2). Between these
+// cuts the ends of the admitted arcs move smoothly with theta up to square-root behaviour at the
+// cuts, which the substitution theta = t0 + (t1 - t0)(3 s^2 - 2 s^3) removes; s in [0, 1] is split
+// into ceil((t1 - t0) / (pi/8)) equal parts, each with the 6-point Gauss-Legendre rule. At each
+// such theta the circle is split at its crossings with the four lines, and an arc whose middle
+// point lies in the closed rectangle is split into ceil(width / (pi/8)) equal angular parts, each
+// with the 6-point rule in phi. n = -u: out of the physical domain, into the obstacle.
+// ---------------------------------------------------------------------------------------------
+void sphere_points(const Prob& P, const double* lo, double h, std::vector<APt>& out) {
+  const double two_pi = 2.0 * M_PI;
+  auto gl6 = [](int g, double* xi, double* wg) {
+    *xi = g < 3 ? -kGL6x[2 - g] : kGL6x[g - 3];
+    *wg = g < 3 ? kGL6w[2 - g] : kGL6w[g - 3];
+  };
+  for (const Ball& B : P.balls) {
+    double a[3], b[3];
+    for (int k = 0; k < 3; ++k) {
+      a[k] = (lo[k] - B.c[k]) / B.r;
+      b[k] = (lo[k] + h - B.c[k]) / B.r;
+    }
+    // cos theta = u_2 in [a_2, b_2]
+    if (!(std::min(b[2], 1.0) > std::max(a[2], -1.0))) continue;
+    const double th_lo = b[2] >= 1.0 ? 0.0 : std::acos(b[2]);
+    const double th_hi = a[2] <= -1.0 ? M_PI : std::acos(a[2]);
+    if (!(th_hi > th_lo)) continue;
+    std::vector<double> tcut = {th_lo, th_hi};
+    auto cut_at_radius2 = [&](double rho2) {
+      if (!(rho2 >= 0.0 && rho2 < 1.0)) return;
+      const double q = std::asin(std::sqrt(rho2));  // sin theta = rho at q and pi - q
+      if (q > th_lo && q < th_hi) tcut.push_back(q);
+      if (M_PI - q > th_lo && M_PI - q < th_hi) tcut.push_back(M_PI - q);
+    };
+    const double xl[2] = {a[0], b[0]}, yl[2] = {a[1], b[1]};
+    for (int i = 0; i < 2; ++i) cut_at_radius2(xl[i] * xl[i]);
+    for (int j = 0; j < 2; ++j) cut_at_radius2(yl[j] * yl[j]);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) cut_at_radius2(xl[i] * xl[i] + yl[j] * yl[j]);
+    std::sort(tcut.begin(), tcut.end());
+    for (size_t i = 0; i + 1 < tcut.size(); ++i) {
+      const double t0 = tcut[i], t1 = tcut[i + 1];
+      if (!(t1 > t0)) continue;
+      const int tparts = (int)std::ceil((t1 - t0) / (M_PI / 8));
+      for (int pt = 0; pt < tparts; ++pt) {
+        const double s0 = (double)pt / tparts, s1 = (double)(pt + 1) / tparts;
+        for (int gt = 0; gt < 6; ++gt) {
+          double xi, wg;
+          gl6(gt, &xi, &wg);
+          const double s = 0.5 * (s0 + s1) + 0.5 * (s1 - s0) * xi;
+          const double th = t0 + (t1 - t0) * s * s * (3.0 - 2.0 * s);
+          const double rho = std::sin(th), t = std::cos(th);
+          const double wt = 0.5 * (s1 - s0) * wg * (t1 - t0) * 6.0 * s * (1.0 - s) * rho;
+          if (!(rho > 0.0)) continue;
+          // the circle of radius rho against the lines of the rectangle [a0, b0] x [a1, b1]
+          std::vector<double> ph = {0.0, two_pi};
+          for (int k = 0; k < 2; ++k) {
+            const double v = xl[k] / rho;
+            if (std::fabs(v) < 1.0) {
+              const double q = std::acos(v);
+              ph.push_back(q);
+              ph.push_back(two_pi - q);
+            }
+          }
+          for (int k = 0; k < 2; ++k) {
+            const double v = yl[k] / rho;
+            if (std::fabs(v) < 1.0) {
+              const double q = std::asin(v);
+              ph.push_back(q < 0 ? q + two_pi : q);
+              ph.push_back(M_PI - q);
+            }
+          }
+          std::sort(ph.begin(), ph.end());
+          for (size_t j = 0; j + 1 < ph.size(); ++j) {
+            const double f0 = ph[j], f1 = ph[j + 1];
+            if (!(f1 > f0)) continue;
+            const double fm = 0.5 * (f0 + f1);
+            const double um = rho * std::cos(fm), vm = rho * std::sin(fm);
+            if (!(um >= a[0] && um <= b[0] && vm >= a[1] && vm <= b[1])) continue;
+            const int fparts = (int)std::ceil((f1 - f0) / (M_PI / 8));
+            for (int pf = 0; pf < fparts; ++pf) {
+              const double e0 = f0 + (f1 - f0) * pf / fparts, e1 = f0 + (f1 - f0) * (pf + 1) / fparts;
+              for (int gf = 0; gf < 6; ++gf) {
+                double xf, wf;
+                gl6(gf, &xf, &wf);
+                const double phi = 0.5 * (e0 + e1) + 0.5 * (e1 - e0) * xf;
+                const double u[3] = {rho * std::cos(phi), rho * std::sin(phi), t};
+                APt q;
+                for (int k = 0; k < 3; ++k) {
+                  q.x[k] = B.c[k] + B.r * u[k];
+                  q.n[k] = -u[k];
+                }
+                q.w = B.r * B.r * wt * 0.5 * (e1 - e0) * wf;
+                out.push_back(q);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Q1 basis of the cell with lower corner lo and size h, local node a has bit k of a as its
 // k-th coordinate offset (tensor ordering). Returns values and physical gradients at x.
 void q1_basis(int d, const double* lo, double h, const double* x, double* phi, double (*grad)[3]) {
@@ -390,10 +497,13 @@ void element_matrix(const Prob& P, const Level& L, long cell, std::vector<double
           }
       }
     }
-  // Nitsche terms on the immersed obstacle surfaces (2D, cut cells): the same forms as on the walls.
-  if (P.immersed && d == 2 && box_kind(P, lo, h) == 2) {
+  // Nitsche terms on the immersed obstacle surfaces (cut cells): the same forms as on the walls.
+  if (P.immersed && box_kind(P, lo, h) == 2) {
     std::vector<APt> ap;
-    arc_points(P, lo, h, ap);
+    if (d == 2)
+      arc_points(P, lo, h, ap);
+    else
+      sphere_points(P, lo, h, ap);
     for (const APt& q : ap) {
       q1_basis(d, lo, h, q.x, phi, grad);
       for (int a = 0; a < nn; ++a)
@@ -977,7 +1087,7 @@ void* orc_create(int d, int n, int nlev, int q, double eta, double alpha_f, doub
                  const double* balls, const int* bc, double ubar, int force, int immersed) {
   if (d < 2 || d > 3 || n < 1 || nlev < 1 || (n >> (nlev - 1)) < 1 || ((n >> (nlev - 1)) << (nlev - 1)) != n)
     return nullptr;
-  if (immersed != 0 && (immersed != 1 || d != 2)) return nullptr;
+  if (immersed != 0 && immersed != 1) return nullptr;
   Prob* P = new Prob;
   P->immersed = immersed;
   P->d = d;
@@ -1032,22 +1142,24 @@ void orc_element_matrix(void* h, int l, long cell, double* out) {
   std::copy(Le.begin(), Le.end(), out);
 }
 
-// Immersed-boundary quadrature of one cell (2D): up to max points as [x, y, w, n_x, n_y]; returns
-// the number of points (which may exceed max; then only max are written).
+// Immersed-boundary quadrature of one cell: up to max points as [x (d), w, n (d)] (2D: arcs, 3D:
+// sphere pieces); returns the number of points (which may exceed max; then only max are written).
 long orc_arc_points(void* h, int l, long cell, double* out, long max) {
   Prob* P = static_cast<Prob*>(h);
   const Level& L = P->lev[l];
+  const int d = P->d, stride = 2 * d + 1;
   double lo[3];
   int ci[3];
   cell_lo(*P, L, cell, lo, ci);
   std::vector<APt> ap;
-  if (P->d == 2) arc_points(*P, lo, L.h, ap);
+  if (d == 2)
+    arc_points(*P, lo, L.h, ap);
+  else
+    sphere_points(*P, lo, L.h, ap);
   for (long i = 0; i < (long)ap.size() && i < max; ++i) {
-    out[5 * i + 0] = ap[i].x[0];
-    out[5 * i + 1] = ap[i].x[1];
-    out[5 * i + 2] = ap[i].w;
-    out[5 * i + 3] = ap[i].n[0];
-    out[5 * i + 4] = ap[i].n[1];
+    for (int k = 0; k < d; ++k) out[stride * i + k] = ap[i].x[k];
+    out[stride * i + d] = ap[i].w;
+    for (int k = 0; k < d; ++k) out[stride * i + d + 1 + k] = ap[i].n[k];
   }
   return (long)ap.size();
 }

@@ -158,11 +158,13 @@ class Oracle:
         return out
 
     def arc_points(self, level: int, cell: int) -> np.ndarray:
-        """Immersed-boundary quadrature points of one cell (2D): rows [x, y, w, n_x, n_y]."""
+        """Immersed-boundary quadrature points of one cell: rows [x (d), w, n (d)] (2D: circle arcs,
+        3D: sphere pieces)."""
+        st = 2 * self.d + 1
         cnt = lib().orc_arc_points(self.h, level, cell, None, 0)
-        out = np.zeros(max(cnt, 1) * 5)
+        out = np.zeros(max(cnt, 1) * st)
         lib().orc_arc_points(self.h, level, cell, _dp(out), cnt)
-        return out[: cnt * 5].reshape(cnt, 5)
+        return out[: cnt * st].reshape(cnt, st)
 
     def cell_kinds(self, level: int) -> np.ndarray:
         n = self.prob.level_cells(level)

@@ -567,3 +567,104 @@ def test_immersed_nitsche_closed_forms_full_circle():
     assert abs(Y @ B2 @ one + np.pi * r ** 2) <= 1e-14
     assert abs(one @ B1 @ one) <= 1e-15 and abs(one @ B2 @ one) <= 1e-15
     assert np.allclose(D[8:12, 8:12], 0, atol=1e-15)
+
+
+def _sphere_cells(o, p):
+    n = p.n_cells
+    h = 1.0 / n
+    for cell in range(n ** 3):
+        a = o.arc_points(0, cell)
+        if len(a):
+            lo = np.array([cell % n, (cell // n) % n, cell // (n * n)]) * h
+            yield cell, lo, h, a
+
+
+def test_immersed_sphere_quadrature_closed_forms():
+    # Surface quadrature of the obstacle spheres (3D): over all cells, the total area is 4 pi sum r^2,
+    # the normals (into the obstacles) integrate to zero, x_k n_k integrates to -4/3 pi sum r^3 for
+    # each k and (x_k - c_k)^2 to 4/3 pi r^4 per sphere (divergence theorem and symmetry); every point
+    # lies on a sphere and inside its closed cell. The spheres sit in general position, so the cells
+    # cut them in every way (faces, edges, corners). The rule is not exact there: where two of its
+    # cuts in theta nearly coincide (a corner just beside a tangency) a branch point lies just
+    # outside the next piece, and the rule's error on these sums is about 1e-6 of each; a missing,
+    # doubled or misweighted piece changes them by the piece's share, 1e-3 or more.
+    balls = np.array([[0.413, 0.377, 0.521, 0.161], [0.702, 0.668, 0.309, 0.093], [0.251, 0.733, 0.745, 0.118]])
+    p = inputs.Problem(dim=3, n_cells=12, n_levels=1, balls=balls, bcs=(0,) * 6, immersed_nitsche=1)
+    o = Oracle(p)
+    area, sn, sxn = 0.0, np.zeros(3), np.zeros(3)
+    for cell, lo, h, a in _sphere_cells(o, p):
+        x, w, nrm = a[:, 0:3], a[:, 3], a[:, 4:7]
+        assert np.all(x >= lo - 1e-15) and np.all(x <= lo + h + 1e-15)
+        dist = np.min(np.abs(np.linalg.norm(x[:, None, :] - balls[None, :, 0:3], axis=2) - balls[None, :, 3]), axis=1)
+        assert np.all(dist < 1e-14)
+        assert np.allclose(np.linalg.norm(nrm, axis=1), 1.0, atol=1e-14)
+        assert np.all(w > 0)
+        area += w.sum()
+        sn += (w[:, None] * nrm).sum(0)
+        sxn += (w[:, None] * x * nrm).sum(0)
+    r = balls[:, 3]
+    assert abs(area - 4 * np.pi * (r ** 2).sum()) <= 1e-5 * area
+    assert np.all(np.abs(sn) <= 1e-5 * area)
+    assert np.allclose(sxn, -4.0 / 3.0 * np.pi * (r ** 3).sum(), rtol=1e-5, atol=0)
+    # one sphere alone: its second moments
+    p1 = inputs.Problem(dim=3, n_cells=12, n_levels=1, balls=balls[:1], bcs=(0,) * 6, immersed_nitsche=1)
+    o1 = Oracle(p1)
+    m2 = np.zeros(3)
+    for cell, lo, h, a in _sphere_cells(o1, p1):
+        m2 += (a[:, 3:4] * (a[:, 0:3] - balls[0, 0:3]) ** 2).sum(0)
+    assert np.allclose(m2, 4.0 / 3.0 * np.pi * balls[0, 3] ** 4, rtol=1e-5, atol=0)
+
+
+def test_immersed_sphere_quadrature_octants():
+    # A sphere centred on a grid node, smaller than a cell: each of the 8 cells around the node holds
+    # one octant, of area pi r^2 / 2, whose inward normal integrates to -(pi r^2 / 4) along each axis
+    # towards that octant.
+    n, r = 8, 0.07
+    c = np.array([3, 4, 5]) / n
+    p = inputs.Problem(dim=3, n_cells=n, n_levels=1, balls=np.array([[*c, r]]), bcs=(0,) * 6, immersed_nitsche=1)
+    o = Oracle(p)
+    seen = 0
+    for cell, lo, h, a in _sphere_cells(o, p):
+        s = np.where(lo + 0.5 * h > c, 1.0, -1.0)
+        w, nrm = a[:, 3], a[:, 4:7]
+        assert abs(w.sum() - np.pi * r ** 2 / 2) <= 1e-13
+        assert np.allclose((w[:, None] * nrm).sum(0), -np.pi * r ** 2 / 4 * s, rtol=0, atol=1e-13)
+        seen += 1
+    assert seen == 8
+
+
+def test_immersed_nitsche_closed_forms_full_sphere():
+    # A sphere of radius r inside one cell (3D analogue of the full-circle test): with n into the
+    # obstacle and lambda = beta eta / h, the immersed terms give 1'K1 = lambda 4 pi r^2,
+    # 1'KX = lambda 4 pi r^2 c_x, X'KX = 2 eta V + lambda (4 pi r^2 c_x^2 + 4/3 pi r^4) with
+    # V = 4/3 pi r^3, X'B_x 1 = -V, 1'B_c 1 = 0; symmetric, equal for the three velocity components.
+    import dataclasses
+    n, eta, beta = 4, 0.9, 20.0
+    h = 1.0 / n
+    cx, cy, cz, r = 0.37, 0.41, 0.62, 0.05
+    p0 = inputs.Problem(dim=3, n_cells=n, n_levels=1, balls=np.array([[cx, cy, cz, r]]), bcs=(2,) * 6, eta=eta,
+                        nitsche_beta=beta)
+    p1 = dataclasses.replace(p0, immersed_nitsche=1)
+    cell = 1 + n * 1 + n * n * 2
+    D = Oracle(p1).element_matrix(0, cell) - Oracle(p0).element_matrix(0, cell)
+    lam = beta * eta / h
+    a = np.arange(8)
+    X = h * (1 + (a & 1))
+    Z = h * (2 + ((a >> 2) & 1))
+    one = np.ones(8)
+    K = D[0:8, 0:8]
+    V = 4.0 / 3.0 * np.pi * r ** 3
+    scale = lam * 4 * np.pi * r ** 2
+    assert np.allclose(D, D.T, atol=1e-12 * scale)
+    for c in (1, 2):
+        assert np.allclose(D[8 * c:8 * c + 8, 8 * c:8 * c + 8], K, atol=1e-14 * scale)
+    assert np.allclose(D[0:8, 8:24], 0, atol=1e-15)
+    assert abs(one @ K @ one - scale) <= 1e-12 * scale
+    assert abs(one @ K @ X - scale * cx) <= 1e-12 * scale
+    assert abs(X @ K @ X - (2 * eta * V + lam * (4 * np.pi * r ** 2 * cx ** 2 + 4.0 / 3.0 * np.pi * r ** 4))) <= 1e-12 * scale
+    B = [D[8 * c:8 * c + 8, 24:32] for c in range(3)]
+    assert abs(X @ B[0] @ one + V) <= 1e-12 * V
+    assert abs(Z @ B[2] @ one + V) <= 1e-12 * V
+    for c in range(3):
+        assert abs(one @ B[c] @ one) <= 1e-15
+    assert np.allclose(D[24:32, 24:32], 0, atol=1e-15)
