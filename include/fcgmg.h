@@ -82,10 +82,12 @@ typedef struct {
   int solver;        /* FCGMG_SOLVER_*: outer iteration of fcgmg_solve                            */
   int krylov_restart; /* FGMRES restart length m, 1..63 (ignored by FCGMG_SOLVER_GMG)              */
   int immersed_nitsche; /* 1: the obstacle surfaces are no-slip Dirichlet boundaries (Eq. 5, Gamma_D),
-                           imposed by the Nitsche forms of the walls on arcs through the cut cells;
-                           2D only. The local blocks may then be indefinite and are factorised by a
-                           dense LU with partial pivoting under every cache policy. 0: obstacles are
-                           fictitious regions only.                                                  */
+                           imposed by the Nitsche forms of the walls on the circle arcs (2D) or
+                           sphere pieces (3D) through the cut cells. The local blocks may then be
+                           indefinite and are factorised by a dense LU with partial pivoting: in 2D
+                           under every cache policy, in 3D at set-up for cache_inverse, the only
+                           policy 3D accepts with it (E_ARG otherwise). 0: obstacles are fictitious
+                           regions only.                                                             */
 } fcgmg_params;
 
 /* Outer iteration of fcgmg_solve. GMG: the standalone multigrid of Sec. 4, x <- V(x, b) until the

@@ -500,7 +500,11 @@ int setup_impl(Ctx& c, hipStream_t s) {
       }
     }
     L.n_cut = (int64_t)cut_list.size();
-    L.dense_lu = D == 2 && (P.immersed_nitsche || obstacle_on_dirichlet_face<D>(P, L, kinds));
+    // blocks that may be indefinite are factorised by a dense LU with pivoting: in 2D with immersed
+    // Nitsche terms or an obstacle over a Dirichlet face of the box, in 3D with immersed Nitsche
+    // terms (cache_inverse, at set-up)
+    L.dense_lu = D == 2 ? (P.immersed_nitsche || obstacle_on_dirichlet_face<D>(P, L, kinds))
+                        : (P.immersed_nitsche && P.cache_policy == FCGMG_CACHE_INVERSE);
     if ((rc = alloc_n(c, &L.cell_info, L.ncells))) return rc;
     FCG_HIP(hipMemcpyAsync(L.cell_info, info.data(), L.ncells * sizeof(int), hipMemcpyHostToDevice, s));
     int* cut_d = nullptr;
@@ -1246,7 +1250,8 @@ static int validate_params(const fcgmg_params& prm, const double* balls, int n_b
   if (P.solver == FCGMG_SOLVER_FGMRES && (P.krylov_restart < 1 || P.krylov_restart > 63))
     return fail(FCGMG_E_ARG, "krylov_restart must be in [1,63]");
   if (P.immersed_nitsche != 0 && P.immersed_nitsche != 1) return fail(FCGMG_E_ARG, "immersed_nitsche must be 0 or 1");
-  if (P.immersed_nitsche && P.dim != 2) return fail(FCGMG_E_ARG, "immersed_nitsche needs dim 2");
+  if (P.immersed_nitsche && P.dim == 3 && P.cache_policy != FCGMG_CACHE_INVERSE)
+    return fail(FCGMG_E_ARG, "immersed_nitsche in 3D needs the cache_inverse policy");
   if (!(P.eta > 0) || !(P.alpha_fict >= 0) || !(P.nitsche_beta > 0) || !std::isfinite(P.omega))
     return fail(FCGMG_E_ARG, "eta, nitsche_beta must be > 0, alpha_fict >= 0, omega finite");
   if (P.nu_pre < 0 || P.nu_post < 0) return fail(FCGMG_E_ARG, "negative smoothing steps");

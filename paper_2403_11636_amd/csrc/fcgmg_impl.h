@@ -424,6 +424,137 @@ __host__ __device__ inline void arc_quadrature2(const Geom& g, const double* lo,
   }
 }
 
+// Immersed boundary (3D): Gauss points on the pieces of the obstacle spheres inside the cell box
+// [lo, lo + h]^3, the obstacle surfaces taken as part of Gamma_D in Eq. 5. A sphere point is
+// c + r (sin th cos ph, sin th sin ph, cos th), area element r^2 sin th dth dph. The polar range
+// (cos th within the box's z-extent) is cut where the circle of latitude, radius sin th in the
+// (x, y) plane, becomes tangent to one of the box's four x/y lines or passes one of their four
+// corners; on each piece th = t0 + (t1 - t0)(3 s^2 - 2 s^3), which smooths the square-root ends, with
+// s in ceil((t1 - t0) / (pi/8)) equal parts of 6 Gauss-Legendre points. At each th the circle is cut
+// at its crossings with the four lines, and an arc whose middle lies in the closed rectangle is cut
+// into ceil(width / (pi/8)) equal parts of 6 points in ph. visit(x, w, nrm): point, weight, unit
+// normal pointing into the obstacle.
+template <class F>
+__host__ __device__ inline void sphere_quadrature3(const Geom& g, const double* lo, double h, F&& visit) {
+  const double gx[3] = {0.2386191860831969086305017, 0.6612093864662645136613996, 0.9324695142031520278123016};
+  const double gw[3] = {0.4679139345726910473898703, 0.3607615730481386075698335, 0.1713244923791703450402961};
+  const double pi = 3.141592653589793238462643, two_pi = 6.283185307179586476925287, piece = 0.125 * pi;
+  auto sort_small = [](double* v, int n) {
+    for (int a = 1; a < n; ++a)
+      for (int c = a; c > 0 && v[c - 1] > v[c]; --c) {
+        const double tmp = v[c];
+        v[c] = v[c - 1];
+        v[c - 1] = tmp;
+      }
+  };
+  for (int i = 0; i < g.nballs; ++i) {
+    const double* bl = g.balls + 4 * i;
+    const double r = bl[3];
+    double lo_n[3], hi_n[3];  // box bounds relative to the centre, in radii
+    for (int k = 0; k < 3; ++k) {
+      lo_n[k] = (lo[k] - bl[k]) / r;
+      hi_n[k] = (lo[k] + h - bl[k]) / r;
+    }
+    if (!(fmin(hi_n[2], 1.0) > fmax(lo_n[2], -1.0))) continue;
+    const double th_a = hi_n[2] >= 1.0 ? 0.0 : acos(hi_n[2]);
+    const double th_b = lo_n[2] <= -1.0 ? pi : acos(lo_n[2]);
+    if (!(th_b > th_a)) continue;
+    double cut[18];
+    int nc = 0;
+    cut[nc++] = th_a;
+    cut[nc++] = th_b;
+    // radius^2 of the circle of latitude at which it touches a line or passes a corner
+    double rr[8];
+    rr[0] = lo_n[0] * lo_n[0];
+    rr[1] = hi_n[0] * hi_n[0];
+    rr[2] = lo_n[1] * lo_n[1];
+    rr[3] = hi_n[1] * hi_n[1];
+    rr[4] = rr[0] + rr[2];
+    rr[5] = rr[0] + rr[3];
+    rr[6] = rr[1] + rr[2];
+    rr[7] = rr[1] + rr[3];
+    for (int k = 0; k < 8; ++k) {
+      if (!(rr[k] >= 0.0 && rr[k] < 1.0)) continue;
+      const double q = asin(sqrt(rr[k]));
+      if (q > th_a && q < th_b) cut[nc++] = q;
+      if (pi - q > th_a && pi - q < th_b) cut[nc++] = pi - q;
+    }
+    sort_small(cut, nc);
+    for (int j = 0; j + 1 < nc; ++j) {
+      const double t0 = cut[j], t1 = cut[j + 1];
+      if (!(t1 > t0)) continue;
+      const int tparts = (int)ceil((t1 - t0) / piece);
+      for (int pt = 0; pt < tparts; ++pt) {
+        const double s0 = (double)pt / tparts, s1 = (double)(pt + 1) / tparts;
+        for (int qt = 0; qt < 6; ++qt) {
+          const double xs = qt < 3 ? -gx[2 - qt] : gx[qt - 3];
+          const double ws = qt < 3 ? gw[2 - qt] : gw[qt - 3];
+          const double s = 0.5 * (s0 + s1) + 0.5 * (s1 - s0) * xs;
+          const double th = t0 + (t1 - t0) * s * s * (3.0 - 2.0 * s);
+          const double rho = sin(th), ct = cos(th);
+          if (!(rho > 0.0)) continue;
+          const double wth = 0.5 * (s1 - s0) * ws * (t1 - t0) * 6.0 * s * (1.0 - s) * rho;
+          // the circle of radius rho against the lines x = lo_n[0], hi_n[0], y = lo_n[1], hi_n[1]
+          double ph[10];
+          int np = 0;
+          ph[np++] = 0.0;
+          ph[np++] = two_pi;
+          for (int k = 0; k < 2; ++k) {
+            const double v = (k ? hi_n[0] : lo_n[0]) / rho;
+            if (fabs(v) < 1.0) {
+              const double q = acos(v);
+              ph[np++] = q;
+              ph[np++] = two_pi - q;
+            }
+          }
+          for (int k = 0; k < 2; ++k) {
+            const double v = (k ? hi_n[1] : lo_n[1]) / rho;
+            if (fabs(v) < 1.0) {
+              const double q = asin(v);
+              ph[np++] = q < 0.0 ? q + two_pi : q;
+              ph[np++] = pi - q;
+            }
+          }
+          sort_small(ph, np);
+          for (int m = 0; m + 1 < np; ++m) {
+            const double f0 = ph[m], f1 = ph[m + 1];
+            if (!(f1 > f0)) continue;
+            const double fm = 0.5 * (f0 + f1);
+            const double xm = rho * cos(fm), ym = rho * sin(fm);
+            if (!(xm >= lo_n[0] && xm <= hi_n[0] && ym >= lo_n[1] && ym <= hi_n[1])) continue;
+            const int fparts = (int)ceil((f1 - f0) / piece);
+            for (int pf = 0; pf < fparts; ++pf) {
+              const double e0 = f0 + (f1 - f0) * pf / fparts, e1 = f0 + (f1 - f0) * (pf + 1) / fparts;
+              for (int qf = 0; qf < 6; ++qf) {
+                const double xf = qf < 3 ? -gx[2 - qf] : gx[qf - 3];
+                const double wf = qf < 3 ? gw[2 - qf] : gw[qf - 3];
+                const double phi = 0.5 * (e0 + e1) + 0.5 * (e1 - e0) * xf;
+                const double u[3] = {rho * cos(phi), rho * sin(phi), ct};
+                const double x[3] = {bl[0] + r * u[0], bl[1] + r * u[1], bl[2] + r * u[2]};
+                const double nrm[3] = {-u[0], -u[1], -u[2]};
+                visit(x, r * r * wth * 0.5 * (e1 - e0) * wf, nrm);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Entry e of a 3D cut cell's element data from the Nitsche forms at one boundary point (see
+// nitsche_entry2): K[a][b] (e < 64) or B_c[a][b] (c = e / 64 - 1).
+__host__ __device__ inline double nitsche_entry3(int e, double eta, double lam, double w, const double* nrm,
+                                                 const double* phi, double (*gr)[3]) {
+  const int blk = e / 64, ab = e % 64, a = ab / 8, b = ab % 8;
+  if (blk == 0) {
+    const double dna = nrm[0] * gr[a][0] + nrm[1] * gr[a][1] + nrm[2] * gr[a][2];
+    const double dnb = nrm[0] * gr[b][0] + nrm[1] * gr[b][1] + nrm[2] * gr[b][2];
+    return w * (-eta * phi[a] * dnb - eta * dna * phi[b] + lam * phi[a] * phi[b]);
+  }
+  return w * phi[a] * nrm[blk - 1] * phi[b];
+}
+
 // Entry e of a cell's element data from the Nitsche forms at one boundary point (weight w, normal
 // nrm), the wall forms of Eq. 5 with w = 0: K[a][b] += -eta phi_a (n.grad phi_b) - eta (n.grad phi_a)
 // phi_b + lambda phi_a phi_b; B_c[a][b] += phi_a n_c phi_b.

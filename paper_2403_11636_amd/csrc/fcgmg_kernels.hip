@@ -155,6 +155,16 @@ __global__ void __launch_bounds__(64) cut_matrices_kernel(Geom g, int n, double 
             if (e < NEL) acc[k] += nitsche_entry2(e, eta, lam, w, nrm, phi, gr);
           }
         });
+    } else {
+      if (immersed)
+        sphere_quadrature3(gl, lo, h, [&](const double* x, double w, const double* nrm) {
+          double phi[8], gr[8][3];
+          q1<3>(lo, h, x, phi, gr);
+          for (int k = 0; k < NPER; ++k) {
+            const int e = (int)threadIdx.x + 64 * k;
+            if (e < NEL) acc[k] += nitsche_entry3(e, eta, lam, w, nrm, phi, gr);
+          }
+        });
     }
     for (int k = 0; k < NPER; ++k) {
       const int e = (int)threadIdx.x + 64 * k;

@@ -674,10 +674,205 @@ __global__ void __launch_bounds__(64) patch_inverse_rows_lu2_kernel(
   }
 }
 
+// Dense LU of a 3D patch block (immersed boundary terms; see the 2D form above): the whole block
+// (402 x 402: u_x, u_y, u_z, p over the window) does not fit LDS, so each workgroup factorises it in
+// its own slot of a device buffer, row operations spread over the lanes, then takes the d+1 centre
+// rows of the inverse by transposed solves with the d+1 right-hand sides in LDS. Set-up only.
+constexpr int kLU3 = PT<3>::ZS;
+constexpr int64_t kLU3Slot = (int64_t)kLU3 * kLU3;  // doubles of one workgroup's slot
+constexpr int kLU3Blocks = 512;                      // workgroups (slots) of one launch
+
+struct LU3LDS {
+  double z[4][kLU3];  // the four right-hand sides, then the inverse rows
+  int piv[kLU3];
+  double red_v[4];
+  int red_i[4];
+  int pk;
+  int bad;
+};
+
+// A (row-major, device memory) = I_3 (x) K_i (from the lower band), B_c and B_c^T, C_i.
+__device__ void patch_dense3(const PatchLDS<3>& sh, double* __restrict__ A) {
+  constexpr int NV = PT<3>::NV, NP = PT<3>::NP, NB = PT<3>::NB, NPX = NP + 2, ZS = kLU3;
+  for (int i = threadIdx.x >> 6; i < ZS; i += blockDim.x >> 6)
+    for (int j = threadIdx.x & 63; j < ZS; j += 64) {
+      double v = 0;
+      if (i < 3 * NV && j < 3 * NV) {
+        const int vi = i % NV, vj = j % NV;
+        if (i / NV == j / NV) {
+          const int hi = vi > vj ? vi : vj, lo = vi > vj ? vj : vi;
+          if (hi - lo < NB) v = sh.Kb[hi * NB + (hi - lo)];
+        }
+      } else if (i < 3 * NV) {
+        v = sh.X[((i / NV) * NV + i % NV) * NPX + (j - 3 * NV)];
+      } else if (j < 3 * NV) {
+        v = sh.X[((j / NV) * NV + j % NV) * NPX + (i - 3 * NV)];
+      } else {
+        v = sh.S[(i - 3 * NV) * NP + (j - 3 * NV)];
+      }
+      A[(int64_t)i * ZS + j] = v;
+    }
+  __syncthreads();
+}
+
+// P A = L U in place (unit L below the diagonal, U on and above), the row interchanges in lu.piv;
+// pivot: largest |A[i][k]|, lowest row on ties. lu.bad is set when a pivot column is zero. Each
+// wavefront updates whole rows (lanes over the columns).
+__device__ void lu_factor3(double* __restrict__ A, LU3LDS& lu) {
+  constexpr int ZS = kLU3;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) lu.bad = 0;
+  __syncthreads();
+  for (int k = 0; k < ZS; ++k) {
+    double pv = -1.0;
+    int pr = ZS;
+    for (int i = k + tid; i < ZS; i += blockDim.x) {
+      const double v = fabs(A[(int64_t)i * ZS + k]);
+      if (v > pv) {  // rows ascend per thread: the first of equal values is kept
+        pv = v;
+        pr = i;
+      }
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+      const double ov = __shfl_xor(pv, m, 64);
+      const int orow = __shfl_xor(pr, m, 64);
+      if (ov > pv || (ov == pv && orow < pr)) {
+        pv = ov;
+        pr = orow;
+      }
+    }
+    if (lane == 0) {
+      lu.red_v[wave] = pv;
+      lu.red_i[wave] = pr;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double bv = lu.red_v[0];
+      int br = lu.red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (lu.red_v[w] > bv || (lu.red_v[w] == bv && lu.red_i[w] < br)) {
+          bv = lu.red_v[w];
+          br = lu.red_i[w];
+        }
+      lu.pk = br;
+      lu.piv[k] = br;
+      if (!(bv > 0)) lu.bad = 1;
+    }
+    __syncthreads();
+    if (lu.bad) return;
+    const int p = lu.pk;
+    if (p != k)
+      for (int j = tid; j < ZS; j += blockDim.x) {
+        const double t = A[(int64_t)k * ZS + j];
+        A[(int64_t)k * ZS + j] = A[(int64_t)p * ZS + j];
+        A[(int64_t)p * ZS + j] = t;
+      }
+    __syncthreads();
+    const double inv = 1.0 / A[(int64_t)k * ZS + k];
+    for (int i = k + 1 + tid; i < ZS; i += blockDim.x) A[(int64_t)i * ZS + k] *= inv;
+    __syncthreads();
+    for (int i = k + 1 + wave; i < ZS; i += nw) {
+      const double lik = A[(int64_t)i * ZS + k];
+      for (int j = k + 1 + lane; j < ZS; j += 64) A[(int64_t)i * ZS + j] -= lik * A[(int64_t)k * ZS + j];
+    }
+    __syncthreads();
+  }
+}
+
+// lu.z[r] <- row rows[r] of A^{-1} for r < 4: A^T z = e_row, i.e. U^T w = e_row, L^T v = w,
+// z = P^T v, all four at once; thread (r, j) updates entry j of right-hand side r after each step.
+__device__ void lu_inverse_rows3(const double* __restrict__ A, LU3LDS& lu, const int* rows) {
+  constexpr int ZS = kLU3;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 4 * ZS; e += blockDim.x) lu.z[e / ZS][e % ZS] = (e % ZS) == rows[e / ZS] ? 1.0 : 0.0;
+  __syncthreads();
+  // U^T w = e: w_i = z_i / U_ii, then z_j -= U_ij w_i for j > i
+  for (int i = 0; i < ZS; ++i) {
+    const double uii = A[(int64_t)i * ZS + i];
+    for (int e = tid; e < 4 * (ZS - i); e += blockDim.x) {
+      const int r = e / (ZS - i), j = i + e % (ZS - i);
+      const double wi = lu.z[r][i] / uii;
+      if (j > i) lu.z[r][j] -= A[(int64_t)i * ZS + j] * wi;
+    }
+    __syncthreads();
+    if (tid < 4) lu.z[tid][i] /= uii;
+    __syncthreads();
+  }
+  // L^T v = w (unit diagonal): v_i = z_i, then z_j -= L_ij v_i for j < i
+  for (int i = ZS - 1; i > 0; --i) {
+    for (int e = tid; e < 4 * i; e += blockDim.x) {
+      const int r = e / i, j = e % i;
+      lu.z[r][j] -= A[(int64_t)i * ZS + j] * lu.z[r][i];
+    }
+    __syncthreads();
+  }
+  // z = P^T v: the interchanges undone in reverse order
+  if (tid < 4)
+    for (int k = ZS - 1; k >= 0; --k) {
+      const int p = lu.piv[k];
+      if (p != k) {
+        const double t = lu.z[tid][k];
+        lu.z[tid][k] = lu.z[tid][p];
+        lu.z[tid][p] = t;
+      }
+    }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) patch_inverse_rows_lu3_kernel(
+    const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
+    double eta, const int* __restrict__ nodes, int64_t count, double* __restrict__ Z, double* __restrict__ slots,
+    int* err) {
+  constexpr int D = 3, NV = PT<3>::NV, ZS = kLU3, ZSP = PT<3>::ZSP;
+  __shared__ PatchLDS<3> sh;
+  __shared__ LU3LDS lu;
+  const int tid = threadIdx.x;
+  const int n = oc->n;
+  const int centre[D + 1] = {vel_center<3>(), NV + vel_center<3>(), 2 * NV + vel_center<3>(),
+                             D * NV + pres_center<3>()};
+  double* A = slots + (int64_t)blockIdx.x * kLU3Slot;
+  for (int64_t pi = blockIdx.x; pi < count; pi += gridDim.x) {
+    const int64_t node = nodes[pi];
+    int c[3];
+    node_coords<D>(node, n, c);
+    patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 0);
+    patch_pad<D>(sh, c, n);
+    patch_dense3(sh, A);
+    lu_factor3(A, lu);
+    const bool bad = lu.bad != 0;
+    if (!bad) lu_inverse_rows3(A, lu, centre);
+    double* Zp = Z + pi * (int64_t)(D + 1) * ZSP;
+    for (int e = tid; e < (D + 1) * ZSP; e += blockDim.x) {
+      const int f = e / ZSP, col = e % ZSP;
+      double val = 0;
+      if (!bad && col < ZS) {
+        const bool in = col < D * NV ? vel_in_grid<D>(c, n, col % NV) : pres_in_grid<D>(c, n, col - D * NV);
+        if (in) val = lu.z[f][col];
+      }
+      Zp[e] = val;
+    }
+    if (tid == 0 && bad) atomicMin(err, (int)node);
+    __syncthreads();
+  }
+}
+
 template <int D>
 hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count, double* Z,
                                 hipStream_t s) {
   if (count == 0) return hipSuccess;
+  if constexpr (D == 3) {
+    if (L.dense_lu) {
+      const int64_t nb = count < kLU3Blocks ? count : kLU3Blocks;
+      double* slots = nullptr;
+      hipError_t e = hipMallocAsync((void**)&slots, (size_t)nb * kLU3Slot * sizeof(double), s);
+      if (e != hipSuccess) return e;
+      patch_inverse_rows_lu3_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(
+          L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, nodes, count, Z, slots, c.err);
+      e = hipGetLastError();
+      const hipError_t f = hipFreeAsync(slots, s);
+      return e != hipSuccess ? e : f;
+    }
+  }
   if constexpr (D == 2) {
     if (L.dense_lu) {
       const int64_t nb = count < 262144 ? count : 262144;

@@ -39,7 +39,7 @@ class Problem:
     nu_post: int = 2
     omega: float = 0.8
     name: str = ""
-    immersed_nitsche: int = 0    # 1: obstacle surfaces are no-slip Dirichlet boundaries (Nitsche, 2D)
+    immersed_nitsche: int = 0    # 1: obstacle surfaces are no-slip Dirichlet boundaries (Nitsche)
 
     @property
     def n_nodes(self) -> int:

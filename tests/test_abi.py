@@ -64,7 +64,9 @@ def test_kernel_kinds_match_header():
     (lambda p: (setattr(p, "precision", 1), setattr(p, "cache_policy", 1)), "mixed precision"),
     (lambda p: setattr(p, "immersed_nitsche", 2), "immersed_nitsche"),
     (lambda p: (setattr(p, "immersed_nitsche", 1), setattr(p, "dim", 3), setattr(p, "n_cells", 8),
-                setattr(p, "n_levels", 2)), "immersed_nitsche"),
+                setattr(p, "n_levels", 2), setattr(p, "cache_policy", 1)), "immersed_nitsche"),
+    (lambda p: (setattr(p, "immersed_nitsche", 1), setattr(p, "dim", 3), setattr(p, "n_cells", 8),
+                setattr(p, "n_levels", 2), setattr(p, "cache_policy", 2)), "immersed_nitsche"),
 ])
 def test_setup_rejects_bad_arguments_on_host(mutate, msg):
     from paper_2403_11636_amd import inputs

@@ -1,9 +1,9 @@
-"""Immersed Nitsche (2D, cache_inverse): the obstacle surfaces as no-slip Dirichlet boundaries of
-Eq. 5, imposed by the wall forms on the obstacle arcs of the cut cells; the HIP path against the
-oracle with the same option.
+"""Immersed Nitsche (cache_inverse; 2D also cache_matrix and cache_none): the obstacle surfaces as
+no-slip Dirichlet boundaries of Eq. 5, imposed by the wall forms on the obstacle arcs (2D) or sphere
+pieces (3D) of the cut cells; the HIP path against the oracle with the same option.
 
-Both sides take the arc quadrature from the same reading and factorise the local blocks, which may
-be indefinite here, by LU with partial pivoting. Tolerances follow test_gpu_parity: residual
+Both sides take the surface quadrature from the same reading and factorise the local blocks, which
+may be indefinite here, by LU with partial pivoting (3D: 402 x 402 blocks at set-up). Tolerances follow test_gpu_parity: residual
 componentwise 1e-13 (|b| + |L||x|); one or two sweeps relative 2-norm 1e-12 (measured up to 3.7e-13);
 V-cycles 1e-9, bounded by the condition of the coarse solve (measured up to 1e-11); solves by the
 oracle's residual of the GPU iterate.
@@ -25,6 +25,8 @@ CASES = {
     "2d_32_l3_s2": lambda: inputs.small_problem(2, 32, 3, seed=2, n_balls=3),
     "c1_32_l3": lambda: inputs.config1(32, 3),
     "2d_64_l4_discs": lambda: inputs.config2(0, n_cells=64, n_levels=4),
+    "3d_8_l2_s0": lambda: inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2),
+    "3d_12_l2_s3": lambda: inputs.small_problem(3, 12, 2, seed=3, n_balls=2, rmin=0.08, rmax=0.14),
 }
 
 _cache = {}
@@ -139,8 +141,9 @@ def test_immersed_matrix_and_none_policies(name, policy):
     h.close()
 
 
-def test_immersed_needs_2d():
+@pytest.mark.parametrize("policy", [1, 2])
+def test_immersed_3d_needs_cache_inverse(policy):
     from paper_2403_11636_amd import fcgmg
     p = dataclasses.replace(inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2), immersed_nitsche=1)
     with pytest.raises(fcgmg.FcgmgError):
-        fcgmg.Hierarchy(p, fcgmg.CACHE_INVERSE)
+        fcgmg.Hierarchy(p, policy)
