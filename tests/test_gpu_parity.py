@@ -335,6 +335,17 @@ def test_config3_full_size_sampled():
     assert st["n_cut_cells"] > 1000
 
 
+def test_config3_immersed_full_size_sampled():
+    # 3D 64^3 with the sphere surfaces as Nitsche walls: the dense-LU inverse rows of every individual
+    # patch (more patches than the 512 workgroups of one launch, so each takes several in turn) and
+    # the surface terms of every cut cell, on sampled nodes; the residual bound as for the 2D
+    # immersed case (cancelling surface-quadrature sums)
+    import dataclasses
+    p = dataclasses.replace(inputs.config3(0), immersed_nitsche=1)
+    st = _sampled_sweep(p, 0, 40, res_tol=1e-12)
+    assert st["n_cut_cells"] > 1000
+
+
 @pytest.mark.parametrize("policy", [1, 2])
 def test_config3_full_size_sampled_factorising_policies(policy):
     # 274,625 patches: more than the 131,072 workgroups of one launch, so the grid-stride pass of the
