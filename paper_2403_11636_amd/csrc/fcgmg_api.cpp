@@ -452,6 +452,11 @@ int setup_impl(Ctx& c, hipStream_t s) {
     FCG_HIP(hipMemcpyAsync(c.balls, c.balls_h.data(), c.balls_h.size() * sizeof(double), hipMemcpyHostToDevice, s));
   }
   if ((rc = alloc_n(c, &c.red, kRedBlocks + 1))) return rc;
+  if (D == 3 && P.cache_policy == FCGMG_CACHE_INVERSE) {
+    FCG_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    FCG_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    FCG_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+  }
   FCG_HIP(hipHostMalloc((void**)&c.red_host, sizeof(double), hipHostMallocDefault));
   FCG_HIP(hipHostGetDevicePointer((void**)&c.red_host_dev, c.red_host, 0));
   if (P.cache_policy == FCGMG_CACHE_MATRIX) {
@@ -693,6 +698,19 @@ int sweep_impl(const Ctx& c, int l, T* x, const T* b, hipStream_t s, T* rbuf = n
   int rc;
   if ((rc = residual_impl<D, T>(c, l, x, b, r, s))) return rc;
   if (c.prm.cache_policy == FCGMG_CACHE_INVERSE) {
+    if (D == 3 && c.side && L.n_classes && L.n_irr) {
+      // the shared-class patches on the second stream, concurrently with the streamed ones: each
+      // node is written by one of the two applies, both read only r
+      FCG_HIP(hipEventRecord(c.ev_fork, s));
+      FCG_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+      if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, c.side, [&] { return k_apply_regular<D, T>(c, L, r, x, c.side); })))
+        return rc;
+      FCG_HIP(hipEventRecord(c.ev_join, c.side));
+      if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s, [&] { return k_apply_irregular<D, T>(c, L, r, x, s); })))
+        return rc;
+      FCG_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+      return FCGMG_OK;
+    }
     if (L.n_classes)
       if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s, [&] { return k_apply_regular<D, T>(c, L, r, x, s); })))
         return rc;
@@ -1275,6 +1293,12 @@ void fcgmg_destroy(fcgmg_h h) {
     h->prof_pool.push_back(r.stop);
   }
   for (hipEvent_t e : h->prof_pool) (void)hipEventDestroy(e);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->red_host) (void)hipHostFree(h->red_host);
   if (h->kh_host) (void)hipHostFree(h->kh_host);

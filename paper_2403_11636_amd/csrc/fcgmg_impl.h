@@ -247,8 +247,13 @@ struct Ctx {
   int* err = nullptr;            // device error flag: first failing patch node, or INT_MAX
   int* pattern = nullptr;        // cache_matrix sparse pattern (encoded entries)
   int n_pattern = 0;
-  bool none_integrate = false;
-  bool multi_ready = false;     // fcgmg_vcycle_multi workspace allocated  // cache_none: assemble from element integrals, cut cells integrated per sweep
+  bool none_integrate = false;  // cache_none: assemble from element integrals, cut cells integrated per sweep
+  bool multi_ready = false;     // fcgmg_vcycle_multi workspace allocated
+  // 3D cache_inverse: a second stream on which the shared-class apply of a sweep runs beside the
+  // streamed-patch apply (the two write disjoint nodes), forked from and joined to the caller's
+  // stream by the two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t bytes = 0;
   std::vector<void*> allocs;
   // event profiler
