@@ -842,18 +842,28 @@ int sweeps_multi(const Ctx& c, int l, double* x, const double* b, double* r, int
   const Level& L = c.lev[l];
   const int64_t nd = (D + 1) * L.N;
   int rc;
+  // 3D: the shared-class applies on the handle's second stream, beside the stacked streamed apply
+  // (disjoint nodes, both read only r), as in sweep_impl
+  const bool fork = D == 3 && c.side && L.n_classes && L.n_irr;
+  const hipStream_t sr = fork ? c.side : s;
   for (int it = 0; it < sweeps; ++it) {
     for (int k = 0; k < nrhs; ++k)
       if ((rc = residual_impl<D>(c, l, x + k * nd, b + k * nd, r + k * nd, s))) return rc;
+    if (fork) {
+      FCG_HIP(hipEventRecord(c.ev_fork, s));
+      FCG_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    }
     if (L.n_classes)
       for (int k = 0; k < nrhs; ++k)
-        if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, s,
-                         [&] { return k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, s); })))
+        if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, sr,
+                         [&] { return k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, sr); })))
           return rc;
+    if (fork) FCG_HIP(hipEventRecord(c.ev_join, c.side));
     if (L.n_irr)
       if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s,
                        [&] { return k_apply_irregular_multi<D, double>(c, L, r, x, nd, nrhs, s); })))
         return rc;
+    if (fork) FCG_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
   }
   return FCGMG_OK;
 }

@@ -27,6 +27,11 @@ CASES = {
     "2d_64_l4_discs": lambda: inputs.config2(0, n_cells=64, n_levels=4),
     "3d_8_l2_s0": lambda: inputs.small_problem(3, 8, 2, seed=0, n_balls=1, rmin=0.15, rmax=0.2),
     "3d_12_l2_s3": lambda: inputs.small_problem(3, 12, 2, seed=3, n_balls=2, rmin=0.08, rmax=0.14),
+    # a sphere through the inflow face (its surface clipped by the box), and two spheres whose gap
+    # lies inside one cell (that cell's surface terms come from both)
+    "2d_16_edge_inflow": lambda: inputs.edge_problem(2, 16, 3, "inflow_wall"),
+    "3d_8_edge_inflow": lambda: inputs.edge_problem(3, 8, 2, "inflow_wall"),
+    "3d_8_edge_two": lambda: inputs.edge_problem(3, 8, 2, "two_in_cell"),
 }
 
 _cache = {}
