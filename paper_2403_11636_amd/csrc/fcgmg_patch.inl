@@ -716,65 +716,95 @@ __device__ void patch_dense3(const PatchLDS<3>& sh, double* __restrict__ A) {
 }
 
 // P A = L U in place (unit L below the diagonal, U on and above), the row interchanges in lu.piv;
-// pivot: largest |A[i][k]|, lowest row on ties. lu.bad is set when a pivot column is zero. Each
-// wavefront updates whole rows (lanes over the columns).
+// pivot: largest |A[i][k]|, lowest row on ties. lu.bad is set when a pivot column is zero.
+// Right-looking in panels of kLU3Panel columns: within a panel each column is pivoted, its rows
+// swapped in full, scaled and applied to the rest of the panel; then the panel's block row of U is
+// formed and the trailing block updated once by the panel's rank-kLU3Panel product, so the trailing
+// block streams through memory once per panel instead of once per column.
+constexpr int kLU3Panel = 16;
+
 __device__ void lu_factor3(double* __restrict__ A, LU3LDS& lu) {
-  constexpr int ZS = kLU3;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  constexpr int ZS = kLU3, NBP = kLU3Panel;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6, nt = blockDim.x;
   if (tid == 0) lu.bad = 0;
   __syncthreads();
-  for (int k = 0; k < ZS; ++k) {
-    double pv = -1.0;
-    int pr = ZS;
-    for (int i = k + tid; i < ZS; i += blockDim.x) {
-      const double v = fabs(A[(int64_t)i * ZS + k]);
-      if (v > pv) {  // rows ascend per thread: the first of equal values is kept
-        pv = v;
-        pr = i;
-      }
-    }
-    for (int m = 32; m >= 1; m >>= 1) {
-      const double ov = __shfl_xor(pv, m, 64);
-      const int orow = __shfl_xor(pr, m, 64);
-      if (ov > pv || (ov == pv && orow < pr)) {
-        pv = ov;
-        pr = orow;
-      }
-    }
-    if (lane == 0) {
-      lu.red_v[wave] = pv;
-      lu.red_i[wave] = pr;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double bv = lu.red_v[0];
-      int br = lu.red_i[0];
-      for (int w = 1; w < nw; ++w)
-        if (lu.red_v[w] > bv || (lu.red_v[w] == bv && lu.red_i[w] < br)) {
-          bv = lu.red_v[w];
-          br = lu.red_i[w];
+  for (int k0 = 0; k0 < ZS; k0 += NBP) {
+    const int ke = k0 + NBP < ZS ? k0 + NBP : ZS;
+    for (int k = k0; k < ke; ++k) {
+      double pv = -1.0;
+      int pr = ZS;
+      for (int i = k + tid; i < ZS; i += nt) {
+        const double v = fabs(A[(int64_t)i * ZS + k]);
+        if (v > pv) {  // rows ascend per thread: the first of equal values is kept
+          pv = v;
+          pr = i;
         }
-      lu.pk = br;
-      lu.piv[k] = br;
-      if (!(bv > 0)) lu.bad = 1;
+      }
+      for (int msk = 32; msk >= 1; msk >>= 1) {
+        const double ov = __shfl_xor(pv, msk, 64);
+        const int orow = __shfl_xor(pr, msk, 64);
+        if (ov > pv || (ov == pv && orow < pr)) {
+          pv = ov;
+          pr = orow;
+        }
+      }
+      if (lane == 0) {
+        lu.red_v[wave] = pv;
+        lu.red_i[wave] = pr;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double bv = lu.red_v[0];
+        int br = lu.red_i[0];
+        for (int w = 1; w < nw; ++w)
+          if (lu.red_v[w] > bv || (lu.red_v[w] == bv && lu.red_i[w] < br)) {
+            bv = lu.red_v[w];
+            br = lu.red_i[w];
+          }
+        lu.pk = br;
+        lu.piv[k] = br;
+        if (!(bv > 0)) lu.bad = 1;
+      }
+      __syncthreads();
+      if (lu.bad) return;
+      const int p = lu.pk;
+      if (p != k)
+        for (int j = tid; j < ZS; j += nt) {
+          const double t = A[(int64_t)k * ZS + j];
+          A[(int64_t)k * ZS + j] = A[(int64_t)p * ZS + j];
+          A[(int64_t)p * ZS + j] = t;
+        }
+      __syncthreads();
+      const double inv = 1.0 / A[(int64_t)k * ZS + k];
+      for (int i = k + 1 + tid; i < ZS; i += nt) A[(int64_t)i * ZS + k] *= inv;
+      __syncthreads();
+      // the rest of the panel: columns k+1 .. ke-1
+      const int w = ke - k - 1;
+      if (w > 0) {
+        for (int e = tid; e < (ZS - k - 1) * w; e += nt) {
+          const int i = k + 1 + e / w, jj = k + 1 + e % w;
+          A[(int64_t)i * ZS + jj] -= A[(int64_t)i * ZS + k] * A[(int64_t)k * ZS + jj];
+        }
+        __syncthreads();
+      }
     }
-    __syncthreads();
-    if (lu.bad) return;
-    const int p = lu.pk;
-    if (p != k)
-      for (int j = tid; j < ZS; j += blockDim.x) {
-        const double t = A[(int64_t)k * ZS + j];
-        A[(int64_t)k * ZS + j] = A[(int64_t)p * ZS + j];
-        A[(int64_t)p * ZS + j] = t;
+    if (ke == ZS) break;
+    // block row of U: rows k0+1 .. ke-1, columns ke .. ZS-1, by the unit lower panel triangle (each
+    // thread one column, rows in order)
+    for (int j = ke + tid; j < ZS; j += nt)
+      for (int i = k0 + 1; i < ke; ++i) {
+        double s = A[(int64_t)i * ZS + j];
+        for (int t = k0; t < i; ++t) s -= A[(int64_t)i * ZS + t] * A[(int64_t)t * ZS + j];
+        A[(int64_t)i * ZS + j] = s;
       }
     __syncthreads();
-    const double inv = 1.0 / A[(int64_t)k * ZS + k];
-    for (int i = k + 1 + tid; i < ZS; i += blockDim.x) A[(int64_t)i * ZS + k] *= inv;
-    __syncthreads();
-    for (int i = k + 1 + wave; i < ZS; i += nw) {
-      const double lik = A[(int64_t)i * ZS + k];
-      for (int j = k + 1 + lane; j < ZS; j += 64) A[(int64_t)i * ZS + j] -= lik * A[(int64_t)k * ZS + j];
-    }
+    // trailing block: A[i][j] -= sum over the panel's columns t of L[i][t] U[t][j]
+    for (int i = ke + wave; i < ZS; i += nw)
+      for (int j = ke + lane; j < ZS; j += 64) {
+        double s = A[(int64_t)i * ZS + j];
+        for (int t = k0; t < ke; ++t) s -= A[(int64_t)i * ZS + t] * A[(int64_t)t * ZS + j];
+        A[(int64_t)i * ZS + j] = s;
+      }
     __syncthreads();
   }
 }
