@@ -36,6 +36,13 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(FCGMG_E_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// A value for a message, in scientific notation (std::to_string prints every digit of a large one).
+std::string sci(double v) {
+  char buf[32];
+  std::snprintf(buf, sizeof buf, "%.3e", v);
+  return buf;
+}
+
 int dev_alloc(Ctx& c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return FCGMG_OK;
@@ -1106,7 +1113,7 @@ int fgmres_impl(const Ctx& c, double* x, const double* b, double rtol, int max_i
     if (beta <= rtol * r0) return FCGMG_OK;
     if (its >= max_iter)
       return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
-                                      std::to_string(*rel_res) + ")");
+                                      sci(*rel_res) + ")");
     (void)done;  // the estimate converged but the true residual did not: restart
   }
 }
@@ -1534,7 +1541,7 @@ int fcgmg_solve(fcgmg_h h, double* x, const double* b, double rtol, int max_iter
     if (rn <= rtol * r0) return FCGMG_OK;
   }
   return fail(FCGMG_E_NOCONV, "no convergence in " + std::to_string(max_iter) + " cycles (rel. residual " +
-                                  std::to_string(*rel_res) + ")");
+                                  sci(*rel_res) + ")");
 }
 
 int fcgmg_autotune(fcgmg_h h, int reps, int* shape_out, double* us_out, void* stream) {
