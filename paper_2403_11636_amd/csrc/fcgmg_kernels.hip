@@ -3,6 +3,7 @@
 // Method: Saberi & Vogel, arXiv 2403.11636 (equation numbers refer to the paper).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <climits>
 #include <cstdint>
 

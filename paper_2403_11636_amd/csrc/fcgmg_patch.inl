@@ -2849,18 +2849,20 @@ hipError_t k_batch_fused2(const Fused2Job<double>* jobs, const int* block_job, i
 // Workgroups of the persistent batched sweep that the device holds at once (occupancy per CU times
 // CUs), looked up once per device.
 int batch_fused2_resident_blocks() {
-  static int cache[64] = {0};
+  // several host threads may ask at once (the solve server's workers); each stores the same value
+  static std::atomic<int> cache[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cache[dev] > 0) return cache[dev];
+  const int known = cache[dev].load(std::memory_order_relaxed);
+  if (known > 0) return known;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &per_cu, sweep_fused2_batch_persistent_kernel<kBatchTX, kBatchTY, kBatchNT, 5, double>, kBatchNT, 0) !=
           hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 || cus < 1)
     return 0;
-  cache[dev] = per_cu * cus;
-  return cache[dev];
+  cache[dev].store(per_cu * cus, std::memory_order_relaxed);
+  return per_cu * cus;
 }
 
 hipError_t k_batch_fused2_persistent(const Fused2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s) {
