@@ -875,6 +875,69 @@ int sweeps_multi(const Ctx& c, int l, double* x, const double* b, double* r, int
   return FCGMG_OK;
 }
 
+// The sweeps of smooth_impl (2D, FP64, cache_inverse) for nrhs vectors of one level, nd apart: the
+// entry mode and an odd first sweep are taken as smooth_impl takes them, then pairs of stacked fused
+// sweeps between x and alt (nrhs vectors of scratch). xc: the coarse vectors of mode 2, ndc apart.
+// Per vector the result is that of smooth_impl.
+int smooth_multi2(const Ctx& c, int l, double* x, const double* b, double* alt, int nrhs, int sweeps, hipStream_t s,
+                  int mode = 0, const double* xc = nullptr, int64_t ndc = 0) {
+  const Level& L = c.lev[l];
+  const int64_t nd = 3 * L.N;
+  int rc;
+  if (mode != 0 && (sweeps % 2 == 1 || sweeps == 0)) {
+    for (int k = 0; k < nrhs; ++k) {
+      if (mode == 1)
+        rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x + k * nd, nd, s); });
+      else
+        rc = prolong_impl<2, double>(c, l, xc + k * ndc, x + k * nd, s);
+      if (rc) return rc;
+    }
+    mode = 0;
+  }
+  int i = 0;
+  if (sweeps % 2 == 1) {
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = sweep_impl<2, double>(c, l, x + k * nd, b + k * nd, s))) return rc;
+    i = 1;
+  }
+  for (; i < sweeps; i += 2) {
+    const int md = i == 0 ? mode : 0;
+    const double* xcm = md == 2 ? xc : nullptr;
+    if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s,
+                     [&] { return k_sweep_fused2_multi(c, L, x, b, alt, md, xcm, nrhs, nd, ndc, s); })))
+      return rc;
+    if ((rc = launch(c, FCGMG_K_SWEEP_FUSED, l, s,
+                     [&] { return k_sweep_fused2_multi(c, L, alt, b, x, 0, nullptr, nrhs, nd, ndc, s); })))
+      return rc;
+  }
+  return FCGMG_OK;
+}
+
+// The V-cycle of vcycle_impl (2D, fused sweeps) for nrhs vectors of one geometry: the smoothing of
+// every level by stacked fused sweeps, the residual + restriction and the coarsest solve per vector.
+// The coarse levels use the handle's multi-vector workspace. Per vector the result is that of
+// vcycle_impl.
+int vcycle_multi2(const Ctx& c, int l, double* x, const double* b, int nrhs, hipStream_t s, bool x_zero) {
+  const Level& L = c.lev[l];
+  const int64_t nd = 3 * L.N;
+  int rc;
+  if (l == 0) {
+    for (int k = 0; k < nrhs; ++k)
+      if ((rc = coarse_impl<double>(c, b + k * nd, x + k * nd, s))) return rc;
+    return FCGMG_OK;
+  }
+  if ((rc = smooth_multi2(c, l, x, b, L.rm, nrhs, c.prm.nu_pre, s, x_zero ? 1 : 0))) return rc;
+  const Level& C = c.lev[l - 1];
+  const int64_t ndc = 3 * C.N;
+  for (int k = 0; k < nrhs; ++k)
+    if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s, [&] {
+           return k_residual_restrict2<double>(c, L, x + k * nd, b + k * nd, C.bm + k * ndc, s);
+         })))
+      return rc;
+  if ((rc = vcycle_multi2(c, l - 1, C.xm, C.bm, nrhs, s, true))) return rc;
+  return smooth_multi2(c, l, x, b, L.rm, nrhs, c.prm.nu_post, s, 2, C.xm, ndc);
+}
+
 // The V-cycle of vcycle_impl (3D, unfused sweeps) for nrhs vectors of one geometry: every step per
 // vector, except the streamed patch rows, which each sweep reads once for all vectors. The coarse
 // levels use the handle's multi-vector workspace. Per vector the result is that of vcycle_impl.
@@ -1434,12 +1497,9 @@ int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double*
     const fcg::Level& L = c.lev[level];
     const int64_t nd = (D + 1) * L.N;
     if constexpr (D == 2) {
-      int rc;
-      // 2D: the fused sweep of each vector (x and r in LDS per tile) is faster than the stacked
-      // unfused sweep; the results are the same bits either way
-      for (int k = 0; k < nrhs; ++k)
-        if ((rc = smooth_impl<2>(c, level, x + k * nd, b + k * nd, sweeps, s))) return rc;
-      return FCGMG_OK;
+      // 2D: stacked fused sweeps (r serves as the second iterate of each vector)
+      (void)nd;
+      return smooth_multi2(c, level, x, b, r, nrhs, sweeps, s);
     }
     return sweeps_multi<D>(c, level, x, b, r, nrhs, sweeps, s);
   };
@@ -1454,13 +1514,9 @@ int fcgmg_vcycle_multi(fcgmg_h h, double* x, const double* b, int nrhs, void* st
   const int top = (int)h->lev.size() - 1;
   const int64_t nd = (int64_t)(h->prm.dim + 1) * h->lev[top].N;
   int rc;
-  if (h->prm.dim == 2) {
-    // 2D: the fused per-vector cycle is faster than stacking (see fcgmg_smooth_multi); same bits
-    for (int k = 0; k < nrhs; ++k)
-      if ((rc = vcycle_impl<2>(*h, top, x + k * nd, b + k * nd, s))) return rc;
-    return FCGMG_OK;
-  }
+  (void)nd;
   if ((rc = multi_workspace(*h))) return rc;
+  if (h->prm.dim == 2) return vcycle_multi2(*h, top, x, b, nrhs, s, false);
   return vcycle_multi_impl<3>(*h, top, x, b, nrhs, s, false);
 }
 

@@ -2554,6 +2554,29 @@ sweep_fused2_kernel(Fused2Job<T> J) {
   fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(J, (int)blockIdx.x, threadIdx.x);
 }
 
+// Stacked form: nrhs vectors of one level (x_in, b and x_out sv elements apart, xc sc apart) in one
+// launch; each workgroup sweeps its tile (or tile part) for every vector in turn, so the tile's
+// operator rows, classes and patch rows come from HBM once and from the caches after that. Per
+// vector the arithmetic is that of sweep_fused2_kernel.
+template <int TX, int TY, int NT, int WPE, class T>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+sweep_fused2_multi_kernel(Fused2Job<T> J, int nrhs, int64_t sv, int64_t sc) {
+  for (int k = 0; k < nrhs; ++k) {
+    // the thread index, opaque to the compiler: nothing derived from it is hoisted out of the loop,
+    // where it would stay live across every vector and spill
+    unsigned tid;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
+    Fused2Job<T> Jk = J;
+    Jk.x_in += k * sv;
+    Jk.b += k * sv;
+    Jk.x_out += k * sv;
+    if (Jk.xc) Jk.xc += k * sc;
+    fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(Jk, (int)blockIdx.x, tid);
+    // every thread is done with this vector's LDS before the next one's stores
+    __syncthreads();
+  }
+}
+
 // Batched form: the workgroups of several jobs (levels of independent problems) in one launch;
 // block_job maps a workgroup to its job, whose workgroups start at job.block0. There are no extra
 // parts: one part holds the whole tile.
@@ -2678,6 +2701,38 @@ hipError_t k_sweep_fused2(const Ctx& c, const Level& L, const T* x_in, const T* 
   if (L.N >= kFusedBigTileNodes) return launch_fused2<B.tx, B.ty, B.nt, B.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
   if (L.N >= kFusedMidTileNodes) return launch_fused2<M.tx, M.ty, M.nt, M.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
   return launch_fused2<S.tx, S.ty, S.nt, S.wpe, T>(c, L, x_in, b, x_out, mode, xc, s);
+}
+
+template <int TX, int TY, int NT, int WPE>
+hipError_t launch_fused2_multi(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                               int mode, const double* xc, int nrhs, int64_t sv, int64_t sc, hipStream_t s) {
+  const int ntx = (L.n + 1 + TX - 1) / TX, nty = (L.n + 1 + TY - 1) / TY;
+  const Fused2Job<double> J{L.consts, L.node_op, L.nsten, L.fused_extra, (int)L.n_fused_extra,
+                            L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc, c.prm.omega, ntx, nty, mode, 0};
+  sweep_fused2_multi_kernel<TX, TY, NT, WPE, double>
+      <<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(J, nrhs, sv, sc);
+  return hipGetLastError();
+}
+
+// One fused sweep of nrhs stacked vectors (FP64). Levels on the small tile shapes, whose sweep is a
+// short chain per workgroup, take the stacked kernel: one launch instead of nrhs. Levels on the
+// large tiles, and levels with an autotuned shape, take one launch per vector: there the stacked
+// kernel was slower (4096^2 sweep of 8 vectors 4.50 -> 5.04 ms), as sweeping the tile again finds
+// nothing shorter than the first time.
+hipError_t k_sweep_fused2_multi(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
+                                int mode, const double* xc, int nrhs, int64_t sv, int64_t sc, hipStream_t s) {
+  if (L.fshape >= 0 || L.N >= kFusedBigTileNodes) {
+    for (int k = 0; k < nrhs; ++k) {
+      const hipError_t e =
+          k_sweep_fused2<double>(c, L, x_in + k * sv, b + k * sv, x_out + k * sv, mode, xc ? xc + k * sc : nullptr, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  constexpr Fused2Shape M = kFusedMid, S = kFusedSmall;
+  if (L.N >= kFusedMidTileNodes)
+    return launch_fused2_multi<M.tx, M.ty, M.nt, M.wpe>(c, L, x_in, b, x_out, mode, xc, nrhs, sv, sc, s);
+  return launch_fused2_multi<S.tx, S.ty, S.nt, S.wpe>(c, L, x_in, b, x_out, mode, xc, nrhs, sv, sc, s);
 }
 
 // Residual and restriction in one pass (2D, V-cycle): b_c = P^T (b - L x) for a TXC x TYC tile of
