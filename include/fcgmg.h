@@ -165,9 +165,9 @@ int fcgmg_smooth_noalloc(fcgmg_h h, int level, double* x, const double* b, int s
  * one after another (vector k at offset k (d+1) N_l); r is caller-owned scratch of the same size (3D:
  * it holds the residuals of the last sweep on return; 2D: the second iterate of the fused sweeps). In
  * 3D the inverse rows of every streamed patch are read once per sweep for all right-hand sides; in 2D
- * levels on the small fused tiles sweep all vectors in one launch, each workgroup taking its tile for
- * every vector in turn, and larger levels take one fused launch per vector. Each x_k ends bitwise
- * equal to fcgmg_smooth on x_k, b_k. cache_inverse only.
+ * one fused launch sweeps every vector (the vector is the launch's second grid index; levels from
+ * 2^21 nodes take one launch per vector). Each x_k ends bitwise equal to fcgmg_smooth on x_k, b_k.
+ * cache_inverse only.
  * Asynchronous on `stream`; E_ARG for a bad level, pointer, nrhs or policy. */
 int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double* r, int nrhs, int sweeps,
                        void* stream);
@@ -176,8 +176,8 @@ int fcgmg_smooth_multi(fcgmg_h h, int level, double* x, const double* b, double*
  * finest-level vectors one after another (device, FP64, each (d+1) N_fine). cache_inverse only.
  * Every result is bitwise that of fcgmg_vcycle on its vector. In 3D each sweep of every level
  * streams the individual patches' inverse rows once for all vectors (as fcgmg_smooth_multi); in 2D
- * every level smooths all vectors as fcgmg_smooth_multi does, the residual + restriction and the
- * coarsest solve run per vector. The first call allocates a workspace of 8 vectors of r per level and
+ * every level smooths all vectors as fcgmg_smooth_multi does, and the residual + restriction and the
+ * coarsest solve also take all vectors in one launch. The first call allocates a workspace of 8 vectors of r per level and
  * of x and b per coarse level, kept by the handle (counted by fcgmg_device_bytes, not by
  * fcgmg_footprint_bytes). Errors: E_ARG (nrhs outside 1..8, another policy),
  * E_NOMEM, E_HIP. */

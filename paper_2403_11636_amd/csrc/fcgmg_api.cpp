@@ -875,6 +875,11 @@ int sweeps_multi(const Ctx& c, int l, double* x, const double* b, double* r, int
   return FCGMG_OK;
 }
 
+// The coarsest solve of coarse_impl for nrhs vectors (b, x coarse_n apart), one launch.
+int coarse_multi(const Ctx& c, const double* b, double* x, int nrhs, hipStream_t s) {
+  return launch(c, FCGMG_K_COARSE, 0, s, [&] { return k_dense_matvec_multi(c.coarse_inv, c.coarse_n, b, x, nrhs, s); });
+}
+
 // The sweeps of smooth_impl (2D, FP64, cache_inverse) for nrhs vectors of one level, nd apart: the
 // entry mode and an odd first sweep are taken as smooth_impl takes them, then pairs of stacked fused
 // sweeps between x and alt (nrhs vectors of scratch). xc: the coarse vectors of mode 2, ndc apart.
@@ -921,19 +926,13 @@ int vcycle_multi2(const Ctx& c, int l, double* x, const double* b, int nrhs, hip
   const Level& L = c.lev[l];
   const int64_t nd = 3 * L.N;
   int rc;
-  if (l == 0) {
-    for (int k = 0; k < nrhs; ++k)
-      if ((rc = coarse_impl<double>(c, b + k * nd, x + k * nd, s))) return rc;
-    return FCGMG_OK;
-  }
+  if (l == 0) return coarse_multi(c, b, x, nrhs, s);
   if ((rc = smooth_multi2(c, l, x, b, L.rm, nrhs, c.prm.nu_pre, s, x_zero ? 1 : 0))) return rc;
   const Level& C = c.lev[l - 1];
   const int64_t ndc = 3 * C.N;
-  for (int k = 0; k < nrhs; ++k)
-    if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s, [&] {
-           return k_residual_restrict2<double>(c, L, x + k * nd, b + k * nd, C.bm + k * ndc, s);
-         })))
-      return rc;
+  if ((rc = launch(c, FCGMG_K_RESIDUAL_RESTRICT, l, s,
+                   [&] { return k_residual_restrict2_multi(L, x, b, C.bm, nrhs, nd, ndc, s); })))
+    return rc;
   if ((rc = vcycle_multi2(c, l - 1, C.xm, C.bm, nrhs, s, true))) return rc;
   return smooth_multi2(c, l, x, b, L.rm, nrhs, c.prm.nu_post, s, 2, C.xm, ndc);
 }
@@ -946,11 +945,7 @@ int vcycle_multi_impl(const Ctx& c, int l, double* x, const double* b, int nrhs,
   const Level& L = c.lev[l];
   const int64_t nd = (D + 1) * L.N;
   int rc;
-  if (l == 0) {
-    for (int k = 0; k < nrhs; ++k)
-      if ((rc = coarse_impl<double>(c, b + k * nd, x + k * nd, s))) return rc;
-    return FCGMG_OK;
-  }
+  if (l == 0) return coarse_multi(c, b, x, nrhs, s);
   if (x_zero)
     for (int k = 0; k < nrhs; ++k)
       if ((rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x + k * nd, nd, s); }))) return rc;

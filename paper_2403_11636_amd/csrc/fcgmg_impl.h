@@ -659,6 +659,10 @@ hipError_t k_batch_fused2(const Fused2Job<double>* jobs, const int* block_job, i
 // nrhs stacked vectors of one 2D level (x_in, b, x_out sv apart; xc sc apart), FP64
 hipError_t k_sweep_fused2_multi(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                                 int mode, const double* xc, int nrhs, int64_t sv, int64_t sc, hipStream_t s);
+hipError_t k_residual_restrict2_multi(const Level& F, const double* x, const double* b, double* bc, int nrhs,
+                                      int64_t sv, int64_t sc, hipStream_t s);
+// x_k = A b_k for nrhs vectors (b, x n apart), one launch
+hipError_t k_dense_matvec_multi(const double* A, int n, const double* b, double* x, int nrhs, hipStream_t s);
 hipError_t k_batch_fused2_persistent(const Fused2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s);
 hipError_t k_batch_rr2(const RR2Job<double>* jobs, const int* block_job, int nblocks, hipStream_t s);
 hipError_t k_batch_dense(const DenseJob* jobs, const int* block_job, int nblocks, hipStream_t s);

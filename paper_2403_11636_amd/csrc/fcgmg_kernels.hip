@@ -1166,6 +1166,19 @@ hipError_t k_batch_dense(const DenseJob* jobs, const int* block_job, int nblocks
   return hipGetLastError();
 }
 
+// nrhs right-hand sides (b and x n apart), blockIdx.y the vector.
+__global__ void dense_matvec_multi_kernel(const double* __restrict__ A, int n, const double* __restrict__ b,
+                                          double* __restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t k = blockIdx.y;
+  if (row < n) dense_row<double>(A, n, b + k * n, x + k * n, row, threadIdx.x & 63);
+}
+
+hipError_t k_dense_matvec_multi(const double* A, int n, const double* b, double* x, int nrhs, hipStream_t s) {
+  dense_matvec_multi_kernel<<<dim3((unsigned)((n + 3) / 4), (unsigned)nrhs), dim3(256), 0, s>>>(A, n, b, x);
+  return hipGetLastError();
+}
+
 template <class T>
 hipError_t k_dense_matvec(const T* A, int n, const T* b, T* x, hipStream_t s) {
   dense_matvec_kernel<T><<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s>>>(A, n, b, x);

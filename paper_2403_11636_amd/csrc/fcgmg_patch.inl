@@ -2555,26 +2555,17 @@ sweep_fused2_kernel(Fused2Job<T> J) {
 }
 
 // Stacked form: nrhs vectors of one level (x_in, b and x_out sv elements apart, xc sc apart) in one
-// launch; each workgroup sweeps its tile (or tile part) for every vector in turn, so the tile's
-// operator rows, classes and patch rows come from HBM once and from the caches after that. Per
-// vector the arithmetic is that of sweep_fused2_kernel.
+// launch, blockIdx.y the vector: the workgroups of all vectors fill the chip together instead of one
+// launch after another. Per vector the arithmetic is that of sweep_fused2_kernel.
 template <int TX, int TY, int NT, int WPE, class T>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-sweep_fused2_multi_kernel(Fused2Job<T> J, int nrhs, int64_t sv, int64_t sc) {
-  for (int k = 0; k < nrhs; ++k) {
-    // the thread index, opaque to the compiler: nothing derived from it is hoisted out of the loop,
-    // where it would stay live across every vector and spill
-    unsigned tid;
-    asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"(threadIdx.x));
-    Fused2Job<T> Jk = J;
-    Jk.x_in += k * sv;
-    Jk.b += k * sv;
-    Jk.x_out += k * sv;
-    if (Jk.xc) Jk.xc += k * sc;
-    fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(Jk, (int)blockIdx.x, tid);
-    // every thread is done with this vector's LDS before the next one's stores
-    __syncthreads();
-  }
+sweep_fused2_multi_kernel(Fused2Job<T> J, int64_t sv, int64_t sc) {
+  const int64_t k = blockIdx.y;
+  J.x_in += k * sv;
+  J.b += k * sv;
+  J.x_out += k * sv;
+  if (J.xc) J.xc += k * sc;
+  fused2_body<TX, TY, NT, fused2_part_cap(Fused2Shape{TX, TY, NT}), T>(J, (int)blockIdx.x, threadIdx.x);
 }
 
 // Batched form: the workgroups of several jobs (levels of independent problems) in one launch;
@@ -2710,18 +2701,20 @@ hipError_t launch_fused2_multi(const Ctx& c, const Level& L, const double* x_in,
   const Fused2Job<double> J{L.consts, L.node_op, L.nsten, L.fused_extra, (int)L.n_fused_extra,
                             L.node_class, L.Zcls, L.Zirr, x_in, b, x_out, xc, c.prm.omega, ntx, nty, mode, 0};
   sweep_fused2_multi_kernel<TX, TY, NT, WPE, double>
-      <<<dim3((unsigned)(ntx * nty + L.n_fused_extra)), dim3(NT), 0, s>>>(J, nrhs, sv, sc);
+      <<<dim3((unsigned)(ntx * nty + L.n_fused_extra), (unsigned)nrhs), dim3(NT), 0, s>>>(J, sv, sc);
   return hipGetLastError();
 }
 
-// One fused sweep of nrhs stacked vectors (FP64). Levels on the small tile shapes, whose sweep is a
-// short chain per workgroup, take the stacked kernel: one launch instead of nrhs. Levels on the
-// large tiles, and levels with an autotuned shape, take one launch per vector: there the stacked
-// kernel was slower (4096^2 sweep of 8 vectors 4.50 -> 5.04 ms), as sweeping the tile again finds
-// nothing shorter than the first time.
+// Levels from this many nodes on take one fused launch per stacked vector: one vector's workgroups
+// already fill the chip many times over there (4096^2 sweep of 8 vectors 4.49 ms one by one, 4.67 ms
+// stacked).
+constexpr int64_t kFusedStackMaxNodes = int64_t(1) << 21;
+
+// One fused sweep of nrhs stacked vectors (FP64): one launch of the level's default tile shape for
+// all vectors; a level with an autotuned shape, or a very large one, takes one launch per vector.
 hipError_t k_sweep_fused2_multi(const Ctx& c, const Level& L, const double* x_in, const double* b, double* x_out,
                                 int mode, const double* xc, int nrhs, int64_t sv, int64_t sc, hipStream_t s) {
-  if (L.fshape >= 0 || L.N >= kFusedBigTileNodes) {
+  if (L.fshape >= 0 || L.N >= kFusedStackMaxNodes) {
     for (int k = 0; k < nrhs; ++k) {
       const hipError_t e =
           k_sweep_fused2<double>(c, L, x_in + k * sv, b + k * sv, x_out + k * sv, mode, xc ? xc + k * sc : nullptr, s);
@@ -2729,7 +2722,9 @@ hipError_t k_sweep_fused2_multi(const Ctx& c, const Level& L, const double* x_in
     }
     return hipSuccess;
   }
-  constexpr Fused2Shape M = kFusedMid, S = kFusedSmall;
+  constexpr Fused2Shape B = kFusedBig, M = kFusedMid, S = kFusedSmall;
+  if (L.N >= kFusedBigTileNodes)
+    return launch_fused2_multi<B.tx, B.ty, B.nt, B.wpe>(c, L, x_in, b, x_out, mode, xc, nrhs, sv, sc, s);
   if (L.N >= kFusedMidTileNodes)
     return launch_fused2_multi<M.tx, M.ty, M.nt, M.wpe>(c, L, x_in, b, x_out, mode, xc, nrhs, sv, sc, s);
   return launch_fused2_multi<S.tx, S.ty, S.nt, S.wpe>(c, L, x_in, b, x_out, mode, xc, nrhs, sv, sc, s);
@@ -2849,12 +2844,27 @@ __global__ void __launch_bounds__(NT) residual_restrict2_batch_kernel(const RR2J
   residual_restrict2_body<TXC, TYC, NT, T>(J, (int)blockIdx.x - J.block0);
 }
 
+// Stacked form: nrhs vectors (x and b sv apart, bc sc apart), blockIdx.y the vector.
 template <int TXC, int TYC, int NT, class T>
-hipError_t launch_residual_restrict2(const Level& F, const T* x, const T* b, T* bc, hipStream_t s) {
+__global__ void __launch_bounds__(NT) residual_restrict2_multi_kernel(RR2Job<T> J, int64_t sv, int64_t sc) {
+  const int64_t k = blockIdx.y;
+  J.x += k * sv;
+  J.b += k * sv;
+  J.bc += k * sc;
+  residual_restrict2_body<TXC, TYC, NT, T>(J, (int)blockIdx.x);
+}
+
+template <int TXC, int TYC, int NT, class T>
+hipError_t launch_residual_restrict2(const Level& F, const T* x, const T* b, T* bc, hipStream_t s, int nrhs = 1,
+                                     int64_t sv = 0, int64_t sc = 0) {
   const int mc = (F.n >> 1) + 1;
   const int ntx = (mc + TXC - 1) / TXC, nty = (mc + TYC - 1) / TYC;
   const RR2Job<T> J{F.consts, F.node_op, LV<T>::nsten(F), x, b, bc, ntx, nty, 0};
-  residual_restrict2_kernel<TXC, TYC, NT, T><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(J);
+  if (nrhs > 1)
+    residual_restrict2_multi_kernel<TXC, TYC, NT, T>
+        <<<dim3((unsigned)(ntx * nty), (unsigned)nrhs), dim3(NT), 0, s>>>(J, sv, sc);
+  else
+    residual_restrict2_kernel<TXC, TYC, NT, T><<<dim3((unsigned)(ntx * nty)), dim3(NT), 0, s>>>(J);
   return hipGetLastError();
 }
 
@@ -2863,6 +2873,15 @@ hipError_t k_residual_restrict2(const Ctx&, const Level& F, const T* x, const T*
   if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256, T>(F, x, b, bc, s);
   if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128, T>(F, x, b, bc, s);
   return launch_residual_restrict2<4, 4, 128, T>(F, x, b, bc, s);
+}
+
+// The fused residual + restriction of nrhs stacked vectors (FP64; x, b sv apart, bc sc apart) in one
+// launch.
+hipError_t k_residual_restrict2_multi(const Level& F, const double* x, const double* b, double* bc, int nrhs,
+                                      int64_t sv, int64_t sc, hipStream_t s) {
+  if (F.N >= kFusedBigTileNodes) return launch_residual_restrict2<16, 8, 256, double>(F, x, b, bc, s, nrhs, sv, sc);
+  if (F.N >= kFusedMidTileNodes) return launch_residual_restrict2<8, 4, 128, double>(F, x, b, bc, s, nrhs, sv, sc);
+  return launch_residual_restrict2<4, 4, 128, double>(F, x, b, bc, s, nrhs, sv, sc);
 }
 
 // ---- batched launches (independent 2D problems, one launch per V-cycle step) -------------------
