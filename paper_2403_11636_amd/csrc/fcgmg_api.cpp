@@ -854,17 +854,17 @@ int sweeps_multi(const Ctx& c, int l, double* x, const double* b, double* r, int
   const bool fork = D == 3 && c.side && L.n_classes && L.n_irr;
   const hipStream_t sr = fork ? c.side : s;
   for (int it = 0; it < sweeps; ++it) {
-    for (int k = 0; k < nrhs; ++k)
-      if ((rc = residual_impl<D>(c, l, x + k * nd, b + k * nd, r + k * nd, s))) return rc;
+    // the residuals and the shared-class applies of all vectors, one launch each
+    if ((rc = launch(c, FCGMG_K_RESIDUAL, l, s, [&] { return k_residual<D, double>(c, L, x, b, r, s, nrhs, nd); })))
+      return rc;
     if (fork) {
       FCG_HIP(hipEventRecord(c.ev_fork, s));
       FCG_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
     }
     if (L.n_classes)
-      for (int k = 0; k < nrhs; ++k)
-        if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, sr,
-                         [&] { return k_apply_regular<D, double>(c, L, r + k * nd, x + k * nd, sr); })))
-          return rc;
+      if ((rc = launch(c, FCGMG_K_APPLY_REGULAR, l, sr,
+                       [&] { return k_apply_regular<D, double>(c, L, r, x, sr, nrhs, nd); })))
+        return rc;
     if (fork) FCG_HIP(hipEventRecord(c.ev_join, c.side));
     if (L.n_irr)
       if ((rc = launch(c, FCGMG_K_APPLY_IRREGULAR, l, s,
@@ -890,13 +890,11 @@ int smooth_multi2(const Ctx& c, int l, double* x, const double* b, double* alt, 
   const int64_t nd = 3 * L.N;
   int rc;
   if (mode != 0 && (sweeps % 2 == 1 || sweeps == 0)) {
-    for (int k = 0; k < nrhs; ++k) {
-      if (mode == 1)
-        rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x + k * nd, nd, s); });
-      else
-        rc = prolong_impl<2, double>(c, l, xc + k * ndc, x + k * nd, s);
-      if (rc) return rc;
-    }
+    if (mode == 1)
+      rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x, nrhs * nd, s); });
+    else
+      rc = launch(c, FCGMG_K_PROLONG, l, s, [&] { return k_prolong_add<2, double>(c, l, xc, x, s, nrhs, ndc, nd); });
+    if (rc) return rc;
     mode = 0;
   }
   int i = 0;
@@ -946,19 +944,21 @@ int vcycle_multi_impl(const Ctx& c, int l, double* x, const double* b, int nrhs,
   const int64_t nd = (D + 1) * L.N;
   int rc;
   if (l == 0) return coarse_multi(c, b, x, nrhs, s);
+  // the vectors lie one after another: zeroing, residuals and transfers take all of them in one launch
   if (x_zero)
-    for (int k = 0; k < nrhs; ++k)
-      if ((rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x + k * nd, nd, s); }))) return rc;
+    if ((rc = launch(c, FCGMG_K_ZERO, l, s, [&] { return k_zero<double>(x, nrhs * nd, s); }))) return rc;
   if ((rc = sweeps_multi<D>(c, l, x, b, L.rm, nrhs, c.prm.nu_pre, s))) return rc;
   const Level& C = c.lev[l - 1];
   const int64_t ndc = (D + 1) * C.N;
-  for (int k = 0; k < nrhs; ++k) {
-    if ((rc = residual_impl<D>(c, l, x + k * nd, b + k * nd, L.rm + k * nd, s))) return rc;
-    if ((rc = restrict_impl<D>(c, l, L.rm + k * nd, C.bm + k * ndc, s))) return rc;
-  }
+  if ((rc = launch(c, FCGMG_K_RESIDUAL, l, s, [&] { return k_residual<D, double>(c, L, x, b, L.rm, s, nrhs, nd); })))
+    return rc;
+  if ((rc = launch(c, FCGMG_K_RESTRICT, l, s,
+                   [&] { return k_restrict<D, double>(c, l, L.rm, C.bm, s, nrhs, nd, ndc); })))
+    return rc;
   if ((rc = vcycle_multi_impl<D>(c, l - 1, C.xm, C.bm, nrhs, s, true))) return rc;
-  for (int k = 0; k < nrhs; ++k)
-    if ((rc = prolong_impl<D, double>(c, l, C.xm + k * ndc, x + k * nd, s))) return rc;
+  if ((rc = launch(c, FCGMG_K_PROLONG, l, s,
+                   [&] { return k_prolong_add<D, double>(c, l, C.xm, x, s, nrhs, ndc, nd); })))
+    return rc;
   return sweeps_multi<D>(c, l, x, b, L.rm, nrhs, c.prm.nu_post, s);
 }
 

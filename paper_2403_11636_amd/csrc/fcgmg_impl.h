@@ -632,11 +632,13 @@ template <int D> hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cu
 template <int D> hipError_t k_node_stencils(const Ctx& c, const Level& L, const int* nodes, hipStream_t s);
 template <int D> hipError_t k_rhs(const Ctx& c, const Level& L, double* b, hipStream_t s);
 template <int D, class T>
-hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s);
+hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s, int nrhs = 1,
+                      int64_t sv = 0);
 template <int D> hipError_t k_patch_inverse_rows(const Ctx& c, const Level& L, const int* nodes, int64_t count,
                                                  double* Z, hipStream_t s);
 template <int D, class T>
-hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
+hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s, int nrhs = 1,
+                           int64_t sv = 0);
 template <int D, class T>
 hipError_t k_apply_irregular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s);
 constexpr int kMaxRhs = 8;  // right-hand sides of one stacked sweep (fcgmg_smooth_multi)
@@ -680,9 +682,11 @@ template <int D> hipError_t k_store_matrices(const Ctx& c, const Level& L, const
                                              double* M, hipStream_t s);
 template <int D> hipError_t k_coarse_matrix(const Ctx& c, const Level& L, double* A, int lda, hipStream_t s);
 template <int D, class T>
-hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s);
+hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s, int nrhs = 1, int64_t sf = 0,
+                      int64_t sc = 0);
 template <int D, class T>
-hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s);
+hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s, int nrhs = 1, int64_t sc = 0,
+                         int64_t sf = 0);
 template <class T>
 hipError_t k_dense_matvec(const T* A, int n, const T* b, T* x, hipStream_t s);
 hipError_t k_sumsq(const double* v, int64_t n, double* partial, int nblocks, hipStream_t s);

@@ -773,7 +773,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                                                            const int* __restrict__ node_op,
                                                            const T* __restrict__ nsten, int ntx, int nty, int ntz,
                                                            const T* __restrict__ x, const T* __restrict__ b,
-                                                           T* __restrict__ r) {
+                                                           T* __restrict__ r, int64_t sv) {
+  // stacked vectors (sv apart): blockIdx.y is the vector
+  x += (int64_t)blockIdx.y * sv;
+  b += (int64_t)blockIdx.y * sv;
+  r += (int64_t)blockIdx.y * sv;
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int XW = TX + 2, XH = TY + 2, XD = D == 3 ? TZ + 2 : 1, XP = XW * XH * XD;
   constexpr int NXL = ((D + 1) * XP + 255) / 256;
@@ -925,12 +929,13 @@ void tile_grid(int n, int* nt) {
 }
 
 template <int D, class T>
-hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s) {
+hipError_t k_residual(const Ctx& c, const Level& L, const T* x, const T* b, T* r, hipStream_t s, int nrhs,
+                      int64_t sv) {
   int nt[3];
   tile_grid<D>(L.n, nt);
   const int nb = nt[0] * nt[1] * nt[2];
-  residual_tile_kernel<D, T><<<dim3((unsigned)nb), dim3(256), 0, s>>>(L.consts, L.node_op, LV<T>::nsten(L), nt[0],
-                                                                       nt[1], nt[2], x, b, r);
+  residual_tile_kernel<D, T><<<dim3((unsigned)nb, (unsigned)nrhs), dim3(256), 0, s>>>(
+      L.consts, L.node_op, LV<T>::nsten(L), nt[0], nt[1], nt[2], x, b, r, sv);
   return hipGetLastError();
 }
 
@@ -1008,35 +1013,43 @@ __device__ __forceinline__ void prolong_node(int nf, int64_t Nf, int nc, int64_t
   for (int f = 0; f <= D; ++f) xf[f * Nf + node] += prolong_value<D, T>(nc, Nc, xc, c, f);
 }
 
+// Stacked vectors: blockIdx.y is the vector, fine vectors sf apart, coarse ones sc apart.
 template <int D, class T>
 __global__ void restrict_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ rf,
-                                T* __restrict__ bc) {
+                                T* __restrict__ bc, int64_t sf, int64_t sc) {
+  rf += (int64_t)blockIdx.y * sf;
+  bc += (int64_t)blockIdx.y * sc;
   const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (node < Nc) restrict_node<D, T>(nf, Nf, nc, Nc, rf, bc, node);
 }
 
 template <int D, class T>
 __global__ void prolong_add_kernel(int nf, int64_t Nf, int nc, int64_t Nc, const T* __restrict__ xc,
-                                   T* __restrict__ xf) {
+                                   T* __restrict__ xf, int64_t sc, int64_t sf) {
+  xc += (int64_t)blockIdx.y * sc;
+  xf += (int64_t)blockIdx.y * sf;
   const int64_t node = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (node < Nf) prolong_node<D, T>(nf, Nf, nc, Nc, xc, xf, node);
 }
 
 template <int D, class T>
-hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s) {
+hipError_t k_restrict(const Ctx& c, int fine, const T* rf, T* bc, hipStream_t s, int nrhs, int64_t sf, int64_t sc) {
   const Level& F = c.lev[fine];
   const Level& C = c.lev[fine - 1];
   const int bs = 256;
-  restrict_kernel<D, T><<<dim3((unsigned)((C.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, rf, bc);
+  restrict_kernel<D, T><<<dim3((unsigned)((C.N + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, s>>>(
+      F.n, F.N, C.n, C.N, rf, bc, sf, sc);
   return hipGetLastError();
 }
 
 template <int D, class T>
-hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s) {
+hipError_t k_prolong_add(const Ctx& c, int fine, const T* xc, T* xf, hipStream_t s, int nrhs, int64_t sc,
+                         int64_t sf) {
   const Level& F = c.lev[fine];
   const Level& C = c.lev[fine - 1];
   const int bs = 256;
-  prolong_add_kernel<D, T><<<dim3((unsigned)((F.N + bs - 1) / bs)), dim3(bs), 0, s>>>(F.n, F.N, C.n, C.N, xc, xf);
+  prolong_add_kernel<D, T><<<dim3((unsigned)((F.N + bs - 1) / bs), (unsigned)nrhs), dim3(bs), 0, s>>>(
+      F.n, F.N, C.n, C.N, xc, xf, sc, sf);
   return hipGetLastError();
 }
 
@@ -1349,19 +1362,25 @@ namespace fcg {
   template hipError_t k_cut_matrices<D>(const Ctx&, Level&, const int*, hipStream_t);                         \
   template hipError_t k_rhs<D>(const Ctx&, const Level&, double*, hipStream_t);                               \
   template hipError_t k_residual<D, double>(const Ctx&, const Level&, const double*, const double*, double*,   \
-                                            hipStream_t);                                                     \
+                                            hipStream_t, int, int64_t);                                       \
   template hipError_t k_residual<D, float>(const Ctx&, const Level&, const float*, const float*, float*,       \
-                                           hipStream_t);                                                      \
+                                           hipStream_t, int, int64_t);                                        \
   template hipError_t k_node_stencils<D>(const Ctx&, const Level&, const int*, hipStream_t);                  \
-  template hipError_t k_restrict<D, double>(const Ctx&, int, const double*, double*, hipStream_t);            \
-  template hipError_t k_restrict<D, float>(const Ctx&, int, const float*, float*, hipStream_t);               \
-  template hipError_t k_prolong_add<D, double>(const Ctx&, int, const double*, double*, hipStream_t);         \
-  template hipError_t k_prolong_add<D, float>(const Ctx&, int, const float*, float*, hipStream_t);            \
+  template hipError_t k_restrict<D, double>(const Ctx&, int, const double*, double*, hipStream_t, int, int64_t, \
+                                            int64_t);                                                         \
+  template hipError_t k_restrict<D, float>(const Ctx&, int, const float*, float*, hipStream_t, int, int64_t,  \
+                                           int64_t);                                                          \
+  template hipError_t k_prolong_add<D, double>(const Ctx&, int, const double*, double*, hipStream_t, int,     \
+                                               int64_t, int64_t);                                             \
+  template hipError_t k_prolong_add<D, float>(const Ctx&, int, const float*, float*, hipStream_t, int,        \
+                                              int64_t, int64_t);                                              \
   template hipError_t k_coarse_matrix<D>(const Ctx&, const Level&, double*, int, hipStream_t);                \
   template hipError_t k_patch_inverse_rows<D>(const Ctx&, const Level&, const int*, int64_t, double*,         \
                                               hipStream_t);                                                   \
-  template hipError_t k_apply_regular<D, double>(const Ctx&, const Level&, const double*, double*, hipStream_t); \
-  template hipError_t k_apply_regular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t);  \
+  template hipError_t k_apply_regular<D, double>(const Ctx&, const Level&, const double*, double*, hipStream_t, \
+                                                 int, int64_t);                                               \
+  template hipError_t k_apply_regular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t,  \
+                                                int, int64_t);                                                \
   template hipError_t k_apply_irregular<D, double>(const Ctx&, const Level&, const double*, double*,          \
                                                    hipStream_t);                                              \
   template hipError_t k_apply_irregular<D, float>(const Ctx&, const Level&, const float*, float*, hipStream_t); \

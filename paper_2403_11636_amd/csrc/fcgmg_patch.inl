@@ -2143,7 +2143,10 @@ __global__ void __launch_bounds__(256) apply_regular_kernel(int n, int ntx, int 
                                                             const int* __restrict__ node_class,
                                                             const T* __restrict__ Zcls,
                                                             const T* __restrict__ r, T* __restrict__ x,
-                                                            T omega) {
+                                                            T omega, int64_t sv) {
+  // stacked vectors (sv apart): blockIdx.y is the vector
+  r += (int64_t)blockIdx.y * sv;
+  x += (int64_t)blockIdx.y * sv;
   constexpr int TX = TileShape<D>::TX, TY = TileShape<D>::TY, TZ = TileShape<D>::TZ;
   constexpr int HX = TX + 4, HY = TY + 4, HZ = D == 3 ? TZ + 4 : 1;
   constexpr int PLANE = HX * HY * HZ;
@@ -2626,21 +2629,22 @@ void plan_fused2(const Level& L, const std::vector<int>& node_class, std::vector
 constexpr int64_t kRolledRegularNodes = 100000;
 
 template <int D, class T>
-hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s) {
+hipError_t k_apply_regular(const Ctx& c, const Level& L, const T* r, T* x, hipStream_t s, int nrhs, int64_t sv) {
   if (L.n_classes == 0) return hipSuccess;
   int nt[3];
   tile_grid<D>(L.n, nt);
+  const dim3 grid((unsigned)(nt[0] * nt[1] * nt[2]), (unsigned)nrhs);
   // 3D grids from kRolledRegularNodes nodes on: the rolled loop (occupancy over instruction count);
   // smaller levels, one short chain per workgroup, keep the unrolled one
   if constexpr (D == 3) {
     if (L.N >= kRolledRegularNodes) {
-      apply_regular_kernel<D, false, T><<<dim3((unsigned)(nt[0] * nt[1] * nt[2])), dim3(256), 0, s>>>(
-          L.n, nt[0], nt[1], nt[2], L.node_class, LV<T>::Zcls(L), r, x, (T)c.prm.omega);
+      apply_regular_kernel<D, false, T><<<grid, dim3(256), 0, s>>>(L.n, nt[0], nt[1], nt[2], L.node_class,
+                                                                   LV<T>::Zcls(L), r, x, (T)c.prm.omega, sv);
       return hipGetLastError();
     }
   }
-  apply_regular_kernel<D, true, T><<<dim3((unsigned)(nt[0] * nt[1] * nt[2])), dim3(256), 0, s>>>(
-      L.n, nt[0], nt[1], nt[2], L.node_class, LV<T>::Zcls(L), r, x, (T)c.prm.omega);
+  apply_regular_kernel<D, true, T><<<grid, dim3(256), 0, s>>>(L.n, nt[0], nt[1], nt[2], L.node_class, LV<T>::Zcls(L),
+                                                              r, x, (T)c.prm.omega, sv);
   return hipGetLastError();
 }
 
