@@ -2096,35 +2096,52 @@ __device__ __forceinline__ void patch_column(int col, int* field, int* o) {
 }
 
 // acc[f] = Z[f,:] . g for an irregular patch, computed by a group of 16 lanes (j16 = lane in the
-// group; columns j16, j16+16, ...); rg(field, o) = r at centre + o, or 0 outside the grid. Every
-// lane of the group returns the full sums. A wavefront holds 4 groups and each group takes two
-// patches at once (A, B), so the rows of 8 patches stream from HBM per wavefront and loop trip.
-// The arithmetic of each patch does not depend on which patch it is paired with.
+// group); rg(field, o) = r at centre + o, or 0 outside the grid. Each lane takes the neighbouring
+// columns 2 j16 and 2 j16 + 1 of every step of 32 (the rows start 16-byte aligned, so the pair loads
+// as one vector; an odd last column stands alone), summing them in that order. Every lane of the
+// group returns the full sums. A wavefront holds 4 groups and each group takes two patches at once
+// (A, B), so the rows of 8 patches stream from memory per wavefront and loop trip. The arithmetic
+// of each patch does not depend on which patch it is paired with.
+template <class T>
+struct Pair2 {
+  using type = typename std::conditional<std::is_same<T, double>::value, double2, float2>::type;
+};
+
 template <int D, class T, class RGA, class RGB, class PZ>
 __device__ __forceinline__ void irregular_pair(PZ __restrict__ ZA, PZ __restrict__ ZB,
                                                bool has_b, int j16, RGA&& rga, RGB&& rgb, T* acca,
                                                T* accb) {
+  using V2 = typename Pair2<T>::type;
   constexpr int ZS = PT<D>::ZS, ZSP = PT<D>::ZSP;
+  static_assert(ZSP % 2 == 0, "rows of an even length, for aligned pairs");
 #pragma unroll
   for (int f = 0; f <= D; ++f) acca[f] = accb[f] = 0;
   const PZ ZBs = has_b ? ZB : ZA;
-  // 2D: the four column steps are unrolled so that all row loads are in flight at once
-#pragma unroll(D == 2 ? 4 : 4)
-  for (int col = j16; col < ZS; col += 16) {
-    int field, o[3];
-    patch_column<D>(col, &field, o);
-    T za[D + 1], zb[D + 1];
+#pragma unroll 2
+  for (int c0 = 2 * j16; c0 < ZS; c0 += 32) {
+    const bool two = c0 + 1 < ZS;
+    int fa, fb, oa[3], ob[3];
+    patch_column<D>(c0, &fa, oa);
+    patch_column<D>(two ? c0 + 1 : c0, &fb, ob);
+    V2 za[D + 1], zb[D + 1];
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
-      za[f] = ZA[f * ZSP + col];
-      zb[f] = ZBs[f * ZSP + col];
+      za[f] = *(const V2*)(ZA + f * ZSP + c0);
+      zb[f] = *(const V2*)(ZBs + f * ZSP + c0);
     }
-    const T ga = rga(field, o);
-    const T gb = has_b ? rgb(field, o) : T(0);
+    const T ga0 = rga(fa, oa), gb0 = has_b ? rgb(fa, oa) : T(0);
 #pragma unroll
     for (int f = 0; f <= D; ++f) {
-      acca[f] += za[f] * ga;
-      accb[f] += zb[f] * gb;
+      acca[f] += za[f].x * ga0;
+      accb[f] += zb[f].x * gb0;
+    }
+    if (two) {
+      const T ga1 = rga(fb, ob), gb1 = has_b ? rgb(fb, ob) : T(0);
+#pragma unroll
+      for (int f = 0; f <= D; ++f) {
+        acca[f] += za[f].y * ga1;
+        accb[f] += zb[f].y * gb1;
+      }
     }
   }
 #pragma unroll
@@ -2250,23 +2267,35 @@ __global__ void __launch_bounds__(256) apply_irregular_multi_kernel(int n, int64
     for (int k = 0; k < kMaxRhs; ++k)
 #pragma unroll
       for (int f = 0; f <= D; ++f) acc[k][f] = 0;
-#pragma unroll 2
-    for (int col = j16; col < ZS; col += 16) {
+    auto node_of = [&](int col, bool* in) {
       int field, o[3];
       patch_column<D>(col, &field, o);
-      T z[D + 1];
-#pragma unroll
-      for (int f = 0; f <= D; ++f) z[f] = Z[f * ZSP + col];
       const int cc[3] = {ca[0] + o[0], ca[1] + o[1], ca[2] + o[2]};
-      bool in = true;
-      for (int k = 0; k < D; ++k) in = in && cc[k] >= 0 && cc[k] < m;
-      const int64_t gi = field * N + (D == 2 ? cc[0] + (int64_t)m * cc[1] : cc[0] + (int64_t)m * (cc[1] + (int64_t)m * cc[2]));
+      *in = true;
+      for (int k = 0; k < D; ++k) *in = *in && cc[k] >= 0 && cc[k] < m;
+      return field * N + (D == 2 ? cc[0] + (int64_t)m * cc[1] : cc[0] + (int64_t)m * (cc[1] + (int64_t)m * cc[2]));
+    };
+    // the column pairs and the order of irregular_pair
+    using V2 = typename Pair2<T>::type;
+#pragma unroll 2
+    for (int c0 = 2 * j16; c0 < ZS; c0 += 32) {
+      const bool two = c0 + 1 < ZS;
+      bool in0, in1;
+      const int64_t g0i = node_of(c0, &in0), g1i = node_of(two ? c0 + 1 : c0, &in1);
+      V2 z[D + 1];
+#pragma unroll
+      for (int f = 0; f <= D; ++f) z[f] = *(const V2*)(Z + f * ZSP + c0);
 #pragma unroll
       for (int k = 0; k < kMaxRhs; ++k)
         if (k < nrhs) {
-          const T g = in ? r[k * nd + gi] : T(0);
+          const T g0 = in0 ? r[k * nd + g0i] : T(0);
 #pragma unroll
-          for (int f = 0; f <= D; ++f) acc[k][f] += z[f] * g;
+          for (int f = 0; f <= D; ++f) acc[k][f] += z[f].x * g0;
+          if (two) {
+            const T g1 = in1 ? r[k * nd + g1i] : T(0);
+#pragma unroll
+            for (int f = 0; f <= D; ++f) acc[k][f] += z[f].y * g1;
+          }
         }
     }
 #pragma unroll
