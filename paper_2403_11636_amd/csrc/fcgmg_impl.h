@@ -40,6 +40,14 @@ struct PT {
   static constexpr int NSTEN = (2 * D + 2) * NST;     // stored stencil of one node (see node_op)
 };
 
+// Position of coefficient j (0 K, 1..D B_c, D+1..2D B_c^T, 2D+1 C) of stencil offset o in a stored
+// node row (Level::nsten): 2D coefficient-major (j 9 + o), 3D offset-major (o 8 + j), so that a 3D
+// offset's eight coefficients lie together in 64 bytes and load as wide vectors.
+template <int D>
+__host__ __device__ constexpr int sten_index(int j, int o) {
+  return D == 2 ? j * PT<2>::NST + o : o * (2 * D + 2) + j;
+}
+
 // Layout of the level constants as the residual kernels stage them into LDS: the reference
 // matrices of a physical uncut cell (a fictitious uncut cell is alpha_f times them), C, the Nitsche
 // face matrices of the 2d faces and the node stencils of uniform neighbourhoods.
@@ -105,9 +113,9 @@ struct Level {
   int* node_class = nullptr;  // >=0 regular class id, <0: -(irregular index)-1
   // Operator row of each node: -1 / -2 when its 2^d cells are uncut, all physical / all fictitious
   // and it is at least 2 nodes from every wall (the level's reference stencil applies), otherwise
-  // the index of its assembled stencil in nsten: NSTEN doubles [j][o] over the 3^d neighbour
-  // offsets o, j = 0 velocity-velocity (every component), 1..d velocity c / pressure, d+1..2d
-  // pressure / velocity c, 2d+1 pressure-pressure.
+  // the index of its assembled stencil in nsten: NSTEN doubles over the 3^d neighbour offsets o and
+  // the coefficients j = 0 velocity-velocity (every component), 1..d velocity c / pressure, d+1..2d
+  // pressure / velocity c, 2d+1 pressure-pressure, at sten_index<D>(j, o).
   int* node_op = nullptr;
   double* nsten = nullptr;
   int64_t n_nsten = 0;

@@ -553,7 +553,7 @@ __device__ __forceinline__ void stored_row_apply(int op, PN __restrict__ nsten, 
 #pragma unroll
     for (int f = 0; f < 3; ++f) acc[f] += t[f];
   } else {
-    stencil_apply<D, false, T>([&](int j, int o) { return p[j * PT<D>::NST + o]; }, xat, acc);
+    stencil_apply<D, false, T>([&](int j, int o) { return p[sten_index<D>(j, o)]; }, xat, acc);
   }
 }
 
@@ -750,12 +750,12 @@ __global__ void __launch_bounds__(256) node_stencil_kernel(const OpConsts* __res
         acc);
     double* p = nsten + k * PT<D>::NSTEN;
     if (g < D) {
-      if (g == 0) p[o] = acc[0];
-      p[(1 + D + g) * NS + o] = acc[D];
+      if (g == 0) p[sten_index<D>(0, o)] = acc[0];
+      p[sten_index<D>(1 + D + g, o)] = acc[D];
     } else {
 #pragma unroll
-      for (int f = 0; f < D; ++f) p[(1 + f) * NS + o] = acc[f];
-      p[(1 + 2 * D) * NS + o] = acc[D];
+      for (int f = 0; f < D; ++f) p[sten_index<D>(1 + f, o)] = acc[f];
+      p[sten_index<D>(1 + 2 * D, o)] = acc[D];
     }
   }
 }

@@ -987,7 +987,7 @@ __device__ void patch_retrieve3(PatchLDS<3>& sh, const OpConsts* __restrict__ oc
       const int ku = op >= 0 ? 0 : -op - 1;
       // coefficient j of offset o: 0 K, 1..3 B_x, B_y, B_z, 7 C (the layout of the stored stencils)
       auto coef = [&](int j, int o) -> double {
-        if (st) return st[j * NS + o];
+        if (st) return st[sten_index<3>(j, o)];
         if (j == 0) return pk[RL::oSK + ku * NS + o];
         if (j <= 3) return pk[RL::oSB + (ku * 3 + j - 1) * NS + o];
         return pk[RL::oSC + o];
@@ -1158,7 +1158,7 @@ __device__ void patch3_load(Patch3LDS& sh, int pass, bool rows, const OpConsts* 
     const int ku = op >= 0 ? 0 : -op - 1;
     // coefficient j of offset o: 0 K, 1..3 B_x, B_y, B_z, 7 C (the layout of the stored stencils)
     auto coef = [&](int j, int o) -> double {
-      if (st) return st[j * NS + o];
+      if (st) return st[sten_index<3>(j, o)];
       if (j == 0) return pk[RL::oSK + ku * NS + o];
       if (j <= 3) return pk[RL::oSB + (ku * 3 + j - 1) * NS + o];
       return pk[RL::oSC + o];
