@@ -175,14 +175,221 @@ __global__ void __launch_bounds__(64) cut_matrices_kernel(Geom g, int n, double 
   }
 }
 
+// Split form of the cut-cell integration (3D): the coarse levels have few cut cells and deep trees
+// (the tree depth grows by one per coarser level), so one workgroup per cell leaves the GPU nearly
+// idle. Each cell's tree is cut at depth sd into work items, in the order of the depth-first
+// traversal: a box at depth sd whose ancestors are all cut, or a shallower leaf. One workgroup
+// integrates each item's subtree (the same boxes and points as the whole traversal), and the cell's
+// entries are the items' sums added in traversal order.
+//
+// Candidate `cand` of a cell (digits of D bits from depth 1 down to sd: the child taken at each
+// depth) stops at the first box that is not descended into; it stands for that box only if all its
+// digits below that depth are 0. item_depth = that depth, or -1.
+template <int D>
+__device__ __forceinline__ int cut_item_box(const Geom& g, int n, double h, int cell, int cand, int sd, int stop,
+                                            double* lo, double* size) {
+  lo[0] = (double)(cell % n) * h;
+  lo[1] = (double)((cell / n) % n) * h;
+  lo[2] = D == 3 ? (double)(cell / ((int64_t)n * n)) * h : 0.0;
+  *size = h;
+  int t = 0;
+  for (; t < sd; ++t) {
+    if (stop >= 0 ? t == stop : !(t < g.q && box_kind<D>(g, lo, *size) == 2)) break;
+    const int digit = (cand >> (D * (sd - 1 - t))) & ((1 << D) - 1);
+    const double half = 0.5 * *size;
+    for (int k = 0; k < D; ++k) lo[k] += ((digit >> k) & 1) ? half : 0.0;
+    *size = half;
+  }
+  return t;
+}
+
+template <int D>
+__global__ void cut_frontier_kernel(Geom g, int n, double h, const int* __restrict__ cut_cells, int64_t ncut, int sd,
+                                    int* __restrict__ item_depth) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (ncut << (D * sd))) return;
+  const int cand = (int)(gid & ((1 << (D * sd)) - 1));
+  double lo[3], size;
+  const int t = cut_item_box<D>(g, n, h, cut_cells[gid >> (D * sd)], cand, sd, -1, lo, &size);
+  item_depth[gid] = (cand & ((1 << (D * (sd - t))) - 1)) == 0 ? t : -1;
+}
+
+// Volume entries of one work item: the tree below the item's box, Q1 functions of its cell.
+template <int D>
+__global__ void __launch_bounds__(64) cut_items_kernel(Geom g, int n, double h, double eta,
+                                                       const int* __restrict__ cut_cells, int sd,
+                                                       const int* __restrict__ item_cell,
+                                                       const int* __restrict__ item_cand,
+                                                       const int* __restrict__ item_stop, int64_t nitems,
+                                                       double* __restrict__ part) {
+  __shared__ double lball[4 * kMaxLocalBalls];
+  __shared__ int cnt;
+  constexpr int NN = 1 << D, NEL = PT<D>::NEL, NPER = (NEL + 63) / 64;
+  for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int cell = cut_cells[item_cell[it]];
+    double lo[3], size;
+    const int t = cut_item_box<D>(g, n, h, cell, item_cand[it], sd, item_stop[it], lo, &size);
+    double clo[3] = {(double)(cell % n) * h, (double)((cell / n) % n) * h,
+                     D == 3 ? (double)(cell / ((int64_t)n * n)) * h : 0.0};
+    const int nb = cull_balls<D>(g, lo, size, lball, &cnt);
+    Geom gl = g;
+    if (nb >= 0) {
+      gl.balls = lball;
+      gl.nballs = nb;
+    }
+    gl.q = g.q - t;
+    double acc[NPER];
+    for (int k = 0; k < NPER; ++k) acc[k] = 0;
+    tree_quadrature<D>(gl, lo, size, [&](const double* x, double w, double alpha) {
+      double phi[NN], gr[NN][3];
+      q1<D>(clo, h, x, phi, gr);
+      const double wa = w * alpha;
+      for (int k = 0; k < NPER; ++k) {
+        const int e = (int)threadIdx.x + 64 * k;
+        if (e < NEL) acc[k] += point_entry<D>(e, eta, wa, phi, gr);
+      }
+    });
+    for (int k = 0; k < NPER; ++k) {
+      const int e = (int)threadIdx.x + 64 * k;
+      if (e < NEL) part[it * NEL + e] = acc[k];
+    }
+    __syncthreads();
+  }
+}
+
+// A cell's entries: its items' volume sums in traversal order, then the immersed surface terms.
+template <int D>
+__global__ void __launch_bounds__(64) cut_sum_kernel(Geom g, int n, double h, double eta, int immersed, double lam,
+                                                     const int* __restrict__ cut_cells,
+                                                     const int* __restrict__ item_start, int64_t ncut,
+                                                     const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double lball[4 * kMaxLocalBalls];
+  __shared__ int cnt;
+  constexpr int NEL = PT<D>::NEL, NPER = (NEL + 63) / 64;
+  for (int64_t ic = blockIdx.x; ic < ncut; ic += gridDim.x) {
+    double acc[NPER];
+    for (int k = 0; k < NPER; ++k) acc[k] = 0;
+    for (int it = item_start[ic]; it < item_start[ic + 1]; ++it)
+      for (int k = 0; k < NPER; ++k) {
+        const int e = (int)threadIdx.x + 64 * k;
+        if (e < NEL) acc[k] += part[(int64_t)it * NEL + e];
+      }
+    if (immersed) {
+      const int64_t cell = cut_cells[ic];
+      const double lo[3] = {(double)(cell % n) * h, (double)((cell / n) % n) * h,
+                            D == 3 ? (double)(cell / ((int64_t)n * n)) * h : 0.0};
+      const int nb = cull_balls<D>(g, lo, h, lball, &cnt);
+      Geom gl = g;
+      if (nb >= 0) {
+        gl.balls = lball;
+        gl.nballs = nb;
+      }
+      if constexpr (D == 2)
+        arc_quadrature2(gl, lo, h, [&](const double* x, double w, const double* nrm) {
+          double phi[4], gr[4][3];
+          q1<2>(lo, h, x, phi, gr);
+          for (int k = 0; k < NPER; ++k) {
+            const int e = (int)threadIdx.x + 64 * k;
+            if (e < NEL) acc[k] += nitsche_entry2(e, eta, lam, w, nrm, phi, gr);
+          }
+        });
+      else
+        sphere_quadrature3(gl, lo, h, [&](const double* x, double w, const double* nrm) {
+          double phi[8], gr[8][3];
+          q1<3>(lo, h, x, phi, gr);
+          for (int k = 0; k < NPER; ++k) {
+            const int e = (int)threadIdx.x + 64 * k;
+            if (e < NEL) acc[k] += nitsche_entry3(e, eta, lam, w, nrm, phi, gr);
+          }
+        });
+    }
+    for (int k = 0; k < NPER; ++k) {
+      const int e = (int)threadIdx.x + 64 * k;
+      if (e < NEL) out[ic * NEL + e] = acc[k];
+    }
+    __syncthreads();
+  }
+}
+
+// Cut cells whose work the split form spreads: the split depth is the smallest that gives at least
+// this many work candidates (at most 3, and at most the tree depth).
+constexpr int64_t kCutWorkItems = 12000;
+
 template <int D>
 hipError_t k_cut_matrices(const Ctx& c, Level& L, const int* cut_cells, hipStream_t s) {
   if (L.n_cut == 0) return hipSuccess;
-  const int64_t nb = L.n_cut < 65536 ? L.n_cut : 65536;
-  cut_matrices_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(
-      c.geom(L), L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, c.prm.nitsche_beta * c.prm.eta / L.h, cut_cells,
-      L.n_cut, L.cut_mats);
-  return hipGetLastError();
+  const Geom g = c.geom(L);
+  const double lam = c.prm.nitsche_beta * c.prm.eta / L.h;
+  int sd = 0;
+  if constexpr (D == 3)
+    while (sd < 3 && sd < g.q && (L.n_cut << (D * sd)) < kCutWorkItems) ++sd;
+  if (sd == 0) {
+    const int64_t nb = L.n_cut < 65536 ? L.n_cut : 65536;
+    cut_matrices_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(g, L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, lam,
+                                                                 cut_cells, L.n_cut, L.cut_mats);
+    return hipGetLastError();
+  }
+  // work items: candidates on the GPU (the same box tests as the traversal), listed on the host
+  const int64_t ncand = L.n_cut << (D * sd);
+  int* depth_d = nullptr;
+  hipError_t e = hipMallocAsync((void**)&depth_d, (size_t)ncand * sizeof(int), s);
+  if (e != hipSuccess) return e;
+  cut_frontier_kernel<D><<<dim3((unsigned)((ncand + 255) / 256)), dim3(256), 0, s>>>(g, L.n, L.h, cut_cells, L.n_cut, sd,
+                                                                                     depth_d);
+  std::vector<int> depth(ncand);
+  if ((e = hipGetLastError()) == hipSuccess)
+    e = hipMemcpyAsync(depth.data(), depth_d, (size_t)ncand * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t f = hipFreeAsync(depth_d, s);
+  if (e != hipSuccess) return e;
+  if (f != hipSuccess) return f;
+  std::vector<int> items;  // per item: cell index, candidate, stop depth
+  std::vector<int> start(L.n_cut + 1, 0);
+  for (int64_t i = 0; i < L.n_cut; ++i) {
+    start[i] = (int)(items.size() / 3);
+    for (int64_t k = 0; k < ((int64_t)1 << (D * sd)); ++k) {
+      const int t = depth[(i << (D * sd)) + k];
+      if (t >= 0) {
+        items.push_back((int)i);
+        items.push_back((int)k);
+        items.push_back(t);
+      }
+    }
+  }
+  const int64_t nitems = (int64_t)(items.size() / 3);
+  start[L.n_cut] = (int)nitems;
+  std::vector<int> cols(3 * nitems);  // item_cell | item_cand | item_stop
+  for (int64_t k = 0; k < nitems; ++k)
+    for (int j = 0; j < 3; ++j) cols[j * nitems + k] = items[3 * k + j];
+  int* meta_d = nullptr;
+  double* part_d = nullptr;
+  if ((e = hipMallocAsync((void**)&meta_d, (cols.size() + start.size()) * sizeof(int), s)) != hipSuccess) return e;
+  if ((e = hipMallocAsync((void**)&part_d, (size_t)nitems * PT<D>::NEL * sizeof(double), s)) != hipSuccess) {
+    (void)hipFreeAsync(meta_d, s);
+    return e;
+  }
+  e = hipMemcpyAsync(meta_d, cols.data(), cols.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(meta_d + cols.size(), start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    const int64_t nb = nitems < 262144 ? nitems : 262144;
+    cut_items_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(g, L.n, L.h, c.prm.eta, cut_cells, sd, meta_d,
+                                                                 meta_d + nitems, meta_d + 2 * nitems, nitems, part_d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    const int64_t nb = L.n_cut < 65536 ? L.n_cut : 65536;
+    cut_sum_kernel<D><<<dim3((unsigned)nb), dim3(64), 0, s>>>(g, L.n, L.h, c.prm.eta, c.prm.immersed_nitsche, lam,
+                                                              cut_cells, meta_d + cols.size(), L.n_cut, part_d,
+                                                              L.cut_mats);
+    e = hipGetLastError();
+  }
+  // the host vectors must outlive the copies from them
+  const hipError_t w = hipStreamSynchronize(s);
+  const hipError_t f1 = hipFreeAsync(part_d, s), f2 = hipFreeAsync(meta_d, s);
+  if (e != hipSuccess) return e;
+  if (w != hipSuccess) return w;
+  return f1 != hipSuccess ? f1 : f2;
 }
 
 // ================================================================================================
