@@ -422,12 +422,15 @@ __global__ void rhs_kernel(Geom g, const OpConsts* __restrict__ oc, int force, d
     if (!in) continue;
     double lo[3] = {0, 0, 0};
     for (int k = 0; k < D; ++k) lo[k] = cc[k] * h;
-    tree_quadrature<D>(g, lo, h, [&](const double* x, double w, double alpha) {
-      double phi[NN], gr[NN][3], fv[3];
-      q1<D>(lo, h, x, phi, gr);
-      body_force<D>(force, eta, x, fv);
-      for (int f = 0; f < D; ++f) acc[f] += w * alpha * fv[f] * phi[a];
-    });
+    // the volume term (v, alpha f); body_force is zero for every kind but 1, and then it adds only
+    // zeros
+    if (force == 1)
+      tree_quadrature<D>(g, lo, h, [&](const double* x, double w, double alpha) {
+        double phi[NN], gr[NN][3], fv[3];
+        q1<D>(lo, h, x, phi, gr);
+        body_force<D>(force, eta, x, fv);
+        for (int f = 0; f < D; ++f) acc[f] += w * alpha * fv[f] * phi[a];
+      });
     for (int k = 0; k < D; ++k)
       for (int sd = 0; sd < 2; ++sd) {
         const bool on = sd ? (cc[k] == n - 1) : (cc[k] == 0);
