@@ -83,6 +83,10 @@ struct fcgmg_server {
   std::deque<Request*> pending;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::vector<std::unique_ptr<Entry>> entries;
+  // device bytes of every problem (parameters with the policy, and obstacles) seen so far: the host
+  // planning behind fcgmg_footprint_bytes takes up to a second on the largest grids, and a stream of
+  // requests repeats its problems
+  std::map<std::string, int64_t> footprints;
   int64_t in_use = 0;
   int64_t next_id = 1;
   uint64_t tick = 0;
@@ -401,25 +405,38 @@ int fcgmg_server_submit(fcgmg_server_h srv, const fcgmg_params* prm, const doubl
                         double* x_out, int64_t* request_id) {
   if (!srv || !prm || !x_out || !request_id || !(rtol > 0)) return set_error(FCGMG_E_ARG, "bad argument");
   auto r = std::make_unique<Request>();
+  r->t_submit = Clock::now();  // latency counts from the call, footprint planning included
   r->prm = *prm;
   r->balls.assign(balls, balls + 4 * (size_t)std::max(n_balls, 0));
   r->rtol = rtol;
   r->x = x_out;
-  // footprints of the candidate policies, computed here (host only) so that admission is cheap
+  // footprints of the candidate policies, computed here (host only) so that admission is cheap;
+  // a problem seen before takes its footprints from the server's table
   bool any = false;
   for (int pol = 0; pol < 3; ++pol) {
     if (prm->cache_policy >= 0 && pol != prm->cache_policy) continue;
     if (prm->precision == FCGMG_PREC_MIXED && pol != FCGMG_CACHE_INVERSE) continue;
     fcgmg_params p = *prm;
     p.cache_policy = pol;
-    size_t fp = 0;
-    const int rc = fcgmg_footprint_bytes(&p, r->balls.data(), n_balls, &fp);
-    if (rc != FCGMG_OK) return rc;
-    r->fp[pol] = (int64_t)fp;
+    const std::string key = problem_key(p, r->balls);
+    int64_t known = -1;
+    {
+      std::lock_guard<std::mutex> lk(srv->mu);
+      const auto it = srv->footprints.find(key);
+      if (it != srv->footprints.end()) known = it->second;
+    }
+    if (known < 0) {
+      size_t fp = 0;
+      const int rc = fcgmg_footprint_bytes(&p, r->balls.data(), n_balls, &fp);
+      if (rc != FCGMG_OK) return rc;
+      known = (int64_t)fp;
+      std::lock_guard<std::mutex> lk(srv->mu);
+      srv->footprints[key] = known;
+    }
+    r->fp[pol] = known;
     any = true;
   }
   if (!any) return set_error(FCGMG_E_ARG, "no cache policy applies to this request");
-  r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     r->id = srv->next_id++;
