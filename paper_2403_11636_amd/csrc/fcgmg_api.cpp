@@ -999,6 +999,35 @@ int correction_fp32_impl(const Ctx& c, const double* r, double* x, hipStream_t s
 // Device bytes that setup_impl would allocate, from the same host-side planning (cell kinds by the
 // exact ball-box test on the host, operator codes, patch classes, fused-sweep plan). Temporaries
 // freed during set-up are not counted.
+// Cell kinds of a level on the host, as box_kind gives them cell by cell (0 physical, 1 inside a
+// ball, 2 cut), but visiting each ball's bounding box of cells only: a cell outside it is at least
+// the radius away from the ball in one axis, so that ball neither contains nor cuts it.
+template <int D>
+void classify_cells_host(const Geom& g, const Level& L, std::vector<signed char>& kinds) {
+  kinds.assign(L.ncells, 0);
+  std::vector<unsigned char> inside(L.ncells, 0);
+  for (int i = 0; i < g.nballs; ++i) {
+    const double* b = g.balls + 4 * i;
+    int lo_c[3] = {0, 0, 0}, hi_c[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) {
+      lo_c[k] = std::max(0, (int)std::floor((b[k] - b[3]) / L.h) - 1);
+      hi_c[k] = std::min(L.n - 1, (int)std::floor((b[k] + b[3]) / L.h) + 1);
+    }
+    for (int z = lo_c[2]; z <= hi_c[2]; ++z)
+      for (int y = lo_c[1]; y <= hi_c[1]; ++y)
+        for (int x = lo_c[0]; x <= hi_c[0]; ++x) {
+          const int64_t cell = x + (int64_t)L.n * (y + (int64_t)L.n * z);
+          const double lo[3] = {(double)x * L.h, (double)y * L.h, D == 3 ? (double)z * L.h : 0.0};
+          const Geom one{b, 1, g.q, g.alpha_f};
+          const int kd = box_kind<D>(one, lo, L.h);
+          if (kd == 1) inside[cell] = 1;
+          else if (kd == 2) kinds[cell] = 2;
+        }
+  }
+  for (int64_t cell = 0; cell < L.ncells; ++cell)
+    if (inside[cell]) kinds[cell] = 1;
+}
+
 template <int D>
 size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
   const int nlev = P.n_levels;
@@ -1028,14 +1057,9 @@ size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
     if (l == 0) nd0 = (int64_t)nd;
     bytes += nd * sizeof(double) * (l < nlev - 1 ? 3 : 1);
     if (D == 2 && inverse) bytes += nd * sizeof(double);
-    std::vector<signed char> kinds(L.ncells);
-    int64_t n_cut = 0;
-    for (int64_t cell = 0; cell < L.ncells; ++cell) {
-      const double lo[3] = {(double)(cell % L.n) * L.h, (double)((cell / L.n) % L.n) * L.h,
-                            D == 3 ? (double)(cell / ((int64_t)L.n * L.n)) * L.h : 0.0};
-      kinds[cell] = (signed char)box_kind<D>(g, lo, L.h);
-      if (kinds[cell] == 2) ++n_cut;
-    }
+    std::vector<signed char> kinds;
+    classify_cells_host<D>(g, L, kinds);
+    const int64_t n_cut = std::count(kinds.begin(), kinds.end(), (signed char)2);
     bytes += L.ncells * sizeof(int) + (size_t)n_cut * PT<D>::NEL * sizeof(double) + sizeof(OpConsts);
     std::vector<int> op(L.N), sten, ncls, reps, irr, zrow, znodes, extra;
     node_operator_codes<D>(L, kinds, op, sten);
