@@ -996,9 +996,6 @@ int correction_fp32_impl(const Ctx& c, const double* r, double* x, hipStream_t s
   return FCGMG_OK;
 }
 
-// Device bytes that setup_impl would allocate, from the same host-side planning (cell kinds by the
-// exact ball-box test on the host, operator codes, patch classes, fused-sweep plan). Temporaries
-// freed during set-up are not counted.
 // Cell kinds of a level on the host, as box_kind gives them cell by cell (0 physical, 1 inside a
 // ball, 2 cut), but visiting each ball's bounding box of cells only: a cell outside it is at least
 // the radius away from the ball in one axis, so that ball neither contains nor cuts it.
@@ -1028,6 +1025,9 @@ void classify_cells_host(const Geom& g, const Level& L, std::vector<signed char>
     if (inside[cell]) kinds[cell] = 1;
 }
 
+// Device bytes that setup_impl would allocate, from the same host-side planning (cell kinds by the
+// exact ball-box test on the host, operator codes, patch classes, fused-sweep plan). Temporaries
+// freed during set-up are not counted.
 template <int D>
 size_t footprint_impl(const fcgmg_params& P, const std::vector<double>& balls) {
   const int nlev = P.n_levels;

@@ -83,9 +83,10 @@ struct fcgmg_server {
   std::deque<Request*> pending;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::vector<std::unique_ptr<Entry>> entries;
-  // device bytes of every problem (parameters with the policy, and obstacles) seen so far: the host
+  // device bytes of the problems (parameters with the policy, and obstacles) seen so far: the host
   // planning behind fcgmg_footprint_bytes takes up to a second on the largest grids, and a stream of
-  // requests repeats its problems
+  // requests repeats its problems. At most kFootprintTable entries; a full table starts over.
+  static constexpr size_t kFootprintTable = 4096;
   std::map<std::string, int64_t> footprints;
   int64_t in_use = 0;
   int64_t next_id = 1;
@@ -431,6 +432,7 @@ int fcgmg_server_submit(fcgmg_server_h srv, const fcgmg_params* prm, const doubl
       if (rc != FCGMG_OK) return rc;
       known = (int64_t)fp;
       std::lock_guard<std::mutex> lk(srv->mu);
+      if (srv->footprints.size() >= fcgmg_server::kFootprintTable) srv->footprints.clear();
       srv->footprints[key] = known;
     }
     r->fp[pol] = known;
