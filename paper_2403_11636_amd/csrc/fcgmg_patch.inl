@@ -1465,7 +1465,7 @@ __global__ void __launch_bounds__(64) patch_solve_lu2_kernel(
     const OpConsts* __restrict__ oc, const int* __restrict__ cell_info, const double* __restrict__ cut, Geom g,
     double eta, int policy, const int* __restrict__ node_class, const double* __restrict__ Mcls,
     const double* __restrict__ Mirr, const int* __restrict__ pattern, int npat, int64_t N,
-    const double* __restrict__ r, double* __restrict__ x, double omega, int* err) {
+    const double* __restrict__ r, double* __restrict__ x, double omega, int* err, int integrate) {
   constexpr int D = 2, NV = PT<2>::NV, ZS = kLU2;
   __shared__ PatchLDS<2> sh;
   __shared__ double A[ZS * ZS];
@@ -1482,7 +1482,9 @@ __global__ void __launch_bounds__(64) patch_solve_lu2_kernel(
       const double* vals = cls >= 0 ? Mcls + (int64_t)cls * npat : Mirr + (int64_t)(-cls - 1) * npat;
       patch_load_pattern<D>(sh, pattern, npat, vals);
     } else {
-      patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, 1);
+      // cache_none: the element matrices the residual applies (reference ones and the cut cells'
+      // set-up integrals), or with `integrate` the cut cells integrated again here
+      patch_assemble<D>(sh, oc, cell_info, cut, g, eta, c, integrate ? 1 : 0);
     }
     patch_pad<D>(sh, c, n);
     // g = R_i r, zero outside the grid
@@ -1985,7 +1987,7 @@ hipError_t k_patch_solve(const Ctx& c, const Level& L, int policy, const double*
     if (L.dense_lu) {
       patch_solve_lu2_kernel<<<dim3((unsigned)nb), dim3(64), 0, s>>>(
           L.consts, L.cell_info, L.cut_mats, c.geom(L), c.prm.eta, policy, L.node_class, L.Mcls, L.Mirr,
-          c.pattern, c.n_pattern, L.N, r, x, c.prm.omega, c.err);
+          c.pattern, c.n_pattern, L.N, r, x, c.prm.omega, c.err, c.none_integrate ? 1 : 0);
       return hipGetLastError();
     }
     if (c.n_pattern > kMaxPattern2) return hipErrorInvalidValue;
