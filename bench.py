@@ -506,6 +506,57 @@ def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0, n_war
     }
 
 
+def serving_fallback_extra(fcgmg, inputs, n_req=12, rate=8.0, workers=4, seed=2, restart=30):
+    """Admission under memory pressure: FP64 FGMRES(`restart`) requests from 2D 256^2 (seeds 0, 1) and
+    512^2 (seed 0) problems on a server whose device-memory budget lies between what the 512^2
+    problem needs under cache_none and under the two faster policies, so that it is admitted with
+    cache_none (Sec. 3.1.2's trade of speed for memory), while a 256^2 problem alone fits under
+    cache_inverse. Cold start, Poisson arrivals; latency is submit to completion."""
+    rng = np.random.default_rng(seed)
+    pool = [inputs.config2(0, n_cells=256, n_levels=6), inputs.config2(1, n_cells=256, n_levels=6), inputs.config2(0)]
+
+    def need(prob, pol):
+        ndof = (prob.dim + 1) * (prob.n_cells + 1) ** prob.dim
+        return fcgmg.footprint_bytes(prob, pol, fcgmg.PREC_FP64, fcgmg.SOLVER_FGMRES, restart) + 8 * ndof
+
+    big = pool[2]
+    fast = min(need(big, fcgmg.CACHE_INVERSE), need(big, fcgmg.CACHE_MATRIX))
+    budget = (need(big, fcgmg.CACHE_NONE) + fast) // 2
+    assert need(big, fcgmg.CACHE_NONE) < budget < fast and need(pool[0], fcgmg.CACHE_INVERSE) < budget
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    picks = rng.integers(0, len(pool), n_req)
+    srv = fcgmg.Server(workers=workers, hbm_budget=budget)
+    t0 = time.perf_counter()
+    ids = []
+    for k in range(n_req):
+        delay = t0 + arrivals[k] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(pool[picks[k]], solver=fcgmg.SOLVER_FGMRES, krylov_restart=restart))
+    res = [srv.wait(i)[1] for i in ids]
+    wall = time.perf_counter() - t0
+    srv.close()
+    ok = [r for r in res if r["status"] == fcgmg.OK]
+    by_size = {}
+    for k, r in zip(picks, res):
+        if r["status"] != fcgmg.OK:
+            continue
+        key = f"{pool[k].n_cells}^2"
+        d = by_size.setdefault(key, {fcgmg.POLICY_NAMES[q]: 0 for q in (0, 1, 2)})
+        d[fcgmg.POLICY_NAMES[r["policy"]]] += 1
+    lat = [r["t_total_ms"] for r in ok]
+    return {
+        "requests": n_req, "arrival_rate_per_s": rate, "workers": workers, "hbm_budget_bytes": int(budget),
+        "need_bytes_512": {fcgmg.POLICY_NAMES[q]: int(need(big, q)) for q in (0, 1, 2)},
+        "need_bytes_256_cache_inverse": int(need(pool[0], fcgmg.CACHE_INVERSE)),
+        "completed": len(ok), "policies_by_size": by_size,
+        "latency_ms_p50": round(pct(lat, 50), 2) if ok else None,
+        "latency_ms_p99": round(pct(lat, 99), 2) if ok else None,
+        "max_rel_res": float(max(r["rel_res"] for r in ok)) if ok else None,
+        "wall_s": round(wall, 2),
+    }
+
+
 def serving_batched_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=8, n_pool=32, seed=1):
     """Continuous batching: standalone GMG solves (V(2,2), FP64, cache_inverse, tolerance 1e-8) drawn
     from `n_pool` problems of the batching workload (2D, 64^2..256^2, 1..12 discs, alpha_f in
@@ -910,6 +961,8 @@ def main():
         out["batching"] = batch_extra(torch, fcgmg, inputs)
         log("serving ...")
         out["serving"] = serving_extra(fcgmg, inputs)
+        log("serving under a memory budget (policy fallback) ...")
+        out["serving_fallback"] = serving_fallback_extra(fcgmg, inputs)
         log("serving with continuous batching ...")
         out["serving_batched"] = serving_batched_extra(fcgmg, inputs)
         log("2D 4096^2 ...")
