@@ -318,13 +318,15 @@ def policy_extras(torch, fcgmg, prob, sweeps=4, integrated=False):
         h.smooth(x, b, 1)
         lat = time_sweeps(torch, h, x, b, sweeps)
         ms = float(np.median(lat))
+        vc_ms, _ = time_vcycles(torch, h, x, b, 2)  # every level under this policy
         st = h.stats()
         # one local solve per node and sweep, FP64 vector arithmetic: the fraction of the FP64 peak
         flops = patch_solve_flops(prob.dim) * st["n_nodes"]
         tflops = flops / (ms * 1e-3) / 1e12
         name = fcgmg.POLICY_NAMES[pol] + ("_integrated" if integ else "")
         out[name] = {
-            "sweep_ms_p50": round(ms, 4), "smoother_dof_per_s": round(h.ndofs() / (ms * 1e-3), 1),
+            "sweep_ms_p50": round(ms, 4), "vcycle_ms": round(vc_ms, 3),
+            "smoother_dof_per_s": round(h.ndofs() / (ms * 1e-3), 1),
             "cached_bytes_finest": st["cached_bytes"], "device_bytes": h.device_bytes(),
             "setup_s": round(setup, 3), "solve_gflop_per_sweep": round(flops / 1e9, 3),
             "achieved_tflops": round(tflops, 4), "fp64_vector_peak_frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 5)}
