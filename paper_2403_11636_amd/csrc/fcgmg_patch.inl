@@ -612,27 +612,36 @@ __device__ void lu_inverse_row2(const double* A, const int* piv, int row, double
   }
 }
 
-// y = A^{-1} g in place: g <- P g, L u = g, U y = u (one thread).
-__device__ void lu_solve2(const double* A, const int* piv, double* g) {
+// y = A^{-1} g in place (g <- P g, L u = g, U y = u with the factors of lu_factor2) by the whole
+// (single) wavefront of the workgroup: lane i keeps entry i, and each solved entry is broadcast to
+// the lanes below (forward: columns in ascending order) or above it (backward: descending order).
+// Every lane calls it.
+__device__ void lu_solve2_wave(const double* A, const int* piv, double* g) {
   constexpr int ZS = kLU2;
-  for (int k = 0; k < ZS; ++k) {
-    const int p = piv[k];
-    if (p != k) {
-      const double t = g[k];
-      g[k] = g[p];
-      g[p] = t;
+  static_assert(ZS <= 64, "one lane per row");
+  const int lane = (int)(threadIdx.x & 63);
+  if (lane == 0)
+    for (int k = 0; k < ZS; ++k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double t = g[k];
+        g[k] = g[p];
+        g[p] = t;
+      }
     }
+  __syncthreads();
+  double v = lane < ZS ? g[lane] : 0.0;
+  for (int j = 0; j < ZS; ++j) {
+    const double gj = __shfl(v, j);
+    if (lane > j && lane < ZS) v -= A[lane * ZS + j] * gj;
   }
-  for (int i = 0; i < ZS; ++i) {
-    double sum = g[i];
-    for (int j = 0; j < i; ++j) sum -= A[i * ZS + j] * g[j];
-    g[i] = sum;
+  for (int j = ZS - 1; j >= 0; --j) {
+    if (lane == j) v = v / A[j * ZS + j];
+    const double xj = __shfl(v, j);
+    if (lane < j) v -= A[lane * ZS + j] * xj;
   }
-  for (int i = ZS - 1; i >= 0; --i) {
-    double sum = g[i];
-    for (int j = i + 1; j < ZS; ++j) sum -= A[i * ZS + j] * g[j];
-    g[i] = sum / A[i * ZS + i];
-  }
+  __syncthreads();
+  if (lane < ZS) g[lane] = v;
 }
 
 // cache_inverse set-up with the immersed boundary terms (2D): the centre rows of L_i^{-1} from the
@@ -1507,7 +1516,7 @@ __global__ void __launch_bounds__(64) patch_solve_lu2_kernel(
     }
     patch_dense2(sh, A);
     const bool bad = lu_factor2(A, piv);
-    if (tid == 0 && !bad) lu_solve2(A, piv, gv);
+    if (!bad) lu_solve2_wave(A, piv, gv);
     __syncthreads();
     if (x != nullptr && tid <= D && !bad) x[tid * N + node] += omega * gv[centre[tid]];
     if (tid == 0 && bad) atomicMin(err, (int)node);
