@@ -508,13 +508,11 @@ def serving_extra(fcgmg, inputs, n_req=200, rate=200.0, workers=4, seed=0, n_war
     }
 
 
-def serving_fallback_extra(fcgmg, inputs, n_req=12, rate=8.0, workers=4, seed=2, restart=30):
-    """Admission under memory pressure: FP64 FGMRES(`restart`) requests from 2D 256^2 (seeds 0, 1) and
-    512^2 (seed 0) problems on a server whose device-memory budget lies between what the 512^2
-    problem needs under cache_none and under the two faster policies, so that it is admitted with
-    cache_none (Sec. 3.1.2's trade of speed for memory), while a 256^2 problem alone fits under
-    cache_inverse. Cold start, Poisson arrivals; latency is submit to completion."""
-    rng = np.random.default_rng(seed)
+def fallback_plan(fcgmg, inputs, restart=30):
+    """Pool and device-memory budget of serving_fallback_extra (host only): the budget is halfway
+    between what the 512^2 problem needs under cache_none and under the faster of the other two
+    policies (fcgmg_footprint_bytes of an FGMRES(`restart`) hierarchy plus the solution vector, as
+    the server admits it). Returns (pool, budget, need(prob, policy))."""
     pool = [inputs.config2(0, n_cells=256, n_levels=6), inputs.config2(1, n_cells=256, n_levels=6), inputs.config2(0)]
 
     def need(prob, pol):
@@ -525,6 +523,18 @@ def serving_fallback_extra(fcgmg, inputs, n_req=12, rate=8.0, workers=4, seed=2,
     fast = min(need(big, fcgmg.CACHE_INVERSE), need(big, fcgmg.CACHE_MATRIX))
     budget = (need(big, fcgmg.CACHE_NONE) + fast) // 2
     assert need(big, fcgmg.CACHE_NONE) < budget < fast and need(pool[0], fcgmg.CACHE_INVERSE) < budget
+    return pool, budget, need
+
+
+def serving_fallback_extra(fcgmg, inputs, n_req=12, rate=8.0, workers=4, seed=2, restart=30):
+    """Admission under memory pressure: FP64 FGMRES(`restart`) requests from 2D 256^2 (seeds 0, 1) and
+    512^2 (seed 0) problems on a server whose device-memory budget lies between what the 512^2
+    problem needs under cache_none and under the two faster policies, so that it is admitted with
+    cache_none (Sec. 3.1.2's trade of speed for memory), while a 256^2 problem alone fits under
+    cache_inverse. Cold start, Poisson arrivals; latency is submit to completion."""
+    rng = np.random.default_rng(seed)
+    pool, budget, need = fallback_plan(fcgmg, inputs, restart)
+    big = pool[2]
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
     picks = rng.integers(0, len(pool), n_req)
     srv = fcgmg.Server(workers=workers, hbm_budget=budget)

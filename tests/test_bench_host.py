@@ -92,3 +92,17 @@ def test_patch_solve_count_is_below_dense_lu_and_grows_with_dimension():
         size = d * 5 ** d + 3 ** d  # 59 / 402 DoFs of a patch
         assert 0 < bench.patch_solve_flops(d) < 2 * size ** 3 // 3
     assert bench.patch_solve_flops(3) > 50 * bench.patch_solve_flops(2)
+
+
+def test_fallback_leg_budget_forces_cache_none_for_the_large_problem():
+    # The serving leg under memory pressure: with nothing else resident, the 512^2 problem fits its
+    # budget only under cache_none, while a 256^2 problem fits under cache_inverse (footprints are
+    # host-only planning, no GPU).
+    from paper_2403_11636_amd import fcgmg, inputs
+    pool, budget, need = bench.fallback_plan(fcgmg, inputs)
+    big = pool[2]
+    assert big.n_cells == 512
+    assert need(big, fcgmg.CACHE_NONE) <= budget
+    assert need(big, fcgmg.CACHE_INVERSE) > budget and need(big, fcgmg.CACHE_MATRIX) > budget
+    for small in pool[:2]:
+        assert small.n_cells == 256 and need(small, fcgmg.CACHE_INVERSE) <= budget
